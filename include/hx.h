@@ -1,0 +1,277 @@
+/*
+ * hx — asynchronous copies and stencil launches composed as a future graph,
+ * for one AMD Instinct MI355X (gfx950).
+ *
+ * The paper (Diehl et al., "Integration of CUDA Processing within HPX",
+ * arXiv:1810.11482) gives every accelerator operation an asynchronous return
+ * value (Sec. III-A "Futurization"), organises the accelerator as a device
+ * with its own work queue, buffers on that device and programs run on it
+ * (Sec. IV, the device/buffer/program classes), and composes copies and kernel
+ * runs through those return values so that copies overlap computation
+ * (Sec. IV-B, Listing 2; Sec. V-A.2, Algorithm 1).  This header is that
+ * interface as a C ABI:
+ *
+ *   paper                                  hx
+ *   device (own async work queue)          hx_ctx (one GPU, its stream set)
+ *   device.create_buffer(bytes)            hx_buffer_create
+ *   buffer.enqueue_write / enqueue_read    hx_copy_async (H2D / D2H)
+ *   program.run(args, grid, block)         hx_launch_* (deps = futures)
+ *   hpx::future<void>                      hx_event
+ *   hpx::when_all / wait_all / .get()      hx_when_all / hx_wait
+ *   cudaMallocHost                         hx_host_alloc
+ *
+ * Conventions
+ *  - Every function returns an hx_status: HX_OK (0) or a negative error.
+ *  - Handles (hx_buffer, hx_event, hx_plan) are opaque 64-bit values tagged
+ *    with a generation; a released or foreign handle gives HX_ERR_INVALID.
+ *    The value 0 is never a valid handle; as a dependency, event 0 means
+ *    "already complete" and is ignored.
+ *  - Argument and validation errors are reported synchronously: nothing is
+ *    enqueued and the output event is left untouched.
+ *  - Operations take a list of events they depend on.  The dependency is
+ *    resolved on the GPU (stream-waits on the producers' events); the host
+ *    blocks only in hx_wait.  If a dependency has failed the operation is not
+ *    run and its event completes with HX_ERR_DEP_FAILED (exception-carrying
+ *    futures).  A dependency on a user event that is not yet set holds the
+ *    operation back on the host until it is.
+ *  - Byte offsets are into the buffer; element counts are in cells of the
+ *    operation's dtype.
+ *  - All calls on one context are thread-safe.
+ */
+#ifndef HX_H
+#define HX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ----------------------------------------------------------------- status */
+typedef int32_t hx_status;
+
+#define HX_OK 0
+#define HX_PENDING 1           /* event not complete yet (hx_event_query) */
+#define HX_ERR_INVALID (-1)    /* unknown, released or foreign handle */
+#define HX_ERR_ARG (-2)        /* invalid argument */
+#define HX_ERR_NO_DEVICE (-3)  /* no GPU, or a host-only context */
+#define HX_ERR_HIP (-4)        /* the HIP runtime reported an error */
+#define HX_ERR_OOM (-5)        /* allocation failed */
+#define HX_ERR_DEP_FAILED (-6) /* a dependency failed; the operation did not run */
+#define HX_ERR_TIMEOUT (-7)    /* hx_wait timed out; the event is still pending */
+#define HX_ERR_INJECTED (-8)   /* failure injected by hx_debug_inject */
+#define HX_ERR_HAZARD (-9)     /* hazard checker found an unordered conflict */
+#define HX_ERR_UNSUPPORTED (-10)
+#define HX_ERR_RANGE (-11)     /* byte range outside a buffer */
+
+typedef struct hx_ctx_s* hx_ctx;
+typedef uint64_t hx_buffer;
+typedef uint64_t hx_event;
+typedef uint64_t hx_plan;
+
+typedef enum { HX_F32 = 0, HX_F64 = 1 } hx_dtype;
+
+/* Human-readable name of a status code (static string). */
+const char* hx_status_string(hx_status s);
+
+/* ----------------------------------------------------------------- device */
+typedef struct {
+    char name[64];
+    char arch[64];          /* e.g. "gfx950" */
+    int compute_units;
+    int wavefront_size;
+    int clock_khz;
+    int memory_clock_khz;
+    int memory_bus_bits;
+    size_t hbm_bytes;
+    size_t lds_bytes_per_cu;
+    size_t l2_bytes;
+} hx_device_info_t;
+
+/* Number of visible GPUs (0 when there is none). */
+hx_status hx_device_count(int* count);
+
+/* Properties of device `dev`.  Stands in for the paper's device discovery with
+ * a capability filter (Sec. IV-A, Listing 1), restricted to local devices. */
+hx_status hx_device_info(int dev, hx_device_info_t* info);
+
+/* ---------------------------------------------------------------- context */
+typedef struct {
+    int compute_streams;        /* kernel streams; 0 = 4 */
+    void* external_stream;      /* optional hipStream_t used as compute stream 0
+                                   (e.g. torch's current stream); not owned */
+    int check;                  /* 1 = record accesses and run the hazard checker */
+    int timing;                 /* 1 = events carry timestamps (hx_event_elapsed) */
+} hx_ctx_opts;
+
+/* Create a context on device `dev` (the paper's device with its own work
+ * queue, Sec. IV).  dev = -1 creates a host-only context: events, user events,
+ * hx_when_all, hx_wait and the hazard checker work, every GPU operation returns
+ * HX_ERR_NO_DEVICE.  `opts` may be NULL.  On error *ctx is untouched. */
+hx_status hx_ctx_create(int dev, const hx_ctx_opts* opts, hx_ctx* ctx);
+
+/* Wait for all outstanding work, then free every buffer, plan and event the
+ * context owns (wrapped memory is not freed). */
+hx_status hx_ctx_destroy(hx_ctx ctx);
+
+/* Block until every operation submitted so far has finished. */
+hx_status hx_ctx_synchronize(hx_ctx ctx);
+
+/* Last error message recorded on the context (truncated to len-1 bytes). */
+hx_status hx_last_error(hx_ctx ctx, char* buf, size_t len);
+
+/* ---------------------------------------------------------------- buffers */
+/* Device allocation of `bytes` (the paper's create_buffer, Sec. IV and
+ * Listing 2).  The memory is uninitialised and owned by the context. */
+hx_status hx_buffer_create(hx_ctx ctx, size_t bytes, hx_buffer* buf);
+
+/* Wrap existing device memory (e.g. a torch tensor's storage) without taking
+ * ownership; hx_buffer_destroy never frees it. */
+hx_status hx_buffer_wrap(hx_ctx ctx, void* dev_ptr, size_t bytes, hx_buffer* buf);
+
+/* Release a buffer handle.  The handle is invalid at once; the memory of an
+ * owned buffer is freed only after every submitted operation that uses it has
+ * completed. */
+hx_status hx_buffer_destroy(hx_ctx ctx, hx_buffer buf);
+
+/* Device address and size of a buffer. */
+hx_status hx_buffer_ptr(hx_ctx ctx, hx_buffer buf, void** dev_ptr, size_t* bytes);
+
+/* Page-locked host memory (cudaMallocHost in Listing 2), which makes host
+ * copies truly asynchronous.  Freed with hx_host_free or at context destroy. */
+hx_status hx_host_alloc(hx_ctx ctx, size_t bytes, void** host_ptr);
+hx_status hx_host_free(hx_ctx ctx, void* host_ptr);
+
+/* ----------------------------------------------------------------- copies */
+typedef enum { HX_H2D = 0, HX_D2H = 1, HX_D2D = 2 } hx_copy_dir;
+
+typedef struct {
+    int dir;                 /* hx_copy_dir */
+    void* host;              /* H2D: source, D2H: destination (caller-owned; must
+                                stay valid until the event completes; pinned
+                                memory from hx_host_alloc makes it asynchronous) */
+    hx_buffer buf;           /* H2D/D2D: destination, D2H: source */
+    size_t offset;           /* byte offset into buf */
+    hx_buffer src_buf;       /* D2D: source buffer */
+    size_t src_offset;       /* D2D: byte offset into src_buf */
+    size_t bytes;
+} hx_copy_desc;
+
+/* Asynchronous copy (the paper's enqueue_write / enqueue_read, Sec. IV and
+ * Listing 2; cudaMemcpyAsync in Algorithm 1).  H2D copies run on the
+ * context's host-to-device stream, D2H copies on its device-to-host stream, so
+ * the two directions and the kernels of other partitions overlap.  Ranges are
+ * checked against the buffer (HX_ERR_RANGE). */
+hx_status hx_copy_async(hx_ctx ctx, const hx_copy_desc* desc, const hx_event* deps, int ndeps,
+                        hx_event* out);
+
+/* ---------------------------------------------------------------- stencil */
+typedef enum {
+    HX_BC_PERIODIC = 0,      /* wrap around the array (1D only, both sides) */
+    HX_BC_DIRICHLET0 = 1,    /* cells outside are held at 0 at every step */
+    HX_BC_GHOST = 2          /* cells outside come from a halo region */
+} hx_bc;
+
+typedef struct {
+    int dims;                /* 1 = 3-point line, 2 = 5-point grid */
+    int dtype;               /* hx_dtype */
+    int64_t nx;              /* 1D: cells; 2D: cells per row (row-major, no padding) */
+    int64_t ny;              /* 2D: rows; ignored in 1D */
+    int steps;               /* explicit time steps to take */
+    double r;                /* diffusion number (dt / h^2 times the diffusivity) */
+    hx_buffer in;  size_t in_offset;
+    hx_buffer out; size_t out_offset;   /* must not overlap in */
+    hx_buffer tmp; size_t tmp_offset;   /* ping-pong space of the same size, needed only
+                                           when the run takes more than one pass */
+    int bc_lo;               /* 1D: left end, 2D: top edge (hx_bc) */
+    int bc_hi;               /* 1D: right end, 2D: bottom edge (hx_bc) */
+    hx_buffer halo_lo; size_t halo_lo_offset;  /* HX_BC_GHOST: halo_width cells (1D) or rows
+                                                  (2D) that precede the first cell/row; its
+                                                  last cell/row is index -1 */
+    hx_buffer halo_hi; size_t halo_hi_offset;  /* HX_BC_GHOST: halo_width cells/rows that
+                                                  follow the last; its first is index n */
+    int halo_width;
+    /* Launch geometry (the paper keeps block and grid sizes in the user's hands,
+     * Sec. IV-B and Sec. VI).  0 = the tuned default. */
+    int cells_per_lane;      /* 1D: 8, 16, 32 or 64; 2D: 4 or 8 */
+    int time_block;          /* steps fused per kernel pass */
+    int waves_per_group;     /* 1, 2 or 4 */
+    int rows_per_block;      /* 2D: output rows per wave */
+} hx_stencil_args;
+
+/* Advance the heat equation `steps` explicit steps from `in` into `out`
+ * (the data-parallel kernel run of Sec. IV-B / Algorithm 1, with the
+ * 3-point stencil of Sec. V-A.1 in heat form):
+ *   1D  u'_i  = u_i + r (u_{i-1} - 2 u_i + u_{i+1})
+ *   2D  u'_ij = u_ij + r (u_{i-1,j} + u_{i+1,j} + u_{i,j-1} + u_{i,j+1} - 4 u_ij)
+ * In 2D the left and right edges are always zero-Dirichlet.  With a GHOST side
+ * the run is one fused pass and needs steps <= halo_width (the halo supplies
+ * the whole light cone); otherwise steps may be anything and passes of
+ * `time_block` steps ping-pong between out and tmp, ending in out.
+ * Stable for r <= 1/2 (1D) and r <= 1/4 (2D); other r are accepted. */
+hx_status hx_launch_stencil(hx_ctx ctx, const hx_stencil_args* args, const hx_event* deps,
+                            int ndeps, hx_event* out);
+
+/* ------------------------------------------------------------------ events */
+/* An event that completes when every event in `events` has completed (the
+ * paper's when_all, Sec. III-A); it fails with HX_ERR_DEP_FAILED if any of them
+ * fails.  n = 0 gives an already-complete event. */
+hx_status hx_when_all(hx_ctx ctx, const hx_event* events, int n, hx_event* out);
+
+/* Block until `ev` completes (the paper's wait_all / future::get) or
+ * `timeout_ns` elapses (< 0 = no limit).  Returns the event's final status
+ * (HX_OK or its error) or HX_ERR_TIMEOUT. */
+hx_status hx_wait(hx_ctx ctx, hx_event ev, int64_t timeout_ns);
+
+/* Non-blocking: *state = HX_PENDING, HX_OK or the event's error. */
+hx_status hx_event_query(hx_ctx ctx, hx_event ev, hx_status* state);
+
+/* Drop the caller's reference.  Operations that depend on the event are not
+ * affected. */
+hx_status hx_event_release(hx_ctx ctx, hx_event ev);
+
+/* Milliseconds between two completed events of a context created with
+ * timing = 1 (both must be GPU operations). */
+hx_status hx_event_elapsed(hx_ctx ctx, hx_event start, hx_event stop, double* ms);
+
+/* A host-completed event: operations that depend on it are held back until
+ * hx_user_event_set is called; status HX_OK releases them, an error fails them
+ * with HX_ERR_DEP_FAILED. */
+hx_status hx_user_event_create(hx_ctx ctx, hx_event* out);
+hx_status hx_user_event_set(hx_ctx ctx, hx_event ev, hx_status status);
+
+/* Interop with foreign streams (e.g. torch's current stream): an event that
+ * completes when the work queued on `hip_stream` so far has, and a stream-wait
+ * that makes `hip_stream` wait for `ev` on the GPU. */
+hx_status hx_event_record_stream(hx_ctx ctx, void* hip_stream, hx_event* out);
+hx_status hx_stream_wait_event(hx_ctx ctx, void* hip_stream, hx_event ev);
+
+/* ------------------------------------------------------ diagnostics/testing */
+/* Sequence number the next submitted operation will get. */
+hx_status hx_debug_next_seq(hx_ctx ctx, uint64_t* seq);
+
+/* Make the operation with sequence number `seq` fail validation: it does not
+ * run and its event completes with HX_ERR_INJECTED.  The environment variable
+ * HX_FAULT_INJECT=<seq> does the same at context creation. */
+hx_status hx_debug_inject(hx_ctx ctx, uint64_t seq);
+
+/* Hazard checker (contexts created with check = 1): every operation declares
+ * the byte ranges it reads and writes; two accesses to overlapping ranges of a
+ * buffer, at least one a write, must be ordered by the dependency graph (or by
+ * an hx_wait on the earlier one).  Unordered pairs are counted and described. */
+hx_status hx_hazard_count(hx_ctx ctx, int64_t* count);
+hx_status hx_hazard_report(hx_ctx ctx, char* buf, size_t len);
+
+/* -------------------------------------------------------------- autotuner */
+/* Write the process-wide tuned-geometry cache to `path` as JSON; the cache is
+ * read back from the file named by HX_TUNE_CACHE on first use. */
+hx_status hx_tune_cache_save(const char* path);
+/* Forget every tuned geometry (built-in defaults apply again). */
+hx_status hx_tune_cache_clear(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HX_H */

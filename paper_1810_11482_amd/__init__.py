@@ -1,0 +1,329 @@
+"""Python binding of libhx (include/hx.h): argument marshalling only.
+
+Every function keeps the C name and signature shape; handles are plain ints,
+argument structs are ctypes mirrors of the C structs, and a negative status
+raises HxError carrying the context's last error message.  All computation
+runs in the HIP kernels of libhx.so; importing this module without a built
+library raises ImportError (there is no fallback).
+
+torch is imported first: libhx links the HIP runtime that torch ships, and
+loading torch first makes both use that one runtime instance.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # noqa: F401  (loads the HIP runtime libhx links against)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhx.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1810_11482_amd.build`")
+lib = ctypes.CDLL(LIB_PATH)
+
+# ------------------------------------------------------------------ constants
+HX_OK = 0
+HX_PENDING = 1
+HX_ERR_INVALID = -1
+HX_ERR_ARG = -2
+HX_ERR_NO_DEVICE = -3
+HX_ERR_HIP = -4
+HX_ERR_OOM = -5
+HX_ERR_DEP_FAILED = -6
+HX_ERR_TIMEOUT = -7
+HX_ERR_INJECTED = -8
+HX_ERR_HAZARD = -9
+HX_ERR_UNSUPPORTED = -10
+HX_ERR_RANGE = -11
+
+HX_F32, HX_F64 = 0, 1
+HX_H2D, HX_D2H, HX_D2D = 0, 1, 2
+HX_BC_PERIODIC, HX_BC_DIRICHLET0, HX_BC_GHOST = 0, 1, 2
+
+_u64 = ctypes.c_uint64
+_i64 = ctypes.c_int64
+_sz = ctypes.c_size_t
+_i32 = ctypes.c_int32
+_vp = ctypes.c_void_p
+
+
+# -------------------------------------------------------------------- structs
+class hx_device_info_t(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 64), ("arch", ctypes.c_char * 64),
+                ("compute_units", ctypes.c_int), ("wavefront_size", ctypes.c_int),
+                ("clock_khz", ctypes.c_int), ("memory_clock_khz", ctypes.c_int),
+                ("memory_bus_bits", ctypes.c_int), ("hbm_bytes", _sz),
+                ("lds_bytes_per_cu", _sz), ("l2_bytes", _sz)]
+
+
+class hx_ctx_opts(ctypes.Structure):
+    _fields_ = [("compute_streams", ctypes.c_int), ("external_stream", _vp),
+                ("check", ctypes.c_int), ("timing", ctypes.c_int)]
+
+
+class hx_copy_desc(ctypes.Structure):
+    _fields_ = [("dir", ctypes.c_int), ("host", _vp), ("buf", _u64), ("offset", _sz),
+                ("src_buf", _u64), ("src_offset", _sz), ("bytes", _sz)]
+
+
+class hx_stencil_args(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int), ("dtype", ctypes.c_int), ("nx", _i64), ("ny", _i64),
+                ("steps", ctypes.c_int), ("r", ctypes.c_double),
+                ("in_", _u64), ("in_offset", _sz), ("out", _u64), ("out_offset", _sz),
+                ("tmp", _u64), ("tmp_offset", _sz),
+                ("bc_lo", ctypes.c_int), ("bc_hi", ctypes.c_int),
+                ("halo_lo", _u64), ("halo_lo_offset", _sz),
+                ("halo_hi", _u64), ("halo_hi_offset", _sz),
+                ("halo_width", ctypes.c_int),
+                ("cells_per_lane", ctypes.c_int), ("time_block", ctypes.c_int),
+                ("waves_per_group", ctypes.c_int), ("rows_per_block", ctypes.c_int)]
+
+
+# ----------------------------------------------------------------- prototypes
+_PROTOS = {
+    "hx_status_string": (ctypes.c_char_p, [_i32]),
+    "hx_device_count": (_i32, [ctypes.POINTER(ctypes.c_int)]),
+    "hx_device_info": (_i32, [ctypes.c_int, ctypes.POINTER(hx_device_info_t)]),
+    "hx_ctx_create": (_i32, [ctypes.c_int, ctypes.POINTER(hx_ctx_opts), ctypes.POINTER(_vp)]),
+    "hx_ctx_destroy": (_i32, [_vp]),
+    "hx_ctx_synchronize": (_i32, [_vp]),
+    "hx_last_error": (_i32, [_vp, ctypes.c_char_p, _sz]),
+    "hx_buffer_create": (_i32, [_vp, _sz, ctypes.POINTER(_u64)]),
+    "hx_buffer_wrap": (_i32, [_vp, _vp, _sz, ctypes.POINTER(_u64)]),
+    "hx_buffer_destroy": (_i32, [_vp, _u64]),
+    "hx_buffer_ptr": (_i32, [_vp, _u64, ctypes.POINTER(_vp), ctypes.POINTER(_sz)]),
+    "hx_host_alloc": (_i32, [_vp, _sz, ctypes.POINTER(_vp)]),
+    "hx_host_free": (_i32, [_vp, _vp]),
+    "hx_copy_async": (_i32, [_vp, ctypes.POINTER(hx_copy_desc), ctypes.POINTER(_u64),
+                             ctypes.c_int, ctypes.POINTER(_u64)]),
+    "hx_launch_stencil": (_i32, [_vp, ctypes.POINTER(hx_stencil_args), ctypes.POINTER(_u64),
+                                 ctypes.c_int, ctypes.POINTER(_u64)]),
+    "hx_when_all": (_i32, [_vp, ctypes.POINTER(_u64), ctypes.c_int, ctypes.POINTER(_u64)]),
+    "hx_wait": (_i32, [_vp, _u64, _i64]),
+    "hx_event_query": (_i32, [_vp, _u64, ctypes.POINTER(_i32)]),
+    "hx_event_release": (_i32, [_vp, _u64]),
+    "hx_event_elapsed": (_i32, [_vp, _u64, _u64, ctypes.POINTER(ctypes.c_double)]),
+    "hx_user_event_create": (_i32, [_vp, ctypes.POINTER(_u64)]),
+    "hx_user_event_set": (_i32, [_vp, _u64, _i32]),
+    "hx_event_record_stream": (_i32, [_vp, _vp, ctypes.POINTER(_u64)]),
+    "hx_stream_wait_event": (_i32, [_vp, _vp, _u64]),
+    "hx_debug_next_seq": (_i32, [_vp, ctypes.POINTER(_u64)]),
+    "hx_debug_inject": (_i32, [_vp, _u64]),
+    "hx_hazard_count": (_i32, [_vp, ctypes.POINTER(_i64)]),
+    "hx_hazard_report": (_i32, [_vp, ctypes.c_char_p, _sz]),
+    "hx_tune_cache_save": (_i32, [ctypes.c_char_p]),
+    "hx_tune_cache_clear": (_i32, []),
+}
+for _name, (_res, _args) in _PROTOS.items():
+    _f = getattr(lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class HxError(RuntimeError):
+    def __init__(self, status: int, msg: str = ""):
+        self.status = status
+        super().__init__(f"{hx_status_string(status)}: {msg}" if msg else hx_status_string(status))
+
+
+def hx_status_string(s: int) -> str:
+    return lib.hx_status_string(s).decode()
+
+
+def _err(ctx, s: int):
+    msg = ""
+    if ctx:
+        buf = ctypes.create_string_buffer(1024)
+        if lib.hx_last_error(ctx, buf, 1024) == 0:
+            msg = buf.value.decode(errors="replace")
+    raise HxError(s, msg)
+
+
+def _ok(ctx, s: int) -> None:
+    if s < 0:
+        _err(ctx, s)
+
+
+def _deps(deps):
+    deps = [int(d) for d in (deps or []) if d]
+    arr = (_u64 * max(1, len(deps)))(*deps)
+    return arr, len(deps)
+
+
+# ------------------------------------------------------------------ functions
+def hx_device_count() -> int:
+    n = ctypes.c_int()
+    _ok(None, lib.hx_device_count(ctypes.byref(n)))
+    return n.value
+
+
+def hx_device_info(dev: int = 0) -> hx_device_info_t:
+    info = hx_device_info_t()
+    _ok(None, lib.hx_device_info(dev, ctypes.byref(info)))
+    return info
+
+
+def hx_ctx_create(dev: int = 0, compute_streams: int = 0, external_stream=None, check=False,
+                  timing=False):
+    opts = hx_ctx_opts(compute_streams, external_stream, int(bool(check)), int(bool(timing)))
+    ctx = _vp()
+    _ok(None, lib.hx_ctx_create(dev, ctypes.byref(opts), ctypes.byref(ctx)))
+    return ctx
+
+
+def hx_ctx_destroy(ctx) -> None:
+    _ok(None, lib.hx_ctx_destroy(ctx))
+
+
+def hx_ctx_synchronize(ctx) -> None:
+    _ok(ctx, lib.hx_ctx_synchronize(ctx))
+
+
+def hx_last_error(ctx) -> str:
+    buf = ctypes.create_string_buffer(4096)
+    _ok(None, lib.hx_last_error(ctx, buf, 4096))
+    return buf.value.decode(errors="replace")
+
+
+def hx_buffer_create(ctx, nbytes: int) -> int:
+    h = _u64()
+    _ok(ctx, lib.hx_buffer_create(ctx, nbytes, ctypes.byref(h)))
+    return h.value
+
+
+def hx_buffer_wrap(ctx, dev_ptr: int, nbytes: int) -> int:
+    h = _u64()
+    _ok(ctx, lib.hx_buffer_wrap(ctx, dev_ptr, nbytes, ctypes.byref(h)))
+    return h.value
+
+
+def hx_buffer_destroy(ctx, buf: int) -> None:
+    _ok(ctx, lib.hx_buffer_destroy(ctx, buf))
+
+
+def hx_buffer_ptr(ctx, buf: int):
+    p, n = _vp(), _sz()
+    _ok(ctx, lib.hx_buffer_ptr(ctx, buf, ctypes.byref(p), ctypes.byref(n)))
+    return p.value or 0, n.value
+
+
+def hx_host_alloc(ctx, nbytes: int) -> int:
+    p = _vp()
+    _ok(ctx, lib.hx_host_alloc(ctx, nbytes, ctypes.byref(p)))
+    return p.value
+
+
+def hx_host_free(ctx, ptr: int) -> None:
+    _ok(ctx, lib.hx_host_free(ctx, ptr))
+
+
+def hx_copy_async(ctx, desc: hx_copy_desc, deps=()) -> int:
+    arr, n = _deps(deps)
+    ev = _u64()
+    _ok(ctx, lib.hx_copy_async(ctx, ctypes.byref(desc), arr, n, ctypes.byref(ev)))
+    return ev.value
+
+
+def hx_launch_stencil(ctx, args: hx_stencil_args, deps=()) -> int:
+    arr, n = _deps(deps)
+    ev = _u64()
+    _ok(ctx, lib.hx_launch_stencil(ctx, ctypes.byref(args), arr, n, ctypes.byref(ev)))
+    return ev.value
+
+
+def hx_when_all(ctx, events) -> int:
+    evs = [int(e) for e in events]
+    arr = (_u64 * max(1, len(evs)))(*evs)
+    ev = _u64()
+    _ok(ctx, lib.hx_when_all(ctx, arr, len(evs), ctypes.byref(ev)))
+    return ev.value
+
+
+def hx_wait(ctx, ev: int, timeout_ns: int = -1) -> int:
+    """Returns the event's final status (or HX_ERR_TIMEOUT); raises only for an
+    invalid handle."""
+    s = lib.hx_wait(ctx, ev, timeout_ns)
+    if s == HX_ERR_INVALID:
+        _err(ctx, s)
+    return s
+
+
+def hx_event_query(ctx, ev: int) -> int:
+    st = _i32()
+    _ok(ctx, lib.hx_event_query(ctx, ev, ctypes.byref(st)))
+    return st.value
+
+
+def hx_event_release(ctx, ev: int) -> None:
+    _ok(ctx, lib.hx_event_release(ctx, ev))
+
+
+def hx_event_elapsed(ctx, start: int, stop: int) -> float:
+    ms = ctypes.c_double()
+    _ok(ctx, lib.hx_event_elapsed(ctx, start, stop, ctypes.byref(ms)))
+    return ms.value
+
+
+def hx_user_event_create(ctx) -> int:
+    ev = _u64()
+    _ok(ctx, lib.hx_user_event_create(ctx, ctypes.byref(ev)))
+    return ev.value
+
+
+def hx_user_event_set(ctx, ev: int, status: int = HX_OK) -> None:
+    _ok(ctx, lib.hx_user_event_set(ctx, ev, status))
+
+
+def hx_event_record_stream(ctx, hip_stream: int) -> int:
+    ev = _u64()
+    _ok(ctx, lib.hx_event_record_stream(ctx, hip_stream, ctypes.byref(ev)))
+    return ev.value
+
+
+def hx_stream_wait_event(ctx, hip_stream: int, ev: int) -> None:
+    _ok(ctx, lib.hx_stream_wait_event(ctx, hip_stream, ev))
+
+
+def hx_debug_next_seq(ctx) -> int:
+    s = _u64()
+    _ok(ctx, lib.hx_debug_next_seq(ctx, ctypes.byref(s)))
+    return s.value
+
+
+def hx_debug_inject(ctx, seq: int) -> None:
+    _ok(ctx, lib.hx_debug_inject(ctx, seq))
+
+
+def hx_hazard_count(ctx) -> int:
+    n = _i64()
+    _ok(ctx, lib.hx_hazard_count(ctx, ctypes.byref(n)))
+    return n.value
+
+
+def hx_hazard_report(ctx) -> str:
+    buf = ctypes.create_string_buffer(65536)
+    _ok(ctx, lib.hx_hazard_report(ctx, buf, 65536))
+    return buf.value.decode(errors="replace")
+
+
+def hx_tune_cache_save(path: str) -> None:
+    _ok(None, lib.hx_tune_cache_save(path.encode()))
+
+
+def hx_tune_cache_clear() -> None:
+    _ok(None, lib.hx_tune_cache_clear())
+
+
+def stencil_args(**kw) -> hx_stencil_args:
+    """hx_stencil_args with keyword fields (`in_` may be given as `inp`)."""
+    if "inp" in kw:
+        kw["in_"] = kw.pop("inp")
+    a = hx_stencil_args()
+    a.dims = 1
+    a.ny = 1
+    for k, v in kw.items():
+        if not hasattr(a, k):
+            raise TypeError(f"hx_stencil_args has no field {k}")
+        setattr(a, k, v)
+    return a

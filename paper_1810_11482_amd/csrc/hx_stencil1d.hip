@@ -1,0 +1,244 @@
+// 1D explicit heat stencil with temporal blocking, for gfx950.
+//
+// Operation: u'_i = u_i + r (u_{i-1} - 2 u_i + u_{i+1}) (the 3-point stencil of
+// the paper's Sec. V-A.1 in heat form), `steps` steps fused per pass.
+//
+// Mapping.  Every wave owns a tile of 64*C consecutive cells held in registers,
+// C per lane and lane-contiguous (lane l holds cells l*C .. l*C+C-1 of the
+// tile).  The outer `halo` cells on each side are context: they are loaded,
+// advanced with the rest and discarded, so after `steps` <= halo steps the
+// inner 64*C - 2*halo cells are exact and are written.  A step needs, per lane,
+// only the last cell of the lane below and the first cell of the lane above;
+// both come from a single DPP wave shift (wave_shr:1 / wave_shl:1), so the
+// whole time loop runs out of registers with no LDS and no barrier, and waves
+// are fully independent.  HBM traffic per pass is one read and one write of
+// every cell plus 2*halo/(64*C) of re-read context.
+//
+// Per cell-step the arithmetic is s = l + r_; d = fma(-2, c, s);
+// c' = fma(r, d, c), written with explicit fma so every kernel in this library
+// that advances a cell does so with the same rounding.
+#include <hip/hip_runtime.h>
+
+#include "hx_internal.h"
+
+namespace hx {
+namespace {
+
+enum { BC_PERIODIC = 0, BC_DIRICHLET0 = 1, BC_GHOST = 2 };
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+template <typename T> struct V16;
+template <> struct V16<float> { typedef f32x4 t; enum { N = 4 }; };
+template <> struct V16<double> { typedef f64x2 t; enum { N = 2 }; };
+
+// DPP controls of the wave-wide shifts: lane i reads lane i-1 (shr) or i+1 (shl);
+// the lane with no source reads 0.
+constexpr int DPP_WAVE_SHL1 = 0x130;
+constexpr int DPP_WAVE_SHR1 = 0x138;
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+    int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, true);
+    int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// One cell-step: c + r*((l + rt) - 2c).
+template <typename T>
+__device__ __forceinline__ T heat_point(T l, T c, T rt, T k) {
+    T s = l + rt;
+    T d = fmaT(T(-2), c, s);
+    return fmaT(k, d, c);
+}
+
+// Value of cell g (any integer) of segment s at the start of the pass.
+template <typename T>
+__device__ __forceinline__ T load_cell(const Seg1D& s, int64_t g) {
+    const T* in = static_cast<const T*>(s.in);
+    if (g >= 0 && g < s.n) return in[g];
+    if (g < 0) {
+        if (s.bc_lo == BC_PERIODIC) {
+            int64_t m = g % s.n;
+            if (m < 0) m += s.n;
+            return in[m];
+        }
+        if (s.bc_lo == BC_GHOST && g >= -(int64_t)s.hw)
+            return static_cast<const T*>(s.halo_lo)[s.hw + g];
+        return T(0);
+    }
+    if (s.bc_hi == BC_PERIODIC) return in[g % s.n];
+    if (s.bc_hi == BC_GHOST && g - s.n < (int64_t)s.hw)
+        return static_cast<const T*>(s.halo_hi)[g - s.n];
+    return T(0);
+}
+
+// One step of a whole wave tile: a (registers, lane-contiguous) -> b.  The cell
+// left of a lane's first comes from the lane below, the cell right of its last
+// from the lane above (DPP wave shifts).  Cells outside a zero-Dirichlet end are
+// reset to 0 after the step.
+template <typename T, int C>
+__device__ __forceinline__ void step_tile(const T (&a)[C], T (&b)[C], T k, bool zero_lo,
+                                          bool zero_hi, int64_t lbase, int64_t n) {
+    const T left = dpp_move<DPP_WAVE_SHR1>(a[C - 1]);
+    const T right = dpp_move<DPP_WAVE_SHL1>(a[0]);
+#pragma unroll
+    for (int j = 0; j < C; ++j)
+        b[j] = heat_point<T>(j > 0 ? a[j - 1] : left, a[j], j + 1 < C ? a[j + 1] : right, k);
+    if (zero_lo || zero_hi) {
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            const int64_t g = lbase + j;
+            if ((zero_lo && g < 0) || (zero_hi && g >= n)) b[j] = T(0);
+        }
+    }
+}
+
+__device__ __forceinline__ bool aligned16(const void* p) {
+    return (reinterpret_cast<uintptr_t>(p) & 15u) == 0;
+}
+
+// Advance tile `tile` of segment `s` by `steps` steps (see the file comment).
+template <typename T, int C>
+__device__ __forceinline__ void tile1d(const Seg1D& s, int64_t tile, int steps, int halo) {
+    typedef typename V16<T>::t VT;
+    constexpr int VN = V16<T>::N;
+    static_assert(C % VN == 0, "cells per lane must be a multiple of the vector width");
+    const int lane = threadIdx.x & 63;
+    const int64_t n = s.n;
+    const int64_t wout = 64LL * C - 2LL * halo;
+    const int64_t o0 = tile * wout;
+    const int64_t base = o0 - halo;
+    const int64_t lbase = base + (int64_t)lane * C;
+    const T* in = static_cast<const T*>(s.in);
+    T* out = static_cast<T*>(s.out);
+    const bool interior = base >= 0 && base + 64LL * C <= n;
+
+    T v[C];
+    if (interior && aligned16(in + base)) {
+        const VT* src = reinterpret_cast<const VT*>(in + lbase);
+#pragma unroll
+        for (int q = 0; q < C / VN; ++q) {
+            const VT x = __builtin_nontemporal_load(src + q);
+#pragma unroll
+            for (int e = 0; e < VN; ++e) v[q * VN + e] = x[e];
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < C; ++j) v[j] = load_cell<T>(s, lbase + j);
+    }
+
+    const T k = static_cast<T>(s.r);
+    const bool zero_lo = s.bc_lo == BC_DIRICHLET0 && base < 0;
+    const bool zero_hi = s.bc_hi == BC_DIRICHLET0 && base + 64LL * C > n;
+    // Two register arrays alternate as source and destination, so a pair of
+    // steps needs no register copies.
+    T w[C];
+    int t = 0;
+    for (; t + 2 <= steps; t += 2) {
+        step_tile<T, C>(v, w, k, zero_lo, zero_hi, lbase, n);
+        step_tile<T, C>(w, v, k, zero_lo, zero_hi, lbase, n);
+    }
+    if (t < steps) {
+        step_tile<T, C>(v, w, k, zero_lo, zero_hi, lbase, n);
+#pragma unroll
+        for (int j = 0; j < C; ++j) v[j] = w[j];
+    }
+
+    const int64_t oend = (o0 + wout < n) ? o0 + wout : n;
+    if (interior && aligned16(out + base)) {
+        VT* dst = reinterpret_cast<VT*>(out + lbase);
+#pragma unroll
+        for (int q = 0; q < C / VN; ++q) {
+            const int lc = lane * C + q * VN;
+            if (lc >= halo && lc < 64 * C - halo) {
+                VT x;
+#pragma unroll
+                for (int e = 0; e < VN; ++e) x[e] = v[q * VN + e];
+                __builtin_nontemporal_store(x, dst + q);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            const int64_t g = lbase + j;
+            if (g >= o0 && g < oend) out[g] = v[j];
+        }
+    }
+}
+
+template <typename T, int C>
+__global__ __launch_bounds__(256) void k_stencil1d(Seg1D s, int steps, int halo, int64_t ntiles) {
+    const int wpg = blockDim.x >> 6;
+    const int64_t tile = (int64_t)blockIdx.x * wpg + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (tile >= ntiles) return;
+    tile1d<T, C>(s, tile, steps, halo);
+}
+
+template <typename T, int C>
+__global__ __launch_bounds__(256) void k_stencil1d_batched(const Seg1D* __restrict__ segs,
+                                                           const uint32_t* __restrict__ tseg,
+                                                           const uint32_t* __restrict__ tidx,
+                                                           int64_t ntiles, int steps, int halo) {
+    const int wpg = blockDim.x >> 6;
+    const int64_t nwaves = (int64_t)gridDim.x * wpg;
+    for (int64_t t = (int64_t)blockIdx.x * wpg + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+         t < ntiles; t += nwaves) {
+        const Seg1D s = segs[tseg[t]];
+        tile1d<T, C>(s, tidx[t], steps, halo);
+    }
+}
+
+template <typename T>
+hipError_t launch_single(const Seg1D& s, const Geom1D& g, hipStream_t st) {
+    const int64_t wout = tile_out_1d(g);
+    const int64_t ntiles = (s.n + wout - 1) / wout;
+    const dim3 block(64 * g.wpg);
+    const dim3 grid((unsigned)((ntiles + g.wpg - 1) / g.wpg));
+    switch (g.cpl) {
+    case 8: hipLaunchKernelGGL((k_stencil1d<T, 8>), grid, block, 0, st, s, g.steps, g.halo, ntiles); break;
+    case 16: hipLaunchKernelGGL((k_stencil1d<T, 16>), grid, block, 0, st, s, g.steps, g.halo, ntiles); break;
+    case 32: hipLaunchKernelGGL((k_stencil1d<T, 32>), grid, block, 0, st, s, g.steps, g.halo, ntiles); break;
+    case 64: hipLaunchKernelGGL((k_stencil1d<T, 64>), grid, block, 0, st, s, g.steps, g.halo, ntiles); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_batched(const Seg1D* segs, const uint32_t* tseg, const uint32_t* tidx,
+                          int64_t ntiles, const Geom1D& g, int64_t grid_waves, hipStream_t st) {
+    const dim3 block(64 * g.wpg);
+    const dim3 grid((unsigned)((grid_waves + g.wpg - 1) / g.wpg));
+    switch (g.cpl) {
+    case 8: hipLaunchKernelGGL((k_stencil1d_batched<T, 8>), grid, block, 0, st, segs, tseg, tidx, ntiles, g.steps, g.halo); break;
+    case 16: hipLaunchKernelGGL((k_stencil1d_batched<T, 16>), grid, block, 0, st, segs, tseg, tidx, ntiles, g.steps, g.halo); break;
+    case 32: hipLaunchKernelGGL((k_stencil1d_batched<T, 32>), grid, block, 0, st, segs, tseg, tidx, ntiles, g.steps, g.halo); break;
+    case 64: hipLaunchKernelGGL((k_stencil1d_batched<T, 64>), grid, block, 0, st, segs, tseg, tidx, ntiles, g.steps, g.halo); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_stencil1d(int dtype, const Seg1D& seg, const Geom1D& g, hipStream_t stream) {
+    return dtype == 0 ? launch_single<float>(seg, g, stream) : launch_single<double>(seg, g, stream);
+}
+
+hipError_t launch_stencil1d_batched(int dtype, const Seg1D* segs_dev, const uint32_t* tile_seg,
+                                    const uint32_t* tile_idx, int64_t ntiles, const Geom1D& g,
+                                    int64_t grid_waves, hipStream_t stream) {
+    return dtype == 0
+               ? launch_batched<float>(segs_dev, tile_seg, tile_idx, ntiles, g, grid_waves, stream)
+               : launch_batched<double>(segs_dev, tile_seg, tile_idx, ntiles, g, grid_waves, stream);
+}
+
+}  // namespace hx

@@ -1,0 +1,148 @@
+// hx_launch_stencil: argument validation, launch geometry and the pass
+// schedule for the 1D and 2D heat stencils.
+#include <algorithm>
+#include <string>
+
+#include "hx_internal.h"
+#include "hx_runtime.hpp"
+#include "hx_tune.hpp"
+
+namespace hx {
+
+static inline size_t esize(int dtype) { return dtype == HX_F64 ? 8 : 4; }
+static inline int vec_cells(int dtype) { return dtype == HX_F64 ? 2 : 4; }
+static inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+static bool valid_bc(int b) { return b == HX_BC_PERIODIC || b == HX_BC_DIRICHLET0 || b == HX_BC_GHOST; }
+
+// Largest time block a 1D tile of `cpl` cells per lane can take: it must keep
+// at least one vector of output cells.
+int max_time_block_1d(int dtype, int cpl) {
+    const int vn = vec_cells(dtype);
+    return (64 * cpl - vn) / 2 / vn * vn;
+}
+
+static hx_status launch_1d(Ctx* c, const hx_stencil_args* a, const hx_event* deps, int ndeps,
+                           hx_event* out) {
+    const int dt = a->dtype;
+    const size_t es = esize(dt);
+    const int64_t n = a->nx;
+    if (n <= 0) return c->fail(HX_ERR_ARG, "nx must be positive");
+    if (!valid_bc(a->bc_lo) || !valid_bc(a->bc_hi)) return c->fail(HX_ERR_ARG, "bad boundary");
+    if ((a->bc_lo == HX_BC_PERIODIC) != (a->bc_hi == HX_BC_PERIODIC))
+        return c->fail(HX_ERR_ARG, "periodic must apply to both ends");
+    const bool ghost = a->bc_lo == HX_BC_GHOST || a->bc_hi == HX_BC_GHOST;
+
+    std::vector<Access> acc;
+    Access ac{};
+    char *pin = nullptr, *pout = nullptr, *ptmp = nullptr, *plo = nullptr, *phi = nullptr;
+    const size_t bytes = (size_t)n * es;
+    hx_status s = resolve_range(c, a->in, a->in_offset, bytes, &pin, &ac, false);
+    if (s) return s;
+    acc.push_back(ac);
+    s = resolve_range(c, a->out, a->out_offset, bytes, &pout, &ac, true);
+    if (s) return s;
+    if (ac.buf_slot == acc[0].buf_slot && ac.lo < acc[0].hi && acc[0].lo < ac.hi)
+        return c->fail(HX_ERR_ARG, "in and out overlap");
+    acc.push_back(ac);
+
+    Geom1D g;
+    TuneKey key = tune_key_1d(dt, n, a->steps, ghost);
+    Geom1D def = default_geom_1d(c, key);
+    g.cpl = a->cells_per_lane ? a->cells_per_lane : def.cpl;
+    if (g.cpl != 8 && g.cpl != 16 && g.cpl != 32 && g.cpl != 64)
+        return c->fail(HX_ERR_ARG, "cells_per_lane must be 8, 16, 32 or 64");
+    g.wpg = a->waves_per_group ? a->waves_per_group : def.wpg;
+    if (g.wpg != 1 && g.wpg != 2 && g.wpg != 4)
+        return c->fail(HX_ERR_ARG, "waves_per_group must be 1, 2 or 4");
+    const int maxd = max_time_block_1d(dt, g.cpl);
+    int D = a->time_block ? a->time_block : std::min(def.steps, maxd);
+    if (a->steps < 0) return c->fail(HX_ERR_ARG, "negative steps");
+    if (ghost) {
+        if (a->halo_width <= 0) return c->fail(HX_ERR_ARG, "GHOST needs halo_width > 0");
+        if (a->steps > a->halo_width)
+            return c->fail(HX_ERR_ARG, "steps exceed halo_width (the halo must cover the light cone)");
+        D = a->steps;  // one fused pass
+        if (a->time_block && a->time_block < a->steps)
+            return c->fail(HX_ERR_ARG, "a GHOST run is one pass: time_block must be >= steps");
+        const size_t hb = (size_t)a->halo_width * es;
+        if (a->bc_lo == HX_BC_GHOST) {
+            s = resolve_range(c, a->halo_lo, a->halo_lo_offset, hb, &plo, &ac, false);
+            if (s) return s;
+            acc.push_back(ac);
+        }
+        if (a->bc_hi == HX_BC_GHOST) {
+            s = resolve_range(c, a->halo_hi, a->halo_hi_offset, hb, &phi, &ac, false);
+            if (s) return s;
+            acc.push_back(ac);
+        }
+    }
+    if (D < 1) D = 1;
+    if (D > maxd)
+        return c->fail(HX_ERR_ARG, "time block " + std::to_string(D) + " exceeds the tile limit " +
+                                       std::to_string(maxd) + " for cells_per_lane " +
+                                       std::to_string(g.cpl));
+    const int passes = a->steps == 0 ? 1 : (a->steps + D - 1) / D;
+    if (passes > 1) {
+        if (a->tmp == 0)
+            return c->fail(HX_ERR_ARG, "a run of more than one pass needs a tmp buffer");
+        s = resolve_range(c, a->tmp, a->tmp_offset, bytes, &ptmp, &ac, true);
+        if (s) return c->fail(s, "a run of more than one pass needs a valid tmp buffer");
+        for (const Access& x : acc)
+            if (x.buf_slot == ac.buf_slot && x.lo < ac.hi && ac.lo < x.hi)
+                return c->fail(HX_ERR_ARG, "tmp overlaps another operand");
+        acc.push_back(ac);
+    }
+
+    Seg1D seg{};
+    seg.n = n;
+    seg.r = a->r;
+    seg.bc_lo = a->bc_lo;
+    seg.bc_hi = a->bc_hi;
+    seg.hw = a->halo_width;
+    seg.halo_lo = plo;
+    seg.halo_hi = phi;
+    const int steps = a->steps;
+    const int vn = vec_cells(dt);
+    std::string what = "stencil1d n=" + std::to_string(n) + " steps=" + std::to_string(steps);
+    return c->submit(
+        SC_COMPUTE, deps, ndeps, acc, what,
+        [=](hipStream_t st) -> hipError_t {
+            // passes ping-pong so that the last one lands in out
+            const char* src = pin;
+            int left = steps;
+            for (int p = 0; p < passes; ++p) {
+                const int d = (p == passes - 1) ? left : D;
+                char* dst = ((passes - 1 - p) % 2 == 0) ? pout : ptmp;
+                Seg1D sg = seg;
+                sg.in = src;
+                sg.out = dst;
+                Geom1D gg = g;
+                gg.steps = d;
+                gg.halo = std::max(vn, round_up(d, vn));
+                hipError_t e = launch_stencil1d(dt, sg, gg, st);
+                if (e != hipSuccess) return e;
+                src = dst;
+                left -= d;
+            }
+            return hipSuccess;
+        },
+        out);
+}
+
+}  // namespace hx
+
+using namespace hx;
+
+extern "C" hx_status hx_launch_stencil(hx_ctx ctx, const hx_stencil_args* a, const hx_event* deps,
+                                       int ndeps, hx_event* out) {
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    if (!c) return HX_ERR_INVALID;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    if (!a || !out) return c->fail(HX_ERR_ARG, "null argument");
+    if (c->host_only) return c->fail(HX_ERR_NO_DEVICE, "host-only context");
+    if (a->dtype != HX_F32 && a->dtype != HX_F64) return c->fail(HX_ERR_ARG, "bad dtype");
+    hipSetDevice(c->device);
+    if (a->dims == 1) return launch_1d(c, a, deps, ndeps, out);
+    return c->fail(HX_ERR_ARG, "dims must be 1 or 2");
+}

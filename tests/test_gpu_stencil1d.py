@@ -1,0 +1,146 @@
+"""GPU parity of the 1D heat stencil against the FP64 oracle.
+
+Bars: FP64 path <= 1e-12 relative (L2 and max) to the oracle; FP32 path
+<= 1e-5 relative L2 to the FP64 oracle run on the same FP32-rounded input.
+Different launch geometries and pass splits must give bit-identical results
+(the per-cell arithmetic never changes).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from conftest import rel_l2, rel_max
+
+pytestmark = pytest.mark.gpu
+
+hx = pytest.importorskip("paper_1810_11482_amd")
+from hxutil import download, run, upload  # noqa: E402
+
+TOL = {np.float64: 1e-12, np.float32: 1e-5}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if hx.hx_device_count() == 0:
+        pytest.skip("no GPU")
+    c = hx.hx_ctx_create(0)
+    yield c
+    hx.hx_ctx_destroy(c)
+
+
+def gpu_run(ctx, u0, r, steps, bc=hx.HX_BC_PERIODIC, **geom):
+    dt = u0.dtype.type
+    code = hx.HX_F64 if dt == np.float64 else hx.HX_F32
+    n = u0.size
+    bin_ = upload(ctx, u0)
+    bout = hx.hx_buffer_create(ctx, u0.nbytes)
+    btmp = hx.hx_buffer_create(ctx, u0.nbytes)
+    args = hx.stencil_args(dims=1, dtype=code, nx=n, steps=steps, r=r, inp=bin_, out=bout,
+                           tmp=btmp, bc_lo=bc, bc_hi=bc, **geom)
+    run(ctx, args)
+    res = download(ctx, bout, n, dt)
+    for b in (bin_, bout, btmp):
+        hx.hx_buffer_destroy(ctx, b)
+    return res
+
+
+def test_full_size_fp64_periodic_modes(ctx):
+    """2^20 fp64 cells, r = 1/4, 100 steps, sine modes + noise: <= 1e-12."""
+    spec = workloads.Periodic1D()
+    u0 = workloads.periodic1d_u0(spec)
+    ref = oracle.heat1d_periodic(u0, spec.r, spec.steps)
+    for geom in [{}, dict(cells_per_lane=16, time_block=100), dict(time_block=1),
+                 dict(cells_per_lane=64, time_block=25, waves_per_group=2)]:
+        got = gpu_run(ctx, u0, spec.r, spec.steps, **geom)
+        e2, em = rel_l2(got, ref), rel_max(got, ref)
+        print(f"fp64 2^20 geom={geom}: rel_l2={e2:.3e} rel_max={em:.3e}")
+        assert e2 <= 1e-12 and em <= 1e-12
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("bc", [hx.HX_BC_PERIODIC, hx.HX_BC_DIRICHLET0])
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 255, 1000, 4099, 65537])
+@pytest.mark.parametrize("steps", [0, 1, 5, 33])
+def test_small_and_ragged(ctx, dtype, bc, n, steps):
+    u0 = workloads.uniform(n, 200, n, -1, 1, dtype)
+    ref_fn = oracle.heat1d_periodic if bc == hx.HX_BC_PERIODIC else oracle.heat1d_dirichlet
+    ref = ref_fn(u0.astype(np.float64), 0.3, steps)
+    got = gpu_run(ctx, u0, 0.3, steps, bc, cells_per_lane=8, time_block=4)
+    e = rel_l2(got, ref)
+    assert e <= TOL[dtype], e
+
+
+@pytest.mark.parametrize("cpl,tb,wpg", [(8, 1, 1), (16, 3, 2), (32, 32, 4), (64, 50, 4),
+                                        (32, 13, 1)])
+def test_geometries_bitwise_equal(ctx, cpl, tb, wpg):
+    u0 = workloads.uniform(300007, 201, 0, 0, 1, np.float32)
+    base = gpu_run(ctx, u0, 0.25, 50, cells_per_lane=8, time_block=1, waves_per_group=4)
+    got = gpu_run(ctx, u0, 0.25, 50, cells_per_lane=cpl, time_block=tb, waves_per_group=wpg)
+    assert np.array_equal(base, got)
+    ref = oracle.heat1d_periodic(u0.astype(np.float64), 0.25, 50)
+    assert rel_l2(got, ref) <= 1e-5
+
+
+def test_paper_kernel_identity_on_gpu(ctx):
+    """Sec. V-A.1's s(x) = 0.5 x_{i-1} + x_i + 0.5 x_{i+1} is 2 x one heat step at r = 1/4."""
+    x = workloads.uniform(100003, 202, 0, -1, 1, np.float64)
+    got = gpu_run(ctx, x, 0.25, 1)
+    assert rel_max(2 * got, oracle.prk_stencil(x)) <= 1e-15
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("parts,steps", [(4, 10), (7, 33), (16, 1)])
+def test_partitions_with_neighbour_halos(ctx, dtype, parts, steps):
+    """A periodic array split into uneven partitions; each partition's halos are
+    read straight from its neighbours' buffers (GHOST), one fused pass."""
+    n = 123457
+    u0 = workloads.uniform(n, 203, parts, 0, 1, dtype)
+    bounds = workloads.partition_bounds(n, parts)
+    es = u0.itemsize
+    code = hx.HX_F64 if dtype == np.float64 else hx.HX_F32
+    bins = [upload(ctx, u0[o:o + s]) for o, s in bounds]
+    bouts = [hx.hx_buffer_create(ctx, s * es) for _, s in bounds]
+    evs = []
+    for p, (o, s) in enumerate(bounds):
+        lp, rp = (p - 1) % parts, (p + 1) % parts
+        args = hx.stencil_args(dims=1, dtype=code, nx=s, steps=steps, r=0.25, inp=bins[p],
+                               out=bouts[p], bc_lo=hx.HX_BC_GHOST, bc_hi=hx.HX_BC_GHOST,
+                               halo_lo=bins[lp], halo_lo_offset=(bounds[lp][1] - steps) * es,
+                               halo_hi=bins[rp], halo_hi_offset=0, halo_width=steps)
+        evs.append(hx.hx_launch_stencil(ctx, args))
+    all_ = hx.hx_when_all(ctx, evs)
+    assert hx.hx_wait(ctx, all_) == hx.HX_OK
+    got = np.concatenate([download(ctx, b, s, dtype) for b, (_, s) in zip(bouts, bounds)])
+    ref = oracle.heat1d_periodic(u0.astype(np.float64), 0.25, steps)
+    assert rel_l2(got, ref) <= TOL[dtype] and rel_max(got, ref) <= 10 * TOL[dtype]
+
+
+def test_argument_errors(ctx):
+    b = hx.hx_buffer_create(ctx, 4096)
+    c = hx.hx_buffer_create(ctx, 4096)
+    ok = dict(dims=1, dtype=hx.HX_F32, nx=1024, steps=1, r=0.25, inp=b, out=c)
+    with pytest.raises(hx.HxError) as e:
+        hx.hx_launch_stencil(ctx, hx.stencil_args(**{**ok, "nx": 1025}))
+    assert e.value.status == hx.HX_ERR_RANGE
+    with pytest.raises(hx.HxError) as e:
+        hx.hx_launch_stencil(ctx, hx.stencil_args(**{**ok, "out": b}))
+    assert e.value.status == hx.HX_ERR_ARG
+    with pytest.raises(hx.HxError) as e:
+        hx.hx_launch_stencil(ctx, hx.stencil_args(**{**ok, "steps": 70, "time_block": 8}))
+    assert e.value.status == hx.HX_ERR_ARG  # more than one pass and no tmp
+    with pytest.raises(hx.HxError) as e:
+        hx.hx_launch_stencil(ctx, hx.stencil_args(**{**ok, "bc_lo": hx.HX_BC_GHOST,
+                                                     "halo_width": 0}))
+    assert e.value.status == hx.HX_ERR_ARG
+    with pytest.raises(hx.HxError) as e:
+        hx.hx_launch_stencil(ctx, hx.stencil_args(**{**ok, "cells_per_lane": 12}))
+    assert e.value.status == hx.HX_ERR_ARG
+    with pytest.raises(hx.HxError) as e:
+        hx.hx_launch_stencil(ctx, hx.stencil_args(**ok), deps=[12345])
+    assert e.value.status == hx.HX_ERR_INVALID
+    hx.hx_buffer_destroy(ctx, b)
+    with pytest.raises(hx.HxError) as e:
+        hx.hx_launch_stencil(ctx, hx.stencil_args(**ok))
+    assert e.value.status == hx.HX_ERR_INVALID
+    hx.hx_buffer_destroy(ctx, c)
