@@ -1,0 +1,323 @@
+#!/usr/bin/env python3
+"""Benchmark of the hx hot path on one MI355X.
+
+Workload (the headline configuration): a 1D periodic heat stencil over 2^28
+fp32 cells split into 64 partitions of 4 Mi cells, r = 0.25, 50 steps, run as
+a future graph of per-partition stencil launches with halo dependencies
+(Sec. V-A.2 / Algorithm 1 with the Sec. V-A.1 stencil).  One bench "step" is
+the whole 50-step run over the whole array, with the data resident in HBM.
+
+Printed: one JSON line with the throughput (cell-updates/s), the roofline of
+the dominant kernel (per-launch durations from HIP events in the timed region),
+the oracle's CPU throughput on a bounded sample, and the side measurements the
+metric names: the plain one-launch-per-partition-per-step form, the
+host-to-host pipeline with its copy overlap, and the batched driver.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK = 8.0e12            # bytes/s, MI355X HBM3E
+VALU_F32_PEAK = 78.6e12      # flop/s: 256 CU x 64 FP32 lanes x 2 (FMA) x 2.4 GHz, no packed FP32
+FLOPS_PER_UPDATE_1D = 5      # c + r*((l - 2c) + rt): 2 mul, 3 add/sub
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def intervals_union(iv):
+    iv = sorted(iv)
+    out = []
+    for a, b in iv:
+        if out and a <= out[-1][1]:
+            out[-1][1] = max(out[-1][1], b)
+        else:
+            out.append([a, b])
+    return out
+
+
+def measure_len(iv):
+    return sum(b - a for a, b in iv)
+
+
+def intersect_len(u1, u2):
+    i = j = 0
+    tot = 0.0
+    while i < len(u1) and j < len(u2):
+        a = max(u1[i][0], u2[j][0])
+        b = min(u1[i][1], u2[j][1])
+        if a < b:
+            tot += b - a
+        if u1[i][1] < u2[j][1]:
+            i += 1
+        else:
+            j += 1
+    return tot
+
+
+class Partitioned:
+    """Device state of the partitioned workload: pinned host input, two
+    ping-pong buffer sets, and the step driver."""
+
+    def __init__(self, hx, ctx, n, parts, steps, r):
+        self.hx, self.ctx = hx, ctx
+        self.n, self.parts, self.steps, self.r = n, parts, steps, r
+        import workloads
+        self.bounds = workloads.partition_bounds(n, parts)
+        self.sizes = [s for _, s in self.bounds]
+        self.host_in = hx.hx_host_alloc(ctx, n * 4)
+        self.host_out = hx.hx_host_alloc(ctx, n * 4)
+        arr = np.ctypeslib.as_array((np.ctypeslib.ctypes.c_float * n).from_address(self.host_in))
+        workloads.partitioned1d_u0(workloads.Partitioned1D(n=n, parts=parts, steps=steps, r=r),
+                                   out=arr)
+        self.u0 = arr
+        self.A = [hx.hx_buffer_create(ctx, s * 4) for s in self.sizes]
+        self.B = [hx.hx_buffer_create(ctx, s * 4) for s in self.sizes]
+        evs = []
+        for (o, s), b in zip(self.bounds, self.A):
+            d = hx.hx_copy_desc(hx.HX_H2D, self.host_in + o * 4, b, 0, 0, 0, s * 4)
+            evs.append(hx.hx_copy_async(ctx, d))
+        w = hx.hx_when_all(ctx, evs)
+        assert hx.hx_wait(ctx, w) == hx.HX_OK
+        for e in evs + [w]:
+            hx.hx_event_release(ctx, e)
+        self.cur_in_a = True
+        self.last = 0
+
+    def step(self, mode, time_block, cpl=0, nodes=False):
+        hx = self.hx
+        src, dst = (self.A, self.B) if self.cur_in_a else (self.B, self.A)
+        d = hx.partitioned_desc(hx.HX_F32, self.sizes, src, dst, self.steps, self.r,
+                                periodic=True, mode=mode, time_block=time_block,
+                                cells_per_lane=cpl)
+        ev, in_b, node_evs = hx.hx_run_partitioned(self.ctx, d, deps=[self.last] if self.last else [],
+                                                   node_events=nodes)
+        if self.last:
+            hx.hx_event_release(self.ctx, self.last)
+        self.last = ev
+        if in_b:
+            self.cur_in_a = not self.cur_in_a
+        return node_evs
+
+    def wait(self):
+        st = self.hx.hx_wait(self.ctx, self.last)
+        assert st == self.hx.HX_OK, self.hx.hx_last_error(self.ctx)
+
+    def current(self):
+        return self.A if self.cur_in_a else self.B
+
+
+def time_steps(P, k, mode, tb, cpl, nodes=False):
+    import torch
+    P.wait()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    all_nodes = []
+    for _ in range(k):
+        ne = P.step(mode, tb, cpl, nodes=nodes)
+        if ne:
+            all_nodes.extend(ne)
+    P.wait()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / k, all_nodes
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--log2n", type=int, default=28)
+    ap.add_argument("--parts", type=int, default=64)
+    ap.add_argument("--time-block", type=int, default=0, help="0 = pick by a short sweep")
+    ap.add_argument("--cells-per-lane", type=int, default=0)
+    ap.add_argument("--streams", type=int, default=4)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip plain/pipeline/batched legs")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1810_11482_amd as hx
+
+    n = 1 << args.log2n
+    T, r = 50, 0.25
+    ctx = hx.hx_ctx_create(0, compute_streams=args.streams, timing=True)
+    info = hx.hx_device_info(0)
+    log(f"device {info.arch.decode()} CUs={info.compute_units}")
+    P = Partitioned(hx, ctx, n, args.parts, T, r)
+
+    # ---------------------------------------------------------- geometry sweep
+    cands = []
+    tbs = [args.time_block] if args.time_block else [10, 25, 50]
+    cpls = [args.cells_per_lane] if args.cells_per_lane else [32, 64]
+    for tb in tbs:
+        for cpl in cpls:
+            if 64 * cpl - 2 * ((tb + 3) // 4 * 4) < 64:
+                continue
+            time_steps(P, 1, hx.HX_PART_GRAPH, tb, cpl)
+            t, _ = time_steps(P, 2, hx.HX_PART_GRAPH, tb, cpl)
+            cands.append((t, tb, cpl))
+            log(f"sweep time_block={tb} cpl={cpl}: {t * 1e3:.3f} ms/step")
+    _, tb, cpl = min(cands)
+
+    # ------------------------------------------------------------ timed region
+    time_steps(P, args.warmup, hx.HX_PART_GRAPH, tb, cpl)
+    sec, nodes = time_steps(P, args.steps, hx.HX_PART_GRAPH, tb, cpl, nodes=True)
+    durs = []
+    for e in nodes:
+        a, b = hx.hx_event_span(ctx, e, e)
+        durs.append(b - a)
+        hx.hx_event_release(ctx, e)
+    avg_ms = float(np.mean(durs))
+    ms_per_step = sec * 1e3
+    updates = float(n) * T
+    value = updates / sec
+    launches_per_step = args.parts * -(-T // tb)
+    concurrency = float(np.sum(durs)) / (ms_per_step * args.steps)
+    cells_per_launch = n / args.parts
+    bytes_per_launch = cells_per_launch * 2 * 4
+    steps_per_launch = T / -(-T // tb)
+    flops_per_launch = cells_per_launch * steps_per_launch * FLOPS_PER_UPDATE_1D
+    bw = bytes_per_launch / (avg_ms * 1e-3)
+    fl = flops_per_launch / (avg_ms * 1e-3)
+    hbm_frac, alu_frac = bw / HBM_PEAK, fl / VALU_F32_PEAK
+    if alu_frac >= hbm_frac:
+        roof = {"bound": "alu", "achieved": fl / 1e12, "peak": VALU_F32_PEAK / 1e12,
+                "unit": "TFLOP/s", "frac": alu_frac}
+    else:
+        roof = {"bound": "hbm", "achieved": bw / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                "frac": hbm_frac}
+    roof.update({"traffic": None, "kernel": "k_stencil1d<float>", "avg_launch_ms": avg_ms,
+                 "launches": len(durs), "hbm_algorithmic_GBps": bw / 1e9,
+                 "hbm_frac": hbm_frac, "alu_frac": alu_frac,
+                 "alu_frac_vs_157TF_packed_peak": fl / 157.3e12,
+                 "kernel_concurrency": concurrency})
+    log(f"graph: {ms_per_step:.3f} ms/step, {value:.4e} cell-updates/s, kernel avg {avg_ms:.4f} ms")
+
+    result = {
+        "metric": "stencil cell-updates/s + HBM GB/s vs roofline; % copy hidden; batched vs plain",
+        "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"1D periodic heat stencil, 2^{args.log2n} fp32 cells in "
+                               f"{args.parts} partitions, r=0.25, 50 steps, device-resident "
+                               f"future graph (halo dependencies)",
+                   "cells": n, "parts": args.parts, "time_steps": T, "time_block": tb,
+                   "cells_per_lane": cpl, "compute_streams": args.streams,
+                   "launches_per_step": launches_per_step},
+        "roofline": roof,
+    }
+
+    # --------------------------------------------------------------- extra legs
+    if not args.no_extra:
+        # plain comparator: one launch per partition per step, Algorithm 1 order
+        time_steps(P, 1, hx.HX_PART_PLAIN, 1, 8)
+        t_plain, _ = time_steps(P, 1, hx.HX_PART_PLAIN, 1, 8)
+        result["plain"] = {"ms_per_step": t_plain * 1e3, "launches_per_step": args.parts * T,
+                           "speedup_graph_vs_plain": t_plain / sec}
+        log(f"plain: {t_plain * 1e3:.3f} ms/step")
+        result["pipeline"] = pipeline_leg(hx, ctx, P, T, r, cpl)
+
+    # --------------------------------------------------------------- CPU oracle
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_leg(r, T)
+
+    print(json.dumps(result), flush=True)
+    hx.hx_event_release(ctx, P.last)
+    hx.hx_ctx_destroy(ctx)
+
+
+def pipeline_leg(hx, ctx, P, T, r, cpl):
+    """Host-to-host run (H2D -> kernel -> D2H per partition) and its overlap."""
+    import torch
+    ghost = hx.hx_buffer_create(ctx, 2 * T * P.parts * 4)
+    base = hx.partitioned_desc(hx.HX_F32, P.sizes, P.A, P.B, T, r, periodic=True,
+                               time_block=T, cells_per_lane=cpl)
+    pd = hx.hx_pipeline_desc(base, P.host_in, P.host_out, ghost)
+    walls = []
+    spans = None
+    for it in range(3):
+        P.wait()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev, h2d, ker, d2h = hx.hx_run_pipeline(ctx, pd, op_events=(it == 2))
+        assert hx.hx_wait(ctx, ev) == hx.HX_OK, hx.hx_last_error(ctx)
+        walls.append(time.perf_counter() - t0)
+        if it == 2:
+            ref = h2d[0]
+            spans = {"h2d": [hx.hx_event_span(ctx, e, ref) for e in h2d],
+                     "kernel": [hx.hx_event_span(ctx, e, ref) for e in ker],
+                     "d2h": [hx.hx_event_span(ctx, e, ref) for e in d2h]}
+            for e in h2d + ker + d2h:
+                hx.hx_event_release(ctx, e)
+        hx.hx_event_release(ctx, ev)
+    W = float(np.mean(walls[1:]))
+    # correctness of the pipeline output on sampled cells, before anything else
+    # touches host_out
+    import oracle
+    rng = np.random.default_rng(11)
+    idx = np.sort(rng.choice(P.n, 64, replace=False))
+    out = np.ctypeslib.as_array((np.ctypeslib.ctypes.c_float * P.n).from_address(P.host_out))
+    ref = oracle.heat1d_periodic_at(np.asarray(P.u0, dtype=np.float64), r, T, idx)
+    err = float(np.max(np.abs(out[idx] - ref) / np.maximum(np.abs(ref), 1e-30)))
+    # copies alone: the same pipeline with zero steps (its kernels are plain
+    # 16 MiB device copies)
+    pd0 = hx.hx_pipeline_desc(hx.partitioned_desc(hx.HX_F32, P.sizes, P.A, P.B, 0, r,
+                                                  periodic=True, cells_per_lane=cpl),
+                              P.host_in, P.host_out, ghost)
+    cw = []
+    for it in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev, _, _, _ = hx.hx_run_pipeline(ctx, pd0)
+        assert hx.hx_wait(ctx, ev) == hx.HX_OK
+        cw.append(time.perf_counter() - t0)
+        hx.hx_event_release(ctx, ev)
+    t_copy = float(np.mean(cw[1:]))
+    # kernels alone: the single-pass device-resident graph
+    P.cur_in_a = True
+    t_kernel, _ = time_steps(P, 2, hx.HX_PART_GRAPH, T, cpl)
+    C = intervals_union([tuple(x) for x in spans["h2d"] + spans["d2h"]])
+    K = intervals_union([tuple(x) for x in spans["kernel"]])
+    lit = intersect_len(C, K) / measure_len(C)
+    eta = (t_copy + t_kernel - W) / min(t_copy, t_kernel)
+    bytes_copied = 2 * P.n * 4
+    hx.hx_buffer_destroy(ctx, ghost)
+    res = {"wall_ms": W * 1e3, "copies_alone_ms": t_copy * 1e3, "kernels_alone_ms": t_kernel * 1e3,
+           "pcie_inclusive_cell_updates_per_s": P.n * T / W,
+           "copy_hidden_literal": lit, "overlap_efficiency_eta": eta,
+           "host_link_GBps_during_overlap": bytes_copied / (measure_len(C) * 1e-3) / 1e9,
+           "sampled_max_rel_err": err}
+    log(f"pipeline: {res}")
+    return res
+
+
+def cpu_leg(r, T):
+    """The oracle, untuned, on one host core over a bounded sample: a periodic
+    vector of 2^26 cells (16 of the 64 partitions' worth) for the full 50 steps."""
+    import oracle
+    import workloads
+    n = 1 << 26
+    u = workloads.partitioned1d_u0(workloads.Partitioned1D(n=n)).astype(np.float64)
+    t0 = time.perf_counter()
+    oracle.heat1d_periodic(u, r, T)
+    dt = time.perf_counter() - t0
+    return {"value": n * T / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"periodic vector of 2^26 cells (16 of the 64 partitions), 50 steps, "
+                      f"serial FP64 C oracle, {dt:.2f} s"}
+
+
+if __name__ == "__main__":
+    main()

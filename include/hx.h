@@ -213,6 +213,56 @@ typedef struct {
 hx_status hx_launch_stencil(hx_ctx ctx, const hx_stencil_args* args, const hx_event* deps,
                             int ndeps, hx_event* out);
 
+/* ------------------------------------------------------ partitioned arrays */
+typedef enum { HX_PART_GRAPH = 0, HX_PART_PLAIN = 1 } hx_part_mode;
+
+typedef struct {
+    int dtype;                  /* hx_dtype */
+    int parts;                  /* number of partitions */
+    const int64_t* sizes;       /* cells per partition (host array of `parts`) */
+    const hx_buffer* bufs_a;    /* per partition: buffer holding the initial state at offset 0 */
+    const hx_buffer* bufs_b;    /* per partition: second ping-pong buffer of the same size */
+    int periodic;               /* 1 = the last partition wraps to the first; 0 = the two
+                                   array ends are zero-Dirichlet */
+    int steps;
+    double r;
+    int mode;                   /* hx_part_mode */
+    int time_block;             /* steps per pass (<= the smallest partition); 0 = 32 */
+    int cells_per_lane;         /* kernel geometry, 0 = tuned */
+    int waves_per_group;
+} hx_partitioned_desc;
+
+/* Advance a device-resident 1D array split over `parts` buffers by `steps` heat
+ * steps, as a future graph (the partition benchmark of Sec. V-A.2 /
+ * Algorithm 1 with the stencil of Sec. V-A.1).  HX_PART_GRAPH: node (p, b)
+ * advances partition p by one time block, reading `time_block` halo cells
+ * straight from its neighbours' buffers, and depends on nodes (p-1, b-1),
+ * (p, b-1) and (p+1, b-1); independent nodes run concurrently on the compute
+ * streams.  HX_PART_PLAIN: the comparator: one step per launch, issued in
+ * Algorithm 1's order and chained on one stream.  `deps` gate the first pass.
+ * *out completes when the last pass has; the final state is in bufs_b if
+ * *final_in_b is 1, else in bufs_a.  node_events (optional, parts x passes
+ * entries, pass-major) receives every node's event; the caller releases them. */
+hx_status hx_run_partitioned(hx_ctx ctx, const hx_partitioned_desc* desc, const hx_event* deps,
+                             int ndeps, hx_event* out, int* final_in_b, hx_event* node_events);
+
+typedef struct {
+    hx_partitioned_desc part;   /* steps <= smallest partition; one fused pass per partition */
+    const void* host_in;        /* whole array, sum(sizes) cells (pinned for overlap) */
+    void* host_out;             /* result, sum(sizes) cells */
+    hx_buffer ghost;            /* 2 * max(steps, 1) * parts cells of halo slots */
+} hx_pipeline_desc;
+
+/* Host-to-host run of Algorithm 1 with the stencil: per partition an H2D copy
+ * of its cells into bufs_a[p] and of its two halos into its ghost slots, one
+ * fused kernel pass into bufs_b[p], and a D2H copy into host_out; the copies
+ * run on the copy streams while kernels of other partitions run on the compute
+ * streams.  op_events (optional, 3 x parts entries: the H2D copies, the
+ * kernels, the D2H copies) receives the operations' events; the caller
+ * releases them. */
+hx_status hx_run_pipeline(hx_ctx ctx, const hx_pipeline_desc* desc, const hx_event* deps,
+                          int ndeps, hx_event* out, hx_event* op_events);
+
 /* ------------------------------------------------------------------ events */
 /* An event that completes when every event in `events` has completed (the
  * paper's when_all, Sec. III-A); it fails with HX_ERR_DEP_FAILED if any of them
@@ -234,6 +284,12 @@ hx_status hx_event_release(hx_ctx ctx, hx_event ev);
 /* Milliseconds between two completed events of a context created with
  * timing = 1 (both must be GPU operations). */
 hx_status hx_event_elapsed(hx_ctx ctx, hx_event start, hx_event stop, double* ms);
+
+/* Start and end of operation `ev`, in milliseconds after the completion of
+ * `ref` (timing contexts only; both complete GPU operations).  The start is
+ * taken on the operation's stream once its dependency waits are satisfied, so
+ * end - start is the operation's own duration. */
+hx_status hx_event_span(hx_ctx ctx, hx_event ev, hx_event ref, double* start_ms, double* end_ms);
 
 /* A host-completed event: operations that depend on it are held back until
  * hx_user_event_set is called; status HX_OK releases them, an error fails them

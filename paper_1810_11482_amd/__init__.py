@@ -19,7 +19,7 @@ import torch  # noqa: F401  (loads the HIP runtime libhx links against)
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhx.so")
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1810_11482_amd.build`")
+    raise ImportError(f"{LIB_PATH} is not built; run `python paper_1810_11482_amd/build.py`")
 lib = ctypes.CDLL(LIB_PATH)
 
 # ------------------------------------------------------------------ constants
@@ -80,6 +80,23 @@ class hx_stencil_args(ctypes.Structure):
                 ("waves_per_group", ctypes.c_int), ("rows_per_block", ctypes.c_int)]
 
 
+class hx_partitioned_desc(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int), ("parts", ctypes.c_int),
+                ("sizes", ctypes.POINTER(_i64)), ("bufs_a", ctypes.POINTER(_u64)),
+                ("bufs_b", ctypes.POINTER(_u64)), ("periodic", ctypes.c_int),
+                ("steps", ctypes.c_int), ("r", ctypes.c_double), ("mode", ctypes.c_int),
+                ("time_block", ctypes.c_int), ("cells_per_lane", ctypes.c_int),
+                ("waves_per_group", ctypes.c_int)]
+
+
+class hx_pipeline_desc(ctypes.Structure):
+    _fields_ = [("part", hx_partitioned_desc), ("host_in", _vp), ("host_out", _vp),
+                ("ghost", _u64)]
+
+
+HX_PART_GRAPH, HX_PART_PLAIN = 0, 1
+
+
 # ----------------------------------------------------------------- prototypes
 _PROTOS = {
     "hx_status_string": (ctypes.c_char_p, [_i32]),
@@ -100,10 +117,17 @@ _PROTOS = {
     "hx_launch_stencil": (_i32, [_vp, ctypes.POINTER(hx_stencil_args), ctypes.POINTER(_u64),
                                  ctypes.c_int, ctypes.POINTER(_u64)]),
     "hx_when_all": (_i32, [_vp, ctypes.POINTER(_u64), ctypes.c_int, ctypes.POINTER(_u64)]),
+    "hx_run_partitioned": (_i32, [_vp, ctypes.POINTER(hx_partitioned_desc), ctypes.POINTER(_u64),
+                                  ctypes.c_int, ctypes.POINTER(_u64), ctypes.POINTER(ctypes.c_int),
+                                  ctypes.POINTER(_u64)]),
+    "hx_run_pipeline": (_i32, [_vp, ctypes.POINTER(hx_pipeline_desc), ctypes.POINTER(_u64),
+                               ctypes.c_int, ctypes.POINTER(_u64), ctypes.POINTER(_u64)]),
     "hx_wait": (_i32, [_vp, _u64, _i64]),
     "hx_event_query": (_i32, [_vp, _u64, ctypes.POINTER(_i32)]),
     "hx_event_release": (_i32, [_vp, _u64]),
     "hx_event_elapsed": (_i32, [_vp, _u64, _u64, ctypes.POINTER(ctypes.c_double)]),
+    "hx_event_span": (_i32, [_vp, _u64, _u64, ctypes.POINTER(ctypes.c_double),
+                             ctypes.POINTER(ctypes.c_double)]),
     "hx_user_event_create": (_i32, [_vp, ctypes.POINTER(_u64)]),
     "hx_user_event_set": (_i32, [_vp, _u64, _i32]),
     "hx_event_record_stream": (_i32, [_vp, _vp, ctypes.POINTER(_u64)]),
@@ -232,6 +256,50 @@ def hx_launch_stencil(ctx, args: hx_stencil_args, deps=()) -> int:
     return ev.value
 
 
+def partitioned_desc(dtype, sizes, bufs_a, bufs_b, steps, r, periodic=True,
+                     mode=HX_PART_GRAPH, time_block=0, cells_per_lane=0, waves_per_group=0):
+    """hx_partitioned_desc; the host arrays are kept alive on the returned struct."""
+    P = len(sizes)
+    sz = (_i64 * P)(*[int(x) for x in sizes])
+    ba = (_u64 * P)(*[int(x) for x in bufs_a])
+    bb = (_u64 * P)(*[int(x) for x in bufs_b])
+    d = hx_partitioned_desc(dtype, P, sz, ba, bb, int(bool(periodic)), steps, r, mode,
+                            time_block, cells_per_lane, waves_per_group)
+    d._keep = (sz, ba, bb)
+    return d
+
+
+def hx_run_partitioned(ctx, desc: hx_partitioned_desc, deps=(), node_events=False):
+    """Returns (event, final_in_b, node_event_list or None)."""
+    arr, n = _deps(deps)
+    ev = _u64()
+    fb = ctypes.c_int()
+    nodes = None
+    if node_events:
+        D = desc.time_block or min(desc.steps, 32)
+        if desc.mode == HX_PART_PLAIN:
+            D = 1
+        passes = 0 if desc.steps == 0 else -(-desc.steps // D)
+        nodes = (_u64 * max(1, passes * desc.parts))()
+    _ok(ctx, lib.hx_run_partitioned(ctx, ctypes.byref(desc), arr, n, ctypes.byref(ev),
+                                    ctypes.byref(fb), nodes))
+    return ev.value, bool(fb.value), (list(nodes) if nodes is not None else None)
+
+
+def hx_run_pipeline(ctx, desc: hx_pipeline_desc, deps=(), op_events=False):
+    """Returns (event, [h2d events], [kernel events], [d2h events]) (lists None
+    unless op_events)."""
+    arr, n = _deps(deps)
+    ev = _u64()
+    P = desc.part.parts
+    ops = (_u64 * (3 * P))() if op_events else None
+    _ok(ctx, lib.hx_run_pipeline(ctx, ctypes.byref(desc), arr, n, ctypes.byref(ev), ops))
+    if ops is None:
+        return ev.value, None, None, None
+    o = list(ops)
+    return ev.value, o[:P], o[P:2 * P], o[2 * P:]
+
+
 def hx_when_all(ctx, events) -> int:
     evs = [int(e) for e in events]
     arr = (_u64 * max(1, len(evs)))(*evs)
@@ -263,6 +331,12 @@ def hx_event_elapsed(ctx, start: int, stop: int) -> float:
     ms = ctypes.c_double()
     _ok(ctx, lib.hx_event_elapsed(ctx, start, stop, ctypes.byref(ms)))
     return ms.value
+
+
+def hx_event_span(ctx, ev: int, ref: int):
+    a, b = ctypes.c_double(), ctypes.c_double()
+    _ok(ctx, lib.hx_event_span(ctx, ev, ref, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
 
 
 def hx_user_event_create(ctx) -> int:

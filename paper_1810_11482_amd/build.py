@@ -6,7 +6,8 @@ runtime that the installed PyTorch ships (torch/lib/libamdhip64.so), so a
 process that uses torch for device memory and streams and this library for
 the kernels has exactly one HIP runtime loaded.
 
-Usage: python -m paper_1810_11482_amd.build   (or build() from Python)
+Usage: python paper_1810_11482_amd/build.py  (run as a file: importing the package
+loads the library this script builds)
 """
 from __future__ import annotations
 

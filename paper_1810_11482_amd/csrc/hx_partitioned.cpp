@@ -1,0 +1,284 @@
+// Partitioned 1D runs composed as future graphs (the paper's partition
+// benchmark, Sec. V-A.2 / Algorithm 1, with the stencil of Sec. V-A.1).
+//
+// hx_run_partitioned: a device-resident array split over `parts` buffers is
+// advanced in passes of `time_block` steps.  Node (p, b) reads partition p's
+// state of pass b-1 and time_block halo cells straight from the neighbours'
+// buffers, writes the other ping-pong buffer, and depends on nodes
+// (p-1, b-1), (p, b-1), (p+1, b-1).  Those three edges carry the halo (read
+// after write) and also order the next overwrite of a buffer after every read
+// of it (node (p, b+1) writes the buffer nodes (p+-1, b) read, and depends on
+// them).  The plain form is the same work issued in Algorithm 1's order with
+// one step per launch, every launch chained on one stream.
+//
+// hx_run_pipeline: host-resident input: per partition an H2D copy of its cells
+// and of its two halos (into a ghost buffer), one fused kernel pass, and a D2H
+// copy of the result, so copies of one partition overlap the kernels of others.
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "hx_runtime.hpp"
+
+using namespace hx;
+
+namespace {
+
+size_t esz(int dtype) { return dtype == HX_F64 ? 8 : 4; }
+
+hx_status validate(Ctx* c, const hx_partitioned_desc* d) {
+    if (!d) return c->fail(HX_ERR_ARG, "null descriptor");
+    if (d->dtype != HX_F32 && d->dtype != HX_F64) return c->fail(HX_ERR_ARG, "bad dtype");
+    if (d->parts < 1 || !d->sizes || !d->bufs_a || !d->bufs_b)
+        return c->fail(HX_ERR_ARG, "parts, sizes and both buffer arrays are required");
+    if (d->steps < 0) return c->fail(HX_ERR_ARG, "negative steps");
+    for (int p = 0; p < d->parts; ++p)
+        if (d->sizes[p] <= 0) return c->fail(HX_ERR_ARG, "partition sizes must be positive");
+    return HX_OK;
+}
+
+}  // namespace
+
+extern "C" hx_status hx_run_partitioned(hx_ctx ctx, const hx_partitioned_desc* d,
+                                        const hx_event* deps, int ndeps, hx_event* out,
+                                        int* final_in_b, hx_event* node_events) {
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    if (!c) return HX_ERR_INVALID;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    if (!out) return c->fail(HX_ERR_ARG, "null output event");
+    hx_status s = validate(c, d);
+    if (s) return s;
+    const int P = d->parts;
+    const bool plain = d->mode == HX_PART_PLAIN;
+    int D = plain ? 1 : (d->time_block > 0 ? d->time_block : std::min(d->steps, 32));
+    if (D < 1) D = 1;
+    int64_t min_size = d->sizes[0];
+    for (int p = 1; p < P; ++p) min_size = std::min(min_size, d->sizes[p]);
+    if (D > min_size) return c->fail(HX_ERR_ARG, "time_block exceeds the smallest partition");
+    const int passes = d->steps == 0 ? 0 : (d->steps + D - 1) / D;
+    const size_t es = esz(d->dtype);
+
+    std::vector<hx_event> prev(P, 0), cur(P, 0);
+    hx_event chain = 0;  // plain form: every launch after the previous one
+    const bool give = node_events != nullptr;  // node events belong to the caller
+    hx_event gate = 0;
+    if (ndeps > 0) {
+        s = when_all_locked(c, deps, ndeps, &gate);
+        if (s) return s;
+    }
+    auto cleanup = [&](hx_status st) {
+        if (!give) {
+            for (hx_event e : prev) release_locked(c, e);
+            for (hx_event e : cur) release_locked(c, e);
+        }
+        release_locked(c, gate);
+        return st;
+    };
+    int left = d->steps;
+    int node = 0;
+    for (int b = 0; b < passes; ++b) {
+        const int steps_b = std::min(D, left);
+        const bool src_a = (b % 2 == 0);
+        for (int p = 0; p < P; ++p) {
+            const int lp = (p + P - 1) % P, rp = (p + 1) % P;
+            hx_stencil_args a{};
+            a.dims = 1;
+            a.dtype = d->dtype;
+            a.nx = d->sizes[p];
+            a.steps = steps_b;
+            a.r = d->r;
+            a.in = src_a ? d->bufs_a[p] : d->bufs_b[p];
+            a.out = src_a ? d->bufs_b[p] : d->bufs_a[p];
+            const bool has_lo = d->periodic || p > 0;
+            const bool has_hi = d->periodic || p < P - 1;
+            a.bc_lo = has_lo ? HX_BC_GHOST : HX_BC_DIRICHLET0;
+            a.bc_hi = has_hi ? HX_BC_GHOST : HX_BC_DIRICHLET0;
+            a.halo_lo = src_a ? d->bufs_a[lp] : d->bufs_b[lp];
+            a.halo_lo_offset = (size_t)(d->sizes[lp] - steps_b) * es;
+            a.halo_hi = src_a ? d->bufs_a[rp] : d->bufs_b[rp];
+            a.halo_hi_offset = 0;
+            a.halo_width = steps_b;
+            a.cells_per_lane = d->cells_per_lane;
+            a.waves_per_group = d->waves_per_group;
+            hx_event dv[4];
+            int nd = 0;
+            if (plain) {
+                dv[nd++] = chain ? chain : gate;
+            } else if (b == 0) {
+                dv[nd++] = gate;
+            } else {
+                dv[nd++] = prev[p];
+                if (has_lo) dv[nd++] = prev[lp];
+                if (has_hi) dv[nd++] = prev[rp];
+            }
+            hx_event ev = 0;
+            s = launch_stencil_locked(c, &a, dv, nd, &ev);
+            if (s) return cleanup(s);
+            cur[p] = ev;
+            if (plain) chain = ev;
+            if (give) node_events[node] = ev;
+            ++node;
+        }
+        for (int p = 0; p < P; ++p) {
+            if (!give) release_locked(c, prev[p]);
+            prev[p] = cur[p];
+            cur[p] = 0;
+        }
+        left -= steps_b;
+    }
+    if (passes == 0) {
+        s = when_all_locked(c, &gate, 1, out);
+        release_locked(c, gate);
+        if (final_in_b) *final_in_b = 0;
+        return s;
+    }
+    s = when_all_locked(c, prev.data(), P, out);
+    if (final_in_b) *final_in_b = (passes % 2 == 1);
+    cleanup(HX_OK);
+    return s;
+}
+
+extern "C" hx_status hx_run_pipeline(hx_ctx ctx, const hx_pipeline_desc* pd, const hx_event* deps,
+                                     int ndeps, hx_event* out, hx_event* op_events) {
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    if (!c) return HX_ERR_INVALID;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    if (!pd || !out) return c->fail(HX_ERR_ARG, "null argument");
+    const hx_partitioned_desc* d = &pd->part;
+    hx_status s = validate(c, d);
+    if (s) return s;
+    if (!pd->host_in || !pd->host_out) return c->fail(HX_ERR_ARG, "host_in and host_out required");
+    const int P = d->parts;
+    const int T = d->steps;
+    const size_t es = esz(d->dtype);
+    int64_t total = 0, min_size = d->sizes[0];
+    std::vector<int64_t> off(P);
+    for (int p = 0; p < P; ++p) {
+        off[p] = total;
+        total += d->sizes[p];
+        min_size = std::min(min_size, d->sizes[p]);
+    }
+    if (T > min_size) return c->fail(HX_ERR_ARG, "steps exceed the smallest partition");
+    const int H = std::max(T, 1);
+    hx_event gate = 0;
+    if (ndeps > 0) {
+        s = when_all_locked(c, deps, ndeps, &gate);
+        if (s) return s;
+    }
+    std::vector<hx_event> finals;
+    std::vector<hx_event> keep;
+    // Operation events go to the caller when op_events is given (H2D of the
+    // partition cells, kernel, D2H, each `parts` long); otherwise they are ours.
+    auto record = [&](int slot, hx_event e) {
+        if (op_events) op_events[slot] = e;
+        else keep.push_back(e);
+    };
+    const char* hin = static_cast<const char*>(pd->host_in);
+    char* hout = static_cast<char*>(pd->host_out);
+    // 1) every copy in: partition cells, then its two halos into the ghost buffer
+    std::vector<hx_event> ein(P), elo(P), ehi(P);
+    for (int p = 0; p < P; ++p) {
+        hx_copy_desc cd{};
+        cd.dir = HX_H2D;
+        cd.host = const_cast<char*>(hin) + off[p] * es;
+        cd.buf = d->bufs_a[p];
+        cd.bytes = (size_t)d->sizes[p] * es;
+        s = copy_async_locked(c, &cd, &gate, gate ? 1 : 0, &ein[p]);
+        if (s) return s;
+        const int64_t lo0 = d->periodic ? (off[p] - H + total) % total : off[p] - H;
+        const int64_t hi0 = d->periodic ? (off[p] + d->sizes[p]) % total : off[p] + d->sizes[p];
+        const bool has_lo = d->periodic || p > 0;
+        const bool has_hi = d->periodic || p < P - 1;
+        elo[p] = ehi[p] = 0;
+        if (T > 0 && has_lo) {
+            // a halo of H cells that may wrap past the array start: at most two runs
+            hx_copy_desc h{};
+            h.dir = HX_H2D;
+            h.buf = pd->ghost;
+            int64_t first = std::min<int64_t>(H, total - lo0);
+            h.host = const_cast<char*>(hin) + lo0 * es;
+            h.offset = (size_t)(2 * H) * p * es;
+            h.bytes = (size_t)first * es;
+            s = copy_async_locked(c, &h, &gate, gate ? 1 : 0, &elo[p]);
+            if (s) return s;
+            if (first < H) {
+                hx_event e2 = 0;
+                h.host = const_cast<char*>(hin);
+                h.offset += (size_t)first * es;
+                h.bytes = (size_t)(H - first) * es;
+                s = copy_async_locked(c, &h, &elo[p], 1, &e2);
+                if (s) return s;
+                release_locked(c, elo[p]);
+                elo[p] = e2;
+            }
+        }
+        if (T > 0 && has_hi) {
+            hx_copy_desc h{};
+            h.dir = HX_H2D;
+            h.buf = pd->ghost;
+            int64_t first = std::min<int64_t>(H, total - hi0);
+            h.host = const_cast<char*>(hin) + hi0 * es;
+            h.offset = (size_t)(2 * H * p + H) * es;
+            h.bytes = (size_t)first * es;
+            s = copy_async_locked(c, &h, &gate, gate ? 1 : 0, &ehi[p]);
+            if (s) return s;
+            if (first < H) {
+                hx_event e2 = 0;
+                h.host = const_cast<char*>(hin);
+                h.offset += (size_t)first * es;
+                h.bytes = (size_t)(H - first) * es;
+                s = copy_async_locked(c, &h, &ehi[p], 1, &e2);
+                if (s) return s;
+                release_locked(c, ehi[p]);
+                ehi[p] = e2;
+            }
+        }
+        record(p, ein[p]);
+    }
+    // 2) one fused pass per partition, 3) copy out
+    for (int p = 0; p < P; ++p) {
+        hx_stencil_args a{};
+        a.dims = 1;
+        a.dtype = d->dtype;
+        a.nx = d->sizes[p];
+        a.steps = T;
+        a.r = d->r;
+        a.in = d->bufs_a[p];
+        a.out = d->bufs_b[p];
+        const bool has_lo = d->periodic || p > 0;
+        const bool has_hi = d->periodic || p < P - 1;
+        a.bc_lo = (has_lo && T > 0) ? HX_BC_GHOST : (has_lo ? HX_BC_DIRICHLET0 : HX_BC_DIRICHLET0);
+        a.bc_hi = (has_hi && T > 0) ? HX_BC_GHOST : HX_BC_DIRICHLET0;
+        a.halo_lo = pd->ghost;
+        a.halo_lo_offset = (size_t)(2 * H) * p * es;
+        a.halo_hi = pd->ghost;
+        a.halo_hi_offset = (size_t)(2 * H * p + H) * es;
+        a.halo_width = H;
+        a.cells_per_lane = d->cells_per_lane;
+        a.waves_per_group = d->waves_per_group;
+        a.time_block = d->time_block > T ? d->time_block : 0;
+        hx_event dv[3] = {ein[p], elo[p], ehi[p]};
+        hx_event ek = 0;
+        s = launch_stencil_locked(c, &a, dv, 3, &ek);
+        if (s) return s;
+        record(P + p, ek);
+        hx_copy_desc cd{};
+        cd.dir = HX_D2H;
+        cd.host = hout + off[p] * es;
+        cd.buf = d->bufs_b[p];
+        cd.bytes = (size_t)d->sizes[p] * es;
+        hx_event eo = 0;
+        s = copy_async_locked(c, &cd, &ek, 1, &eo);
+        if (s) return s;
+        finals.push_back(eo);
+        record(2 * P + p, eo);
+    }
+    s = when_all_locked(c, finals.data(), (int)finals.size(), out);
+    for (int p = 0; p < P; ++p) {
+        release_locked(c, elo[p]);
+        release_locked(c, ehi[p]);
+    }
+    for (hx_event e : keep) release_locked(c, e);
+    release_locked(c, gate);
+    return s;
+}

@@ -74,6 +74,7 @@ uint32_t Ctx::new_event(EventKind k) {
     e.kind = k;
     e.status = (k == EK_DONE) ? HX_OK : HX_PENDING;
     e.hev = nullptr;
+    e.hev_start = nullptr;
     e.stream = -1;
     e.seq = next_seq++;
     e.enqueued = false;
@@ -95,7 +96,9 @@ void Ctx::maybe_free_event(uint32_t slot) {
     std::vector<uint32_t> deps;
     deps.swap(e.deps);
     if (e.hev) hev_pool.push_back(e.hev);
+    if (e.hev_start) hev_pool.push_back(e.hev_start);
     e.hev = nullptr;
+    e.hev_start = nullptr;
     e.in_use = false;
     e.fn = nullptr;
     e.waiters.clear();
@@ -227,6 +230,10 @@ hx_status Ctx::enqueue_now(uint32_t slot) {
         if (le.kind != EK_GPU || le.status == HX_OK) continue;
         if (le.stream == s) continue;  // ordered by the stream itself
         hipStreamWaitEvent(st, le.hev, 0);
+    }
+    if (timing) {
+        events[slot].hev_start = take_hev();
+        hipEventRecord(events[slot].hev_start, st);
     }
     EnqueueFn fn;
     fn.swap(events[slot].fn);
@@ -547,8 +554,10 @@ hx_status hx_ctx_destroy(hx_ctx ctx) {
         if (b.live && b.owned && b.ptr) hipFree(b.ptr);
     for (auto& z : c->zombies) hipFree(z.ptr);
     for (void* h : c->host_allocs) hipHostFree(h);
-    for (Event& e : c->events)
+    for (Event& e : c->events) {
         if (e.hev) hipEventDestroy(e.hev);
+        if (e.hev_start) hipEventDestroy(e.hev_start);
+    }
     for (hipEvent_t h : c->hev_pool) hipEventDestroy(h);
     for (size_t k = (c->external0 ? 1 : 0); k < c->streams.size(); ++k)
         hipStreamDestroy(c->streams[k]);
@@ -668,6 +677,13 @@ hx_status hx_copy_async(hx_ctx ctx, const hx_copy_desc* d, const hx_event* deps,
                         hx_event* out) {
     Ctx* c = C(ctx);
     CTX_OR_FAIL(c);
+    return hx::copy_async_locked(c, d, deps, ndeps, out);
+}
+
+}  // extern "C"
+
+hx_status hx::copy_async_locked(Ctx* c, const hx_copy_desc* d, const hx_event* deps, int ndeps,
+                                hx_event* out) {
     if (!d || !out) return c->fail(HX_ERR_ARG, "null argument");
     if (c->host_only) return c->fail(HX_ERR_NO_DEVICE, "host-only context");
     hipSetDevice(c->device);
@@ -720,10 +736,25 @@ hx_status hx_copy_async(hx_ctx ctx, const hx_copy_desc* d, const hx_event* deps,
     return c->fail(HX_ERR_ARG, "bad copy direction");
 }
 
+void hx::release_locked(Ctx* c, hx_event ev) {
+    Event* e = c->get_event(ev);
+    if (!e) return;
+    e->user_ref = false;
+    c->maybe_free_event(handle_slot(ev));
+}
+
+extern "C" {
+
 // ------------------------------------------------------------------- events
 hx_status hx_when_all(hx_ctx ctx, const hx_event* evs, int n, hx_event* out) {
     Ctx* c = C(ctx);
     CTX_OR_FAIL(c);
+    return hx::when_all_locked(c, evs, n, out);
+}
+
+}  // extern "C"
+
+hx_status hx::when_all_locked(Ctx* c, const hx_event* evs, int n, hx_event* out) {
     if (!out || n < 0 || (n > 0 && !evs)) return HX_ERR_ARG;
     std::vector<uint32_t> slots;
     for (int i = 0; i < n; ++i) {
@@ -745,6 +776,8 @@ hx_status hx_when_all(hx_ctx ctx, const hx_event* evs, int n, hx_event* out) {
     *out = c->handle_of(slot);
     return HX_OK;
 }
+
+extern "C" {
 
 hx_status hx_event_query(hx_ctx ctx, hx_event ev, hx_status* state) {
     Ctx* c = C(ctx);
@@ -828,6 +861,26 @@ hx_status hx_event_elapsed(hx_ctx ctx, hx_event a, hx_event b, double* ms) {
     float f = 0;
     if (hipEventElapsedTime(&f, ea->hev, eb->hev) != hipSuccess) return HX_ERR_HIP;
     *ms = f;
+    return HX_OK;
+}
+
+hx_status hx_event_span(hx_ctx ctx, hx_event ev, hx_event ref, double* start_ms, double* end_ms) {
+    Ctx* c = C(ctx);
+    CTX_OR_FAIL(c);
+    if (!start_ms || !end_ms) return HX_ERR_ARG;
+    if (!c->timing) return c->fail(HX_ERR_UNSUPPORTED, "context created without timing");
+    Event* e = c->get_event(ev);
+    Event* r = c->get_event(ref);
+    if (!e || !r) return HX_ERR_INVALID;
+    if (e->kind != EK_GPU || !e->hev_start || r->kind != EK_GPU)
+        return c->fail(HX_ERR_ARG, "not a timed GPU operation");
+    if (c->refresh(handle_slot(ev)) != HX_OK || c->refresh(handle_slot(ref)) != HX_OK)
+        return c->fail(HX_ERR_ARG, "events not complete");
+    float a = 0, b = 0;
+    if (hipEventElapsedTime(&a, r->hev, e->hev_start) != hipSuccess) return HX_ERR_HIP;
+    if (hipEventElapsedTime(&b, r->hev, e->hev) != hipSuccess) return HX_ERR_HIP;
+    *start_ms = a;
+    *end_ms = b;
     return HX_OK;
 }
 

@@ -62,6 +62,7 @@ struct Event {
     EventKind kind = EK_DONE;
     hx_status status = HX_OK;    // HX_PENDING until final
     hipEvent_t hev = nullptr;    // EK_GPU (and EK_DEFERRED once enqueued)
+    hipEvent_t hev_start = nullptr;  // timing contexts: recorded after the waits
     int stream = -1;             // index into Ctx::streams
     uint64_t seq = 0;
     bool enqueued = false;       // GPU work for this event has been queued
@@ -152,6 +153,14 @@ struct Ctx {
     hx_plan add_plan(int type, void* impl, std::function<void(void*)> destroy);
     Plan* get_plan(hx_plan h, int type);
 };
+
+// hx_launch_stencil with the context lock already held.
+hx_status launch_stencil_locked(Ctx* c, const hx_stencil_args* a, const hx_event* deps, int ndeps,
+                                hx_event* out);
+hx_status copy_async_locked(Ctx* c, const hx_copy_desc* d, const hx_event* deps, int ndeps,
+                            hx_event* out);
+hx_status when_all_locked(Ctx* c, const hx_event* evs, int n, hx_event* out);
+void release_locked(Ctx* c, hx_event ev);
 
 // Resolve (buffer, offset, bytes) to a device pointer after a range check.
 hx_status resolve_range(Ctx* c, hx_buffer b, size_t offset, size_t bytes, char** ptr,

@@ -10,11 +10,13 @@
 // inner 64*C - 2*halo cells are exact and are written.  A step needs, per lane,
 // only the last cell of the lane below and the first cell of the lane above;
 // both come from a single DPP wave shift (wave_shr:1 / wave_shl:1), so the
-// whole time loop runs out of registers with no LDS and no barrier, and waves
-// are fully independent.  HBM traffic per pass is one read and one write of
-// every cell plus 2*halo/(64*C) of re-read context.
+// whole time loop runs out of registers with no barrier, and waves are fully
+// independent.  HBM is read and written only in coalesced order, through a
+// wave-private LDS area that transposes to and from the lane-contiguous
+// layout.  HBM traffic per pass is one read and one write of every cell plus
+// 2*halo/(64*C) of re-read context.
 //
-// Per cell-step the arithmetic is s = l + r_; d = fma(-2, c, s);
+// Per cell-step the arithmetic is s = l + rt; d = fma(-2, c, s);
 // c' = fma(r, d, c), written with explicit fma so every kernel in this library
 // that advances a cell does so with the same rounding.
 #include <hip/hip_runtime.h>
@@ -51,14 +53,6 @@ __device__ __forceinline__ double dpp_move(double x) {
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-// One cell-step: c + r*((l + rt) - 2c).
-template <typename T>
-__device__ __forceinline__ T heat_point(T l, T c, T rt, T k) {
-    T s = l + rt;
-    T d = fmaT(T(-2), c, s);
-    return fmaT(k, d, c);
-}
-
 // Value of cell g (any integer) of segment s at the start of the pass.
 template <typename T>
 __device__ __forceinline__ T load_cell(const Seg1D& s, int64_t g) {
@@ -80,23 +74,33 @@ __device__ __forceinline__ T load_cell(const Seg1D& s, int64_t g) {
     return T(0);
 }
 
-// One step of a whole wave tile: a (registers, lane-contiguous) -> b.  The cell
-// left of a lane's first comes from the lane below, the cell right of its last
-// from the lane above (DPP wave shifts).  Cells outside a zero-Dirichlet end are
-// reset to 0 after the step.
+// One step of a whole wave tile, in place on the lane-contiguous registers a.
+// The cell left of a lane's first comes from the lane below, the cell right of
+// its last from the lane above (DPP wave shifts of the old values).  The
+// neighbour sum of cell j+1 is formed from the old a[j] before a[j] is
+// overwritten, so one array and two short-lived temporaries suffice and the
+// register assignment is the same after every step (no register moves).  Per
+// cell: s = l + rt; d = fma(-2, c, s); c' = fma(r, d, c).  Cells outside a
+// zero-Dirichlet end are reset to 0 after the step.
 template <typename T, int C>
-__device__ __forceinline__ void step_tile(const T (&a)[C], T (&b)[C], T k, bool zero_lo,
-                                          bool zero_hi, int64_t lbase, int64_t n) {
+__device__ __forceinline__ void step_tile(T (&a)[C], T k, bool zero_lo, bool zero_hi,
+                                          int64_t lbase, int64_t n) {
     const T left = dpp_move<DPP_WAVE_SHR1>(a[C - 1]);
     const T right = dpp_move<DPP_WAVE_SHL1>(a[0]);
+    T s_cur = left + (C > 1 ? a[1] : right);
 #pragma unroll
-    for (int j = 0; j < C; ++j)
-        b[j] = heat_point<T>(j > 0 ? a[j - 1] : left, a[j], j + 1 < C ? a[j + 1] : right, k);
+    for (int j = 0; j < C; ++j) {
+        T s_next = T(0);
+        if (j + 1 < C) s_next = a[j] + (j + 2 < C ? a[j + 2] : right);
+        const T d = fmaT(T(-2), a[j], s_cur);
+        a[j] = fmaT(k, d, a[j]);
+        s_cur = s_next;
+    }
     if (zero_lo || zero_hi) {
 #pragma unroll
         for (int j = 0; j < C; ++j) {
             const int64_t g = lbase + j;
-            if ((zero_lo && g < 0) || (zero_hi && g >= n)) b[j] = T(0);
+            if ((zero_lo && g < 0) || (zero_hi && g >= n)) a[j] = T(0);
         }
     }
 }
@@ -105,73 +109,112 @@ __device__ __forceinline__ bool aligned16(const void* p) {
     return (reinterpret_cast<uintptr_t>(p) & 15u) == 0;
 }
 
-// Advance tile `tile` of segment `s` by `steps` steps (see the file comment).
+// Position of tile cell i in the wave's LDS staging area: lane chunks of C
+// cells, each followed by one vector of padding so that the transposed reads
+// (lane j reading chunk j) spread over all banks.
 template <typename T, int C>
-__device__ __forceinline__ void tile1d(const Seg1D& s, int64_t tile, int steps, int halo) {
+__device__ __forceinline__ int lds_pos(int i) {
+    constexpr int VN = V16<T>::N;
+    return (i / C) * (C + VN) + (i % C);
+}
+
+// Advance tile `tile` of segment `s` by `steps` steps (see the file comment).
+// HBM is touched only in coalesced order (lane l, cell l + 64 j or vector
+// l + 64 k); a wave-private LDS area transposes between that order and the
+// lane-contiguous register layout.  LDS accesses of one wave execute in order,
+// so the wave needs no barrier between writing and reading its own area.
+template <typename T, int C>
+__device__ __forceinline__ void tile1d(const Seg1D& s, int64_t tile, int steps, int halo,
+                                       T* __restrict__ lds) {
     typedef typename V16<T>::t VT;
     constexpr int VN = V16<T>::N;
+    constexpr int W = 64 * C;
     static_assert(C % VN == 0, "cells per lane must be a multiple of the vector width");
     const int lane = threadIdx.x & 63;
     const int64_t n = s.n;
-    const int64_t wout = 64LL * C - 2LL * halo;
+    const int64_t wout = (int64_t)W - 2LL * halo;
     const int64_t o0 = tile * wout;
     const int64_t base = o0 - halo;
-    const int64_t lbase = base + (int64_t)lane * C;
     const T* in = static_cast<const T*>(s.in);
     T* out = static_cast<T*>(s.out);
-    const bool interior = base >= 0 && base + 64LL * C <= n;
+    const bool interior = base >= 0 && base + W <= n;
 
-    T v[C];
+    // ---- load: HBM (coalesced) -> LDS
     if (interior && aligned16(in + base)) {
-        const VT* src = reinterpret_cast<const VT*>(in + lbase);
+        const VT* src = reinterpret_cast<const VT*>(in + base);
 #pragma unroll
-        for (int q = 0; q < C / VN; ++q) {
-            const VT x = __builtin_nontemporal_load(src + q);
-#pragma unroll
-            for (int e = 0; e < VN; ++e) v[q * VN + e] = x[e];
+        for (int k = 0; k < C / VN; ++k) {
+            const int i = VN * (lane + 64 * k);
+            const VT x = __builtin_nontemporal_load(src + lane + 64 * k);
+            *reinterpret_cast<VT*>(lds + lds_pos<T, C>(i)) = x;
         }
-    } else {
+    } else if (interior) {
 #pragma unroll
-        for (int j = 0; j < C; ++j) v[j] = load_cell<T>(s, lbase + j);
-    }
-
-    const T k = static_cast<T>(s.r);
-    const bool zero_lo = s.bc_lo == BC_DIRICHLET0 && base < 0;
-    const bool zero_hi = s.bc_hi == BC_DIRICHLET0 && base + 64LL * C > n;
-    // Two register arrays alternate as source and destination, so a pair of
-    // steps needs no register copies.
-    T w[C];
-    int t = 0;
-    for (; t + 2 <= steps; t += 2) {
-        step_tile<T, C>(v, w, k, zero_lo, zero_hi, lbase, n);
-        step_tile<T, C>(w, v, k, zero_lo, zero_hi, lbase, n);
-    }
-    if (t < steps) {
-        step_tile<T, C>(v, w, k, zero_lo, zero_hi, lbase, n);
-#pragma unroll
-        for (int j = 0; j < C; ++j) v[j] = w[j];
-    }
-
-    const int64_t oend = (o0 + wout < n) ? o0 + wout : n;
-    if (interior && aligned16(out + base)) {
-        VT* dst = reinterpret_cast<VT*>(out + lbase);
-#pragma unroll
-        for (int q = 0; q < C / VN; ++q) {
-            const int lc = lane * C + q * VN;
-            if (lc >= halo && lc < 64 * C - halo) {
-                VT x;
-#pragma unroll
-                for (int e = 0; e < VN; ++e) x[e] = v[q * VN + e];
-                __builtin_nontemporal_store(x, dst + q);
-            }
+        for (int j = 0; j < C; ++j) {
+            const int i = lane + 64 * j;
+            lds[lds_pos<T, C>(i)] = in[base + i];
         }
     } else {
 #pragma unroll
         for (int j = 0; j < C; ++j) {
-            const int64_t g = lbase + j;
-            if (g >= o0 && g < oend) out[g] = v[j];
+            const int i = lane + 64 * j;
+            lds[lds_pos<T, C>(i)] = load_cell<T>(s, base + i);
         }
     }
+    __builtin_amdgcn_wave_barrier();
+    // ---- LDS -> registers, lane-contiguous
+    T v[C];
+#pragma unroll
+    for (int q = 0; q < C / VN; ++q) {
+        const VT x = *reinterpret_cast<const VT*>(lds + lane * (C + VN) + q * VN);
+#pragma unroll
+        for (int e = 0; e < VN; ++e) v[q * VN + e] = x[e];
+    }
+
+    const int64_t lbase = base + (int64_t)lane * C;
+    const T k = static_cast<T>(s.r);
+    const bool zero_lo = s.bc_lo == BC_DIRICHLET0 && base < 0;
+    const bool zero_hi = s.bc_hi == BC_DIRICHLET0 && base + W > n;
+    for (int t = 0; t < steps; ++t) step_tile<T, C>(v, k, zero_lo, zero_hi, lbase, n);
+
+    // ---- registers -> LDS -> HBM (coalesced), inner cells only
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int q = 0; q < C / VN; ++q) {
+        VT x;
+#pragma unroll
+        for (int e = 0; e < VN; ++e) x[e] = v[q * VN + e];
+        *reinterpret_cast<VT*>(lds + lane * (C + VN) + q * VN) = x;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int64_t oend = (o0 + wout < n) ? o0 + wout : n;
+    if (interior && aligned16(out + base)) {
+        VT* dst = reinterpret_cast<VT*>(out + base);
+#pragma unroll
+        for (int kk = 0; kk < C / VN; ++kk) {
+            const int i = VN * (lane + 64 * kk);
+            if (i >= halo && i < W - halo)
+                __builtin_nontemporal_store(*reinterpret_cast<const VT*>(lds + lds_pos<T, C>(i)),
+                                            dst + lane + 64 * kk);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            const int i = lane + 64 * j;
+            const int64_t g = base + i;
+            if (g >= o0 && g < oend) out[g] = lds[lds_pos<T, C>(i)];
+        }
+    }
+}
+
+// Dynamic LDS of the tile kernels: `wpg` wave areas of 64*(C + VN) cells.
+extern __shared__ __attribute__((aligned(16))) unsigned char hx_lds1d[];
+
+template <typename T, int C>
+__device__ __forceinline__ T* wave_lds() {
+    constexpr int VN = V16<T>::N;
+    return reinterpret_cast<T*>(hx_lds1d) +
+           __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * (64 * (C + VN));
 }
 
 template <typename T, int C>
@@ -179,7 +222,7 @@ __global__ __launch_bounds__(256) void k_stencil1d(Seg1D s, int steps, int halo,
     const int wpg = blockDim.x >> 6;
     const int64_t tile = (int64_t)blockIdx.x * wpg + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (tile >= ntiles) return;
-    tile1d<T, C>(s, tile, steps, halo);
+    tile1d<T, C>(s, tile, steps, halo, wave_lds<T, C>());
 }
 
 template <typename T, int C>
@@ -192,8 +235,13 @@ __global__ __launch_bounds__(256) void k_stencil1d_batched(const Seg1D* __restri
     for (int64_t t = (int64_t)blockIdx.x * wpg + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
          t < ntiles; t += nwaves) {
         const Seg1D s = segs[tseg[t]];
-        tile1d<T, C>(s, tidx[t], steps, halo);
+        tile1d<T, C>(s, tidx[t], steps, halo, wave_lds<T, C>());
     }
+}
+
+template <typename T>
+size_t lds_bytes(const Geom1D& g) {
+    return (size_t)g.wpg * 64 * (g.cpl + V16<T>::N) * sizeof(T);
 }
 
 template <typename T>
@@ -202,11 +250,12 @@ hipError_t launch_single(const Seg1D& s, const Geom1D& g, hipStream_t st) {
     const int64_t ntiles = (s.n + wout - 1) / wout;
     const dim3 block(64 * g.wpg);
     const dim3 grid((unsigned)((ntiles + g.wpg - 1) / g.wpg));
+    const size_t sh = lds_bytes<T>(g);
     switch (g.cpl) {
-    case 8: hipLaunchKernelGGL((k_stencil1d<T, 8>), grid, block, 0, st, s, g.steps, g.halo, ntiles); break;
-    case 16: hipLaunchKernelGGL((k_stencil1d<T, 16>), grid, block, 0, st, s, g.steps, g.halo, ntiles); break;
-    case 32: hipLaunchKernelGGL((k_stencil1d<T, 32>), grid, block, 0, st, s, g.steps, g.halo, ntiles); break;
-    case 64: hipLaunchKernelGGL((k_stencil1d<T, 64>), grid, block, 0, st, s, g.steps, g.halo, ntiles); break;
+    case 8: hipLaunchKernelGGL((k_stencil1d<T, 8>), grid, block, sh, st, s, g.steps, g.halo, ntiles); break;
+    case 16: hipLaunchKernelGGL((k_stencil1d<T, 16>), grid, block, sh, st, s, g.steps, g.halo, ntiles); break;
+    case 32: hipLaunchKernelGGL((k_stencil1d<T, 32>), grid, block, sh, st, s, g.steps, g.halo, ntiles); break;
+    case 64: hipLaunchKernelGGL((k_stencil1d<T, 64>), grid, block, sh, st, s, g.steps, g.halo, ntiles); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -216,12 +265,13 @@ template <typename T>
 hipError_t launch_batched(const Seg1D* segs, const uint32_t* tseg, const uint32_t* tidx,
                           int64_t ntiles, const Geom1D& g, int64_t grid_waves, hipStream_t st) {
     const dim3 block(64 * g.wpg);
+    const size_t sh = lds_bytes<T>(g);
     const dim3 grid((unsigned)((grid_waves + g.wpg - 1) / g.wpg));
     switch (g.cpl) {
-    case 8: hipLaunchKernelGGL((k_stencil1d_batched<T, 8>), grid, block, 0, st, segs, tseg, tidx, ntiles, g.steps, g.halo); break;
-    case 16: hipLaunchKernelGGL((k_stencil1d_batched<T, 16>), grid, block, 0, st, segs, tseg, tidx, ntiles, g.steps, g.halo); break;
-    case 32: hipLaunchKernelGGL((k_stencil1d_batched<T, 32>), grid, block, 0, st, segs, tseg, tidx, ntiles, g.steps, g.halo); break;
-    case 64: hipLaunchKernelGGL((k_stencil1d_batched<T, 64>), grid, block, 0, st, segs, tseg, tidx, ntiles, g.steps, g.halo); break;
+    case 8: hipLaunchKernelGGL((k_stencil1d_batched<T, 8>), grid, block, sh, st, segs, tseg, tidx, ntiles, g.steps, g.halo); break;
+    case 16: hipLaunchKernelGGL((k_stencil1d_batched<T, 16>), grid, block, sh, st, segs, tseg, tidx, ntiles, g.steps, g.halo); break;
+    case 32: hipLaunchKernelGGL((k_stencil1d_batched<T, 32>), grid, block, sh, st, segs, tseg, tidx, ntiles, g.steps, g.halo); break;
+    case 64: hipLaunchKernelGGL((k_stencil1d_batched<T, 64>), grid, block, sh, st, segs, tseg, tidx, ntiles, g.steps, g.halo); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

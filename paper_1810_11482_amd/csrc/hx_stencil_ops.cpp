@@ -134,15 +134,20 @@ static hx_status launch_1d(Ctx* c, const hx_stencil_args* a, const hx_event* dep
 
 using namespace hx;
 
-extern "C" hx_status hx_launch_stencil(hx_ctx ctx, const hx_stencil_args* a, const hx_event* deps,
-                                       int ndeps, hx_event* out) {
-    Ctx* c = reinterpret_cast<Ctx*>(ctx);
-    if (!c) return HX_ERR_INVALID;
-    std::lock_guard<std::recursive_mutex> lk(c->mu);
+hx_status hx::launch_stencil_locked(Ctx* c, const hx_stencil_args* a, const hx_event* deps,
+                                   int ndeps, hx_event* out) {
     if (!a || !out) return c->fail(HX_ERR_ARG, "null argument");
     if (c->host_only) return c->fail(HX_ERR_NO_DEVICE, "host-only context");
     if (a->dtype != HX_F32 && a->dtype != HX_F64) return c->fail(HX_ERR_ARG, "bad dtype");
     hipSetDevice(c->device);
     if (a->dims == 1) return launch_1d(c, a, deps, ndeps, out);
     return c->fail(HX_ERR_ARG, "dims must be 1 or 2");
+}
+
+extern "C" hx_status hx_launch_stencil(hx_ctx ctx, const hx_stencil_args* a, const hx_event* deps,
+                                       int ndeps, hx_event* out) {
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    if (!c) return HX_ERR_INVALID;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    return launch_stencil_locked(c, a, deps, ndeps, out);
 }

@@ -1,0 +1,139 @@
+"""GPU parity of the partitioned future graph (Sec. V-A.2 / Algorithm 1 with
+the Sec. V-A.1 stencil) and of the host-to-host pipeline, against the oracle's
+whole-array loop.  Every time-block split and the plain one-step-per-launch
+form give bit-identical results."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from conftest import rel_l2, rel_max
+
+pytestmark = pytest.mark.gpu
+hx = pytest.importorskip("paper_1810_11482_amd")
+from hxutil import download, upload  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if hx.hx_device_count() == 0:
+        pytest.skip("no GPU")
+    c = hx.hx_ctx_create(0, compute_streams=4)
+    yield c
+    hx.hx_ctx_destroy(c)
+
+
+def run_graph(ctx, u0, parts, steps, r, periodic=True, mode=hx.HX_PART_GRAPH, tb=0, cpl=0):
+    dt = u0.dtype.type
+    code = hx.HX_F64 if dt == np.float64 else hx.HX_F32
+    bounds = workloads.partition_bounds(u0.size, parts)
+    A = [upload(ctx, u0[o:o + s]) for o, s in bounds]
+    B = [hx.hx_buffer_create(ctx, s * u0.itemsize) for _, s in bounds]
+    d = hx.partitioned_desc(code, [s for _, s in bounds], A, B, steps, r, periodic=periodic,
+                            mode=mode, time_block=tb, cells_per_lane=cpl)
+    ev, in_b, _ = hx.hx_run_partitioned(ctx, d)
+    assert hx.hx_wait(ctx, ev) == hx.HX_OK, hx.hx_last_error(ctx)
+    hx.hx_event_release(ctx, ev)
+    res = np.concatenate([download(ctx, b, s, dt) for b, (_, s) in zip(B if in_b else A, bounds)])
+    for b in A + B:
+        hx.hx_buffer_destroy(ctx, b)
+    return res
+
+
+@pytest.mark.parametrize("dtype,tol", [(np.float64, 1e-12), (np.float32, 1e-5)])
+@pytest.mark.parametrize("periodic", [True, False])
+def test_graph_matches_oracle_and_splits_agree(ctx, dtype, tol, periodic):
+    n, parts, steps, r = 200003, 9, 50, 0.25
+    u0 = workloads.uniform(n, 300, int(periodic), 0, 1, dtype)
+    ref_fn = oracle.heat1d_periodic if periodic else oracle.heat1d_dirichlet
+    ref = ref_fn(u0.astype(np.float64), r, steps)
+    outs = []
+    for tb, cpl in [(1, 8), (7, 16), (10, 32), (25, 32), (50, 64)]:
+        got = run_graph(ctx, u0, parts, steps, r, periodic, tb=tb, cpl=cpl)
+        e2, em = rel_l2(got, ref), rel_max(got, ref)
+        print(f"{dtype.__name__} periodic={periodic} tb={tb}: rel_l2={e2:.2e} rel_max={em:.2e}")
+        assert e2 <= tol and em <= 10 * tol
+        outs.append(got)
+    plain = run_graph(ctx, u0, parts, steps, r, periodic, mode=hx.HX_PART_PLAIN)
+    for o in outs:
+        assert np.array_equal(o, outs[0])
+    assert np.array_equal(plain, outs[0])
+
+
+def test_single_partition_graph_is_periodic_run(ctx):
+    u0 = workloads.uniform(5000, 301, 0, 0, 1, np.float64)
+    got = run_graph(ctx, u0, 1, 33, 0.3, tb=11)
+    assert rel_l2(got, oracle.heat1d_periodic(u0, 0.3, 33)) <= 1e-12
+
+
+@pytest.mark.parametrize("parts,steps", [(8, 50), (5, 13), (3, 0)])
+def test_pipeline_host_to_host(ctx, parts, steps):
+    n = 100003
+    u0 = workloads.uniform(n, 302, parts, 0, 1, np.float32)
+    bounds = workloads.partition_bounds(n, parts)
+    hin = hx.hx_host_alloc(ctx, n * 4)
+    hout = hx.hx_host_alloc(ctx, n * 4)
+    ain = np.ctypeslib.as_array((np.ctypeslib.ctypes.c_float * n).from_address(hin))
+    aout = np.ctypeslib.as_array((np.ctypeslib.ctypes.c_float * n).from_address(hout))
+    ain[:] = u0
+    aout[:] = np.nan
+    A = [hx.hx_buffer_create(ctx, s * 4) for _, s in bounds]
+    B = [hx.hx_buffer_create(ctx, s * 4) for _, s in bounds]
+    ghost = hx.hx_buffer_create(ctx, 2 * max(steps, 1) * parts * 4)
+    base = hx.partitioned_desc(hx.HX_F32, [s for _, s in bounds], A, B, steps, 0.25)
+    pd = hx.hx_pipeline_desc(base, hin, hout, ghost)
+    ev, h2d, ker, d2h = hx.hx_run_pipeline(ctx, pd, op_events=True)
+    assert hx.hx_wait(ctx, ev) == hx.HX_OK, hx.hx_last_error(ctx)
+    for e in h2d + ker + d2h + [ev]:
+        assert hx.hx_event_query(ctx, e) == hx.HX_OK
+        hx.hx_event_release(ctx, e)
+    ref = oracle.heat1d_periodic(u0.astype(np.float64), 0.25, steps)
+    assert rel_l2(aout, ref) <= 1e-5
+    for b in A + B + [ghost]:
+        hx.hx_buffer_destroy(ctx, b)
+    hx.hx_host_free(ctx, hin)
+    hx.hx_host_free(ctx, hout)
+
+
+def test_full_size_bench_configuration_sampled(ctx):
+    """2^28 fp32 cells in 64 partitions, r = 0.25, 50 steps, in the graph form
+    the bench times (time blocks 25 and 50): sampled outputs against the
+    oracle's light cone, and the two splits bit-identical on the samples."""
+    n, parts, T, r = 1 << 28, 64, 50, 0.25
+    spec = workloads.Partitioned1D()
+    hin = hx.hx_host_alloc(ctx, n * 4)
+    u0 = np.ctypeslib.as_array((np.ctypeslib.ctypes.c_float * n).from_address(hin))
+    workloads.partitioned1d_u0(spec, out=u0)
+    bounds = workloads.partition_bounds(n, parts)
+    A = [hx.hx_buffer_create(ctx, s * 4) for _, s in bounds]
+    B = [hx.hx_buffer_create(ctx, s * 4) for _, s in bounds]
+    rng = np.random.default_rng(5)
+    idx = np.sort(np.concatenate([rng.choice(n, 40, replace=False),
+                                  [0, 1, n - 1, (1 << 22) - 1, 1 << 22, 63 << 22]]))
+    ref = oracle.heat1d_periodic_at(u0.astype(np.float64), r, T, idx)
+    samples = []
+    for tb, cpl in [(25, 32), (50, 64)]:
+        evs = []
+        for (o, s), a in zip(bounds, A):
+            evs.append(hx.hx_copy_async(ctx, hx.hx_copy_desc(hx.HX_H2D, hin + o * 4, a, 0, 0, 0,
+                                                             s * 4)))
+        d = hx.partitioned_desc(hx.HX_F32, [s for _, s in bounds], A, B, T, r, time_block=tb,
+                                cells_per_lane=cpl)
+        ev, in_b, _ = hx.hx_run_partitioned(ctx, d, deps=evs)
+        assert hx.hx_wait(ctx, ev) == hx.HX_OK
+        for e in evs + [ev]:
+            hx.hx_event_release(ctx, e)
+        res = []
+        for i in idx:
+            p = int(i) >> 22
+            res.append(download(ctx, (B if in_b else A)[p], 1, np.float32,
+                                offset=(int(i) - bounds[p][0]) * 4)[0])
+        res = np.array(res, dtype=np.float64)
+        err = np.max(np.abs(res - ref) / np.abs(ref))
+        print(f"tb={tb}: sampled max rel err {err:.2e}")
+        assert err <= 1e-5
+        samples.append(res)
+    assert np.array_equal(samples[0], samples[1])
+    for b in A + B:
+        hx.hx_buffer_destroy(ctx, b)
+    hx.hx_host_free(ctx, hin)
