@@ -139,9 +139,12 @@ def main():
     ap.add_argument("--time-block", type=int, default=0, help="0 = pick by a short sweep")
     ap.add_argument("--cells-per-lane", type=int, default=0)
     ap.add_argument("--streams", type=int, default=4)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip plain/pipeline/batched legs")
+    ap.add_argument("--legs", default="graph,batched_pass,plain,pipeline,batched,cpu",
+                    help="comma list of legs: graph (the headline, always run), batched_pass, "
+                         "plain, pipeline, batched, cpu, copy (a zero-step pass: a plain "
+                         "device copy of known size, for counter calibration)")
     args = ap.parse_args()
+    legs = set(args.legs.split(","))
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -220,18 +223,28 @@ def main():
         "roofline": roof,
     }
 
+    # --------------------------------------------- batched-pass form of the graph
+    if "batched_pass" in legs:
+        bp = batched_pass_leg(hx, ctx, P, T, r)
+        result["graph_batched_pass"] = bp
+
     # --------------------------------------------------------------- extra legs
-    if not args.no_extra:
+    if "plain" in legs:
         # plain comparator: one launch per partition per step, Algorithm 1 order
         time_steps(P, 1, hx.HX_PART_PLAIN, 1, 8)
         t_plain, _ = time_steps(P, 1, hx.HX_PART_PLAIN, 1, 8)
         result["plain"] = {"ms_per_step": t_plain * 1e3, "launches_per_step": args.parts * T,
                            "speedup_graph_vs_plain": t_plain / sec}
         log(f"plain: {t_plain * 1e3:.3f} ms/step")
+    if "pipeline" in legs:
         result["pipeline"] = pipeline_leg(hx, ctx, P, T, r, cpl)
+    if "batched" in legs:
+        result["batched"] = batched_leg(hx, ctx)
+    if "copy" in legs:
+        result["copy_calibration"] = copy_leg(hx, ctx, P)
 
     # --------------------------------------------------------------- CPU oracle
-    if not args.no_cpu:
+    if "cpu" in legs:
         result["cpu_baseline"] = cpu_leg(r, T)
 
     print(json.dumps(result), flush=True)
@@ -239,13 +252,153 @@ def main():
     hx.hx_ctx_destroy(ctx)
 
 
-def pipeline_leg(hx, ctx, P, T, r, cpl):
-    """Host-to-host run (H2D -> kernel -> D2H per partition) and its overlap."""
+def batched_pass_leg(hx, ctx, P, T, r, reps=10):
+    """The partitioned graph with one node per pass: each pass is one persistent
+    batched launch over all partitions (halos read from the neighbours'
+    buffers), chained on the previous pass."""
     import torch
-    ghost = hx.hx_buffer_create(ctx, 2 * T * P.parts * 4)
+    best = None
+    for tb, cpl, grid in [(50, 32, 16), (50, 32, -1), (50, 16, -1), (25, 32, -1)]:
+        plans = []
+        for src, dst in ((P.A, P.B), (P.B, P.A)):
+            segs = []
+            for p in range(P.parts):
+                lp, rp = (p - 1) % P.parts, (p + 1) % P.parts
+                segs.append(hx.segment(inp=src[p], out=dst[p], n=P.sizes[p], r=r,
+                                       bc_lo=hx.HX_BC_GHOST, bc_hi=hx.HX_BC_GHOST,
+                                       halo_lo=src[lp], halo_lo_offset=(P.sizes[lp] - tb) * 4,
+                                       halo_hi=src[rp], halo_width=tb))
+            plans.append(hx.hx_plan_create_batched(ctx, hx.HX_F32, tb, segs,
+                                                   hx.HX_BATCH_PERSISTENT, cells_per_lane=cpl,
+                                                   grid_waves_per_cu=grid))
+        passes = T // tb
+        P.wait()
+        last = 0
+        k = 0
+
+        def run(nsteps):
+            nonlocal last, k
+            for _ in range(nsteps * passes):
+                ev = hx.hx_launch_batched(ctx, plans[k % 2], deps=[last] if last else [])
+                if last:
+                    hx.hx_event_release(ctx, last)
+                last = ev
+                k += 1
+            assert hx.hx_wait(ctx, last) == hx.HX_OK
+        run(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run(reps)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / reps
+        hx.hx_event_release(ctx, last)
+        for pl in plans:
+            hx.hx_plan_destroy(ctx, pl)
+        cand = {"ms_per_step": sec * 1e3, "cell_updates_per_s": P.n * T / sec, "time_block": tb,
+                "cells_per_lane": cpl, "grid_waves_per_cu": grid, "launches_per_step": passes}
+        log(f"batched-pass graph tb={tb} cpl={cpl} grid/CU={grid}: {sec * 1e3:.3f} ms/step")
+        if best is None or cand["ms_per_step"] < best["ms_per_step"]:
+            best = cand
+    P.cur_in_a = True  # an even number of passes was run from A
+    return best
+
+
+def batched_leg(hx, ctx, reps=5):
+    """4096 independent periodic problems (sizes log-uniform in [1024, 2^20], r
+    in [0.05, 0.25], 20 steps, fp32): persistent launch, captured graph and the
+    plain one-launch-per-problem-per-step form."""
+    import torch
+    import oracle
+    import workloads
+    spec = workloads.Batched1D()
+    sizes, rs, offs = workloads.batched1d_problems(spec)
+    total = int(sizes.sum())
+    u0 = workloads.batched1d_u0(spec)
+    bufs = [hx.hx_buffer_create(ctx, total * 4) for _ in range(3)]
+    ev = hx.hx_copy_async(ctx, hx.hx_copy_desc(hx.HX_H2D, u0.ctypes.data, bufs[0], 0, 0, 0,
+                                               total * 4))
+    assert hx.hx_wait(ctx, ev) == hx.HX_OK
+    hx.hx_event_release(ctx, ev)
+    segs = [hx.segment(inp=bufs[0], in_offset=int(o) * 4, out=bufs[1], out_offset=int(o) * 4,
+                       tmp=bufs[2], tmp_offset=int(o) * 4, n=int(n), r=float(rr),
+                       bc_lo=hx.HX_BC_PERIODIC, bc_hi=hx.HX_BC_PERIODIC)
+            for o, n, rr in zip(offs, sizes, rs)]
+    updates = float(total) * spec.steps
+    res = {"problems": spec.count, "cells": total, "steps": spec.steps}
+
+    def timed(plan, n):
+        e = hx.hx_launch_batched(ctx, plan)
+        assert hx.hx_wait(ctx, e) == hx.HX_OK, hx.hx_last_error(ctx)
+        hx.hx_event_release(ctx, e)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        evs = [hx.hx_launch_batched(ctx, plan) for _ in range(n)]
+        assert hx.hx_wait(ctx, evs[-1]) == hx.HX_OK
+        sec = (time.perf_counter() - t0) / n
+        for e in evs:
+            hx.hx_event_release(ctx, e)
+        return sec
+
+    best = None
+    for cpl, grid in ((16, 16), (16, 64), (16, -1), (32, -1)):
+        plan = hx.hx_plan_create_batched(ctx, hx.HX_F32, spec.steps, segs, hx.HX_BATCH_PERSISTENT,
+                                         cells_per_lane=cpl, grid_waves_per_cu=grid)
+        sec = timed(plan, reps)
+        log(f"batched persistent cpl={cpl} grid/CU={grid}: {sec * 1e3:.3f} ms")
+        if best is None or sec < best[0]:
+            best = (sec, cpl, grid)
+        hx.hx_plan_destroy(ctx, plan)
+    res["persistent"] = {"ms": best[0] * 1e3, "cell_updates_per_s": updates / best[0],
+                         "hbm_algorithmic_GBps": total * 8 / best[0] / 1e9,
+                         "cells_per_lane": best[1], "grid_waves_per_cu": best[2]}
+    # sampled correctness of the persistent result
+    rng = np.random.default_rng(9)
+    errs = []
+    for k in rng.choice(spec.count, 16, replace=False):
+        o, n = int(offs[k]), int(sizes[k])
+        i = int(rng.integers(0, n))
+        got = np.empty(1, np.float32)
+        e = hx.hx_copy_async(ctx, hx.hx_copy_desc(hx.HX_D2H, got.ctypes.data, bufs[1],
+                                                  (o + i) * 4, 0, 0, 4))
+        assert hx.hx_wait(ctx, e) == hx.HX_OK
+        hx.hx_event_release(ctx, e)
+        ref = oracle.heat1d_periodic_at(u0[o:o + n].astype(np.float64), float(rs[k]),
+                                        spec.steps, [i])[0]
+        errs.append(abs(got[0] - ref) / abs(ref))
+    res["persistent"]["sampled_max_rel_err"] = float(max(errs))
+    plan = hx.hx_plan_create_batched(ctx, hx.HX_F32, spec.steps, segs, hx.HX_BATCH_GRAPH,
+                                     cells_per_lane=best[1])
+    sec = timed(plan, reps)
+    hx.hx_plan_destroy(ctx, plan)
+    res["graph"] = {"ms": sec * 1e3, "cell_updates_per_s": updates / sec}
+    plan = hx.hx_plan_create_batched(ctx, hx.HX_F32, spec.steps, segs, hx.HX_BATCH_PLAIN,
+                                     cells_per_lane=16)
+    sec = timed(plan, 1)
+    hx.hx_plan_destroy(ctx, plan)
+    res["plain"] = {"ms": sec * 1e3, "cell_updates_per_s": updates / sec,
+                    "launches": spec.count * spec.steps}
+    res["speedup_persistent_vs_plain"] = res["plain"]["ms"] / res["persistent"]["ms"]
+    res["speedup_graph_vs_plain"] = res["plain"]["ms"] / res["graph"]["ms"]
+    for b in bufs:
+        hx.hx_buffer_destroy(ctx, b)
+    log(f"batched: {res}")
+    return res
+
+
+def pipeline_leg(hx, ctx0, P, T, r, cpl):
+    """Host-to-host run (H2D -> kernel -> D2H per partition) and its overlap, on a
+    context whose default stream set leaves each copy stream a hardware queue."""
+    import torch
+    ctx = hx.hx_ctx_create(0, timing=True)
+    P.wait()
+    saved = (P.ctx, P.A, P.B, P.last)
+    P.ctx = ctx
+    P.A = [hx.hx_buffer_create(ctx, s * 4) for s in P.sizes]
+    P.B = [hx.hx_buffer_create(ctx, s * 4) for s in P.sizes]
+    P.last = 0
     base = hx.partitioned_desc(hx.HX_F32, P.sizes, P.A, P.B, T, r, periodic=True,
                                time_block=T, cells_per_lane=cpl)
-    pd = hx.hx_pipeline_desc(base, P.host_in, P.host_out, ghost)
+    pd = hx.hx_pipeline_desc(base, P.host_in, P.host_out)
     walls = []
     spans = None
     for it in range(3):
@@ -276,7 +429,7 @@ def pipeline_leg(hx, ctx, P, T, r, cpl):
     # 16 MiB device copies)
     pd0 = hx.hx_pipeline_desc(hx.partitioned_desc(hx.HX_F32, P.sizes, P.A, P.B, 0, r,
                                                   periodic=True, cells_per_lane=cpl),
-                              P.host_in, P.host_out, ghost)
+                              P.host_in, P.host_out)
     cw = []
     for it in range(3):
         torch.cuda.synchronize()
@@ -294,7 +447,12 @@ def pipeline_leg(hx, ctx, P, T, r, cpl):
     lit = intersect_len(C, K) / measure_len(C)
     eta = (t_copy + t_kernel - W) / min(t_copy, t_kernel)
     bytes_copied = 2 * P.n * 4
-    hx.hx_buffer_destroy(ctx, ghost)
+    P.wait()
+    if P.last:
+        hx.hx_event_release(ctx, P.last)
+    hx.hx_ctx_destroy(ctx)
+    P.ctx, P.A, P.B, P.last = saved
+    P.cur_in_a = True
     res = {"wall_ms": W * 1e3, "copies_alone_ms": t_copy * 1e3, "kernels_alone_ms": t_kernel * 1e3,
            "pcie_inclusive_cell_updates_per_s": P.n * T / W,
            "copy_hidden_literal": lit, "overlap_efficiency_eta": eta,
@@ -302,6 +460,23 @@ def pipeline_leg(hx, ctx, P, T, r, cpl):
            "sampled_max_rel_err": err}
     log(f"pipeline: {res}")
     return res
+
+
+def copy_leg(hx, ctx, P, reps=5):
+    """Zero-step passes over the whole array in one launch: a plain device copy
+    of 2^28 fp32 cells (1 GiB read, 1 GiB written), whose HBM counters scale
+    the stencil's."""
+    a = hx.stencil_args(dims=1, dtype=hx.HX_F32, nx=P.sizes[0], steps=0, r=0.0, inp=P.A[0],
+                        out=P.B[0], cells_per_lane=32, time_block=1)
+    evs = [hx.hx_launch_stencil(ctx, a) for _ in range(reps)]
+    assert hx.hx_wait(ctx, evs[-1]) == hx.HX_OK
+    d = [b - s_ for s_, b in (hx.hx_event_span(ctx, e, e) for e in evs)]
+    for e in evs:
+        hx.hx_event_release(ctx, e)
+    ms = float(np.median(d))
+    nbytes = P.sizes[0] * 8
+    return {"cells": P.sizes[0], "bytes_moved": nbytes, "avg_ms": ms,
+            "GBps": nbytes / (ms * 1e-3) / 1e9}
 
 
 def cpu_leg(r, T):

@@ -98,7 +98,9 @@ hx_status hx_device_info(int dev, hx_device_info_t* info);
 
 /* ---------------------------------------------------------------- context */
 typedef struct {
-    int compute_streams;        /* kernel streams; 0 = 4 */
+    int compute_streams;        /* kernel streams; 0 = two fewer than the hardware
+                                   queues HIP uses (GPU_MAX_HW_QUEUES, 4 by default),
+                                   so the copy streams keep queues of their own */
     void* external_stream;      /* optional hipStream_t used as compute stream 0
                                    (e.g. torch's current stream); not owned */
     int check;                  /* 1 = record accesses and run the hazard checker */
@@ -227,16 +229,23 @@ typedef struct {
     int steps;
     double r;
     int mode;                   /* hx_part_mode */
-    int time_block;             /* steps per pass (<= the smallest partition); 0 = 32 */
+    int time_block;             /* steps per pass (<= the smallest partition); 0 = 32 in 1D,
+                                   8 in 2D */
     int cells_per_lane;         /* kernel geometry, 0 = tuned */
     int waves_per_group;
+    int dims;                   /* 0 or 1 = a 1D array split into runs of cells; 2 = a grid
+                                   of nx columns split into bands of sizes[p] rows (top and
+                                   bottom edges zero-Dirichlet; periodic must be 0) */
+    int64_t nx;                 /* 2D: cells per row */
+    int rows_per_block;         /* 2D kernel geometry, 0 = tuned */
 } hx_partitioned_desc;
 
-/* Advance a device-resident 1D array split over `parts` buffers by `steps` heat
+/* Advance a device-resident array split over `parts` buffers by `steps` heat
  * steps, as a future graph (the partition benchmark of Sec. V-A.2 /
- * Algorithm 1 with the stencil of Sec. V-A.1).  HX_PART_GRAPH: node (p, b)
- * advances partition p by one time block, reading `time_block` halo cells
- * straight from its neighbours' buffers, and depends on nodes (p-1, b-1),
+ * Algorithm 1 with the stencil of Sec. V-A.1); 1D runs of cells or 2D row
+ * bands.  HX_PART_GRAPH: node (p, b) advances partition p by one time block,
+ * reading `time_block` halo cells (rows) straight from its neighbours' buffers,
+ * and depends on nodes (p-1, b-1),
  * (p, b-1) and (p+1, b-1); independent nodes run concurrently on the compute
  * streams.  HX_PART_PLAIN: the comparator: one step per launch, issued in
  * Algorithm 1's order and chained on one stream.  `deps` gate the first pass.
@@ -250,18 +259,64 @@ typedef struct {
     hx_partitioned_desc part;   /* steps <= smallest partition; one fused pass per partition */
     const void* host_in;        /* whole array, sum(sizes) cells (pinned for overlap) */
     void* host_out;             /* result, sum(sizes) cells */
-    hx_buffer ghost;            /* 2 * max(steps, 1) * parts cells of halo slots */
 } hx_pipeline_desc;
 
-/* Host-to-host run of Algorithm 1 with the stencil: per partition an H2D copy
- * of its cells into bufs_a[p] and of its two halos into its ghost slots, one
- * fused kernel pass into bufs_b[p], and a D2H copy into host_out; the copies
+/* Host-to-host run of Algorithm 1 with the stencil: an H2D copy of every
+ * partition into bufs_a[p], one fused kernel pass per partition into bufs_b[p]
+ * (its halos read from the neighbours' bufs_a, so it depends on the copies of
+ * p-1, p and p+1), and a D2H copy of every partition into host_out.  Copies
  * run on the copy streams while kernels of other partitions run on the compute
  * streams.  op_events (optional, 3 x parts entries: the H2D copies, the
- * kernels, the D2H copies) receives the operations' events; the caller
- * releases them. */
+ * kernels, the D2H copies, each indexed by partition) receives the operations'
+ * events; the caller releases them. */
 hx_status hx_run_pipeline(hx_ctx ctx, const hx_pipeline_desc* desc, const hx_event* deps,
                           int ndeps, hx_event* out, hx_event* op_events);
+
+/* ------------------------------------------------------------ batched plans */
+typedef enum {
+    HX_BATCH_PERSISTENT = 0,   /* one persistent launch striding over every tile */
+    HX_BATCH_GRAPH = 1,        /* one launch per segment, captured once as a hipGraph */
+    HX_BATCH_PLAIN = 2         /* comparator: one launch per segment per step */
+} hx_batch_mode;
+
+typedef struct {
+    hx_buffer in;  size_t in_offset;      /* n cells, byte offset */
+    hx_buffer out; size_t out_offset;     /* n cells; must not overlap in */
+    hx_buffer tmp; size_t tmp_offset;     /* n cells; HX_BATCH_PLAIN with steps > 1 only */
+    int64_t n;
+    double r;
+    int bc_lo, bc_hi;                     /* hx_bc of each end */
+    hx_buffer halo_lo; size_t halo_lo_offset;   /* as in hx_stencil_args */
+    hx_buffer halo_hi; size_t halo_hi_offset;
+    int halo_width;
+} hx_segment;
+
+typedef struct {
+    int dtype;                  /* hx_dtype, shared by all segments */
+    int steps;                  /* steps per launch: one fused pass per segment */
+    int count;
+    const hx_segment* segs;     /* `count` segments (copied at plan creation) */
+    int mode;                   /* hx_batch_mode */
+    int cells_per_lane;         /* 0 = tuned */
+    int waves_per_group;        /* 0 = tuned */
+    int grid_waves_per_cu;      /* PERSISTENT: > 0 = a persistent grid of that many waves per
+                                   CU striding over the tiles; < 0 = one wave per tile;
+                                   0 = tuned (one wave per tile if untuned) */
+} hx_batch_desc;
+
+/* Build a batch: `count` 1D segments, each with its own size, r, boundaries
+ * and halos, all advanced `steps` steps by one operation (the batched driver:
+ * many uneven partitions or independent problems in one persistent launch or
+ * one captured graph).  Buffers are resolved to addresses now: they must
+ * outlive the plan.  The work table is built and uploaded once. */
+hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* desc, hx_plan* plan);
+
+/* Run a batch plan once after `deps`. */
+hx_status hx_launch_batched(hx_ctx ctx, hx_plan plan, const hx_event* deps, int ndeps,
+                            hx_event* out);
+
+/* Free a plan (waits for the context's queued work first). */
+hx_status hx_plan_destroy(hx_ctx ctx, hx_plan plan);
 
 /* ------------------------------------------------------------------ events */
 /* An event that completes when every event in `events` has completed (the

@@ -86,15 +86,31 @@ class hx_partitioned_desc(ctypes.Structure):
                 ("bufs_b", ctypes.POINTER(_u64)), ("periodic", ctypes.c_int),
                 ("steps", ctypes.c_int), ("r", ctypes.c_double), ("mode", ctypes.c_int),
                 ("time_block", ctypes.c_int), ("cells_per_lane", ctypes.c_int),
-                ("waves_per_group", ctypes.c_int)]
+                ("waves_per_group", ctypes.c_int), ("dims", ctypes.c_int), ("nx", _i64),
+                ("rows_per_block", ctypes.c_int)]
 
 
 class hx_pipeline_desc(ctypes.Structure):
-    _fields_ = [("part", hx_partitioned_desc), ("host_in", _vp), ("host_out", _vp),
-                ("ghost", _u64)]
+    _fields_ = [("part", hx_partitioned_desc), ("host_in", _vp), ("host_out", _vp)]
 
 
 HX_PART_GRAPH, HX_PART_PLAIN = 0, 1
+HX_BATCH_PERSISTENT, HX_BATCH_GRAPH, HX_BATCH_PLAIN = 0, 1, 2
+
+
+class hx_segment(ctypes.Structure):
+    _fields_ = [("in_", _u64), ("in_offset", _sz), ("out", _u64), ("out_offset", _sz),
+                ("tmp", _u64), ("tmp_offset", _sz), ("n", _i64), ("r", ctypes.c_double),
+                ("bc_lo", ctypes.c_int), ("bc_hi", ctypes.c_int),
+                ("halo_lo", _u64), ("halo_lo_offset", _sz),
+                ("halo_hi", _u64), ("halo_hi_offset", _sz), ("halo_width", ctypes.c_int)]
+
+
+class hx_batch_desc(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int), ("steps", ctypes.c_int), ("count", ctypes.c_int),
+                ("segs", ctypes.POINTER(hx_segment)), ("mode", ctypes.c_int),
+                ("cells_per_lane", ctypes.c_int), ("waves_per_group", ctypes.c_int),
+                ("grid_waves_per_cu", ctypes.c_int)]
 
 
 # ----------------------------------------------------------------- prototypes
@@ -117,6 +133,10 @@ _PROTOS = {
     "hx_launch_stencil": (_i32, [_vp, ctypes.POINTER(hx_stencil_args), ctypes.POINTER(_u64),
                                  ctypes.c_int, ctypes.POINTER(_u64)]),
     "hx_when_all": (_i32, [_vp, ctypes.POINTER(_u64), ctypes.c_int, ctypes.POINTER(_u64)]),
+    "hx_plan_create_batched": (_i32, [_vp, ctypes.POINTER(hx_batch_desc), ctypes.POINTER(_u64)]),
+    "hx_launch_batched": (_i32, [_vp, _u64, ctypes.POINTER(_u64), ctypes.c_int,
+                                 ctypes.POINTER(_u64)]),
+    "hx_plan_destroy": (_i32, [_vp, _u64]),
     "hx_run_partitioned": (_i32, [_vp, ctypes.POINTER(hx_partitioned_desc), ctypes.POINTER(_u64),
                                   ctypes.c_int, ctypes.POINTER(_u64), ctypes.POINTER(ctypes.c_int),
                                   ctypes.POINTER(_u64)]),
@@ -257,14 +277,16 @@ def hx_launch_stencil(ctx, args: hx_stencil_args, deps=()) -> int:
 
 
 def partitioned_desc(dtype, sizes, bufs_a, bufs_b, steps, r, periodic=True,
-                     mode=HX_PART_GRAPH, time_block=0, cells_per_lane=0, waves_per_group=0):
-    """hx_partitioned_desc; the host arrays are kept alive on the returned struct."""
+                     mode=HX_PART_GRAPH, time_block=0, cells_per_lane=0, waves_per_group=0,
+                     dims=1, nx=0, rows_per_block=0):
+    """hx_partitioned_desc; the host arrays are kept alive on the returned struct.
+    2D: dims=2, nx = row length, sizes = rows per band, periodic must be False."""
     P = len(sizes)
     sz = (_i64 * P)(*[int(x) for x in sizes])
     ba = (_u64 * P)(*[int(x) for x in bufs_a])
     bb = (_u64 * P)(*[int(x) for x in bufs_b])
     d = hx_partitioned_desc(dtype, P, sz, ba, bb, int(bool(periodic)), steps, r, mode,
-                            time_block, cells_per_lane, waves_per_group)
+                            time_block, cells_per_lane, waves_per_group, dims, nx, rows_per_block)
     d._keep = (sz, ba, bb)
     return d
 
@@ -276,7 +298,7 @@ def hx_run_partitioned(ctx, desc: hx_partitioned_desc, deps=(), node_events=Fals
     fb = ctypes.c_int()
     nodes = None
     if node_events:
-        D = desc.time_block or min(desc.steps, 32)
+        D = desc.time_block or min(desc.steps, 8 if desc.dims == 2 else 32)
         if desc.mode == HX_PART_PLAIN:
             D = 1
         passes = 0 if desc.steps == 0 else -(-desc.steps // D)
@@ -298,6 +320,39 @@ def hx_run_pipeline(ctx, desc: hx_pipeline_desc, deps=(), op_events=False):
         return ev.value, None, None, None
     o = list(ops)
     return ev.value, o[:P], o[P:2 * P], o[2 * P:]
+
+
+def hx_plan_create_batched(ctx, dtype, steps, segs, mode=HX_BATCH_PERSISTENT,
+                           cells_per_lane=0, waves_per_group=0, grid_waves_per_cu=0) -> int:
+    """segs: a list of hx_segment."""
+    arr = (hx_segment * len(segs))(*segs)
+    d = hx_batch_desc(dtype, steps, len(segs), arr, mode, cells_per_lane, waves_per_group,
+                      grid_waves_per_cu)
+    h = _u64()
+    _ok(ctx, lib.hx_plan_create_batched(ctx, ctypes.byref(d), ctypes.byref(h)))
+    return h.value
+
+
+def hx_launch_batched(ctx, plan: int, deps=()) -> int:
+    arr, n = _deps(deps)
+    ev = _u64()
+    _ok(ctx, lib.hx_launch_batched(ctx, plan, arr, n, ctypes.byref(ev)))
+    return ev.value
+
+
+def hx_plan_destroy(ctx, plan: int) -> None:
+    _ok(ctx, lib.hx_plan_destroy(ctx, plan))
+
+
+def segment(**kw) -> hx_segment:
+    if "inp" in kw:
+        kw["in_"] = kw.pop("inp")
+    s = hx_segment()
+    for k, v in kw.items():
+        if not hasattr(s, k):
+            raise TypeError(f"hx_segment has no field {k}")
+        setattr(s, k, v)
+    return s
 
 
 def hx_when_all(ctx, events) -> int:

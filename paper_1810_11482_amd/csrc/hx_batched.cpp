@@ -1,0 +1,277 @@
+// Batched 1D plans: many independent (or halo-coupled) segments advanced by
+// one fused pass in a single operation.
+//
+//  PERSISTENT  one launch over a flat tile table (segment, tile) built once
+//              at plan creation, largest segments first: either one wave per
+//              tile, or a persistent grid of a few waves per CU striding over
+//              the table.  Tiles are of equal size, so a static stride
+//              balances the grid without atomics.
+//  GRAPH       one kernel launch per segment, captured once into a hipGraph
+//              and replayed as a single graph launch.
+//  PLAIN       the comparator: one launch per segment per time step.
+#include <algorithm>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "hx_internal.h"
+#include "hx_runtime.hpp"
+#include "hx_tune.hpp"
+
+using namespace hx;
+
+namespace {
+
+enum { PLAN_BATCHED = 1 };
+
+struct BatchPlan {
+    int dtype = 0;
+    int steps = 0;
+    int mode = 0;
+    Geom1D g{};
+    std::vector<Seg1D> segs;        // host copy (GRAPH / PLAIN modes)
+    std::vector<char*> tmps;        // PLAIN: per-segment ping-pong space
+    Seg1D* segs_dev = nullptr;
+    uint32_t* tseg_dev = nullptr;
+    uint32_t* tidx_dev = nullptr;
+    int64_t ntiles = 0;
+    int64_t grid_waves = 0;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<Access> acc;
+    int device = 0;
+};
+
+void destroy_plan(void* p) {
+    BatchPlan* b = static_cast<BatchPlan*>(p);
+    hipSetDevice(b->device);
+    hipDeviceSynchronize();
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    if (b->cap) hipStreamDestroy(b->cap);
+    if (b->segs_dev) hipFree(b->segs_dev);
+    if (b->tseg_dev) hipFree(b->tseg_dev);
+    if (b->tidx_dev) hipFree(b->tidx_dev);
+    delete b;
+}
+
+size_t esz(int dt) { return dt == HX_F64 ? 8 : 4; }
+int vecn(int dt) { return dt == HX_F64 ? 2 : 4; }
+
+}  // namespace
+
+extern "C" hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* d, hx_plan* out) {
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    if (!c) return HX_ERR_INVALID;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    if (!d || !out) return c->fail(HX_ERR_ARG, "null argument");
+    if (c->host_only) return c->fail(HX_ERR_NO_DEVICE, "host-only context");
+    if (d->dtype != HX_F32 && d->dtype != HX_F64) return c->fail(HX_ERR_ARG, "bad dtype");
+    if (d->count < 1 || !d->segs) return c->fail(HX_ERR_ARG, "count >= 1 segments required");
+    if (d->steps < 0) return c->fail(HX_ERR_ARG, "negative steps");
+    if (d->mode != HX_BATCH_PERSISTENT && d->mode != HX_BATCH_GRAPH && d->mode != HX_BATCH_PLAIN)
+        return c->fail(HX_ERR_ARG, "bad mode");
+    hipSetDevice(c->device);
+    const size_t es = esz(d->dtype);
+    const int vn = vecn(d->dtype);
+
+    auto* bp = new BatchPlan();
+    bp->device = c->device;
+    bp->dtype = d->dtype;
+    bp->steps = d->steps;
+    bp->mode = d->mode;
+    int64_t total = 0;
+    for (int i = 0; i < d->count; ++i) total += d->segs[i].n;
+    TunedGeom tg;
+    const bool tuned = tune_lookup(tune_key_batched(d->dtype, total, d->count, d->steps), &tg);
+    bp->g.cpl = d->cells_per_lane ? d->cells_per_lane : (tuned && tg.cpl ? tg.cpl : 16);
+    bp->g.wpg = d->waves_per_group ? d->waves_per_group : (tuned && tg.wpg ? tg.wpg : 4);
+    if (bp->g.cpl != 8 && bp->g.cpl != 16 && bp->g.cpl != 32 && bp->g.cpl != 64) {
+        delete bp;
+        return c->fail(HX_ERR_ARG, "cells_per_lane must be 8, 16, 32 or 64");
+    }
+    if (bp->g.wpg != 1 && bp->g.wpg != 2 && bp->g.wpg != 4) {
+        delete bp;
+        return c->fail(HX_ERR_ARG, "waves_per_group must be 1, 2 or 4");
+    }
+    const int fused = (d->mode == HX_BATCH_PLAIN) ? 1 : d->steps;
+    bp->g.steps = fused;
+    bp->g.halo = std::max(vn, (fused + vn - 1) / vn * vn);
+    if (fused > max_time_block_1d(d->dtype, bp->g.cpl)) {
+        delete bp;
+        return c->fail(HX_ERR_ARG, "steps exceed the fused-pass limit of the tile geometry");
+    }
+
+    for (int i = 0; i < d->count; ++i) {
+        const hx_segment& s = d->segs[i];
+        auto bad = [&](hx_status st, const std::string& m) {
+            delete bp;
+            return c->fail(st, "segment " + std::to_string(i) + ": " + m);
+        };
+        if (s.n <= 0) return bad(HX_ERR_ARG, "n must be positive");
+        auto okbc = [](int b) { return b >= HX_BC_PERIODIC && b <= HX_BC_GHOST; };
+        if (!okbc(s.bc_lo) || !okbc(s.bc_hi)) return bad(HX_ERR_ARG, "bad boundary");
+        if ((s.bc_lo == HX_BC_PERIODIC) != (s.bc_hi == HX_BC_PERIODIC))
+            return bad(HX_ERR_ARG, "periodic must apply to both ends");
+        const bool ghost = s.bc_lo == HX_BC_GHOST || s.bc_hi == HX_BC_GHOST;
+        if (ghost && (s.halo_width < d->steps || s.halo_width <= 0))
+            return bad(HX_ERR_ARG, "halo_width must cover the steps");
+        if (ghost && d->mode == HX_BATCH_PLAIN && d->steps > 1)
+            return bad(HX_ERR_ARG, "a halo-coupled segment cannot be run step by step alone");
+        Seg1D sg{};
+        char *pi = nullptr, *po = nullptr, *pl = nullptr, *ph = nullptr, *pt = nullptr;
+        Access a{};
+        hx_status st = resolve_range(c, s.in, s.in_offset, (size_t)s.n * es, &pi, &a, false);
+        if (st) return bad(st, "in");
+        bp->acc.push_back(a);
+        Access ao{};
+        st = resolve_range(c, s.out, s.out_offset, (size_t)s.n * es, &po, &ao, true);
+        if (st) return bad(st, "out");
+        if (ao.buf_slot == a.buf_slot && ao.lo < a.hi && a.lo < ao.hi)
+            return bad(HX_ERR_ARG, "in and out overlap");
+        bp->acc.push_back(ao);
+        if (s.bc_lo == HX_BC_GHOST) {
+            st = resolve_range(c, s.halo_lo, s.halo_lo_offset, (size_t)s.halo_width * es, &pl, &a,
+                               false);
+            if (st) return bad(st, "halo_lo");
+            bp->acc.push_back(a);
+        }
+        if (s.bc_hi == HX_BC_GHOST) {
+            st = resolve_range(c, s.halo_hi, s.halo_hi_offset, (size_t)s.halo_width * es, &ph, &a,
+                               false);
+            if (st) return bad(st, "halo_hi");
+            bp->acc.push_back(a);
+        }
+        if (d->mode == HX_BATCH_PLAIN && d->steps > 1) {
+            if (s.tmp == 0) return bad(HX_ERR_ARG, "PLAIN with more than one step needs tmp");
+            st = resolve_range(c, s.tmp, s.tmp_offset, (size_t)s.n * es, &pt, &a, true);
+            if (st) return bad(st, "tmp");
+            bp->acc.push_back(a);
+        }
+        sg.in = pi;
+        sg.out = po;
+        sg.halo_lo = pl;
+        sg.halo_hi = ph;
+        sg.n = s.n;
+        sg.r = s.r;
+        sg.bc_lo = s.bc_lo;
+        sg.bc_hi = s.bc_hi;
+        sg.hw = s.halo_width;
+        sg.shift = tile_shift(pi, (int)es);
+        bp->segs.push_back(sg);
+        bp->tmps.push_back(pt);
+    }
+
+    if (d->mode == HX_BATCH_PERSISTENT) {
+        // tile table, largest segments first
+        std::vector<int> order(d->count);
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int b) { return bp->segs[a].n > bp->segs[b].n; });
+        std::vector<uint32_t> tseg, tidx;
+        for (int i : order) {
+            const int64_t nt = tiles_1d(bp->segs[i], bp->g);
+            for (int64_t t = 0; t < nt; ++t) {
+                tseg.push_back((uint32_t)i);
+                tidx.push_back((uint32_t)t);
+            }
+        }
+        bp->ntiles = (int64_t)tseg.size();
+        // Grid: `wpc` resident waves per CU striding over the tiles, or (the
+        // default, wpc <= 0 after tuning) one wave per tile.
+        const int wpc = d->grid_waves_per_cu ? d->grid_waves_per_cu
+                                             : (tuned && tg.grid ? tg.grid : 0);
+        hipDeviceProp_t prop;
+        hipGetDeviceProperties(&prop, c->device);
+        bp->grid_waves = wpc <= 0 ? bp->ntiles
+                                  : std::min<int64_t>(bp->ntiles,
+                                                      (int64_t)prop.multiProcessorCount * wpc);
+        bool ok = hipMalloc(&bp->segs_dev, sizeof(Seg1D) * bp->segs.size()) == hipSuccess &&
+                  hipMalloc(&bp->tseg_dev, 4 * tseg.size()) == hipSuccess &&
+                  hipMalloc(&bp->tidx_dev, 4 * tidx.size()) == hipSuccess;
+        ok = ok &&
+             hipMemcpy(bp->segs_dev, bp->segs.data(), sizeof(Seg1D) * bp->segs.size(),
+                       hipMemcpyHostToDevice) == hipSuccess &&
+             hipMemcpy(bp->tseg_dev, tseg.data(), 4 * tseg.size(), hipMemcpyHostToDevice) ==
+                 hipSuccess &&
+             hipMemcpy(bp->tidx_dev, tidx.data(), 4 * tidx.size(), hipMemcpyHostToDevice) ==
+                 hipSuccess;
+        if (!ok) {
+            hipGetLastError();
+            destroy_plan(bp);
+            return c->fail(HX_ERR_OOM, "could not allocate the batch tables");
+        }
+    } else if (d->mode == HX_BATCH_GRAPH) {
+        bool ok = hipStreamCreateWithFlags(&bp->cap, hipStreamNonBlocking) == hipSuccess &&
+                  hipStreamBeginCapture(bp->cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+            for (const Seg1D& sg : bp->segs)
+                if (launch_stencil1d(bp->dtype, sg, bp->g, bp->cap) != hipSuccess) ok = false;
+            hipGraph_t g = nullptr;
+            if (hipStreamEndCapture(bp->cap, &g) != hipSuccess) ok = false;
+            bp->graph = g;
+        }
+        ok = ok && hipGraphInstantiate(&bp->exec, bp->graph, nullptr, nullptr, 0) == hipSuccess;
+        if (!ok) {
+            hipGetLastError();
+            destroy_plan(bp);
+            return c->fail(HX_ERR_HIP, "graph capture of the batch failed");
+        }
+    }
+    *out = c->add_plan(PLAN_BATCHED, bp, destroy_plan);
+    return HX_OK;
+}
+
+extern "C" hx_status hx_launch_batched(hx_ctx ctx, hx_plan plan, const hx_event* deps, int ndeps,
+                                       hx_event* out) {
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    if (!c) return HX_ERR_INVALID;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    if (!out) return c->fail(HX_ERR_ARG, "null output event");
+    Plan* p = c->get_plan(plan, PLAN_BATCHED);
+    if (!p) return c->fail(HX_ERR_INVALID, "invalid batched plan");
+    hipSetDevice(c->device);
+    BatchPlan* bp = static_cast<BatchPlan*>(p->impl);
+    std::string what = "batched1d x" + std::to_string(bp->segs.size());
+    return c->submit(
+        SC_COMPUTE, deps, ndeps, bp->acc, what,
+        [bp](hipStream_t st) -> hipError_t {
+            if (bp->mode == HX_BATCH_PERSISTENT)
+                return launch_stencil1d_batched(bp->dtype, bp->segs_dev, bp->tseg_dev,
+                                                bp->tidx_dev, bp->ntiles, bp->g, bp->grid_waves,
+                                                st);
+            if (bp->mode == HX_BATCH_GRAPH) return hipGraphLaunch(bp->exec, st);
+            // PLAIN: step by step, ping-pong so the last step lands in out
+            const int S = bp->steps;
+            for (size_t i = 0; i < bp->segs.size(); ++i) {
+                const Seg1D& s0 = bp->segs[i];
+                const void* src = s0.in;
+                for (int t = 0; t < std::max(S, 1); ++t) {
+                    Seg1D sg = s0;
+                    sg.in = src;
+                    sg.out = (S <= 1 || (S - 1 - t) % 2 == 0) ? s0.out : bp->tmps[i];
+                    Geom1D g = bp->g;
+                    g.steps = S == 0 ? 0 : 1;
+                    hipError_t e = launch_stencil1d(bp->dtype, sg, g, st);
+                    if (e != hipSuccess) return e;
+                    src = sg.out;
+                }
+            }
+            return hipSuccess;
+        },
+        out);
+}
+
+extern "C" hx_status hx_plan_destroy(hx_ctx ctx, hx_plan plan) {
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    if (!c) return HX_ERR_INVALID;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    Plan* p = c->get_plan(plan, -1);
+    if (!p) return HX_ERR_INVALID;
+    for (hipStream_t s : c->streams) hipStreamSynchronize(s);
+    if (p->destroy) p->destroy(p->impl);
+    p->live = false;
+    p->impl = nullptr;
+    return HX_OK;
+}

@@ -18,8 +18,16 @@ struct Seg1D {
     double r;
     int32_t bc_lo, bc_hi;  // hx_bc values
     int32_t hw;            // halo width of the GHOST sides
-    int32_t pad_;
+    int32_t shift;         // tile grid offset: tiles start at t*wout - shift, chosen so
+                           // that interior tiles of `in` start 16-byte aligned
 };
+
+// Tile-grid shift that makes in + (t*wout - shift - halo) 16-byte aligned for
+// every t (wout and halo are multiples of the vector width).
+inline int32_t tile_shift(const void* in, int esize) {
+    const int vn = 16 / esize;
+    return (int32_t)((reinterpret_cast<uintptr_t>(in) / esize) % vn);
+}
 
 // Launch geometry of the 1D tile kernel: each wave owns 64*cpl cells, of which
 // the outer `halo` on each side are recomputed context and 64*cpl - 2*halo are
@@ -32,6 +40,10 @@ struct Geom1D {
 };
 
 inline int64_t tile_out_1d(const Geom1D& g) { return 64LL * g.cpl - 2LL * g.halo; }
+inline int64_t tiles_1d(const Seg1D& s, const Geom1D& g) {
+    const int64_t w = tile_out_1d(g);
+    return (s.n + s.shift + w - 1) / w;
+}
 
 // dtype: 0 = f32, 1 = f64.  Returns hipSuccess or the launch error.
 hipError_t launch_stencil1d(int dtype, const Seg1D& seg, const Geom1D& g, hipStream_t stream);
@@ -42,5 +54,31 @@ hipError_t launch_stencil1d(int dtype, const Seg1D& seg, const Geom1D& g, hipStr
 hipError_t launch_stencil1d_batched(int dtype, const Seg1D* segs_dev, const uint32_t* tile_seg,
                                     const uint32_t* tile_idx, int64_t ntiles, const Geom1D& g,
                                     int64_t grid_waves, hipStream_t stream);
+
+// One 2D band: ny rows of nx cells, row-major, advanced `steps` steps from in
+// into out.  Rows outside [0, ny) come from the top/bottom rule; columns
+// outside [0, nx) are zero-Dirichlet.
+struct Band2D {
+    const void* in;
+    void* out;
+    const void* halo_top;  // GHOST top: hw rows, its last row is row -1
+    const void* halo_bot;  // GHOST bottom: hw rows, its first row is row ny
+    int64_t nx, ny;
+    double r;
+    int32_t bc_top, bc_bot;
+    int32_t hw;
+    int32_t aligned;       // every row of in/out/halos starts 16-byte aligned
+};
+
+struct Geom2D {
+    int cpl;    // columns per lane: 4 (or 8 for f32 with steps <= 8)
+    int steps;  // fused time levels of this pass
+    int halo;   // context columns per side (>= steps, multiple of the vector width)
+    int rows;   // output rows per wave
+    int wpg;    // waves per workgroup
+};
+
+bool stencil2d_supported(int dtype, int cpl, int steps);
+hipError_t launch_stencil2d(int dtype, const Band2D& b, const Geom2D& g, hipStream_t stream);
 
 }  // namespace hx

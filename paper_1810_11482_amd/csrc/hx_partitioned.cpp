@@ -11,9 +11,11 @@
 // them).  The plain form is the same work issued in Algorithm 1's order with
 // one step per launch, every launch chained on one stream.
 //
-// hx_run_pipeline: host-resident input: per partition an H2D copy of its cells
-// and of its two halos (into a ghost buffer), one fused kernel pass, and a D2H
-// copy of the result, so copies of one partition overlap the kernels of others.
+// hx_run_pipeline: host-resident input: Algorithm 1's three loops (every H2D
+// copy, then one fused kernel pass per partition, then every D2H copy), with
+// each kernel depending on its own and its neighbours' copies (it reads its
+// halos from their device buffers), so copies of one partition overlap the
+// kernels of others and the two copy directions overlap each other.
 #include <algorithm>
 #include <string>
 #include <vector>
@@ -26,6 +28,21 @@ namespace {
 
 size_t esz(int dtype) { return dtype == HX_F64 ? 8 : 4; }
 
+// Cells per partition unit: 1 for a 1D run, nx for a row of a 2D band.
+int64_t unit(const hx_partitioned_desc* d) { return d->dims == 2 ? d->nx : 1; }
+
+// Kernel arguments of one partition node: sizes[p] cells (1D) or rows (2D).
+void node_args(const hx_partitioned_desc* d, int p, hx_stencil_args* a) {
+    a->dims = d->dims == 2 ? 2 : 1;
+    a->dtype = d->dtype;
+    a->nx = d->dims == 2 ? d->nx : d->sizes[p];
+    a->ny = d->dims == 2 ? d->sizes[p] : 1;
+    a->r = d->r;
+    a->cells_per_lane = d->cells_per_lane;
+    a->waves_per_group = d->waves_per_group;
+    a->rows_per_block = d->rows_per_block;
+}
+
 hx_status validate(Ctx* c, const hx_partitioned_desc* d) {
     if (!d) return c->fail(HX_ERR_ARG, "null descriptor");
     if (d->dtype != HX_F32 && d->dtype != HX_F64) return c->fail(HX_ERR_ARG, "bad dtype");
@@ -34,6 +51,9 @@ hx_status validate(Ctx* c, const hx_partitioned_desc* d) {
     if (d->steps < 0) return c->fail(HX_ERR_ARG, "negative steps");
     for (int p = 0; p < d->parts; ++p)
         if (d->sizes[p] <= 0) return c->fail(HX_ERR_ARG, "partition sizes must be positive");
+    if (d->dims != 0 && d->dims != 1 && d->dims != 2) return c->fail(HX_ERR_ARG, "bad dims");
+    if (d->dims == 2 && (d->nx <= 0 || d->periodic))
+        return c->fail(HX_ERR_ARG, "2D bands need nx > 0 and periodic = 0");
     return HX_OK;
 }
 
@@ -50,7 +70,8 @@ extern "C" hx_status hx_run_partitioned(hx_ctx ctx, const hx_partitioned_desc* d
     if (s) return s;
     const int P = d->parts;
     const bool plain = d->mode == HX_PART_PLAIN;
-    int D = plain ? 1 : (d->time_block > 0 ? d->time_block : std::min(d->steps, 32));
+    const int defD = d->dims == 2 ? 8 : 32;
+    int D = plain ? 1 : (d->time_block > 0 ? d->time_block : std::min(d->steps, defD));
     if (D < 1) D = 1;
     int64_t min_size = d->sizes[0];
     for (int p = 1; p < P; ++p) min_size = std::min(min_size, d->sizes[p]);
@@ -82,11 +103,8 @@ extern "C" hx_status hx_run_partitioned(hx_ctx ctx, const hx_partitioned_desc* d
         for (int p = 0; p < P; ++p) {
             const int lp = (p + P - 1) % P, rp = (p + 1) % P;
             hx_stencil_args a{};
-            a.dims = 1;
-            a.dtype = d->dtype;
-            a.nx = d->sizes[p];
+            node_args(d, p, &a);
             a.steps = steps_b;
-            a.r = d->r;
             a.in = src_a ? d->bufs_a[p] : d->bufs_b[p];
             a.out = src_a ? d->bufs_b[p] : d->bufs_a[p];
             const bool has_lo = d->periodic || p > 0;
@@ -94,12 +112,10 @@ extern "C" hx_status hx_run_partitioned(hx_ctx ctx, const hx_partitioned_desc* d
             a.bc_lo = has_lo ? HX_BC_GHOST : HX_BC_DIRICHLET0;
             a.bc_hi = has_hi ? HX_BC_GHOST : HX_BC_DIRICHLET0;
             a.halo_lo = src_a ? d->bufs_a[lp] : d->bufs_b[lp];
-            a.halo_lo_offset = (size_t)(d->sizes[lp] - steps_b) * es;
+            a.halo_lo_offset = (size_t)(d->sizes[lp] - steps_b) * unit(d) * es;
             a.halo_hi = src_a ? d->bufs_a[rp] : d->bufs_b[rp];
             a.halo_hi_offset = 0;
             a.halo_width = steps_b;
-            a.cells_per_lane = d->cells_per_lane;
-            a.waves_per_group = d->waves_per_group;
             hx_event dv[4];
             int nd = 0;
             if (plain) {
@@ -155,129 +171,89 @@ extern "C" hx_status hx_run_pipeline(hx_ctx ctx, const hx_pipeline_desc* pd, con
     std::vector<int64_t> off(P);
     for (int p = 0; p < P; ++p) {
         off[p] = total;
-        total += d->sizes[p];
+        total += d->sizes[p] * unit(d);
         min_size = std::min(min_size, d->sizes[p]);
     }
     if (T > min_size) return c->fail(HX_ERR_ARG, "steps exceed the smallest partition");
-    const int H = std::max(T, 1);
     hx_event gate = 0;
     if (ndeps > 0) {
         s = when_all_locked(c, deps, ndeps, &gate);
         if (s) return s;
     }
-    std::vector<hx_event> finals;
+    // Operation events go to the caller when op_events is given (H2D, kernel,
+    // D2H, each `parts` long, indexed by partition); otherwise they are ours.
     std::vector<hx_event> keep;
-    // Operation events go to the caller when op_events is given (H2D of the
-    // partition cells, kernel, D2H, each `parts` long); otherwise they are ours.
     auto record = [&](int slot, hx_event e) {
         if (op_events) op_events[slot] = e;
         else keep.push_back(e);
     };
     const char* hin = static_cast<const char*>(pd->host_in);
     char* hout = static_cast<char*>(pd->host_out);
-    // 1) every copy in: partition cells, then its two halos into the ghost buffer
-    std::vector<hx_event> ein(P), elo(P), ehi(P);
+    auto unwind = [&](hx_status st) {
+        for (hx_event e : keep) release_locked(c, e);
+        release_locked(c, gate);
+        return st;
+    };
+    // 1) every copy in (Algorithm 1's first loop)
+    std::vector<hx_event> ein(P, 0), ek(P, 0);
     for (int p = 0; p < P; ++p) {
         hx_copy_desc cd{};
         cd.dir = HX_H2D;
         cd.host = const_cast<char*>(hin) + off[p] * es;
         cd.buf = d->bufs_a[p];
-        cd.bytes = (size_t)d->sizes[p] * es;
+        cd.bytes = (size_t)(d->sizes[p] * unit(d)) * es;
         s = copy_async_locked(c, &cd, &gate, gate ? 1 : 0, &ein[p]);
-        if (s) return s;
-        const int64_t lo0 = d->periodic ? (off[p] - H + total) % total : off[p] - H;
-        const int64_t hi0 = d->periodic ? (off[p] + d->sizes[p]) % total : off[p] + d->sizes[p];
-        const bool has_lo = d->periodic || p > 0;
-        const bool has_hi = d->periodic || p < P - 1;
-        elo[p] = ehi[p] = 0;
-        if (T > 0 && has_lo) {
-            // a halo of H cells that may wrap past the array start: at most two runs
-            hx_copy_desc h{};
-            h.dir = HX_H2D;
-            h.buf = pd->ghost;
-            int64_t first = std::min<int64_t>(H, total - lo0);
-            h.host = const_cast<char*>(hin) + lo0 * es;
-            h.offset = (size_t)(2 * H) * p * es;
-            h.bytes = (size_t)first * es;
-            s = copy_async_locked(c, &h, &gate, gate ? 1 : 0, &elo[p]);
-            if (s) return s;
-            if (first < H) {
-                hx_event e2 = 0;
-                h.host = const_cast<char*>(hin);
-                h.offset += (size_t)first * es;
-                h.bytes = (size_t)(H - first) * es;
-                s = copy_async_locked(c, &h, &elo[p], 1, &e2);
-                if (s) return s;
-                release_locked(c, elo[p]);
-                elo[p] = e2;
-            }
-        }
-        if (T > 0 && has_hi) {
-            hx_copy_desc h{};
-            h.dir = HX_H2D;
-            h.buf = pd->ghost;
-            int64_t first = std::min<int64_t>(H, total - hi0);
-            h.host = const_cast<char*>(hin) + hi0 * es;
-            h.offset = (size_t)(2 * H * p + H) * es;
-            h.bytes = (size_t)first * es;
-            s = copy_async_locked(c, &h, &gate, gate ? 1 : 0, &ehi[p]);
-            if (s) return s;
-            if (first < H) {
-                hx_event e2 = 0;
-                h.host = const_cast<char*>(hin);
-                h.offset += (size_t)first * es;
-                h.bytes = (size_t)(H - first) * es;
-                s = copy_async_locked(c, &h, &ehi[p], 1, &e2);
-                if (s) return s;
-                release_locked(c, ehi[p]);
-                ehi[p] = e2;
-            }
-        }
+        if (s) return unwind(s);
         record(p, ein[p]);
     }
-    // 2) one fused pass per partition, 3) copy out
-    for (int p = 0; p < P; ++p) {
-        hx_stencil_args a{};
-        a.dims = 1;
-        a.dtype = d->dtype;
-        a.nx = d->sizes[p];
-        a.steps = T;
-        a.r = d->r;
-        a.in = d->bufs_a[p];
-        a.out = d->bufs_b[p];
+    // 2) one fused pass per partition; its halos are read from the neighbours'
+    //    freshly copied buffers, so it waits for their copies too.  Kernels are
+    //    issued in the order they can start: partition 0 of a periodic array
+    //    needs the last copy in, so it goes last and blocks no stream meanwhile.
+    const bool wrap = d->periodic && P > 1 && T > 0;
+    for (int q = 0; q < P; ++q) {
+        const int p = wrap ? (q + 1) % P : q;
+        const int lp = (p + P - 1) % P, rp = (p + 1) % P;
         const bool has_lo = d->periodic || p > 0;
         const bool has_hi = d->periodic || p < P - 1;
-        a.bc_lo = (has_lo && T > 0) ? HX_BC_GHOST : (has_lo ? HX_BC_DIRICHLET0 : HX_BC_DIRICHLET0);
-        a.bc_hi = (has_hi && T > 0) ? HX_BC_GHOST : HX_BC_DIRICHLET0;
-        a.halo_lo = pd->ghost;
-        a.halo_lo_offset = (size_t)(2 * H) * p * es;
-        a.halo_hi = pd->ghost;
-        a.halo_hi_offset = (size_t)(2 * H * p + H) * es;
-        a.halo_width = H;
-        a.cells_per_lane = d->cells_per_lane;
-        a.waves_per_group = d->waves_per_group;
-        a.time_block = d->time_block > T ? d->time_block : 0;
-        hx_event dv[3] = {ein[p], elo[p], ehi[p]};
-        hx_event ek = 0;
-        s = launch_stencil_locked(c, &a, dv, 3, &ek);
-        if (s) return s;
-        record(P + p, ek);
+        hx_stencil_args a{};
+        node_args(d, p, &a);
+        a.steps = T;
+        a.in = d->bufs_a[p];
+        a.out = d->bufs_b[p];
+        const bool halo = T > 0;
+        a.bc_lo = (has_lo && halo) ? HX_BC_GHOST : HX_BC_DIRICHLET0;
+        a.bc_hi = (has_hi && halo) ? HX_BC_GHOST : HX_BC_DIRICHLET0;
+        a.halo_lo = d->bufs_a[lp];
+        a.halo_lo_offset = (size_t)(d->sizes[lp] - T) * unit(d) * es;
+        a.halo_hi = d->bufs_a[rp];
+        a.halo_width = T;
+        hx_event dv[3];
+        int nd = 0;
+        dv[nd++] = ein[p];
+        if (halo && has_lo) dv[nd++] = ein[lp];
+        if (halo && has_hi && rp != lp) dv[nd++] = ein[rp];
+        s = launch_stencil_locked(c, &a, dv, nd, &ek[p]);
+        if (s) return unwind(s);
+        record(P + p, ek[p]);
+    }
+    // 3) copies out, in the order the kernels can finish (partition 0 of a
+    //    periodic array waits for the last copy in, so it goes last)
+    std::vector<hx_event> finals;
+    for (int q = 0; q < P; ++q) {
+        const int p = wrap ? (q + 1) % P : q;
         hx_copy_desc cd{};
         cd.dir = HX_D2H;
         cd.host = hout + off[p] * es;
         cd.buf = d->bufs_b[p];
-        cd.bytes = (size_t)d->sizes[p] * es;
+        cd.bytes = (size_t)(d->sizes[p] * unit(d)) * es;
         hx_event eo = 0;
-        s = copy_async_locked(c, &cd, &ek, 1, &eo);
-        if (s) return s;
+        s = copy_async_locked(c, &cd, &ek[p], 1, &eo);
+        if (s) return unwind(s);
         finals.push_back(eo);
         record(2 * P + p, eo);
     }
     s = when_all_locked(c, finals.data(), (int)finals.size(), out);
-    for (int p = 0; p < P; ++p) {
-        release_locked(c, elo[p]);
-        release_locked(c, ehi[p]);
-    }
     for (hx_event e : keep) release_locked(c, e);
     release_locked(c, gate);
     return s;

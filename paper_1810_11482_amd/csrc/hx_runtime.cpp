@@ -291,8 +291,14 @@ hx_status Ctx::submit(StreamClass sc, const hx_event* deps, int ndeps,
         for (uint32_t d : dslots) dseq.push_back(events[d].seq);
         check_op(seq, dseq, acc, what);
     }
-    for (const Access& a : acc) {
-        Buffer& b = buffers[a.buf_slot];
+    // one reference per buffer (not per access) keeps the buffer's memory alive
+    // until this operation completes
+    std::vector<uint32_t> bslots;
+    for (const Access& a : acc)
+        if (std::find(bslots.begin(), bslots.end(), a.buf_slot) == bslots.end())
+            bslots.push_back(a.buf_slot);
+    for (uint32_t bs : bslots) {
+        Buffer& b = buffers[bs];
         if (b.uses.size() >= 32) {
             std::vector<uint32_t> keep;
             for (uint32_t u : b.uses) {
@@ -501,7 +507,12 @@ hx_status hx_ctx_create(int dev, const hx_ctx_opts* opts, hx_ctx* out) {
         if (hipSetDevice(dev) != hipSuccess) { delete c; return HX_ERR_HIP; }
         c->device = dev;
         c->host_only = false;
-        c->ncompute = o.compute_streams ? o.compute_streams : 4;
+        // Default: leave the copy streams hardware queues of their own.  HIP maps
+        // streams onto GPU_MAX_HW_QUEUES queues (4 unless set); streams sharing
+        // a queue serialise, which stalls copies behind waiting kernels.
+        int hwq = 4;
+        if (const char* q = getenv("GPU_MAX_HW_QUEUES")) hwq = std::max(1, atoi(q));
+        c->ncompute = o.compute_streams ? o.compute_streams : std::max(1, hwq - 2);
         for (int i = 0; i < c->ncompute + 2; ++i) {
             hipStream_t s = nullptr;
             if (i == 0 && o.external_stream) {

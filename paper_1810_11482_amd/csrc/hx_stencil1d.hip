@@ -133,7 +133,7 @@ __device__ __forceinline__ void tile1d(const Seg1D& s, int64_t tile, int steps, 
     const int lane = threadIdx.x & 63;
     const int64_t n = s.n;
     const int64_t wout = (int64_t)W - 2LL * halo;
-    const int64_t o0 = tile * wout;
+    const int64_t o0 = tile * wout - s.shift;
     const int64_t base = o0 - halo;
     const T* in = static_cast<const T*>(s.in);
     T* out = static_cast<T*>(s.out);
@@ -187,6 +187,7 @@ __device__ __forceinline__ void tile1d(const Seg1D& s, int64_t tile, int steps, 
         *reinterpret_cast<VT*>(lds + lane * (C + VN) + q * VN) = x;
     }
     __builtin_amdgcn_wave_barrier();
+    const int64_t ostart = o0 > 0 ? o0 : 0;
     const int64_t oend = (o0 + wout < n) ? o0 + wout : n;
     if (interior && aligned16(out + base)) {
         VT* dst = reinterpret_cast<VT*>(out + base);
@@ -202,7 +203,7 @@ __device__ __forceinline__ void tile1d(const Seg1D& s, int64_t tile, int steps, 
         for (int j = 0; j < C; ++j) {
             const int i = lane + 64 * j;
             const int64_t g = base + i;
-            if (g >= o0 && g < oend) out[g] = lds[lds_pos<T, C>(i)];
+            if (g >= ostart && g < oend) out[g] = lds[lds_pos<T, C>(i)];
         }
     }
 }
@@ -225,6 +226,14 @@ __global__ __launch_bounds__(256) void k_stencil1d(Seg1D s, int steps, int halo,
     tile1d<T, C>(s, tile, steps, halo, wave_lds<T, C>());
 }
 
+// Out-of-line tile for the persistent loop: inlined into a loop, the tile's
+// code is allocated several times more registers than on its own.
+template <typename T, int C>
+__device__ __attribute__((noinline)) void tile1d_call(const Seg1D* __restrict__ segs, uint32_t si,
+                                                      uint32_t ti, int steps, int halo) {
+    tile1d<T, C>(segs[si], ti, steps, halo, wave_lds<T, C>());
+}
+
 template <typename T, int C>
 __global__ __launch_bounds__(256) void k_stencil1d_batched(const Seg1D* __restrict__ segs,
                                                            const uint32_t* __restrict__ tseg,
@@ -232,10 +241,12 @@ __global__ __launch_bounds__(256) void k_stencil1d_batched(const Seg1D* __restri
                                                            int64_t ntiles, int steps, int halo) {
     const int wpg = blockDim.x >> 6;
     const int64_t nwaves = (int64_t)gridDim.x * wpg;
+#pragma clang loop unroll(disable)
     for (int64_t t = (int64_t)blockIdx.x * wpg + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
          t < ntiles; t += nwaves) {
-        const Seg1D s = segs[tseg[t]];
-        tile1d<T, C>(s, tidx[t], steps, halo, wave_lds<T, C>());
+        const uint32_t si = __builtin_amdgcn_readfirstlane(tseg[t]);
+        const uint32_t ti = __builtin_amdgcn_readfirstlane(tidx[t]);
+        tile1d_call<T, C>(segs, si, ti, steps, halo);
     }
 }
 
@@ -244,10 +255,27 @@ size_t lds_bytes(const Geom1D& g) {
     return (size_t)g.wpg * 64 * (g.cpl + V16<T>::N) * sizeof(T);
 }
 
+// One tile per wave (the grid covers the whole tile table): the hardware
+// dispatcher does the load balancing, and with no loop around the tile the
+// register allocation matches the single-segment kernel.
+template <typename T, int C>
+__global__ __launch_bounds__(256) void k_stencil1d_flat(const Seg1D* __restrict__ segs,
+                                                        const uint32_t* __restrict__ tseg,
+                                                        const uint32_t* __restrict__ tidx,
+                                                        int64_t ntiles, int steps, int halo) {
+    const int wpg = blockDim.x >> 6;
+    const int64_t t = (int64_t)blockIdx.x * wpg + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (t >= ntiles) return;
+    const uint32_t si = __builtin_amdgcn_readfirstlane(tseg[t]);
+    const uint32_t ti = __builtin_amdgcn_readfirstlane(tidx[t]);
+    tile1d<T, C>(segs[si], ti, steps, halo, wave_lds<T, C>());
+}
+
 template <typename T>
-hipError_t launch_single(const Seg1D& s, const Geom1D& g, hipStream_t st) {
-    const int64_t wout = tile_out_1d(g);
-    const int64_t ntiles = (s.n + wout - 1) / wout;
+hipError_t launch_single(const Seg1D& s0, const Geom1D& g, hipStream_t st) {
+    Seg1D s = s0;
+    s.shift = tile_shift(s.in, sizeof(T));
+    const int64_t ntiles = tiles_1d(s, g);
     const dim3 block(64 * g.wpg);
     const dim3 grid((unsigned)((ntiles + g.wpg - 1) / g.wpg));
     const size_t sh = lds_bytes<T>(g);
@@ -266,6 +294,17 @@ hipError_t launch_batched(const Seg1D* segs, const uint32_t* tseg, const uint32_
                           int64_t ntiles, const Geom1D& g, int64_t grid_waves, hipStream_t st) {
     const dim3 block(64 * g.wpg);
     const size_t sh = lds_bytes<T>(g);
+    if (grid_waves >= ntiles) {
+        const dim3 grid((unsigned)((ntiles + g.wpg - 1) / g.wpg));
+        switch (g.cpl) {
+        case 8: hipLaunchKernelGGL((k_stencil1d_flat<T, 8>), grid, block, sh, st, segs, tseg, tidx, ntiles, g.steps, g.halo); break;
+        case 16: hipLaunchKernelGGL((k_stencil1d_flat<T, 16>), grid, block, sh, st, segs, tseg, tidx, ntiles, g.steps, g.halo); break;
+        case 32: hipLaunchKernelGGL((k_stencil1d_flat<T, 32>), grid, block, sh, st, segs, tseg, tidx, ntiles, g.steps, g.halo); break;
+        case 64: hipLaunchKernelGGL((k_stencil1d_flat<T, 64>), grid, block, sh, st, segs, tseg, tidx, ntiles, g.steps, g.halo); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     const dim3 grid((unsigned)((grid_waves + g.wpg - 1) / g.wpg));
     switch (g.cpl) {
     case 8: hipLaunchKernelGGL((k_stencil1d_batched<T, 8>), grid, block, sh, st, segs, tseg, tidx, ntiles, g.steps, g.halo); break;

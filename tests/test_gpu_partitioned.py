@@ -79,9 +79,8 @@ def test_pipeline_host_to_host(ctx, parts, steps):
     aout[:] = np.nan
     A = [hx.hx_buffer_create(ctx, s * 4) for _, s in bounds]
     B = [hx.hx_buffer_create(ctx, s * 4) for _, s in bounds]
-    ghost = hx.hx_buffer_create(ctx, 2 * max(steps, 1) * parts * 4)
     base = hx.partitioned_desc(hx.HX_F32, [s for _, s in bounds], A, B, steps, 0.25)
-    pd = hx.hx_pipeline_desc(base, hin, hout, ghost)
+    pd = hx.hx_pipeline_desc(base, hin, hout)
     ev, h2d, ker, d2h = hx.hx_run_pipeline(ctx, pd, op_events=True)
     assert hx.hx_wait(ctx, ev) == hx.HX_OK, hx.hx_last_error(ctx)
     for e in h2d + ker + d2h + [ev]:
@@ -89,7 +88,7 @@ def test_pipeline_host_to_host(ctx, parts, steps):
         hx.hx_event_release(ctx, e)
     ref = oracle.heat1d_periodic(u0.astype(np.float64), 0.25, steps)
     assert rel_l2(aout, ref) <= 1e-5
-    for b in A + B + [ghost]:
+    for b in A + B:
         hx.hx_buffer_destroy(ctx, b)
     hx.hx_host_free(ctx, hin)
     hx.hx_host_free(ctx, hout)
