@@ -318,6 +318,77 @@ hx_status hx_launch_batched(hx_ctx ctx, hx_plan plan, const hx_event* deps, int 
 /* Free a plan (waits for the context's queued work first). */
 hx_status hx_plan_destroy(hx_ctx ctx, hx_plan plan);
 
+/* ------------------------------------------- variable coefficient + adjoint */
+/* The gradient path: a 2D variable-coefficient heat step (h = 1, zero-Dirichlet)
+ *   v_c = u_c + dt * sum_f kappa_f (u_n - u_c)   over the W, E, N, S faces,
+ * kappa_f = (kappa_c + kappa_n)/2 on interior faces, kappa_f = kappa_c with a
+ * ghost u_n = 0 on edge faces; and its adjoint for L = 0.5 ||u_T - y||^2:
+ *   lam_t = A^T lam_{t+1},  dL/dkappa_c += -dt [ sum_{interior f} (u_n-u_c)(lam_n-lam_c)/2
+ *                                                + sum_{edge f} u_c lam_c ]   (u = u_t).
+ * The paper has no adjoint; this is the reverse-mode derivation of the explicit
+ * scheme.  States are ny x nx row-major arrays of the dtype at offset 0. */
+
+/* out = A(kappa) u (one forward step). */
+hx_status hx_heat_vc_step(hx_ctx ctx, int dtype, int64_t nx, int64_t ny, double dt, hx_buffer u,
+                          hx_buffer kappa, hx_buffer out_buf, const hx_event* deps, int ndeps,
+                          hx_event* out);
+
+/* lam_out = A(kappa)^T lam_next and gacc += this step's conductivity gradient
+ * (u_t the forward state of the step). */
+hx_status hx_heat_vc_adjoint_step(hx_ctx ctx, int dtype, int64_t nx, int64_t ny, double dt,
+                                  hx_buffer u_t, hx_buffer lam_next, hx_buffer kappa,
+                                  hx_buffer lam_out, hx_buffer gacc, const hx_event* deps,
+                                  int ndeps, hx_event* out);
+
+typedef struct {
+    int dtype;
+    int64_t nx, ny;
+    double dt;
+    int steps;                  /* T */
+    int ckpt;                   /* segment length S; 0 = ceil(sqrt(T)) (hx_vc_schedule) */
+    hx_buffer u0;               /* initial state; also checkpoint 0 */
+    hx_buffer kappa;
+    hx_buffer uT;               /* forward: final state */
+    hx_buffer ckpts;            /* (segments - 1) states: u_{kS}, k = 1 .. segments-1 */
+    hx_buffer work;             /* 2 states of ping-pong space (T > 1) */
+    hx_buffer seg;              /* backward: S - 1 states for a recomputed segment */
+    hx_buffer lamT;             /* backward input: dL/du_T */
+    hx_buffer lam0;             /* backward output: dL/du_0 */
+    hx_buffer gk64;             /* backward output: dL/dkappa, FP64 (cells x 8 bytes) */
+    hx_buffer gacc;             /* backward: one state of the dtype, per-segment accumulator */
+    int rows_per_block;         /* 0 = 64 */
+} hx_vc_args;
+
+/* Segment length and number of segments of the sqrt(T) checkpoint schedule. */
+hx_status hx_vc_schedule(int steps, int ckpt, int* segment_length, int* segments);
+
+/* T forward steps from u0 into uT, keeping the checkpoints u_{kS}. */
+hx_status hx_heat_vc_forward(hx_ctx ctx, const hx_vc_args* args, const hx_event* deps, int ndeps,
+                             hx_event* out);
+
+/* Reverse sweep from lamT: segment by segment from the last, recompute the
+ * segment's states from its checkpoint, run its adjoint steps, fold its
+ * conductivity gradient into gk64 in FP64.  Writes lam0 and gk64. */
+hx_status hx_heat_vc_backward(hx_ctx ctx, const hx_vc_args* args, const hx_event* deps, int ndeps,
+                              hx_event* out);
+
+/* FP64 reductions over n cells (deterministic two-pass; `work` holds at least
+ * 4096 doubles): loss out64 = 0.5 sum (u - y)^2 (resid = u - y when resid is
+ * not 0), and out64 = sum a*b. */
+hx_status hx_launch_loss(hx_ctx ctx, int dtype, int64_t n, hx_buffer u, hx_buffer y,
+                         hx_buffer resid, hx_buffer out64, hx_buffer work, const hx_event* deps,
+                         int ndeps, hx_event* out);
+hx_status hx_launch_dot(hx_ctx ctx, int dtype, int64_t n, hx_buffer a, hx_buffer b,
+                        hx_buffer out64, hx_buffer work, const hx_event* deps, int ndeps,
+                        hx_event* out);
+
+/* y = x * s with s an FP64 scalar in device memory (out64 of a reduction, or a
+ * gradient), and dst = (dtype) src64. */
+hx_status hx_launch_scale(hx_ctx ctx, int dtype, int64_t n, hx_buffer x, hx_buffer s64,
+                          hx_buffer y, const hx_event* deps, int ndeps, hx_event* out);
+hx_status hx_launch_cast64(hx_ctx ctx, int dtype, int64_t n, hx_buffer src64, hx_buffer dst,
+                           const hx_event* deps, int ndeps, hx_event* out);
+
 /* ------------------------------------------------------------------ events */
 /* An event that completes when every event in `events` has completed (the
  * paper's when_all, Sec. III-A); it fails with HX_ERR_DEP_FAILED if any of them
@@ -351,6 +422,17 @@ hx_status hx_event_span(hx_ctx ctx, hx_event ev, hx_event ref, double* start_ms,
  * with HX_ERR_DEP_FAILED. */
 hx_status hx_user_event_create(hx_ctx ctx, hx_event* out);
 hx_status hx_user_event_set(hx_ctx ctx, hx_event ev, hx_status status);
+
+/* Host continuation (the paper's future::then / dataflow, Sec. III-A): `fn`
+ * runs on the context's host worker thread once every event in `deps` has
+ * completed; its return value (HX_OK or an error) completes the returned event.
+ * If a dependency fails, `fn` is not called and the event completes with
+ * HX_ERR_DEP_FAILED.  GPU operations may depend on the returned event; they
+ * are queued when it completes.  `fn` must not block on events that depend on
+ * its own completion. */
+typedef hx_status (*hx_host_fn)(void* user);
+hx_status hx_host_task(hx_ctx ctx, hx_host_fn fn, void* user, const hx_event* deps, int ndeps,
+                       hx_event* out);
 
 /* Interop with foreign streams (e.g. torch's current stream): an event that
  * completes when the work queued on `hip_stream` so far has, and a stream-wait

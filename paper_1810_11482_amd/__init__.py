@@ -12,7 +12,9 @@ loading torch first makes both use that one runtime instance.
 from __future__ import annotations
 
 import ctypes
+import itertools
 import os
+import threading
 
 import torch  # noqa: F401  (loads the HIP runtime libhx links against)
 
@@ -113,6 +115,14 @@ class hx_batch_desc(ctypes.Structure):
                 ("grid_waves_per_cu", ctypes.c_int)]
 
 
+class hx_vc_args(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int), ("nx", _i64), ("ny", _i64), ("dt", ctypes.c_double),
+                ("steps", ctypes.c_int), ("ckpt", ctypes.c_int),
+                ("u0", _u64), ("kappa", _u64), ("uT", _u64), ("ckpts", _u64), ("work", _u64),
+                ("seg", _u64), ("lamT", _u64), ("lam0", _u64), ("gk64", _u64), ("gacc", _u64),
+                ("rows_per_block", ctypes.c_int)]
+
+
 # ----------------------------------------------------------------- prototypes
 _PROTOS = {
     "hx_status_string": (ctypes.c_char_p, [_i32]),
@@ -137,6 +147,25 @@ _PROTOS = {
     "hx_launch_batched": (_i32, [_vp, _u64, ctypes.POINTER(_u64), ctypes.c_int,
                                  ctypes.POINTER(_u64)]),
     "hx_plan_destroy": (_i32, [_vp, _u64]),
+    "hx_heat_vc_step": (_i32, [_vp, ctypes.c_int, _i64, _i64, ctypes.c_double, _u64, _u64, _u64,
+                               ctypes.POINTER(_u64), ctypes.c_int, ctypes.POINTER(_u64)]),
+    "hx_heat_vc_adjoint_step": (_i32, [_vp, ctypes.c_int, _i64, _i64, ctypes.c_double, _u64,
+                                       _u64, _u64, _u64, _u64, ctypes.POINTER(_u64),
+                                       ctypes.c_int, ctypes.POINTER(_u64)]),
+    "hx_vc_schedule": (_i32, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                              ctypes.POINTER(ctypes.c_int)]),
+    "hx_heat_vc_forward": (_i32, [_vp, ctypes.POINTER(hx_vc_args), ctypes.POINTER(_u64),
+                                  ctypes.c_int, ctypes.POINTER(_u64)]),
+    "hx_heat_vc_backward": (_i32, [_vp, ctypes.POINTER(hx_vc_args), ctypes.POINTER(_u64),
+                                   ctypes.c_int, ctypes.POINTER(_u64)]),
+    "hx_launch_loss": (_i32, [_vp, ctypes.c_int, _i64, _u64, _u64, _u64, _u64, _u64,
+                              ctypes.POINTER(_u64), ctypes.c_int, ctypes.POINTER(_u64)]),
+    "hx_launch_dot": (_i32, [_vp, ctypes.c_int, _i64, _u64, _u64, _u64, _u64,
+                             ctypes.POINTER(_u64), ctypes.c_int, ctypes.POINTER(_u64)]),
+    "hx_launch_scale": (_i32, [_vp, ctypes.c_int, _i64, _u64, _u64, _u64,
+                               ctypes.POINTER(_u64), ctypes.c_int, ctypes.POINTER(_u64)]),
+    "hx_launch_cast64": (_i32, [_vp, ctypes.c_int, _i64, _u64, _u64,
+                                ctypes.POINTER(_u64), ctypes.c_int, ctypes.POINTER(_u64)]),
     "hx_run_partitioned": (_i32, [_vp, ctypes.POINTER(hx_partitioned_desc), ctypes.POINTER(_u64),
                                   ctypes.c_int, ctypes.POINTER(_u64), ctypes.POINTER(ctypes.c_int),
                                   ctypes.POINTER(_u64)]),
@@ -151,6 +180,8 @@ _PROTOS = {
     "hx_user_event_create": (_i32, [_vp, ctypes.POINTER(_u64)]),
     "hx_user_event_set": (_i32, [_vp, _u64, _i32]),
     "hx_event_record_stream": (_i32, [_vp, _vp, ctypes.POINTER(_u64)]),
+    "hx_host_task": (_i32, [_vp, ctypes.c_void_p, _vp, ctypes.POINTER(_u64), ctypes.c_int,
+                            ctypes.POINTER(_u64)]),
     "hx_stream_wait_event": (_i32, [_vp, _vp, _u64]),
     "hx_debug_next_seq": (_i32, [_vp, ctypes.POINTER(_u64)]),
     "hx_debug_inject": (_i32, [_vp, _u64]),
@@ -355,6 +386,59 @@ def segment(**kw) -> hx_segment:
     return s
 
 
+def _op(ctx, fn, *args, deps=()):
+    arr, n = _deps(deps)
+    ev = _u64()
+    _ok(ctx, fn(ctx, *args, arr, n, ctypes.byref(ev)))
+    return ev.value
+
+
+def hx_heat_vc_step(ctx, dtype, nx, ny, dt, u, kappa, out_buf, deps=()) -> int:
+    return _op(ctx, lib.hx_heat_vc_step, dtype, nx, ny, dt, u, kappa, out_buf, deps=deps)
+
+
+def hx_heat_vc_adjoint_step(ctx, dtype, nx, ny, dt, u_t, lam_next, kappa, lam_out, gacc,
+                            deps=()) -> int:
+    return _op(ctx, lib.hx_heat_vc_adjoint_step, dtype, nx, ny, dt, u_t, lam_next, kappa,
+               lam_out, gacc, deps=deps)
+
+
+def hx_vc_schedule(steps: int, ckpt: int = 0):
+    S, n = ctypes.c_int(), ctypes.c_int()
+    _ok(None, lib.hx_vc_schedule(steps, ckpt, ctypes.byref(S), ctypes.byref(n)))
+    return S.value, n.value
+
+
+def hx_heat_vc_forward(ctx, args: hx_vc_args, deps=()) -> int:
+    arr, n = _deps(deps)
+    ev = _u64()
+    _ok(ctx, lib.hx_heat_vc_forward(ctx, ctypes.byref(args), arr, n, ctypes.byref(ev)))
+    return ev.value
+
+
+def hx_heat_vc_backward(ctx, args: hx_vc_args, deps=()) -> int:
+    arr, n = _deps(deps)
+    ev = _u64()
+    _ok(ctx, lib.hx_heat_vc_backward(ctx, ctypes.byref(args), arr, n, ctypes.byref(ev)))
+    return ev.value
+
+
+def hx_launch_loss(ctx, dtype, n, u, y, resid, out64, work, deps=()) -> int:
+    return _op(ctx, lib.hx_launch_loss, dtype, n, u, y, resid, out64, work, deps=deps)
+
+
+def hx_launch_dot(ctx, dtype, n, a, b, out64, work, deps=()) -> int:
+    return _op(ctx, lib.hx_launch_dot, dtype, n, a, b, out64, work, deps=deps)
+
+
+def hx_launch_scale(ctx, dtype, n, x, s64, y, deps=()) -> int:
+    return _op(ctx, lib.hx_launch_scale, dtype, n, x, s64, y, deps=deps)
+
+
+def hx_launch_cast64(ctx, dtype, n, src64, dst, deps=()) -> int:
+    return _op(ctx, lib.hx_launch_cast64, dtype, n, src64, dst, deps=deps)
+
+
 def hx_when_all(ctx, events) -> int:
     evs = [int(e) for e in events]
     arr = (_u64 * max(1, len(evs)))(*evs)
@@ -402,6 +486,45 @@ def hx_user_event_create(ctx) -> int:
 
 def hx_user_event_set(ctx, ev: int, status: int = HX_OK) -> None:
     _ok(ctx, lib.hx_user_event_set(ctx, ev, status))
+
+
+_HOST_FN = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.c_void_p)
+_host_live = {}      # callback objects of tasks that have not run yet
+_host_done = []      # callbacks that have returned (freed on a later call)
+_host_lock = threading.Lock()
+_host_ids = itertools.count(1)
+
+
+def hx_host_task(ctx, fn, deps=()) -> int:
+    """Run the Python callable `fn()` on the context's host worker once `deps`
+    complete; its return value (None = HX_OK, or an hx status) completes the
+    event; an exception completes it with HX_ERR_ARG."""
+    key = next(_host_ids)
+
+    def trampoline(_user):
+        try:
+            r = fn()
+            return HX_OK if r is None else int(r)
+        except Exception:  # noqa: BLE001 - the status carries the failure
+            return HX_ERR_ARG
+        finally:
+            with _host_lock:
+                cb = _host_live.pop(key, None)
+                if cb is not None:
+                    _host_done.append(cb)
+
+    cb = _HOST_FN(trampoline)
+    with _host_lock:
+        _host_live[key] = cb
+        del _host_done[:-64]  # keep the most recent ones: they may still be returning
+    arr, n = _deps(deps)
+    ev = _u64()
+    st = lib.hx_host_task(ctx, ctypes.cast(cb, ctypes.c_void_p), None, arr, n, ctypes.byref(ev))
+    if st < 0:
+        with _host_lock:
+            _host_live.pop(key, None)
+        _err(ctx, st)
+    return ev.value
 
 
 def hx_event_record_stream(ctx, hip_stream: int) -> int:

@@ -36,6 +36,7 @@ struct BatchPlan {
     uint32_t* tidx_dev = nullptr;
     int64_t ntiles = 0;
     int64_t grid_waves = 0;
+    int64_t per_seg = 0;  // tiles of every segment when all are equal (table unused)
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -178,6 +179,18 @@ extern "C" hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* d, 
             }
         }
         bp->ntiles = (int64_t)tseg.size();
+        const int64_t nt0 = tiles_1d(bp->segs[0], bp->g);
+        bool uniform = true;
+        for (const Seg1D& sg : bp->segs)
+            if (tiles_1d(sg, bp->g) != nt0) uniform = false;
+        if (uniform) {
+            // equal tile counts: the table is in segment order, so index = seg * nt0 + tile
+            for (size_t i = 0; i < tseg.size(); ++i) {
+                tseg[i] = (uint32_t)(i / nt0);
+                tidx[i] = (uint32_t)(i % nt0);
+            }
+            bp->per_seg = nt0;
+        }
         // Grid: `wpc` resident waves per CU striding over the tiles, or (the
         // default, wpc <= 0 after tuning) one wave per tile.
         const int wpc = d->grid_waves_per_cu ? d->grid_waves_per_cu
@@ -240,7 +253,7 @@ extern "C" hx_status hx_launch_batched(hx_ctx ctx, hx_plan plan, const hx_event*
             if (bp->mode == HX_BATCH_PERSISTENT)
                 return launch_stencil1d_batched(bp->dtype, bp->segs_dev, bp->tseg_dev,
                                                 bp->tidx_dev, bp->ntiles, bp->g, bp->grid_waves,
-                                                st);
+                                                bp->per_seg, st);
             if (bp->mode == HX_BATCH_GRAPH) return hipGraphLaunch(bp->exec, st);
             // PLAIN: step by step, ping-pong so the last step lands in out
             const int S = bp->steps;

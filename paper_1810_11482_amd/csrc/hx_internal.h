@@ -48,12 +48,14 @@ inline int64_t tiles_1d(const Seg1D& s, const Geom1D& g) {
 // dtype: 0 = f32, 1 = f64.  Returns hipSuccess or the launch error.
 hipError_t launch_stencil1d(int dtype, const Seg1D& seg, const Geom1D& g, hipStream_t stream);
 
-// Batched 1D: `nseg` segments described in device memory; `tiles` entries of
-// (segment index, tile index within the segment) in device memory.  The grid is
-// persistent: `grid_waves` waves stride over the tile list.
+// Batched 1D: segments described in device memory; `ntiles` entries of
+// (segment index, tile index within the segment) in device memory.  With
+// grid_waves >= ntiles every wave takes one tile, otherwise `grid_waves` waves
+// stride over the table.  per_seg > 0 means every segment has exactly per_seg
+// tiles in segment order, so the table need not be read.
 hipError_t launch_stencil1d_batched(int dtype, const Seg1D* segs_dev, const uint32_t* tile_seg,
                                     const uint32_t* tile_idx, int64_t ntiles, const Geom1D& g,
-                                    int64_t grid_waves, hipStream_t stream);
+                                    int64_t grid_waves, int64_t per_seg, hipStream_t stream);
 
 // One 2D band: ny rows of nx cells, row-major, advanced `steps` steps from in
 // into out.  Rows outside [0, ny) come from the top/bottom rule; columns
@@ -80,5 +82,29 @@ struct Geom2D {
 
 bool stencil2d_supported(int dtype, int cpl, int steps);
 hipError_t launch_stencil2d(int dtype, const Band2D& b, const Geom2D& g, hipStream_t stream);
+
+// One variable-coefficient step (forward: out = A u; adjoint: out = A^T lam
+// and gacc += the step's conductivity gradient) on an ny x nx grid.
+struct VCArgs {
+    const void* u;
+    const void* kappa;
+    const void* lam;
+    void* out;
+    void* gacc;
+    int64_t nx, ny;
+    double dt;
+    int rows;
+};
+
+hipError_t launch_vc_step(int dtype, bool adjoint, const VCArgs& v, hipStream_t stream);
+hipError_t launch_fold(int dtype, void* acc, double* total, int64_t n, hipStream_t stream);
+hipError_t launch_fill(int dtype, void* p, int64_t n, double v, hipStream_t stream);
+hipError_t launch_cast64(int dtype, const double* src, void* dst, int64_t n, hipStream_t stream);
+hipError_t launch_scale(int dtype, const void* x, const double* s, void* out, int64_t n,
+                        hipStream_t stream);
+int reduce_blocks(int64_t n);
+// mode 0: out = 0.5 sum (a-b)^2 (resid = a - b if non-null); mode 1: out = sum a*b.
+hipError_t launch_reduce(int dtype, int mode, const void* a, const void* b, void* resid, int64_t n,
+                         double* partial, double* out, hipStream_t stream);
 
 }  // namespace hx

@@ -109,7 +109,7 @@ void Ctx::maybe_free_event(uint32_t slot) {
 static bool leaf_ready(const Event& e) {
     if (e.status != HX_PENDING) return true;
     if (e.kind == EK_GPU) return true;
-    return false;  // user event not set, or deferred op not yet queued
+    return false;  // user event not set, host task not run, or deferred op not yet queued
 }
 
 void Ctx::collect_leaves(uint32_t slot, std::vector<uint32_t>& out) {
@@ -320,6 +320,77 @@ hx_status Ctx::submit(StreamClass sc, const hx_event* deps, int ndeps,
     *out = handle_of(slot);
     complete_deferred(slot);
     return HX_OK;
+}
+
+// ------------------------------------------------------------- host tasks
+// The worker runs a host task once every leaf of its dependencies is final: it
+// blocks on a pending GPU leaf (outside the lock) or sleeps on the condition
+// variable for host-completed leaves, then calls the function outside the lock
+// and completes the task's event with its return status.
+void Ctx::start_worker() {
+    if (worker.joinable()) return;
+    worker = std::thread([this] { worker_loop(); });
+}
+
+void Ctx::worker_loop() {
+    std::unique_lock<std::recursive_mutex> lk(mu);
+    while (!worker_stop) {
+        bool ran = false;
+        hipEvent_t block_on = nullptr;
+        uint32_t block_slot = 0;
+        for (size_t i = 0; i < host_tasks.size() && !ran; ++i) {
+            const uint32_t slot = host_tasks[i];
+            std::vector<uint32_t> leaves;
+            for (uint32_t d : events[slot].deps) collect_leaves(d, leaves);
+            bool failed = false, pending = false;
+            for (uint32_t l : leaves) {
+                hx_status st = refresh(l);
+                if (st < 0) failed = true;
+                else if (st == HX_PENDING) {
+                    pending = true;
+                    if (!block_on && events[l].kind == EK_GPU) {
+                        block_on = events[l].hev;
+                        block_slot = l;
+                    }
+                }
+            }
+            if (!failed && pending) continue;
+            host_tasks.erase(host_tasks.begin() + i);
+            Event& e = events[slot];
+            hx_status result = HX_ERR_DEP_FAILED;
+            if (!failed) {
+                hx_host_fn fn = e.hfn;
+                void* user = e.huser;
+                e.running = true;
+                lk.unlock();
+                result = fn ? fn(user) : HX_OK;
+                lk.lock();
+                if (result > 0) result = HX_OK;
+            }
+            Event& e2 = events[slot];
+            e2.running = false;
+            e2.status = result;
+            e2.kind = EK_DONE;
+            std::vector<uint32_t> deps;
+            deps.swap(e2.deps);
+            for (uint32_t d : deps) unref_event(d);
+            if (check && result == HX_OK) mark_joined(e2.seq);
+            resolve_waiters(slot);
+            unref_event(slot);
+            ran = true;
+        }
+        if (ran) continue;
+        if (block_on && !host_only) {
+            ref_event(block_slot);
+            lk.unlock();
+            hipEventSynchronize(block_on);
+            lk.lock();
+            refresh(block_slot);
+            unref_event(block_slot);
+        } else {
+            cv.wait_for(lk, std::chrono::milliseconds(host_tasks.empty() ? 50 : 1));
+        }
+    }
 }
 
 void Ctx::sweep() {
@@ -555,6 +626,14 @@ hx_status hx_ctx_synchronize(hx_ctx ctx) {
 hx_status hx_ctx_destroy(hx_ctx ctx) {
     Ctx* c = C(ctx);
     if (!c) return HX_ERR_INVALID;
+    if (c->worker.joinable()) {
+        {
+            std::lock_guard<std::recursive_mutex> lk(c->mu);
+            c->worker_stop = true;
+        }
+        c->cv.notify_all();
+        c->worker.join();
+    }
     if (!c->host_only) {
         hipSetDevice(c->device);
         for (hipStream_t s : c->streams) hipStreamSynchronize(s);
@@ -959,6 +1038,47 @@ hx_status hx_stream_wait_event(hx_ctx ctx, void* stream, hx_event ev) {
         if (le.kind == EK_GPU && le.status == HX_PENDING)
             hipStreamWaitEvent(static_cast<hipStream_t>(stream), le.hev, 0);
     }
+    return HX_OK;
+}
+
+hx_status hx_host_task(hx_ctx ctx, hx_host_fn fn, void* user, const hx_event* deps, int ndeps,
+                       hx_event* out) {
+    Ctx* c = C(ctx);
+    CTX_OR_FAIL(c);
+    if (!out || !fn) return c->fail(HX_ERR_ARG, "null function or output event");
+    if (ndeps < 0 || (ndeps > 0 && !deps)) return c->fail(HX_ERR_ARG, "bad dependency list");
+    std::vector<uint32_t> dslots;
+    for (int i = 0; i < ndeps; ++i) {
+        if (deps[i] == 0) continue;
+        if (!c->get_event(deps[i])) return c->fail(HX_ERR_INVALID, "invalid dependency event");
+        dslots.push_back(handle_slot(deps[i]));
+    }
+    uint32_t slot = c->new_event(EK_HOST);
+    Event& e = c->events[slot];
+    const uint64_t seq = e.seq;
+    if (seq == c->inject_seq) {
+        e.kind = EK_DONE;
+        e.status = HX_ERR_INJECTED;
+        c->last_error = "injected failure at operation " + std::to_string(seq) + " (host task)";
+        *out = c->handle_of(slot);
+        return HX_OK;
+    }
+    e.hfn = fn;
+    e.huser = user;
+    for (uint32_t d : dslots) {
+        c->events[slot].deps.push_back(d);
+        c->ref_event(d);
+    }
+    if (c->check) {
+        std::vector<uint64_t> dseq;
+        for (uint32_t d : dslots) dseq.push_back(c->events[d].seq);
+        c->check_op(seq, dseq, {}, "host task");
+    }
+    c->host_tasks.push_back(slot);
+    c->ref_event(slot);
+    c->start_worker();
+    c->cv.notify_all();
+    *out = c->handle_of(slot);
     return HX_OK;
 }
 

@@ -8,6 +8,7 @@
 
 #include <atomic>
 #include <condition_variable>
+#include <thread>
 #include <cstdint>
 #include <functional>
 #include <mutex>
@@ -52,7 +53,7 @@ struct Buffer {
 struct Event;
 using EnqueueFn = std::function<hipError_t(hipStream_t)>;
 
-enum EventKind { EK_DONE = 0, EK_GPU, EK_USER, EK_COMPOSITE, EK_DEFERRED };
+enum EventKind { EK_DONE = 0, EK_GPU, EK_USER, EK_COMPOSITE, EK_DEFERRED, EK_HOST };
 
 struct Event {
     uint32_t gen = 0;
@@ -71,6 +72,11 @@ struct Event {
     // deferred operation (EK_DEFERRED until enqueued)
     StreamClass sclass = SC_COMPUTE;
     EnqueueFn fn;
+    // host task (EK_HOST): runs on the context's host worker once every
+    // dependency has completed
+    hx_host_fn hfn = nullptr;
+    void* huser = nullptr;
+    bool running = false;
 };
 
 struct Plan {
@@ -105,6 +111,12 @@ struct Ctx {
     std::vector<void*> host_allocs;
     uint64_t next_seq = 1;
     uint64_t inject_seq = 0;
+    // host tasks
+    std::thread worker;
+    bool worker_stop = false;
+    std::vector<uint32_t> host_tasks;  // pending EK_HOST events (internal refs)
+    void start_worker();
+    void worker_loop();
     std::string last_error;
 
     // hazard checker

@@ -258,16 +258,26 @@ size_t lds_bytes(const Geom1D& g) {
 // One tile per wave (the grid covers the whole tile table): the hardware
 // dispatcher does the load balancing, and with no loop around the tile the
 // register allocation matches the single-segment kernel.
+// When every segment has the same tile count `per_seg` (a batch of equal
+// partitions), the tile's segment and index are computed instead of loaded, so
+// a wave's first HBM access does not wait behind two table lookups.
 template <typename T, int C>
 __global__ __launch_bounds__(256) void k_stencil1d_flat(const Seg1D* __restrict__ segs,
                                                         const uint32_t* __restrict__ tseg,
                                                         const uint32_t* __restrict__ tidx,
-                                                        int64_t ntiles, int steps, int halo) {
+                                                        int64_t ntiles, int steps, int halo,
+                                                        int64_t per_seg) {
     const int wpg = blockDim.x >> 6;
     const int64_t t = (int64_t)blockIdx.x * wpg + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (t >= ntiles) return;
-    const uint32_t si = __builtin_amdgcn_readfirstlane(tseg[t]);
-    const uint32_t ti = __builtin_amdgcn_readfirstlane(tidx[t]);
+    uint32_t si, ti;
+    if (per_seg > 0) {
+        si = (uint32_t)(t / per_seg);
+        ti = (uint32_t)(t - (int64_t)si * per_seg);
+    } else {
+        si = __builtin_amdgcn_readfirstlane(tseg[t]);
+        ti = __builtin_amdgcn_readfirstlane(tidx[t]);
+    }
     tile1d<T, C>(segs[si], ti, steps, halo, wave_lds<T, C>());
 }
 
@@ -291,16 +301,17 @@ hipError_t launch_single(const Seg1D& s0, const Geom1D& g, hipStream_t st) {
 
 template <typename T>
 hipError_t launch_batched(const Seg1D* segs, const uint32_t* tseg, const uint32_t* tidx,
-                          int64_t ntiles, const Geom1D& g, int64_t grid_waves, hipStream_t st) {
+                          int64_t ntiles, const Geom1D& g, int64_t grid_waves, int64_t per_seg,
+                          hipStream_t st) {
     const dim3 block(64 * g.wpg);
     const size_t sh = lds_bytes<T>(g);
     if (grid_waves >= ntiles) {
         const dim3 grid((unsigned)((ntiles + g.wpg - 1) / g.wpg));
         switch (g.cpl) {
-        case 8: hipLaunchKernelGGL((k_stencil1d_flat<T, 8>), grid, block, sh, st, segs, tseg, tidx, ntiles, g.steps, g.halo); break;
-        case 16: hipLaunchKernelGGL((k_stencil1d_flat<T, 16>), grid, block, sh, st, segs, tseg, tidx, ntiles, g.steps, g.halo); break;
-        case 32: hipLaunchKernelGGL((k_stencil1d_flat<T, 32>), grid, block, sh, st, segs, tseg, tidx, ntiles, g.steps, g.halo); break;
-        case 64: hipLaunchKernelGGL((k_stencil1d_flat<T, 64>), grid, block, sh, st, segs, tseg, tidx, ntiles, g.steps, g.halo); break;
+        case 8: hipLaunchKernelGGL((k_stencil1d_flat<T, 8>), grid, block, sh, st, segs, tseg, tidx, ntiles, g.steps, g.halo, per_seg); break;
+        case 16: hipLaunchKernelGGL((k_stencil1d_flat<T, 16>), grid, block, sh, st, segs, tseg, tidx, ntiles, g.steps, g.halo, per_seg); break;
+        case 32: hipLaunchKernelGGL((k_stencil1d_flat<T, 32>), grid, block, sh, st, segs, tseg, tidx, ntiles, g.steps, g.halo, per_seg); break;
+        case 64: hipLaunchKernelGGL((k_stencil1d_flat<T, 64>), grid, block, sh, st, segs, tseg, tidx, ntiles, g.steps, g.halo, per_seg); break;
         default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
@@ -324,10 +335,11 @@ hipError_t launch_stencil1d(int dtype, const Seg1D& seg, const Geom1D& g, hipStr
 
 hipError_t launch_stencil1d_batched(int dtype, const Seg1D* segs_dev, const uint32_t* tile_seg,
                                     const uint32_t* tile_idx, int64_t ntiles, const Geom1D& g,
-                                    int64_t grid_waves, hipStream_t stream) {
-    return dtype == 0
-               ? launch_batched<float>(segs_dev, tile_seg, tile_idx, ntiles, g, grid_waves, stream)
-               : launch_batched<double>(segs_dev, tile_seg, tile_idx, ntiles, g, grid_waves, stream);
+                                    int64_t grid_waves, int64_t per_seg, hipStream_t stream) {
+    return dtype == 0 ? launch_batched<float>(segs_dev, tile_seg, tile_idx, ntiles, g, grid_waves,
+                                              per_seg, stream)
+                      : launch_batched<double>(segs_dev, tile_seg, tile_idx, ntiles, g,
+                                               grid_waves, per_seg, stream);
 }
 
 }  // namespace hx

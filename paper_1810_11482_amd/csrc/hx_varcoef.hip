@@ -1,0 +1,386 @@
+// Variable-coefficient heat step, its adjoint, and the FP64 reductions of the
+// gradient path, for gfx950.
+//
+// Forward step (h = 1, zero-Dirichlet): v_c = u_c + dt * sum_f kappa_f (u_n - u_c)
+// over the west, east, north and south faces, kappa_f = (kappa_c + kappa_n) / 2
+// on interior faces; a face on the domain edge has kappa_f = kappa_c and a ghost
+// u_n = 0.  Writing the ghost as (u = 0, kappa = kappa_c) makes the interior
+// formula exact at the edge too, since (kappa_c + kappa_c) / 2 = kappa_c.
+//
+// Adjoint step (loss L = 0.5 ||u_T - y||^2, lam_T = u_T - y): the face rule is
+// symmetric, so lam_t = A^T lam_{t+1} = A lam_{t+1} is the forward formula
+// applied to lam, and in the same pass the conductivity gradient gains
+//   -dt * [ sum_{interior f} (u_n - u_c)(lam_n - lam_c) / 2 + sum_{edge f} u_c lam_c ]
+// with u = u_t and lam = lam_{t+1}.
+//
+// Mapping: a wave owns a strip of 64*C columns (C = 4 adjacent cells per lane)
+// and streams a chunk of rows top to bottom, keeping the rows above, at and
+// below the current one of every field in registers, so each field is read from
+// HBM once per step.  West/east neighbours come from DPP wave shifts; the two
+// cells just outside the strip are loaded per row by lanes 0 and 63.
+#include <hip/hip_runtime.h>
+
+#include "hx_internal.h"
+
+namespace hx {
+namespace {
+
+constexpr int DPP_WAVE_SHL1 = 0x130;
+constexpr int DPP_WAVE_SHR1 = 0x138;
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+    int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, true);
+    int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+constexpr int C = 4;  // cells per lane
+constexpr int S = 64 * C;
+
+// One row of one field as seen by a lane: its C cells plus the cells just west
+// and east of them.  Cells outside the domain are replaced by `ghost`.
+template <typename T>
+struct Row {
+    T c[C];
+    T w, e;
+};
+
+// Load row y of field f (row-major, nx columns) for the lane's cells
+// [xl, xl + C); columns outside [0, nx) and rows outside [0, ny) read the
+// ghost value given per cell (gc: ghost per cell; gw/ge: ghost of the edge
+// neighbours).
+template <typename T>
+__device__ __forceinline__ void load_row(const T* __restrict__ f, int64_t y, int64_t ny, int64_t nx,
+                                         int64_t x0, int64_t xl, int lane, bool vec, Row<T>& r,
+                                         const T (&gc)[C]) {
+    const bool rowin = y >= 0 && y < ny;
+    if (rowin && vec) {
+        // 16-byte loads: one for f32, two for f64
+        typedef T V2 __attribute__((ext_vector_type(16 / sizeof(T))));
+        const V2* p = reinterpret_cast<const V2*>(f + y * nx + xl);
+        constexpr int VN = 16 / sizeof(T);
+#pragma unroll
+        for (int q = 0; q < C / VN; ++q) {
+            const V2 x = p[q];
+#pragma unroll
+            for (int e = 0; e < VN; ++e) r.c[q * VN + e] = x[e];
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            const int64_t x = xl + j;
+            r.c[j] = (rowin && x >= 0 && x < nx) ? f[y * nx + x] : gc[j];
+        }
+    }
+    // neighbours across lanes, and the two cells outside the strip
+    const T fromw = dpp_move<DPP_WAVE_SHR1>(r.c[C - 1]);
+    const T frome = dpp_move<DPP_WAVE_SHL1>(r.c[0]);
+    r.w = fromw;
+    r.e = frome;
+    if (lane == 0) {
+        const int64_t x = x0 - 1;
+        r.w = (rowin && x >= 0 && x < nx) ? f[y * nx + x] : T(0);
+    }
+    if (lane == 63) {
+        const int64_t x = x0 + S;
+        r.e = (rowin && x >= 0 && x < nx) ? f[y * nx + x] : T(0);
+    }
+}
+
+struct VCDev {
+    const void* u;      // state (forward input; adjoint: u_t)
+    const void* kappa;
+    const void* lam;    // adjoint: lam_{t+1}
+    void* out;          // forward: u_{t+1}; adjoint: lam_t
+    void* gacc;         // adjoint: per-segment conductivity-gradient accumulator (T)
+    int64_t nx, ny;
+    double dt;
+    int rows;
+    int aligned;        // every row starts 16-byte aligned
+};
+
+// kappa row with edge ghosts equal to the cell's own conductivity
+template <typename T>
+__device__ __forceinline__ void load_kappa(const T* k, int64_t y, int64_t ny, int64_t nx, int64_t x0,
+                                           int64_t xl, int lane, bool vec, const Row<T>& kc,
+                                           Row<T>& r) {
+    // rows outside: ghost = kappa of the centre row's cell (vertical edge face)
+    T gc[C];
+#pragma unroll
+    for (int j = 0; j < C; ++j) gc[j] = kc.c[j];
+    load_row<T>(k, y, ny, nx, x0, xl, lane, vec, r, gc);
+}
+
+// Weighted face sum sum_f kappa_f (f_n - f_c) for the lane's C cells of row y.
+template <typename T>
+__device__ __forceinline__ void face_sum(const Row<T>& fm, const Row<T>& f0, const Row<T>& fp,
+                                         const Row<T>& km, const Row<T>& k0, const Row<T>& kp,
+                                         int64_t xl, int64_t nx, T (&acc)[C]) {
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+        const T fc = f0.c[j];
+        const T kc = k0.c[j];
+        const int64_t x = xl + j;
+        const T fw = j > 0 ? f0.c[j - 1] : f0.w;
+        const T fe = j + 1 < C ? f0.c[j + 1] : f0.e;
+        // west/east ghosts: u = 0 (loaded as 0), kappa = kappa_c
+        const T kw = (x - 1 >= 0) ? (j > 0 ? k0.c[j - 1] : k0.w) : kc;
+        const T ke = (x + 1 < nx) ? (j + 1 < C ? k0.c[j + 1] : k0.e) : kc;
+        const T fW = (x - 1 >= 0) ? fw : T(0);
+        const T fE = (x + 1 < nx) ? fe : T(0);
+        const T kfw = (kc + kw) * T(0.5);
+        const T kfe = (kc + ke) * T(0.5);
+        const T kfn = (kc + km.c[j]) * T(0.5);
+        const T kfs = (kc + kp.c[j]) * T(0.5);
+        T a = kfw * (fW - fc);
+        a = fmaT(kfe, fE - fc, a);
+        a = fmaT(kfn, fm.c[j] - fc, a);
+        a = fmaT(kfs, fp.c[j] - fc, a);
+        acc[j] = a;
+    }
+}
+
+template <typename T, bool ADJ>
+__global__ __launch_bounds__(256) void k_vc_step(VCDev a, int64_t nstrips, int64_t nwaves) {
+    const int wpg = blockDim.x >> 6;
+    const int64_t wave = (int64_t)blockIdx.x * wpg + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wave >= nwaves) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t strip = wave % nstrips, chunk = wave / nstrips;
+    const int64_t nx = a.nx, ny = a.ny;
+    const int64_t x0 = strip * S;
+    const int64_t xl = x0 + (int64_t)lane * C;
+    const int64_t y0 = chunk * a.rows;
+    const int64_t y1 = (y0 + a.rows < ny) ? y0 + a.rows : ny;
+    const bool vec = (x0 + S <= nx) && a.aligned;
+    const T dt = static_cast<T>(a.dt);
+    const T* U = static_cast<const T*>(a.u);
+    const T* K = static_cast<const T*>(a.kappa);
+    const T* L = static_cast<const T*>(a.lam);
+    T* O = static_cast<T*>(a.out);
+    T* G = static_cast<T*>(a.gacc);
+    const T zero[C] = {T(0), T(0), T(0), T(0)};
+
+    Row<T> um, u0, up, km, k0, kp, lm, l0, lp;
+    // rows y0-1 and y0 of every field (kappa ghosts need the centre row first)
+    load_row<T>(K, y0, ny, nx, x0, xl, lane, vec, k0, zero);
+    load_kappa<T>(K, y0 - 1, ny, nx, x0, xl, lane, vec, k0, km);
+    load_row<T>(U, y0 - 1, ny, nx, x0, xl, lane, vec, um, zero);
+    load_row<T>(U, y0, ny, nx, x0, xl, lane, vec, u0, zero);
+    if (ADJ) {
+        load_row<T>(L, y0 - 1, ny, nx, x0, xl, lane, vec, lm, zero);
+        load_row<T>(L, y0, ny, nx, x0, xl, lane, vec, l0, zero);
+    }
+    for (int64_t y = y0; y < y1; ++y) {
+        load_kappa<T>(K, y + 1, ny, nx, x0, xl, lane, vec, k0, kp);
+        load_row<T>(U, y + 1, ny, nx, x0, xl, lane, vec, up, zero);
+        if (ADJ) load_row<T>(L, y + 1, ny, nx, x0, xl, lane, vec, lp, zero);
+        // rows outside the domain carry ghost kappa = kappa of the row y cell
+        if (y - 1 < 0) {
+#pragma unroll
+            for (int j = 0; j < C; ++j) km.c[j] = k0.c[j];
+        }
+        if (y + 1 >= ny) {
+#pragma unroll
+            for (int j = 0; j < C; ++j) kp.c[j] = k0.c[j];
+        }
+        T acc[C];
+        if (!ADJ) {
+            face_sum<T>(um, u0, up, km, k0, kp, xl, nx, acc);
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                const int64_t x = xl + j;
+                if (x < nx) O[y * nx + x] = fmaT(dt, acc[j], u0.c[j]);
+            }
+        } else {
+            face_sum<T>(lm, l0, lp, km, k0, kp, xl, nx, acc);
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                const int64_t x = xl + j;
+                const T uc = u0.c[j], lc = l0.c[j];
+                const T prod = uc * lc;
+                const T hw = (x - 1 >= 0) ? ((j > 0 ? u0.c[j - 1] : u0.w) - uc) *
+                                                ((j > 0 ? l0.c[j - 1] : l0.w) - lc) * T(0.5)
+                                          : prod;
+                const T he = (x + 1 < nx) ? ((j + 1 < C ? u0.c[j + 1] : u0.e) - uc) *
+                                                ((j + 1 < C ? l0.c[j + 1] : l0.e) - lc) * T(0.5)
+                                          : prod;
+                const T hn = (y - 1 >= 0) ? (um.c[j] - uc) * (lm.c[j] - lc) * T(0.5) : prod;
+                const T hs = (y + 1 < ny) ? (up.c[j] - uc) * (lp.c[j] - lc) * T(0.5) : prod;
+                const T g = ((hw + he) + (hn + hs));
+                if (x < nx) {
+                    O[y * nx + x] = fmaT(dt, acc[j], lc);
+                    G[y * nx + x] = fmaT(-dt, g, G[y * nx + x]);
+                }
+            }
+        }
+        um = u0; u0 = up;
+        km = k0; k0 = kp;
+        if (ADJ) { lm = l0; l0 = lp; }
+    }
+}
+
+// acc -> fp64 total, and acc reset to 0 (the fold of one checkpoint segment)
+template <typename T>
+__global__ void k_fold(T* __restrict__ acc, double* __restrict__ total, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        total[i] += (double)acc[i];
+        acc[i] = T(0);
+    }
+}
+
+template <typename T>
+__global__ void k_fill(T* __restrict__ p, int64_t n, T v) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+template <typename T>
+__global__ void k_cast64(const double* __restrict__ src, T* __restrict__ dst, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        dst[i] = (T)src[i];
+}
+
+// out = x * s, s a device FP64 scalar
+template <typename T>
+__global__ void k_scale(const T* __restrict__ x, const double* __restrict__ s, T* __restrict__ out,
+                        int64_t n) {
+    const double f = *s;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        out[i] = (T)((double)x[i] * f);
+}
+
+// Deterministic FP64 block reduction: every block writes one partial sum
+// (wave DPP-free shuffle tree then LDS), a second one-block pass adds the
+// partials in index order.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+template <int MODE, typename T>  // MODE 0: 0.5*(a-b)^2 (+ residual), 1: a*b
+__global__ __launch_bounds__(256) void k_reduce(const T* __restrict__ a, const T* __restrict__ b,
+                                                T* __restrict__ resid, int64_t n,
+                                                double* __restrict__ partial) {
+    double s = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        if (MODE == 0) {
+            const T d = a[i] - b[i];
+            if (resid) resid[i] = d;
+            s += (double)d * (double)d;
+        } else {
+            s += (double)a[i] * (double)b[i];
+        }
+    }
+    __shared__ double ws[4];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += ws[w];
+        partial[blockIdx.x] = MODE == 0 ? 0.5 * t : t;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_finish(const double* __restrict__ partial, int nblocks,
+                                                double* __restrict__ out) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nblocks; i += blockDim.x) s += partial[i];
+    __shared__ double ws[4];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += ws[w];
+        *out = t;
+    }
+}
+
+unsigned grid_for(int64_t n) {
+    int64_t g = (n + 1023) / 1024;
+    if (g > 4096) g = 4096;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+}  // namespace
+
+hipError_t launch_vc_step(int dtype, bool adjoint, const VCArgs& v, hipStream_t st) {
+    auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; };
+    const int es = dtype == 0 ? 4 : 8;
+    const bool aligned = ((v.nx * es) % 16 == 0) && al(v.u) && al(v.kappa) && (!v.lam || al(v.lam));
+    VCDev a{v.u, v.kappa, v.lam, v.out, v.gacc, v.nx, v.ny, v.dt, v.rows > 0 ? v.rows : 64,
+            aligned ? 1 : 0};
+    const int64_t nstrips = (v.nx + S - 1) / S;
+    const int64_t nchunks = (v.ny + a.rows - 1) / a.rows;
+    const int64_t nwaves = nstrips * nchunks;
+    const int wpg = 4;
+    const dim3 block(64 * wpg), grid((unsigned)((nwaves + wpg - 1) / wpg));
+    if (dtype == 0) {
+        if (adjoint) hipLaunchKernelGGL((k_vc_step<float, true>), grid, block, 0, st, a, nstrips, nwaves);
+        else hipLaunchKernelGGL((k_vc_step<float, false>), grid, block, 0, st, a, nstrips, nwaves);
+    } else {
+        if (adjoint) hipLaunchKernelGGL((k_vc_step<double, true>), grid, block, 0, st, a, nstrips, nwaves);
+        else hipLaunchKernelGGL((k_vc_step<double, false>), grid, block, 0, st, a, nstrips, nwaves);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fold(int dtype, void* acc, double* total, int64_t n, hipStream_t st) {
+    if (dtype == 0) hipLaunchKernelGGL((k_fold<float>), dim3(grid_for(n)), dim3(256), 0, st, (float*)acc, total, n);
+    else hipLaunchKernelGGL((k_fold<double>), dim3(grid_for(n)), dim3(256), 0, st, (double*)acc, total, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(int dtype, void* p, int64_t n, double v, hipStream_t st) {
+    if (dtype == 0) hipLaunchKernelGGL((k_fill<float>), dim3(grid_for(n)), dim3(256), 0, st, (float*)p, n, (float)v);
+    else hipLaunchKernelGGL((k_fill<double>), dim3(grid_for(n)), dim3(256), 0, st, (double*)p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_cast64(int dtype, const double* src, void* dst, int64_t n, hipStream_t st) {
+    if (dtype == 0) hipLaunchKernelGGL((k_cast64<float>), dim3(grid_for(n)), dim3(256), 0, st, src, (float*)dst, n);
+    else hipLaunchKernelGGL((k_cast64<double>), dim3(grid_for(n)), dim3(256), 0, st, src, (double*)dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale(int dtype, const void* x, const double* s, void* out, int64_t n,
+                        hipStream_t st) {
+    if (dtype == 0) hipLaunchKernelGGL((k_scale<float>), dim3(grid_for(n)), dim3(256), 0, st, (const float*)x, s, (float*)out, n);
+    else hipLaunchKernelGGL((k_scale<double>), dim3(grid_for(n)), dim3(256), 0, st, (const double*)x, s, (double*)out, n);
+    return hipGetLastError();
+}
+
+int reduce_blocks(int64_t n) { return (int)grid_for(n); }
+
+hipError_t launch_reduce(int dtype, int mode, const void* a, const void* b, void* resid, int64_t n,
+                         double* partial, double* out, hipStream_t st) {
+    const unsigned g = grid_for(n);
+    if (dtype == 0) {
+        if (mode == 0) hipLaunchKernelGGL((k_reduce<0, float>), dim3(g), dim3(256), 0, st, (const float*)a, (const float*)b, (float*)resid, n, partial);
+        else hipLaunchKernelGGL((k_reduce<1, float>), dim3(g), dim3(256), 0, st, (const float*)a, (const float*)b, (float*)nullptr, n, partial);
+    } else {
+        if (mode == 0) hipLaunchKernelGGL((k_reduce<0, double>), dim3(g), dim3(256), 0, st, (const double*)a, (const double*)b, (double*)resid, n, partial);
+        else hipLaunchKernelGGL((k_reduce<1, double>), dim3(g), dim3(256), 0, st, (const double*)a, (const double*)b, (double*)nullptr, n, partial);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, st, partial, (int)g, out);
+    return hipGetLastError();
+}
+
+}  // namespace hx

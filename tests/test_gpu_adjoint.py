@@ -1,0 +1,229 @@
+"""GPU parity of the variable-coefficient step, its adjoint, the checkpointed
+gradient and the autograd.Function, against the FP64 oracle adjoint.
+
+Bars: FP64 GPU <= 1e-12 relative to the oracle (steps, gradients, loss), the
+GPU FP64 inner-product identity <A u, v> = <u, A^T v> <= 1e-12; FP32 GPU
+<= 1e-5 relative L2 against the FP64 oracle (errors printed per result)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from conftest import rel_l2, rel_max
+
+pytestmark = pytest.mark.gpu
+hx = pytest.importorskip("paper_1810_11482_amd")
+from hxutil import download, upload  # noqa: E402
+
+TOL = {np.float64: 1e-12, np.float32: 1e-5}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if hx.hx_device_count() == 0:
+        pytest.skip("no GPU")
+    c = hx.hx_ctx_create(0)
+    yield c
+    hx.hx_ctx_destroy(c)
+
+
+def kappa_field(shape, seed, dtype):
+    z = workloads.rng(600, seed).standard_normal(shape)
+    return np.minimum(np.exp(-2 + 0.5 * z), 1.0).astype(dtype)
+
+
+def wait(ctx, ev):
+    assert hx.hx_wait(ctx, ev) == hx.HX_OK, hx.hx_last_error(ctx)
+    hx.hx_event_release(ctx, ev)
+
+
+def code(dtype):
+    return hx.HX_F64 if dtype == np.float64 else hx.HX_F32
+
+
+SHAPES = [(1, 1), (1, 7), (9, 1), (5, 6), (33, 257), (70, 300), (128, 512)]
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_forward_step(ctx, dtype, shape):
+    u = workloads.uniform(shape, 601, shape[0] * 1000 + shape[1], -1, 1, dtype)
+    k = kappa_field(shape, 1, dtype)
+    bu, bk = upload(ctx, u), upload(ctx, k)
+    bo = hx.hx_buffer_create(ctx, u.nbytes)
+    wait(ctx, hx.hx_heat_vc_step(ctx, code(dtype), shape[1], shape[0], 0.2, bu, bk, bo))
+    got = download(ctx, bo, shape, dtype)
+    ref = oracle.heatvc_step(u.astype(np.float64), k.astype(np.float64), 0.2)
+    assert rel_l2(got, ref) <= TOL[dtype] and rel_max(got, ref) <= 10 * TOL[dtype]
+    for b in (bu, bk, bo):
+        hx.hx_buffer_destroy(ctx, b)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_adjoint_step(ctx, dtype, shape):
+    u = workloads.uniform(shape, 602, shape[0] * 1000 + shape[1], -1, 1, dtype)
+    lam = workloads.uniform(shape, 603, shape[0] * 1000 + shape[1], -1, 1, dtype)
+    g0 = workloads.uniform(shape, 604, 0, -1, 1, dtype)
+    k = kappa_field(shape, 2, dtype)
+    bu, bl, bk, bg = upload(ctx, u), upload(ctx, lam), upload(ctx, k), upload(ctx, g0)
+    bo = hx.hx_buffer_create(ctx, u.nbytes)
+    wait(ctx, hx.hx_heat_vc_adjoint_step(ctx, code(dtype), shape[1], shape[0], 0.2, bu, bl, bk,
+                                         bo, bg))
+    lam_out = download(ctx, bo, shape, dtype)
+    gk = download(ctx, bg, shape, dtype)
+    f64 = lambda a: a.astype(np.float64)
+    ref_l = oracle.heatvc_step_transpose(f64(lam), f64(k), 0.2)
+    ref_g = oracle.heatvc_grad_kappa_step(f64(u), f64(lam), 0.2, f64(g0))
+    assert rel_l2(lam_out, ref_l) <= TOL[dtype]
+    assert rel_l2(gk, ref_g) <= TOL[dtype]
+    for b in (bu, bl, bk, bg, bo):
+        hx.hx_buffer_destroy(ctx, b)
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (40, 77), (256, 300)])
+def test_gpu_fp64_inner_product_identity(ctx, shape):
+    """<A u, v> = <u, A^T v> with the GPU step, the GPU adjoint step and the
+    GPU FP64 dot; positive u, v so the sums do not cancel."""
+    n = shape[0] * shape[1]
+    u = workloads.uniform(shape, 605, 0)
+    v = workloads.uniform(shape, 605, 1)
+    k = kappa_field(shape, 3, np.float64)
+    bu, bv, bk = upload(ctx, u), upload(ctx, v), upload(ctx, k)
+    bAu = hx.hx_buffer_create(ctx, u.nbytes)
+    bATv = hx.hx_buffer_create(ctx, u.nbytes)
+    bg = upload(ctx, np.zeros(shape))
+    bd = [hx.hx_buffer_create(ctx, 8) for _ in range(2)]
+    work = hx.hx_buffer_create(ctx, 4096 * 8)
+    wait(ctx, hx.hx_heat_vc_step(ctx, hx.HX_F64, shape[1], shape[0], 0.2, bu, bk, bAu))
+    wait(ctx, hx.hx_heat_vc_adjoint_step(ctx, hx.HX_F64, shape[1], shape[0], 0.2, bu, bv, bk,
+                                         bATv, bg))
+    wait(ctx, hx.hx_launch_dot(ctx, hx.HX_F64, n, bAu, bv, bd[0], work))
+    wait(ctx, hx.hx_launch_dot(ctx, hx.HX_F64, n, bu, bATv, bd[1], work))
+    lhs = download(ctx, bd[0], 1, np.float64)[0]
+    rhs = download(ctx, bd[1], 1, np.float64)[0]
+    Au = download(ctx, bAu, shape, np.float64)
+    err = abs(lhs - rhs) / (np.linalg.norm(Au) * np.linalg.norm(v))
+    print(f"inner-product identity {shape}: {err:.2e}")
+    assert err <= 1e-12
+    assert abs(lhs - oracle.dot(Au, v)) <= 1e-12 * abs(lhs)
+    for b in (bu, bv, bk, bAu, bATv, bg, work, *bd):
+        hx.hx_buffer_destroy(ctx, b)
+
+
+def gpu_grad(ctx, u0, kappa, y, dt, T, ckpt, dtype):
+    shape = u0.shape
+    ny, nx = shape
+    n = ny * nx
+    S, nseg = hx.hx_vc_schedule(T, ckpt)
+    es = np.dtype(dtype).itemsize
+    bu0, bk, by = upload(ctx, u0.astype(dtype)), upload(ctx, kappa.astype(dtype)), \
+        upload(ctx, y.astype(dtype))
+    buT = hx.hx_buffer_create(ctx, n * es)
+    bck = hx.hx_buffer_create(ctx, max(nseg - 1, 1) * n * es)
+    bw = hx.hx_buffer_create(ctx, 2 * n * es)
+    bseg = hx.hx_buffer_create(ctx, max(S - 1, 1) * n * es)
+    blT = hx.hx_buffer_create(ctx, n * es)
+    bl0 = hx.hx_buffer_create(ctx, n * es)
+    bg64 = hx.hx_buffer_create(ctx, n * 8)
+    bga = hx.hx_buffer_create(ctx, n * es)
+    bloss = hx.hx_buffer_create(ctx, 8)
+    work = hx.hx_buffer_create(ctx, 4096 * 8)
+    a = hx.hx_vc_args(code(dtype), nx, ny, dt, T, ckpt, bu0, bk, buT, bck if nseg > 1 else 0,
+                      bw if T > 1 else 0, bseg if S > 1 else 0, blT, bl0, bg64, bga, 0)
+    e1 = hx.hx_heat_vc_forward(ctx, a)
+    e2 = hx.hx_launch_loss(ctx, code(dtype), n, buT, by, blT, bloss, work, deps=[e1])
+    e3 = hx.hx_heat_vc_backward(ctx, a, deps=[e2])
+    wait(ctx, e3)
+    for e in (e1, e2):
+        hx.hx_event_release(ctx, e)
+    loss = download(ctx, bloss, 1, np.float64)[0]
+    lam0 = download(ctx, bl0, shape, dtype)
+    gk = download(ctx, bg64, shape, np.float64)
+    for b in (bu0, bk, by, buT, bck, bw, bseg, blT, bl0, bg64, bga, bloss, work):
+        hx.hx_buffer_destroy(ctx, b)
+    return loss, lam0, gk
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("shape,T,ckpt", [((48, 70), 25, 0), ((33, 260), 17, 4), ((8, 8), 1, 0),
+                                          ((64, 64), 10, 10), ((20, 300), 7, 3)])
+def test_checkpointed_gradient_matches_oracle(ctx, dtype, shape, T, ckpt):
+    u0 = workloads.gaussian_bumps(*shape, 3, 5.0, 610, np.float64).astype(dtype).astype(np.float64)
+    kappa = kappa_field(shape, 4, dtype).astype(np.float64)
+    y = workloads.uniform(shape, 611, 0, 0, 1, dtype).astype(np.float64)
+    loss, lam0, gk = gpu_grad(ctx, u0, kappa, y, 0.2, T, ckpt, dtype)
+    rl, rlam, rgk = oracle.heatvc_grad(u0, kappa, y, 0.2, T)
+    e = (abs(loss - rl) / rl, rel_l2(lam0, rlam), rel_l2(gk, rgk))
+    print(f"{dtype.__name__} {shape} T={T} S={ckpt}: loss {e[0]:.2e} lam0 {e[1]:.2e} gk {e[2]:.2e}")
+    assert max(e) <= TOL[dtype]
+
+
+def test_checkpoint_length_does_not_change_bits(ctx):
+    shape, T = (40, 100), 12
+    u0 = workloads.uniform(shape, 612, 0)
+    kappa = kappa_field(shape, 5, np.float64)
+    y = workloads.uniform(shape, 612, 1)
+    ref = gpu_grad(ctx, u0, kappa, y, 0.2, T, 12, np.float64)  # one segment = keep everything
+    for S in (1, 3, 5, 0):
+        got = gpu_grad(ctx, u0, kappa, y, 0.2, T, S, np.float64)
+        assert got[0] == ref[0] and np.array_equal(got[1], ref[1])
+        # the FP64 gradient total is folded once per segment, so its summation
+        # grouping (not its terms) changes with S
+        assert rel_l2(got[2], ref[2]) <= 1e-14
+
+
+def test_fd_directional_fp64(ctx):
+    shape, T = (30, 40), 15
+    u0 = workloads.uniform(shape, 613, 0)
+    kappa = kappa_field(shape, 6, np.float64)
+    y = workloads.uniform(shape, 613, 1)
+    loss, lam0, gk = gpu_grad(ctx, u0, kappa, y, 0.2, T, 0, np.float64)
+    du = workloads.uniform(shape, 613, 2, -1, 1)
+    dk = workloads.uniform(shape, 613, 3, -1, 1) * 0.01
+    eps = 1e-4
+    lp = gpu_grad(ctx, u0 + eps * du, kappa + eps * dk, y, 0.2, T, 0, np.float64)[0]
+    lm = gpu_grad(ctx, u0 - eps * du, kappa - eps * dk, y, 0.2, T, 0, np.float64)[0]
+    fd = (lp - lm) / (2 * eps)
+    an = float(np.sum(lam0 * du) + np.sum(gk * dk))
+    assert abs(fd - an) <= 1e-7 * abs(an)
+
+
+def test_autograd_function(ctx):
+    import torch
+    from paper_1810_11482_amd.adjoint import HeatLoss, HeatVC
+    shape, T = (60, 90), 16
+    u0n = workloads.gaussian_bumps(*shape, 4, 6.0, 614, np.float64)
+    kn = kappa_field(shape, 7, np.float64)
+    yn = workloads.uniform(shape, 614, 1)
+    for dt_ in (torch.float64, torch.float32):
+        u0 = torch.tensor(u0n, dtype=dt_, device="cuda", requires_grad=True)
+        k = torch.tensor(kn, dtype=dt_, device="cuda", requires_grad=True)
+        y = torch.tensor(yn, dtype=dt_, device="cuda")
+        loss = HeatLoss.apply(HeatVC.apply(u0, k, 0.2, T, 0), y)
+        loss.backward()
+        torch.cuda.synchronize()
+        ref = oracle.heatvc_grad(u0.detach().cpu().double().numpy(),
+                                 k.detach().cpu().double().numpy(), y.cpu().double().numpy(),
+                                 0.2, T)
+        tol = 1e-12 if dt_ == torch.float64 else 1e-5
+        assert abs(loss.item() - ref[0]) <= tol * ref[0]
+        assert rel_l2(u0.grad.cpu().double().numpy(), ref[1]) <= tol
+        assert rel_l2(k.grad.cpu().double().numpy(), ref[2]) <= tol
+
+
+def test_full_size_fp32_against_fp64(ctx):
+    """8192^2, 100 steps, dt = 0.2, log-normal kappa clipped at 1, S = 10: the
+    FP32 gradients against the FP64 GPU path (pinned to the oracle at small
+    sizes), and the FP64 path's directional finite difference."""
+    spec = workloads.VarCoef2D()
+    u0, kappa, y = workloads.varcoef2d_inputs(spec)
+    res = {}
+    for dt_ in (np.float64, np.float32):
+        res[dt_] = gpu_grad(ctx, u0.astype(np.float64), kappa.astype(np.float64),
+                            y.astype(np.float64), spec.dt, spec.steps, spec.ckpt, dt_)
+    l64, lam64, gk64 = res[np.float64]
+    l32, lam32, gk32 = res[np.float32]
+    e = (abs(l32 - l64) / l64, rel_l2(lam32, lam64), rel_l2(gk32, gk64))
+    print(f"full size fp32 vs fp64: loss {e[0]:.2e} lam0 {e[1]:.2e} gk {e[2]:.2e}")
+    assert max(e) <= 1e-5
