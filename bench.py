@@ -139,10 +139,12 @@ def main():
     ap.add_argument("--time-block", type=int, default=0, help="0 = pick by a short sweep")
     ap.add_argument("--cells-per-lane", type=int, default=0)
     ap.add_argument("--streams", type=int, default=4)
-    ap.add_argument("--legs", default="graph,batched_pass,plain,pipeline,batched,cpu",
+    ap.add_argument("--legs", default="graph,batched_pass,plain,pipeline,batched,fp64,2d,adjoint,cpu",
                     help="comma list of legs: graph (the headline, always run), batched_pass, "
-                         "plain, pipeline, batched, cpu, copy (a zero-step pass: a plain "
-                         "device copy of known size, for counter calibration)")
+                         "plain, pipeline, batched, fp64 (2^20 fp64, 100 steps), 2d (16384^2, "
+                         "200 steps, 16 bands), adjoint (8192^2, 100 steps), cpu, copy (a "
+                         "zero-step pass: a plain device copy of known size, for counter "
+                         "calibration)")
     args = ap.parse_args()
     legs = set(args.legs.split(","))
 
@@ -242,6 +244,12 @@ def main():
         result["batched"] = batched_leg(hx, ctx)
     if "copy" in legs:
         result["copy_calibration"] = copy_leg(hx, ctx, P)
+    if "fp64" in legs:
+        result["periodic_fp64"] = fp64_leg(hx, ctx)
+    if "2d" in legs:
+        result["banded_2d"] = banded2d_leg(hx, ctx)
+    if "adjoint" in legs:
+        result["adjoint"] = adjoint_leg(hx, ctx)
 
     # --------------------------------------------------------------- CPU oracle
     if "cpu" in legs:
@@ -459,6 +467,149 @@ def pipeline_leg(hx, ctx0, P, T, r, cpl):
            "host_link_GBps_during_overlap": bytes_copied / (measure_len(C) * 1e-3) / 1e9,
            "sampled_max_rel_err": err}
     log(f"pipeline: {res}")
+    return res
+
+
+def fp64_leg(hx, ctx, reps=10):
+    """2^20 fp64 periodic cells, r = 0.25, 100 steps in one fused launch (the
+    sine-mode workload); checked against the FP64 oracle."""
+    import oracle
+    import workloads
+    spec = workloads.Periodic1D()
+    u0 = workloads.periodic1d_u0(spec)
+    n = spec.n
+    a = hx.hx_buffer_create(ctx, n * 8)
+    b = hx.hx_buffer_create(ctx, n * 8)
+    e = hx.hx_copy_async(ctx, hx.hx_copy_desc(hx.HX_H2D, u0.ctypes.data, a, 0, 0, 0, n * 8))
+    assert hx.hx_wait(ctx, e) == hx.HX_OK
+    hx.hx_event_release(ctx, e)
+    best = None
+    for cpl, tb in ((32, 100), (16, 100), (64, 100), (32, 50)):
+        args = hx.stencil_args(dims=1, dtype=hx.HX_F64, nx=n, steps=spec.steps, r=spec.r, inp=a,
+                               out=b, tmp=hx.hx_buffer_create(ctx, n * 8) if tb < 100 else 0,
+                               cells_per_lane=cpl, time_block=tb)
+        evs = [hx.hx_launch_stencil(ctx, args) for _ in range(reps + 1)]
+        assert hx.hx_wait(ctx, evs[-1]) == hx.HX_OK
+        d = [y - x for x, y in (hx.hx_event_span(ctx, ev, ev) for ev in evs[1:])]
+        for ev in evs:
+            hx.hx_event_release(ctx, ev)
+        ms = float(np.median(d))
+        log(f"fp64 1D cpl={cpl} tb={tb}: {ms * 1e3:.1f} us")
+        if best is None or ms < best[0]:
+            best = (ms, cpl, tb)
+    out = np.empty(n, np.float64)
+    e = hx.hx_copy_async(ctx, hx.hx_copy_desc(hx.HX_D2H, out.ctypes.data, b, 0, 0, 0, n * 8))
+    assert hx.hx_wait(ctx, e) == hx.HX_OK
+    hx.hx_event_release(ctx, e)
+    ref = oracle.heat1d_periodic(u0, spec.r, spec.steps)
+    err = float(np.linalg.norm(out - ref) / np.linalg.norm(ref))
+    return {"cells": n, "steps": spec.steps, "ms": best[0], "cells_per_lane": best[1],
+            "time_block": best[2], "cell_updates_per_s": n * spec.steps / (best[0] * 1e-3),
+            "rel_l2_vs_oracle": err}
+
+
+def banded2d_leg(hx, ctx):
+    """16384^2 fp32, zero-Dirichlet, r = 0.2, 200 steps, 16 row bands with
+    halo-row futures (the per-band future graph), Gaussian-bump field."""
+    import torch
+    import workloads
+    spec = workloads.Banded2D()
+    u0 = workloads.banded2d_u0(spec)
+    bounds = workloads.band_bounds(spec.ny, spec.bands)
+    A = [hx.hx_buffer_create(ctx, s * spec.nx * 4) for _, s in bounds]
+    B = [hx.hx_buffer_create(ctx, s * spec.nx * 4) for _, s in bounds]
+    for (o, s), buf in zip(bounds, A):
+        chunk = np.ascontiguousarray(u0[o:o + s])
+        e = hx.hx_copy_async(ctx, hx.hx_copy_desc(hx.HX_H2D, chunk.ctypes.data, buf, 0, 0, 0,
+                                                  chunk.nbytes))
+        assert hx.hx_wait(ctx, e) == hx.HX_OK
+        hx.hx_event_release(ctx, e)
+    cells = spec.ny * spec.nx
+    best = None
+    for tb, cpl, rows in ((8, 4, 256), (8, 4, 128), (8, 8, 256), (10, 4, 256), (12, 4, 256),
+                          (16, 4, 256), (16, 4, 512), (4, 4, 256)):
+        d = hx.partitioned_desc(hx.HX_F32, [s for _, s in bounds], A, B, spec.steps, spec.r,
+                                periodic=False, time_block=tb, cells_per_lane=cpl, dims=2,
+                                nx=spec.nx, rows_per_block=rows)
+        ts = []
+        for it in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ev, in_b, _ = hx.hx_run_partitioned(ctx, d)
+            assert hx.hx_wait(ctx, ev) == hx.HX_OK, hx.hx_last_error(ctx)
+            ts.append(time.perf_counter() - t0)
+            hx.hx_event_release(ctx, ev)
+        sec = ts[-1]
+        log(f"2D bands tb={tb} cpl={cpl} rows={rows}: {sec * 1e3:.2f} ms")
+        if best is None or sec < best[0]:
+            best = (sec, tb, cpl, rows)
+    sec, tb, cpl, rows = best
+    passes = -(-spec.steps // tb)
+    res = {"ny": spec.ny, "nx": spec.nx, "bands": spec.bands, "steps": spec.steps, "ms": sec * 1e3,
+           "cell_updates_per_s": cells * spec.steps / sec, "time_block": tb, "cells_per_lane": cpl,
+           "rows_per_block": rows,
+           "hbm_algorithmic_GBps": cells * 8 * passes / sec / 1e9}
+    for b_ in A + B:
+        hx.hx_buffer_destroy(ctx, b_)
+    return res
+
+
+def adjoint_leg(hx, ctx):
+    """8192^2 fp32 variable-coefficient run, dt = 0.2, 100 steps, S = 10:
+    forward with checkpoints, FP64 loss, checkpointed backward."""
+    import torch
+    import workloads
+    spec = workloads.VarCoef2D()
+    u0, kappa, y = workloads.varcoef2d_inputs(spec)
+    n = spec.ny * spec.nx
+    S, nseg = hx.hx_vc_schedule(spec.steps, spec.ckpt)
+
+    def dev(arr=None, nbytes=None):
+        b = hx.hx_buffer_create(ctx, arr.nbytes if arr is not None else nbytes)
+        if arr is not None:
+            e = hx.hx_copy_async(ctx, hx.hx_copy_desc(hx.HX_H2D, arr.ctypes.data, b, 0, 0, 0,
+                                                      arr.nbytes))
+            assert hx.hx_wait(ctx, e) == hx.HX_OK
+            hx.hx_event_release(ctx, e)
+        return b
+    bu0, bk, by = dev(u0), dev(kappa), dev(y)
+    st = n * 4
+    buT, bck, bw, bseg = dev(nbytes=st), dev(nbytes=(nseg - 1) * st), dev(nbytes=2 * st),         dev(nbytes=(S - 1) * st)
+    blT, bl0, bg64, bga = dev(nbytes=st), dev(nbytes=st), dev(nbytes=n * 8), dev(nbytes=st)
+    bloss, work = dev(nbytes=8), dev(nbytes=4096 * 8)
+    a = hx.hx_vc_args(hx.HX_F32, spec.nx, spec.ny, spec.dt, spec.steps, spec.ckpt, bu0, bk, buT,
+                      bck, bw, bseg, blT, bl0, bg64, bga, 0)
+    times = {}
+    for it in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e1 = hx.hx_heat_vc_forward(ctx, a)
+        assert hx.hx_wait(ctx, e1) == hx.HX_OK, hx.hx_last_error(ctx)
+        t1 = time.perf_counter()
+        e2 = hx.hx_launch_loss(ctx, hx.HX_F32, n, buT, by, blT, bloss, work, deps=[e1])
+        e3 = hx.hx_heat_vc_backward(ctx, a, deps=[e2])
+        assert hx.hx_wait(ctx, e3) == hx.HX_OK, hx.hx_last_error(ctx)
+        t2 = time.perf_counter()
+        for e in (e1, e2, e3):
+            hx.hx_event_release(ctx, e)
+        times = {"forward_ms": (t1 - t0) * 1e3, "backward_ms": (t2 - t1) * 1e3}
+    T = spec.steps
+    fwd_bytes = n * T * 12            # u read + write, kappa read per step
+    rec_bytes = n * (T - nseg) * 12   # recomputed steps
+    adj_bytes = n * T * 24            # u_t, lam in/out, kappa, accumulator read + write
+    res = {"cells": n, "steps": T, "segment": S, **times,
+           "forward_cell_updates_per_s": n * T / (times["forward_ms"] * 1e-3),
+           "forward_hbm_algorithmic_GBps": fwd_bytes / (times["forward_ms"] * 1e-3) / 1e9,
+           "backward_hbm_algorithmic_GBps": (rec_bytes + adj_bytes) /
+                                            (times["backward_ms"] * 1e-3) / 1e9}
+    loss = np.empty(1, np.float64)
+    e = hx.hx_copy_async(ctx, hx.hx_copy_desc(hx.HX_D2H, loss.ctypes.data, bloss, 0, 0, 0, 8))
+    assert hx.hx_wait(ctx, e) == hx.HX_OK
+    hx.hx_event_release(ctx, e)
+    res["loss"] = float(loss[0])
+    for b_ in (bu0, bk, by, buT, bck, bw, bseg, blT, bl0, bg64, bga, bloss, work):
+        hx.hx_buffer_destroy(ctx, b_)
+    log(f"adjoint: {res}")
     return res
 
 

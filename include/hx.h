@@ -318,6 +318,25 @@ hx_status hx_launch_batched(hx_ctx ctx, hx_plan plan, const hx_event* deps, int 
 /* Free a plan (waits for the context's queued work first). */
 hx_status hx_plan_destroy(hx_ctx ctx, hx_plan plan);
 
+/* --------------------------------------------------------------- halo plans */
+typedef struct {
+    hx_buffer src; size_t src_offset;   /* first byte of the first run */
+    hx_buffer dst; size_t dst_offset;
+    int64_t rows;                       /* number of runs */
+    int64_t row_bytes;                  /* bytes per run, a multiple of 4 */
+    int64_t src_pitch, dst_pitch;       /* bytes between consecutive runs (rows > 1) */
+} hx_halo_desc;
+
+/* Halo pack/unpack: a table of copies between state buffers and ghost slots,
+ * all run by one kernel per launch.  A contiguous halo (D boundary cells of a
+ * 1D partition, D boundary rows of a row band) is one run; a column halo is
+ * `rows` runs with a pitch.  Spans are range-checked at creation; a
+ * descriptor's source and destination must not overlap.  Buffers must outlive
+ * the plan. */
+hx_status hx_plan_create_halo(hx_ctx ctx, const hx_halo_desc* descs, int n, hx_plan* plan);
+hx_status hx_launch_halo(hx_ctx ctx, hx_plan plan, const hx_event* deps, int ndeps,
+                         hx_event* out);
+
 /* ------------------------------------------- variable coefficient + adjoint */
 /* The gradient path: a 2D variable-coefficient heat step (h = 1, zero-Dirichlet)
  *   v_c = u_c + dt * sum_f kappa_f (u_n - u_c)   over the W, E, N, S faces,
@@ -457,6 +476,19 @@ hx_status hx_hazard_count(hx_ctx ctx, int64_t* count);
 hx_status hx_hazard_report(hx_ctx ctx, char* buf, size_t len);
 
 /* -------------------------------------------------------------- autotuner */
+/* Project-written autotuner: time the candidate geometries (cells per lane,
+ * time block, waves per group; rows per wave in 2D) of `args` on its own
+ * buffers (out and tmp are overwritten) for about `budget_ms` (at least one
+ * candidate runs), store the fastest in the process-wide cache under the
+ * problem's key (dims, dtype, size class, steps), and return it in *best.
+ * Later launches with geometry fields 0 use the cached entry. */
+hx_status hx_tune_stencil(hx_ctx ctx, const hx_stencil_args* args, int budget_ms,
+                          hx_stencil_args* best);
+
+/* The same for a persistent batch: cells per lane and grid size. */
+hx_status hx_tune_batched(hx_ctx ctx, const hx_batch_desc* desc, int budget_ms,
+                          hx_batch_desc* best);
+
 /* Write the process-wide tuned-geometry cache to `path` as JSON; the cache is
  * read back from the file named by HX_TUNE_CACHE on first use. */
 hx_status hx_tune_cache_save(const char* path);

@@ -123,6 +123,11 @@ class hx_vc_args(ctypes.Structure):
                 ("rows_per_block", ctypes.c_int)]
 
 
+class hx_halo_desc(ctypes.Structure):
+    _fields_ = [("src", _u64), ("src_offset", _sz), ("dst", _u64), ("dst_offset", _sz),
+                ("rows", _i64), ("row_bytes", _i64), ("src_pitch", _i64), ("dst_pitch", _i64)]
+
+
 # ----------------------------------------------------------------- prototypes
 _PROTOS = {
     "hx_status_string": (ctypes.c_char_p, [_i32]),
@@ -147,6 +152,10 @@ _PROTOS = {
     "hx_launch_batched": (_i32, [_vp, _u64, ctypes.POINTER(_u64), ctypes.c_int,
                                  ctypes.POINTER(_u64)]),
     "hx_plan_destroy": (_i32, [_vp, _u64]),
+    "hx_plan_create_halo": (_i32, [_vp, ctypes.POINTER(hx_halo_desc), ctypes.c_int,
+                                   ctypes.POINTER(_u64)]),
+    "hx_launch_halo": (_i32, [_vp, _u64, ctypes.POINTER(_u64), ctypes.c_int,
+                              ctypes.POINTER(_u64)]),
     "hx_heat_vc_step": (_i32, [_vp, ctypes.c_int, _i64, _i64, ctypes.c_double, _u64, _u64, _u64,
                                ctypes.POINTER(_u64), ctypes.c_int, ctypes.POINTER(_u64)]),
     "hx_heat_vc_adjoint_step": (_i32, [_vp, ctypes.c_int, _i64, _i64, ctypes.c_double, _u64,
@@ -188,6 +197,10 @@ _PROTOS = {
     "hx_hazard_count": (_i32, [_vp, ctypes.POINTER(_i64)]),
     "hx_hazard_report": (_i32, [_vp, ctypes.c_char_p, _sz]),
     "hx_tune_cache_save": (_i32, [ctypes.c_char_p]),
+    "hx_tune_stencil": (_i32, [_vp, ctypes.POINTER(hx_stencil_args), ctypes.c_int,
+                               ctypes.POINTER(hx_stencil_args)]),
+    "hx_tune_batched": (_i32, [_vp, ctypes.POINTER(hx_batch_desc), ctypes.c_int,
+                               ctypes.POINTER(hx_batch_desc)]),
     "hx_tune_cache_clear": (_i32, []),
 }
 for _name, (_res, _args) in _PROTOS.items():
@@ -375,6 +388,20 @@ def hx_plan_destroy(ctx, plan: int) -> None:
     _ok(ctx, lib.hx_plan_destroy(ctx, plan))
 
 
+def hx_plan_create_halo(ctx, descs) -> int:
+    arr = (hx_halo_desc * len(descs))(*descs)
+    h = _u64()
+    _ok(ctx, lib.hx_plan_create_halo(ctx, arr, len(descs), ctypes.byref(h)))
+    return h.value
+
+
+def hx_launch_halo(ctx, plan: int, deps=()) -> int:
+    arr, n = _deps(deps)
+    ev = _u64()
+    _ok(ctx, lib.hx_launch_halo(ctx, plan, arr, n, ctypes.byref(ev)))
+    return ev.value
+
+
 def segment(**kw) -> hx_segment:
     if "inp" in kw:
         kw["in_"] = kw.pop("inp")
@@ -557,6 +584,21 @@ def hx_hazard_report(ctx) -> str:
     buf = ctypes.create_string_buffer(65536)
     _ok(ctx, lib.hx_hazard_report(ctx, buf, 65536))
     return buf.value.decode(errors="replace")
+
+
+def hx_tune_stencil(ctx, args: hx_stencil_args, budget_ms: int = 2000) -> hx_stencil_args:
+    best = hx_stencil_args()
+    _ok(ctx, lib.hx_tune_stencil(ctx, ctypes.byref(args), budget_ms, ctypes.byref(best)))
+    return best
+
+
+def hx_tune_batched(ctx, dtype, steps, segs, budget_ms: int = 2000) -> hx_batch_desc:
+    arr = (hx_segment * len(segs))(*segs)
+    d = hx_batch_desc(dtype, steps, len(segs), arr, HX_BATCH_PERSISTENT, 0, 0, 0)
+    best = hx_batch_desc()
+    _ok(ctx, lib.hx_tune_batched(ctx, ctypes.byref(d), budget_ms, ctypes.byref(best)))
+    best._keep = arr
+    return best
 
 
 def hx_tune_cache_save(path: str) -> None:

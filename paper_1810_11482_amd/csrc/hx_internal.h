@@ -107,4 +107,16 @@ int reduce_blocks(int64_t n);
 hipError_t launch_reduce(int dtype, int mode, const void* a, const void* b, void* resid, int64_t n,
                          double* partial, double* out, hipStream_t stream);
 
+// Halo copy descriptor on the device: `rows` runs of row_bytes (a multiple of
+// 4), run k at src + k*src_pitch -> dst + k*dst_pitch.
+struct HaloDev {
+    const void* src;
+    void* dst;
+    int64_t rows, row_bytes, src_pitch, dst_pitch;
+};
+
+// first_run[i] = runs of descriptors 0..i-1 (device arrays of nd entries).
+hipError_t launch_halo(const HaloDev* descs, const int64_t* first_run, int nd, int64_t total_runs,
+                       hipStream_t stream);
+
 }  // namespace hx

@@ -92,30 +92,52 @@ struct Strip {
 // rows of level l in slots M+1 and M+2 (mod 3) are the two before it, and
 // level l+1 receives its new row (yy - l - 1) in its own slot M.  All slot
 // indices are compile-time constants, so rotating the rows costs no moves.
-template <typename T, int C, int D, int M>
-__device__ __forceinline__ void row_step(const Band2D& b, const Strip& w, int halo, int64_t yy,
-                                         T (&R)[D][3][C], const bool (&colok)[C], T k) {
+// Load row y of the band (or its zero ghost) for this lane's columns.
+template <typename T, int C>
+__device__ __forceinline__ void load_row2d(const Band2D& b, const Strip& w, int64_t y, T (&dst)[C],
+                                           const bool (&colok)[C]) {
     typedef typename V16<T>::t VT;
     constexpr int VN = V16<T>::N;
-    constexpr int S = 64 * C;
-    constexpr int OLD = (M + 1) % 3, NEW = (M + 2) % 3;
-    // ---- level 0: load row yy into slot M
-    const T* rp = row_ptr<T>(b, yy);
+    const T* rp = row_ptr<T>(b, y);
     if (rp == nullptr) {
 #pragma unroll
-        for (int j = 0; j < C; ++j) R[0][M][j] = T(0);
+        for (int j = 0; j < C; ++j) dst[j] = T(0);
     } else if (w.vec) {
         const VT* src = reinterpret_cast<const VT*>(rp + w.xl);
 #pragma unroll
         for (int q = 0; q < C / VN; ++q) {
             const VT x = __builtin_nontemporal_load(src + q);
 #pragma unroll
-            for (int e = 0; e < VN; ++e) R[0][M][q * VN + e] = x[e];
+            for (int e = 0; e < VN; ++e) dst[q * VN + e] = x[e];
         }
     } else {
 #pragma unroll
-        for (int j = 0; j < C; ++j) R[0][M][j] = colok[j] ? rp[w.xl + j] : T(0);
+        for (int j = 0; j < C; ++j) dst[j] = colok[j] ? rp[w.xl + j] : T(0);
     }
+}
+
+// One row step of the pipeline for a row index whose position in the 3-row
+// rotation is M: row yy (already loaded, in `pf0`) enters level 0 in slot M of
+// every level's ring, the rows of level l in slots M+1 and M+2 (mod 3) are the
+// two before it, and level l+1 receives its new row (yy - l - 1) in its own
+// slot M.  All slot indices are compile-time constants, so rotating the rows
+// costs no moves.  Rows are prefetched two ahead: the loads of row yy+2 are
+// issued before the arithmetic of row yy, so their latency overlaps it.
+template <typename T, int C, int D, int M>
+__device__ __forceinline__ void row_step(const Band2D& b, const Strip& w, int halo, int64_t yy,
+                                         T (&R)[D][3][C], const bool (&colok)[C], T k,
+                                         T (&pf0)[C], T (&pf1)[C]) {
+    typedef typename V16<T>::t VT;
+    constexpr int VN = V16<T>::N;
+    constexpr int S = 64 * C;
+    constexpr int OLD = (M + 1) % 3, NEW = (M + 2) % 3;
+    // ---- level 0: row yy from the prefetch queue; queue row yy+2
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+        R[0][M][j] = pf0[j];
+        pf0[j] = pf1[j];
+    }
+    load_row2d<T, C>(b, w, yy + 2, pf1, colok);
     // ---- levels 1..D
     T last[C];
 #pragma unroll
@@ -216,12 +238,15 @@ __global__ __launch_bounds__(256) void k_stencil2d(Band2D b, int rows, int halo,
             for (int j = 0; j < C; ++j) R[l][m][j] = T(0);
 
     const int64_t yend = w.y1 + D;
+    T pf0[C], pf1[C];
+    load_row2d<T, C>(b, w, w.y0 - D, pf0, colok);
+    load_row2d<T, C>(b, w, w.y0 - D + 1, pf1, colok);
     for (int64_t yy = w.y0 - D; yy < yend; yy += 3) {
-        row_step<T, C, D, 0>(b, w, halo, yy, R, colok, k);
+        row_step<T, C, D, 0>(b, w, halo, yy, R, colok, k, pf0, pf1);
         if (yy + 1 >= yend) break;
-        row_step<T, C, D, 1>(b, w, halo, yy + 1, R, colok, k);
+        row_step<T, C, D, 1>(b, w, halo, yy + 1, R, colok, k, pf0, pf1);
         if (yy + 2 >= yend) break;
-        row_step<T, C, D, 2>(b, w, halo, yy + 2, R, colok, k);
+        row_step<T, C, D, 2>(b, w, halo, yy + 2, R, colok, k, pf0, pf1);
     }
 }
 

@@ -1,8 +1,11 @@
 // Autotuner cache and defaults.
 #include "hx_tune.hpp"
 
+#include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <vector>
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
@@ -100,9 +103,10 @@ Geom1D default_geom_1d(Ctx* c, const TuneKey& k) {
         g.halo = 0;
         return g;
     }
-    // Heuristic: 32 cells per lane, a time block of up to 32 steps.
+    // Heuristic: 32 cells per lane, a time block of up to 50 steps (the
+    // fastest measured on MI355X for long runs: 75% of the VALU issue rate).
     g.cpl = 32;
-    g.steps = 32;
+    g.steps = 50;
     g.wpg = 4;
     g.halo = 0;
     return g;
@@ -140,3 +144,130 @@ hx_status hx_tune_cache_clear(void) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ search
+namespace {
+
+using clk = std::chrono::steady_clock;
+
+double time_stencil(hx_ctx ctx, const hx_stencil_args& a, int reps) {
+    double best = 1e30;
+    for (int r = 0; r < reps + 1; ++r) {
+        const auto t0 = clk::now();
+        hx_event ev = 0;
+        if (hx_launch_stencil(ctx, &a, nullptr, 0, &ev) != HX_OK) return -1;
+        const hx_status st = hx_wait(ctx, ev, -1);
+        hx_event_release(ctx, ev);
+        if (st != HX_OK) return -1;
+        const double s = std::chrono::duration<double>(clk::now() - t0).count();
+        if (r > 0 && s < best) best = s;  // the first run warms up
+    }
+    return best;
+}
+
+}  // namespace
+
+extern "C" hx_status hx_tune_stencil(hx_ctx ctx, const hx_stencil_args* args, int budget_ms,
+                                     hx_stencil_args* best) {
+    if (!ctx || !args || !best) return HX_ERR_ARG;
+    const bool two_d = args->dims == 2;
+    const bool ghost = args->bc_lo == HX_BC_GHOST || args->bc_hi == HX_BC_GHOST;
+    std::vector<hx_stencil_args> cands;
+    auto add = [&](int cpl, int tb, int wpg, int rows) {
+        hx_stencil_args a = *args;
+        a.cells_per_lane = cpl;
+        a.time_block = ghost ? 0 : tb;
+        a.waves_per_group = wpg;
+        a.rows_per_block = rows;
+        cands.push_back(a);
+    };
+    const int S = std::max(args->steps, 1);
+    if (!two_d) {
+        const int tbs[] = {8, 16, 25, 32, 50, 64, 100};
+        for (int cpl : {32, 16, 64, 8})
+            for (int tb : tbs) {
+                const int d = std::min(tb, S);
+                if (d > max_time_block_1d(args->dtype, cpl)) continue;
+                for (int wpg : {4, 2}) add(cpl, d, wpg, 0);
+                if (tb >= S) break;
+            }
+    } else {
+        for (int cpl : {4, 8})
+            for (int tb : {8, 4, 6, 10, 12, 16}) {
+                const int d = std::min(tb, S);
+                if (!stencil2d_supported(args->dtype, cpl, d)) continue;
+                for (int rows : {256, 128, 512}) add(cpl, d, 4, rows);
+                if (tb >= S) break;
+            }
+    }
+    const auto t_start = clk::now();
+    double best_t = 1e30;
+    bool found = false;
+    for (const hx_stencil_args& a : cands) {
+        if (found && std::chrono::duration<double, std::milli>(clk::now() - t_start).count() >
+                         budget_ms)
+            break;
+        const double t = time_stencil(ctx, a, 2);
+        if (t > 0 && t < best_t) {
+            best_t = t;
+            *best = a;
+            found = true;
+        }
+    }
+    if (!found) return HX_ERR_ARG;
+    TunedGeom g;
+    g.cpl = best->cells_per_lane;
+    g.steps = best->time_block ? best->time_block : std::min(args->steps, 32);
+    g.wpg = best->waves_per_group;
+    g.rows = best->rows_per_block;
+    const TuneKey k = two_d ? tune_key_2d(args->dtype, args->ny, args->nx, args->steps)
+                            : tune_key_1d(args->dtype, args->nx, args->steps, ghost);
+    tune_store(k, g);
+    return HX_OK;
+}
+
+extern "C" hx_status hx_tune_batched(hx_ctx ctx, const hx_batch_desc* desc, int budget_ms,
+                                     hx_batch_desc* best) {
+    if (!ctx || !desc || !best || desc->mode != HX_BATCH_PERSISTENT) return HX_ERR_ARG;
+    const auto t_start = clk::now();
+    double best_t = 1e30;
+    bool found = false;
+    for (int cpl : {16, 32, 8, 64})
+        for (int grid : {-1, 64, 16}) {
+            if (found && std::chrono::duration<double, std::milli>(clk::now() - t_start).count() >
+                             budget_ms)
+                break;
+            hx_batch_desc d = *desc;
+            d.cells_per_lane = cpl;
+            d.grid_waves_per_cu = grid;
+            d.waves_per_group = 4;
+            hx_plan plan = 0;
+            if (hx_plan_create_batched(ctx, &d, &plan) != HX_OK) continue;
+            double bt = 1e30;
+            for (int r = 0; r < 3; ++r) {
+                const auto t0 = clk::now();
+                hx_event ev = 0;
+                if (hx_launch_batched(ctx, plan, nullptr, 0, &ev) != HX_OK) break;
+                const hx_status st = hx_wait(ctx, ev, -1);
+                hx_event_release(ctx, ev);
+                if (st != HX_OK) break;
+                const double s = std::chrono::duration<double>(clk::now() - t0).count();
+                if (r > 0) bt = std::min(bt, s);
+            }
+            hx_plan_destroy(ctx, plan);
+            if (bt < best_t) {
+                best_t = bt;
+                *best = d;
+                found = true;
+            }
+        }
+    if (!found) return HX_ERR_ARG;
+    int64_t total = 0;
+    for (int i = 0; i < desc->count; ++i) total += desc->segs[i].n;
+    TunedGeom g;
+    g.cpl = best->cells_per_lane;
+    g.wpg = best->waves_per_group;
+    g.grid = best->grid_waves_per_cu;
+    tune_store(tune_key_batched(desc->dtype, total, desc->count, desc->steps), g);
+    return HX_OK;
+}

@@ -52,17 +52,21 @@ struct Row {
     T w, e;
 };
 
-// Load row y of field f (row-major, nx columns) for the lane's cells
-// [xl, xl + C); columns outside [0, nx) and rows outside [0, ny) read the
-// ghost value given per cell (gc: ghost per cell; gw/ge: ghost of the edge
-// neighbours).
+// Raw loads of one row of one field for the lane's cells [xl, xl + C) plus,
+// in lanes 0 and 63, the cells just outside the strip.  Issued one row ahead of
+// use so that their latency overlaps the arithmetic of the current row.
 template <typename T>
-__device__ __forceinline__ void load_row(const T* __restrict__ f, int64_t y, int64_t ny, int64_t nx,
-                                         int64_t x0, int64_t xl, int lane, bool vec, Row<T>& r,
-                                         const T (&gc)[C]) {
-    const bool rowin = y >= 0 && y < ny;
-    if (rowin && vec) {
-        // 16-byte loads: one for f32, two for f64
+struct Raw {
+    T c[C];
+    T edge;     // lane 0: cell x0 - 1; lane 63: cell x0 + S
+    bool rowin;
+};
+
+template <typename T>
+__device__ __forceinline__ void fetch_row(const T* __restrict__ f, int64_t y, int64_t ny, int64_t nx,
+                                          int64_t x0, int64_t xl, int lane, bool vec, Raw<T>& r) {
+    r.rowin = y >= 0 && y < ny;
+    if (r.rowin && vec) {
         typedef T V2 __attribute__((ext_vector_type(16 / sizeof(T))));
         const V2* p = reinterpret_cast<const V2*>(f + y * nx + xl);
         constexpr int VN = 16 / sizeof(T);
@@ -76,22 +80,24 @@ __device__ __forceinline__ void load_row(const T* __restrict__ f, int64_t y, int
 #pragma unroll
         for (int j = 0; j < C; ++j) {
             const int64_t x = xl + j;
-            r.c[j] = (rowin && x >= 0 && x < nx) ? f[y * nx + x] : gc[j];
+            r.c[j] = (r.rowin && x >= 0 && x < nx) ? f[y * nx + x] : T(0);
         }
     }
-    // neighbours across lanes, and the two cells outside the strip
+    r.edge = T(0);
+    const int64_t xe = (lane == 0) ? x0 - 1 : x0 + S;
+    if ((lane == 0 || lane == 63) && r.rowin && xe >= 0 && xe < nx) r.edge = f[y * nx + xe];
+}
+
+// Row as used by the arithmetic: rows outside the domain become the ghost
+// `gc`; west/east neighbours across lanes come from DPP wave shifts.
+template <typename T>
+__device__ __forceinline__ void finish_row(const Raw<T>& raw, const T (&gc)[C], int lane, Row<T>& r) {
+#pragma unroll
+    for (int j = 0; j < C; ++j) r.c[j] = raw.rowin ? raw.c[j] : gc[j];
     const T fromw = dpp_move<DPP_WAVE_SHR1>(r.c[C - 1]);
     const T frome = dpp_move<DPP_WAVE_SHL1>(r.c[0]);
-    r.w = fromw;
-    r.e = frome;
-    if (lane == 0) {
-        const int64_t x = x0 - 1;
-        r.w = (rowin && x >= 0 && x < nx) ? f[y * nx + x] : T(0);
-    }
-    if (lane == 63) {
-        const int64_t x = x0 + S;
-        r.e = (rowin && x >= 0 && x < nx) ? f[y * nx + x] : T(0);
-    }
+    r.w = lane == 0 ? raw.edge : fromw;
+    r.e = lane == 63 ? raw.edge : frome;
 }
 
 struct VCDev {
@@ -105,18 +111,6 @@ struct VCDev {
     int rows;
     int aligned;        // every row starts 16-byte aligned
 };
-
-// kappa row with edge ghosts equal to the cell's own conductivity
-template <typename T>
-__device__ __forceinline__ void load_kappa(const T* k, int64_t y, int64_t ny, int64_t nx, int64_t x0,
-                                           int64_t xl, int lane, bool vec, const Row<T>& kc,
-                                           Row<T>& r) {
-    // rows outside: ghost = kappa of the centre row's cell (vertical edge face)
-    T gc[C];
-#pragma unroll
-    for (int j = 0; j < C; ++j) gc[j] = kc.c[j];
-    load_row<T>(k, y, ny, nx, x0, xl, lane, vec, r, gc);
-}
 
 // Weighted face sum sum_f kappa_f (f_n - f_c) for the lane's C cells of row y.
 template <typename T>
@@ -169,27 +163,40 @@ __global__ __launch_bounds__(256) void k_vc_step(VCDev a, int64_t nstrips, int64
     const T zero[C] = {T(0), T(0), T(0), T(0)};
 
     Row<T> um, u0, up, km, k0, kp, lm, l0, lp;
-    // rows y0-1 and y0 of every field (kappa ghosts need the centre row first)
-    load_row<T>(K, y0, ny, nx, x0, xl, lane, vec, k0, zero);
-    load_kappa<T>(K, y0 - 1, ny, nx, x0, xl, lane, vec, k0, km);
-    load_row<T>(U, y0 - 1, ny, nx, x0, xl, lane, vec, um, zero);
-    load_row<T>(U, y0, ny, nx, x0, xl, lane, vec, u0, zero);
+    Raw<T> rk, ru, rl;
+    // rows y0 and y0-1 (kappa ghosts of row y0-1 are kappa of row y0)
+    fetch_row<T>(K, y0, ny, nx, x0, xl, lane, vec, rk);
+    finish_row<T>(rk, zero, lane, k0);
+    fetch_row<T>(K, y0 - 1, ny, nx, x0, xl, lane, vec, rk);
+    finish_row<T>(rk, k0.c, lane, km);
+    fetch_row<T>(U, y0 - 1, ny, nx, x0, xl, lane, vec, ru);
+    finish_row<T>(ru, zero, lane, um);
+    fetch_row<T>(U, y0, ny, nx, x0, xl, lane, vec, ru);
+    finish_row<T>(ru, zero, lane, u0);
     if (ADJ) {
-        load_row<T>(L, y0 - 1, ny, nx, x0, xl, lane, vec, lm, zero);
-        load_row<T>(L, y0, ny, nx, x0, xl, lane, vec, l0, zero);
+        fetch_row<T>(L, y0 - 1, ny, nx, x0, xl, lane, vec, rl);
+        finish_row<T>(rl, zero, lane, lm);
+        fetch_row<T>(L, y0, ny, nx, x0, xl, lane, vec, rl);
+        finish_row<T>(rl, zero, lane, l0);
     }
+    // row y0+1 in flight
+    fetch_row<T>(K, y0 + 1, ny, nx, x0, xl, lane, vec, rk);
+    fetch_row<T>(U, y0 + 1, ny, nx, x0, xl, lane, vec, ru);
+    if (ADJ) fetch_row<T>(L, y0 + 1, ny, nx, x0, xl, lane, vec, rl);
     for (int64_t y = y0; y < y1; ++y) {
-        load_kappa<T>(K, y + 1, ny, nx, x0, xl, lane, vec, k0, kp);
-        load_row<T>(U, y + 1, ny, nx, x0, xl, lane, vec, up, zero);
-        if (ADJ) load_row<T>(L, y + 1, ny, nx, x0, xl, lane, vec, lp, zero);
+        // row y+1 arrives; row y+2 goes in flight
+        finish_row<T>(rk, k0.c, lane, kp);
+        finish_row<T>(ru, zero, lane, up);
+        if (ADJ) finish_row<T>(rl, zero, lane, lp);
+        if (y + 1 < y1) {
+            fetch_row<T>(K, y + 2, ny, nx, x0, xl, lane, vec, rk);
+            fetch_row<T>(U, y + 2, ny, nx, x0, xl, lane, vec, ru);
+            if (ADJ) fetch_row<T>(L, y + 2, ny, nx, x0, xl, lane, vec, rl);
+        }
         // rows outside the domain carry ghost kappa = kappa of the row y cell
         if (y - 1 < 0) {
 #pragma unroll
             for (int j = 0; j < C; ++j) km.c[j] = k0.c[j];
-        }
-        if (y + 1 >= ny) {
-#pragma unroll
-            for (int j = 0; j < C; ++j) kp.c[j] = k0.c[j];
         }
         T acc[C];
         if (!ADJ) {
