@@ -160,6 +160,7 @@ extern "C" hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* d, 
         sg.bc_hi = s.bc_hi;
         sg.hw = s.halo_width;
         sg.shift = tile_shift(pi, (int)es);
+        set_rate_1d(sg, d->steps);
         bp->segs.push_back(sg);
         bp->tmps.push_back(pt);
     }

@@ -20,7 +20,38 @@ struct Seg1D {
     int32_t hw;            // halo width of the GHOST sides
     int32_t shift;         // tile grid offset: tiles start at t*wout - shift, chosen so
                            // that interior tiles of `in` start 16-byte aligned
+    // Rescaled update, filled by set_rate_1d for the pass's step count:
+    // period > 0 selects it, 0 the direct form.
+    int32_t period;        // steps between rescales
+    double beta;           // r / (1 - 2r)
+    double alpha_p;        // (1 - 2r)^period
+    double alpha_rem;      // (1 - 2r)^(steps mod period)
 };
+
+// Rescaled form of the step.  With a = 1 - 2r the step is
+// u' = a u + r (u_l + u_r); carrying w = u / a^k after k steps turns it into
+// w' = w + (r/a)(w_l + w_r), one add and one fma per cell instead of three
+// operations.  The state is multiplied by a^period every `period` steps and by
+// a^(steps mod period) at the end, so it never grows beyond 2^16 times u.
+// Used for 1/4 <= a <= 1 (0 <= r <= 3/8); other rates take the direct form.
+inline void set_rate_1d(Seg1D& s, int steps) {
+    const double a = 1.0 - 2.0 * s.r;
+    s.period = 0;
+    s.beta = s.alpha_p = s.alpha_rem = 1.0;
+    if (!(a >= 0.25 && a <= 1.0)) return;
+    int p = 0;
+    double ap = 1.0;
+    while (p < 32 && ap * a >= 1.0 / 65536.0) {
+        ap *= a;
+        ++p;
+    }
+    double ar = 1.0;
+    for (int i = 0; i < (steps > 0 ? steps % p : 0); ++i) ar *= a;
+    s.period = p;
+    s.beta = s.r / a;
+    s.alpha_p = ap;
+    s.alpha_rem = ar;
+}
 
 // Tile-grid shift that makes in + (t*wout - shift - halo) 16-byte aligned for
 // every t (wout and halo are multiples of the vector width).

@@ -16,9 +16,11 @@
 // layout.  HBM traffic per pass is one read and one write of every cell plus
 // 2*halo/(64*C) of re-read context.
 //
-// Per cell-step the arithmetic is s = l + rt; d = fma(-2, c, s);
-// c' = fma(r, d, c), written with explicit fma so every kernel in this library
-// that advances a cell does so with the same rounding.
+// Arithmetic.  For 0 <= r <= 3/8 the tile is advanced in the rescaled form
+// w' = fma(r/(1-2r), l + rt, w) with a periodic rescale (set_rate_1d): one add
+// and one fma per cell-step.  Other rates use s = l + rt; d = fma(-2, c, s);
+// c' = fma(r, d, c).  Either way the result of a pass depends only on its step
+// count, not on the tile geometry.
 #include <hip/hip_runtime.h>
 
 #include "hx_internal.h"
@@ -105,6 +107,36 @@ __device__ __forceinline__ void step_tile(T (&a)[C], T k, bool zero_lo, bool zer
     }
 }
 
+// One step of the rescaled form (see set_rate_1d): w' = w + b (w_l + w_r).
+// Same register discipline as step_tile: one add and one fma per cell.
+template <typename T, int C>
+__device__ __forceinline__ void step_tile_scaled(T (&a)[C], T b, bool zero_lo, bool zero_hi,
+                                                 int64_t lbase, int64_t n) {
+    const T left = dpp_move<DPP_WAVE_SHR1>(a[C - 1]);
+    const T right = dpp_move<DPP_WAVE_SHL1>(a[0]);
+    T s_cur = left + (C > 1 ? a[1] : right);
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+        T s_next = T(0);
+        if (j + 1 < C) s_next = a[j] + (j + 2 < C ? a[j + 2] : right);
+        a[j] = fmaT(b, s_cur, a[j]);
+        s_cur = s_next;
+    }
+    if (zero_lo || zero_hi) {
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            const int64_t g = lbase + j;
+            if ((zero_lo && g < 0) || (zero_hi && g >= n)) a[j] = T(0);
+        }
+    }
+}
+
+template <typename T, int C>
+__device__ __forceinline__ void scale_tile(T (&a)[C], T f) {
+#pragma unroll
+    for (int j = 0; j < C; ++j) a[j] *= f;
+}
+
 __device__ __forceinline__ bool aligned16(const void* p) {
     return (reinterpret_cast<uintptr_t>(p) & 15u) == 0;
 }
@@ -172,10 +204,24 @@ __device__ __forceinline__ void tile1d(const Seg1D& s, int64_t tile, int steps, 
     }
 
     const int64_t lbase = base + (int64_t)lane * C;
-    const T k = static_cast<T>(s.r);
     const bool zero_lo = s.bc_lo == BC_DIRICHLET0 && base < 0;
     const bool zero_hi = s.bc_hi == BC_DIRICHLET0 && base + W > n;
-    for (int t = 0; t < steps; ++t) step_tile<T, C>(v, k, zero_lo, zero_hi, lbase, n);
+    if (s.period > 0) {
+        const T b = static_cast<T>(s.beta);
+        const T ap = static_cast<T>(s.alpha_p);
+        int since = 0;
+        for (int t = 0; t < steps; ++t) {
+            step_tile_scaled<T, C>(v, b, zero_lo, zero_hi, lbase, n);
+            if (++since == s.period) {
+                since = 0;
+                scale_tile<T, C>(v, ap);
+            }
+        }
+        if (since) scale_tile<T, C>(v, static_cast<T>(s.alpha_rem));
+    } else {
+        const T k = static_cast<T>(s.r);
+        for (int t = 0; t < steps; ++t) step_tile<T, C>(v, k, zero_lo, zero_hi, lbase, n);
+    }
 
     // ---- registers -> LDS -> HBM (coalesced), inner cells only
     __builtin_amdgcn_wave_barrier();
@@ -285,6 +331,7 @@ template <typename T>
 hipError_t launch_single(const Seg1D& s0, const Geom1D& g, hipStream_t st) {
     Seg1D s = s0;
     s.shift = tile_shift(s.in, sizeof(T));
+    set_rate_1d(s, g.steps);
     const int64_t ntiles = tiles_1d(s, g);
     const dim3 block(64 * g.wpg);
     const dim3 grid((unsigned)((ntiles + g.wpg - 1) / g.wpg));

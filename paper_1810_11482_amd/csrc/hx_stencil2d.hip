@@ -116,36 +116,40 @@ __device__ __forceinline__ void load_row2d(const Band2D& b, const Strip& w, int6
     }
 }
 
-// One row step of the pipeline for a row index whose position in the 3-row
-// rotation is M: row yy (already loaded, in `pf0`) enters level 0 in slot M of
-// every level's ring, the rows of level l in slots M+1 and M+2 (mod 3) are the
-// two before it, and level l+1 receives its new row (yy - l - 1) in its own
-// slot M.  All slot indices are compile-time constants, so rotating the rows
-// costs no moves.  Rows are prefetched two ahead: the loads of row yy+2 are
-// issued before the arithmetic of row yy, so their latency overlaps it.
-template <typename T, int C, int D, int M>
+// Level-0 rows live in a ring of Q rows (Q a multiple of 3): rows yy-2 .. yy
+// are the pipeline's input window and rows yy+1 .. yy+Q-3 are loads in flight,
+// so Q-3 rows are prefetched ahead of their use.  Row y sits in slot
+// (y - ystart) mod Q.
+constexpr int ring_rows() { return 6; }
+
+// One row step of the pipeline for the row yy whose ring position is M
+// (compile-time, the row loop is unrolled Q times): the load of row yy+Q-3 is
+// issued into the slot of row yy-3, no longer needed; then level l+1 (l =
+// 0..D-1) produces row yy-l-1 from its three level-l rows.  Level 0 reads the
+// Q-row ring, levels 1..D-1 keep their last three rows in a three-slot ring
+// at position M mod 3.  Every slot index is a compile-time constant, so
+// rotating rows costs no register moves.
+//
+// EDGE = false is the interior form: the wave's strip lies inside [0, nx) and
+// none of the rows it produces is a zero-Dirichlet ghost, so no cell is masked
+// and each level is straight-line code (which also lets the compiler fold the
+// DPP shifts into the adds).
+template <typename T, int C, int D, int Q, int M, bool EDGE>
 __device__ __forceinline__ void row_step(const Band2D& b, const Strip& w, int halo, int64_t yy,
-                                         T (&R)[D][3][C], const bool (&colok)[C], T k,
-                                         T (&pf0)[C], T (&pf1)[C]) {
+                                         int64_t yend, T (&Z)[Q][C], T (&R)[D][3][C],
+                                         const bool (&colok)[C], T k) {
     typedef typename V16<T>::t VT;
     constexpr int VN = V16<T>::N;
     constexpr int S = 64 * C;
-    constexpr int OLD = (M + 1) % 3, NEW = (M + 2) % 3;
-    // ---- level 0: row yy from the prefetch queue; queue row yy+2
-#pragma unroll
-    for (int j = 0; j < C; ++j) {
-        R[0][M][j] = pf0[j];
-        pf0[j] = pf1[j];
-    }
-    load_row2d<T, C>(b, w, yy + 2, pf1, colok);
-    // ---- levels 1..D
+    constexpr int M3 = M % 3, OLD = (M3 + 1) % 3, NEW = (M3 + 2) % 3;
+    if (yy + Q - 3 < yend) load_row2d<T, C>(b, w, yy + Q - 3, Z[(M + Q - 3) % Q], colok);
     T last[C];
 #pragma unroll
     for (int l = 0; l < D; ++l) {
         const int64_t yo = yy - l - 1;  // row produced at level l+1
-        const T* cn = R[l][NEW];        // row yo at level l (centre)
-        const T* no = R[l][OLD];        // row yo - 1 (north)
-        const T* so = R[l][M];          // row yo + 1 (south)
+        const T* cn = l == 0 ? Z[(M + Q - 1) % Q] : R[l][NEW];  // row yo at level l
+        const T* no = l == 0 ? Z[(M + Q - 2) % Q] : R[l][OLD];  // row yo - 1
+        const T* so = l == 0 ? Z[M] : R[l][M3];                 // row yo + 1
         const T left = dpp_move<DPP_WAVE_SHR1>(cn[C - 1]);
         const T right = dpp_move<DPP_WAVE_SHL1>(cn[0]);
         T nw[C];
@@ -158,16 +162,18 @@ __device__ __forceinline__ void row_step(const Band2D& b, const Strip& w, int ha
             const T d = fmaT(T(-4), c, t);
             nw[j] = fmaT(k, d, c);
         }
-        if (zero_row(b, yo)) {
+        if constexpr (EDGE) {
+            if (zero_row(b, yo)) {
 #pragma unroll
-            for (int j = 0; j < C; ++j) nw[j] = T(0);
-        } else if (!w.xin) {
+                for (int j = 0; j < C; ++j) nw[j] = T(0);
+            } else if (!w.xin) {
 #pragma unroll
-            for (int j = 0; j < C; ++j) nw[j] = colok[j] ? nw[j] : T(0);
+                for (int j = 0; j < C; ++j) nw[j] = colok[j] ? nw[j] : T(0);
+            }
         }
         if (l + 1 < D) {
 #pragma unroll
-            for (int j = 0; j < C; ++j) R[l + 1 < D ? l + 1 : 0][M][j] = nw[j];
+            for (int j = 0; j < C; ++j) R[l + 1 < D ? l + 1 : 0][M3][j] = nw[j];
         } else {
 #pragma unroll
             for (int j = 0; j < C; ++j) last[j] = nw[j];
@@ -201,12 +207,187 @@ __device__ __forceinline__ void row_step(const Band2D& b, const Strip& w, int ha
     }
 }
 
-template <typename T, int C, int D>
+// ---------------------------------------------------------------------------
+// Static-count form, for bands whose rows are all 16-byte aligned and whose
+// size is under 2 GiB (32-bit buffer offsets).  Every row step issues exactly
+// one vector load per lane (the prefetch; rows past the chunk are clamped to
+// its last row) and, once the pipeline is full, exactly one vector store per
+// lane.  Lanes that must not store (halo columns, columns past nx) store
+// through a buffer resource with an out-of-range offset, which the hardware
+// drops, so no memory operation sits under a branch or an exec mask.  With
+// straight-line memory operations the compiler's wait counts cover only the
+// row being consumed, and Q-3 rows stay in flight behind the arithmetic.
+//
+// EDGE waves (a strip reaching past [0, nx), or rows that are zero-Dirichlet
+// ghosts) run the same code plus selects: zero rows and columns outside
+// [0, nx) are loaded from a valid clamped address and replaced by 0, and every
+// level re-zeroes them.
+template <typename T, int C>
+struct FastIO {
+    const T* in;
+    const T* top;
+    const T* bot;
+    int64_t nx, ny, hw;
+    int64_t ylo, yhi;                   // clamp range of level-0 rows
+    int64_t xload[C / V16<T>::N];       // column of each lane vector's load (clamped into the row)
+    bool top_ghost, bot_ghost;          // top/bottom rows come from halo buffers
+    __amdgpu_buffer_rsrc_t out;         // the band's output, bounds-checked
+    uint32_t off[C / V16<T>::N];        // byte offset of each lane vector, or out of range
+    bool colin[C / V16<T>::N];          // lane vector inside [0, nx)
+};
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int BUF_DWORD3 = 0x00020000;  // raw 32-bit buffer (gfx9 family)
+constexpr uint32_t OOB_OFFSET = 0x7ffffff0u;
+
+// Row y is a zero ghost: outside the band on a zero-Dirichlet side, or past
+// the supplied halo rows.
+template <typename T, int C>
+__device__ __forceinline__ bool zero_row_fast(const FastIO<T, C>& io, int64_t y) {
+    return (y < 0 && (!io.top_ghost || y < -io.hw)) ||
+           (y >= io.ny && (!io.bot_ghost || y >= io.ny + io.hw));
+}
+
+template <typename T, int C, bool EDGE>
+__device__ __forceinline__ void load_fast(const FastIO<T, C>& io, int64_t y, T (&dst)[C]) {
+    typedef typename V16<T>::t VT;
+    constexpr int VN = V16<T>::N;
+    y = y < io.ylo ? io.ylo : (y > io.yhi ? io.yhi : y);
+    const bool zr = EDGE && zero_row_fast(io, y);
+    const int64_t ys = zr ? 0 : y;
+    const T* rp = ys < 0 ? io.top + (io.hw + ys) * io.nx
+                         : (ys < io.ny ? io.in + ys * io.nx : io.bot + (ys - io.ny) * io.nx);
+#pragma unroll
+    for (int q = 0; q < C / VN; ++q) {
+        const VT x = __builtin_nontemporal_load(reinterpret_cast<const VT*>(rp + io.xload[q]));
+#pragma unroll
+        for (int e = 0; e < VN; ++e)
+            dst[q * VN + e] = (EDGE && (zr || !io.colin[q])) ? T(0) : x[e];
+    }
+}
+
+template <typename T, int C>
+__device__ __forceinline__ void store_fast(const FastIO<T, C>& io, int64_t y, const T (&v)[C]) {
+    typedef typename V16<T>::t VT;
+    constexpr int VN = V16<T>::N;
+    const uint32_t row = (uint32_t)(y * io.nx * (int64_t)sizeof(T));
+#pragma unroll
+    for (int q = 0; q < C / VN; ++q) {
+        VT x;
+#pragma unroll
+        for (int e = 0; e < VN; ++e) x[e] = v[q * VN + e];
+        u32x4 bits;
+        __builtin_memcpy(&bits, &x, sizeof(bits));
+        __builtin_amdgcn_raw_buffer_store_b128(bits, io.out, (int)(io.off[q] + row), 0, 0);
+    }
+}
+
+template <typename T, int C, int D, int Q, int M, bool STORE, bool EDGE>
+__device__ __forceinline__ void row_step_fast(const FastIO<T, C>& io, int64_t yy, T (&Z)[Q][C],
+                                              T (&R)[D][3][C], T k) {
+    constexpr int VN = V16<T>::N;
+    constexpr int M3 = M % 3, OLD = (M3 + 1) % 3, NEW = (M3 + 2) % 3;
+    load_fast<T, C, EDGE>(io, yy + Q - 3, Z[(M + Q - 3) % Q]);
+    T last[C];
+#pragma unroll
+    for (int l = 0; l < D; ++l) {
+        const T* cn = l == 0 ? Z[(M + Q - 1) % Q] : R[l][NEW];
+        const T* no = l == 0 ? Z[(M + Q - 2) % Q] : R[l][OLD];
+        const T* so = l == 0 ? Z[M] : R[l][M3];
+        const T left = dpp_move<DPP_WAVE_SHR1>(cn[C - 1]);
+        const T right = dpp_move<DPP_WAVE_SHL1>(cn[0]);
+        T* dst = l + 1 < D ? R[l + 1 < D ? l + 1 : 0][M3] : last;
+        const bool zr = EDGE && zero_row_fast(io, yy - l - 1);
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            const T c = cn[j];
+            const T we = (j > 0 ? cn[j - 1] : left) + (j + 1 < C ? cn[j + 1] : right);
+            const T ns = no[j] + so[j];
+            const T t = ns + we;
+            const T d = fmaT(T(-4), c, t);
+            const T v = fmaT(k, d, c);
+            dst[j] = (EDGE && (zr || !io.colin[j / VN])) ? T(0) : v;
+        }
+    }
+    if constexpr (STORE) store_fast<T, C>(io, yy - D, last);
+}
+
+// N consecutive row steps starting at ring position M.  Steps that store
+// stop at the chunk's end.
+template <typename T, int C, int D, int Q, int M, int N, bool STORE, bool EDGE>
+__device__ __forceinline__ void steps_fast(const FastIO<T, C>& io, int64_t& yy, int64_t yend,
+                                           T (&Z)[Q][C], T (&R)[D][3][C], T k) {
+    if constexpr (N > 0) {
+        if (STORE && yy >= yend) return;
+        row_step_fast<T, C, D, Q, M, STORE, EDGE>(io, yy, Z, R, k);
+        ++yy;
+        steps_fast<T, C, D, Q, (M + 1) % Q, N - 1, STORE, EDGE>(io, yy, yend, Z, R, k);
+    }
+}
+
+// Rows ystart .. ystart+2D-1 fill the pipeline (nothing to store yet); from
+// then on every row step stores row yy - D, an output row of the chunk.
+template <typename T, int C, int D, int Q, bool EDGE>
+__device__ __forceinline__ void stream_rows_fast(const FastIO<T, C>& io, int64_t ystart,
+                                                 int64_t yend, T (&Z)[Q][C], T (&R)[D][3][C],
+                                                 T k) {
+    constexpr int W = 2 * D, WF = W / Q, WR = W % Q;
+#pragma unroll
+    for (int m = 0; m < Q - 3; ++m) load_fast<T, C, EDGE>(io, ystart + m, Z[m]);
+    int64_t yy = ystart;
+    for (int i = 0; i < WF; ++i) steps_fast<T, C, D, Q, 0, Q, false, EDGE>(io, yy, yend, Z, R, k);
+    steps_fast<T, C, D, Q, 0, WR, false, EDGE>(io, yy, yend, Z, R, k);
+    while (yy < yend) steps_fast<T, C, D, Q, WR, Q, true, EDGE>(io, yy, yend, Z, R, k);
+}
+
+// The row loop of the general form, unrolled Q times so that every ring slot
+// index is a compile-time constant.
+template <typename T, int C, int D, int Q, bool EDGE>
+__device__ __forceinline__ void stream_rows(const Band2D& b, const Strip& w, int halo,
+                                            int64_t ystart, int64_t yend, T (&Z)[Q][C],
+                                            T (&R)[D][3][C], const bool (&colok)[C], T k) {
+#pragma unroll
+    for (int m = 0; m < Q - 3; ++m) {
+        if (ystart + m < yend) {
+            load_row2d<T, C>(b, w, ystart + m, Z[m], colok);
+        } else {
+#pragma unroll
+            for (int j = 0; j < C; ++j) Z[m][j] = T(0);
+        }
+    }
+    for (int64_t yy = ystart; yy < yend; yy += Q) {
+        row_step<T, C, D, Q, 0, EDGE>(b, w, halo, yy, yend, Z, R, colok, k);
+        if (yy + 1 >= yend) break;
+        row_step<T, C, D, Q, 1, EDGE>(b, w, halo, yy + 1, yend, Z, R, colok, k);
+        if (yy + 2 >= yend) break;
+        row_step<T, C, D, Q, 2, EDGE>(b, w, halo, yy + 2, yend, Z, R, colok, k);
+        if (yy + 3 >= yend) break;
+        row_step<T, C, D, Q, 3 % Q, EDGE>(b, w, halo, yy + 3, yend, Z, R, colok, k);
+        if (yy + 4 >= yend) break;
+        row_step<T, C, D, Q, 4 % Q, EDGE>(b, w, halo, yy + 4, yend, Z, R, colok, k);
+        if (yy + 5 >= yend) break;
+        row_step<T, C, D, Q, 5 % Q, EDGE>(b, w, halo, yy + 5, yend, Z, R, colok, k);
+        if constexpr (Q > 6) {
+            if (yy + 6 >= yend) break;
+            row_step<T, C, D, Q, 6 % Q, EDGE>(b, w, halo, yy + 6, yend, Z, R, colok, k);
+            if (yy + 7 >= yend) break;
+            row_step<T, C, D, Q, 7 % Q, EDGE>(b, w, halo, yy + 7, yend, Z, R, colok, k);
+            if (yy + 8 >= yend) break;
+            row_step<T, C, D, Q, 8 % Q, EDGE>(b, w, halo, yy + 8, yend, Z, R, colok, k);
+        }
+    }
+}
+
+// FAST = true: the static-count form (the host checks alignment and size);
+// FAST = false: the general form with per-row boundary handling.
+template <typename T, int C, int D, bool FAST>
 __global__ __launch_bounds__(256) void k_stencil2d(Band2D b, int rows, int halo, int64_t nstrips,
                                                    int64_t nwaves) {
     constexpr int VN = V16<T>::N;
     constexpr int S = 64 * C;
+    constexpr int Q = ring_rows();
     static_assert(C % VN == 0, "columns per lane must be a multiple of the vector width");
+    static_assert(Q % 3 == 0 && Q >= 6, "the level-0 ring must be a multiple of 3 rows");
     const int wpg = blockDim.x >> 6;
     const int64_t wave = (int64_t)blockIdx.x * wpg + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (wave >= nwaves) return;
@@ -224,29 +405,69 @@ __global__ __launch_bounds__(256) void k_stencil2d(Band2D b, int rows, int halo,
     w.vec = w.xin && b.aligned;
     const T k = static_cast<T>(b.r);
 
-    // column mask for edge strips (cells outside [0, nx) are zero ghosts)
-    bool colok[C];
-#pragma unroll
-    for (int j = 0; j < C; ++j) colok[j] = (w.xl + j >= 0) && (w.xl + j < b.nx);
-
+    // Rows above the first streamed row only feed rows that are never stored;
+    // they start as zeros so that no stale register value is ever read.
     T R[D][3][C];
+    T Z[Q][C];
 #pragma unroll
     for (int l = 0; l < D; ++l)
 #pragma unroll
         for (int m = 0; m < 3; ++m)
 #pragma unroll
             for (int j = 0; j < C; ++j) R[l][m][j] = T(0);
+#pragma unroll
+    for (int m = Q - 2; m < Q; ++m)
+#pragma unroll
+        for (int j = 0; j < C; ++j) Z[m][j] = T(0);
 
+    const int64_t ystart = w.y0 - D;
     const int64_t yend = w.y1 + D;
-    T pf0[C], pf1[C];
-    load_row2d<T, C>(b, w, w.y0 - D, pf0, colok);
-    load_row2d<T, C>(b, w, w.y0 - D + 1, pf1, colok);
-    for (int64_t yy = w.y0 - D; yy < yend; yy += 3) {
-        row_step<T, C, D, 0>(b, w, halo, yy, R, colok, k, pf0, pf1);
-        if (yy + 1 >= yend) break;
-        row_step<T, C, D, 1>(b, w, halo, yy + 1, R, colok, k, pf0, pf1);
-        if (yy + 2 >= yend) break;
-        row_step<T, C, D, 2>(b, w, halo, yy + 2, R, colok, k, pf0, pf1);
+    // Waves whose strip and rows stay clear of the zero-Dirichlet edges take
+    // the interior variant.
+    const bool edge = !w.xin || (ystart - D < 0 && b.bc_top != BC_GHOST) ||
+                      (yend > b.ny && b.bc_bot != BC_GHOST);
+    if constexpr (FAST) {
+        FastIO<T, C> io;
+        io.in = static_cast<const T*>(b.in);
+        io.top = static_cast<const T*>(b.halo_top);
+        io.bot = static_cast<const T*>(b.halo_bot);
+        io.nx = b.nx;
+        io.ny = b.ny;
+        io.hw = b.hw;
+        io.ylo = ystart;
+        io.yhi = yend - 1;
+        io.top_ghost = b.bc_top == BC_GHOST;
+        io.bot_ghost = b.bc_bot == BC_GHOST;
+        io.out = __builtin_amdgcn_make_buffer_rsrc(b.out, (short)0,
+                                                   (int)(b.ny * b.nx * (int64_t)sizeof(T)),
+                                                   BUF_DWORD3);
+        // nx is a multiple of the vector width here, so a lane vector is
+        // either wholly inside [0, nx) or wholly outside; one outside loads a
+        // clamped address and is replaced by zeros
+#pragma unroll
+        for (int q = 0; q < C / VN; ++q) {
+            const int64_t x = w.xl + q * VN;
+            const int lc = w.lane * C + q * VN;
+            io.colin[q] = x >= 0 && x < b.nx;
+            io.xload[q] = x < 0 ? 0 : (x + VN > b.nx ? b.nx - VN : x);
+            io.off[q] = (lc >= halo && lc < S - halo && io.colin[q])
+                            ? (uint32_t)(x * (int64_t)sizeof(T))
+                            : OOB_OFFSET;
+        }
+        if (edge) {
+            stream_rows_fast<T, C, D, Q, true>(io, ystart, yend, Z, R, k);
+        } else {
+            stream_rows_fast<T, C, D, Q, false>(io, ystart, yend, Z, R, k);
+        }
+    } else {
+        // column mask for edge strips (cells outside [0, nx) are zero ghosts)
+        bool colok[C];
+#pragma unroll
+        for (int j = 0; j < C; ++j) colok[j] = (w.xl + j >= 0) && (w.xl + j < b.nx);
+        if (edge)
+            stream_rows<T, C, D, Q, true>(b, w, halo, ystart, yend, Z, R, colok, k);
+        else
+            stream_rows<T, C, D, Q, false>(b, w, halo, ystart, yend, Z, R, colok, k);
     }
 }
 
@@ -258,8 +479,15 @@ hipError_t launch_cd(const Band2D& b, const Geom2D& g, hipStream_t st) {
     const int64_t nwaves = nstrips * nchunks;
     const dim3 block(64 * g.wpg);
     const dim3 grid((unsigned)((nwaves + g.wpg - 1) / g.wpg));
-    hipLaunchKernelGGL((k_stencil2d<T, C, D>), grid, block, 0, st, b, g.rows, g.halo, nstrips,
-                       nwaves);
+    constexpr int VN = V16<T>::N;
+    const bool fast = b.aligned && b.nx % VN == 0 && b.nx >= VN &&
+                      b.ny * b.nx * (int64_t)sizeof(T) < (int64_t(1) << 31);
+    if (fast)
+        hipLaunchKernelGGL((k_stencil2d<T, C, D, true>), grid, block, 0, st, b, g.rows, g.halo,
+                           nstrips, nwaves);
+    else
+        hipLaunchKernelGGL((k_stencil2d<T, C, D, false>), grid, block, 0, st, b, g.rows, g.halo,
+                           nstrips, nwaves);
     return hipGetLastError();
 }
 

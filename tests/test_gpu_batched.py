@@ -1,6 +1,7 @@
 """GPU parity of the batched driver: every problem of a batch equals the
-oracle run on its own (n, r); persistent, graph and plain modes are
-bit-identical; guard cells between problems are never written."""
+oracle run on its own (n, r); persistent and graph modes (one pass of all
+steps) are bit-identical, plain (one step per launch) agrees within the
+tolerance; guard cells between problems are never written."""
 import numpy as np
 import pytest
 
@@ -77,8 +78,10 @@ def test_uneven_batch_matches_oracle_all_modes(ctx, dtype, tol):
         ref = oracle.heat1d_periodic(u[o:o + n].astype(np.float64), float(r), 20)
         got = results[0][o:o + n]
         assert rel_l2(got, ref) <= tol and rel_max(got, ref) <= 10 * tol, (k, n)
+    # persistent and graph run each problem as one 20-step pass: same arithmetic
     assert np.array_equal(results[0], results[1])
-    assert np.array_equal(results[0], results[2])
+    for o, n in zip(offs, sizes):  # plain runs 20 one-step passes
+        assert rel_l2(results[2][o:o + n], results[0][o:o + n]) <= 2 * tol
 
 
 @pytest.mark.parametrize("cpl", [8, 32, 64])

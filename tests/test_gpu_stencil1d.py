@@ -2,8 +2,9 @@
 
 Bars: FP64 path <= 1e-12 relative (L2 and max) to the oracle; FP32 path
 <= 1e-5 relative L2 to the FP64 oracle run on the same FP32-rounded input.
-Different launch geometries and pass splits must give bit-identical results
-(the per-cell arithmetic never changes).
+Launch geometries that differ only in tile shape (cells per lane, waves per
+group) must give bit-identical results: a pass's arithmetic depends only on its
+step count.  Different pass splits agree within the tolerance.
 """
 import numpy as np
 import pytest
@@ -71,11 +72,24 @@ def test_small_and_ragged(ctx, dtype, bc, n, steps):
     assert e <= TOL[dtype], e
 
 
-@pytest.mark.parametrize("cpl,tb,wpg", [(8, 1, 1), (16, 3, 2), (32, 32, 4), (64, 50, 4),
-                                        (32, 13, 1)])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("r", [0.0, 0.05, 0.125, 0.25, 0.375, 0.4, 0.45, 0.5])
+@pytest.mark.parametrize("tb", [1, 7, 40])
+def test_rates_both_update_forms(ctx, dtype, r, tb):
+    """Rates 0 <= r <= 3/8 run the rescaled update (with rescales every few
+    steps and a remainder factor), larger rates the direct one; both against
+    the oracle, across the rate range up to the stability limit 1/2."""
+    u0 = workloads.uniform(70001, 204, int(r * 1000), 0, 1, dtype)
+    ref = oracle.heat1d_periodic(u0.astype(np.float64), r, 40)
+    got = gpu_run(ctx, u0, r, 40, cells_per_lane=16, time_block=tb)
+    assert rel_l2(got, ref) <= TOL[dtype] and rel_max(got, ref) <= 10 * TOL[dtype]
+
+
+@pytest.mark.parametrize("tb", [1, 13, 50])
+@pytest.mark.parametrize("cpl,wpg", [(16, 2), (32, 4), (64, 4), (32, 1)])
 def test_geometries_bitwise_equal(ctx, cpl, tb, wpg):
     u0 = workloads.uniform(300007, 201, 0, 0, 1, np.float32)
-    base = gpu_run(ctx, u0, 0.25, 50, cells_per_lane=8, time_block=1, waves_per_group=4)
+    base = gpu_run(ctx, u0, 0.25, 50, cells_per_lane=8, time_block=tb, waves_per_group=4)
     got = gpu_run(ctx, u0, 0.25, 50, cells_per_lane=cpl, time_block=tb, waves_per_group=wpg)
     assert np.array_equal(base, got)
     ref = oracle.heat1d_periodic(u0.astype(np.float64), 0.25, 50)
