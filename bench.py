@@ -2,16 +2,20 @@
 """Benchmark of the hx hot path on one MI355X.
 
 Workload (the headline configuration): a 1D periodic heat stencil over 2^28
-fp32 cells split into 64 partitions of 4 Mi cells, r = 0.25, 50 steps, run as
-a future graph of per-partition stencil launches with halo dependencies
-(Sec. V-A.2 / Algorithm 1 with the Sec. V-A.1 stencil).  One bench "step" is
-the whole 50-step run over the whole array, with the data resident in HBM.
+fp32 cells split into 64 partitions of 4 Mi cells (laid out back to back in
+one HBM arena), r = 0.25, 50 steps, run as a device-resident future graph
+(Sec. V-A.2 / Algorithm 1 with the Sec. V-A.1 stencil): each pass of 50 fused
+steps is one node, launched as one batched kernel over all 64 partitions with
+every partition's halos read from its neighbours.  One bench "step" is the
+whole 50-step run over the whole array, with the data resident in HBM.
 
 Printed: one JSON line with the throughput (cell-updates/s), the roofline of
-the dominant kernel (per-launch durations from HIP events in the timed region),
-the oracle's CPU throughput on a bounded sample, and the side measurements the
-metric names: the plain one-launch-per-partition-per-step form, the
-host-to-host pipeline with its copy overlap, and the batched driver.
+that kernel (per-launch durations from HIP events recorded on its stream in
+the timed region), the oracle's CPU throughput on a bounded sample, and the
+side measurements the metric names: the per-partition future graph (one node
+per partition per pass), the plain one-launch-per-partition-per-step form, the
+host-to-host pipeline with its copy overlap, the 4096-problem batched driver,
+the fp64, 2D and adjoint workloads, and a copy kernel for counter calibration.
 """
 from __future__ import annotations
 
@@ -24,8 +28,13 @@ import time
 import numpy as np
 
 HBM_PEAK = 8.0e12            # bytes/s, MI355X HBM3E
-VALU_F32_PEAK = 78.6e12      # flop/s: 256 CU x 64 FP32 lanes x 2 (FMA) x 2.4 GHz, no packed FP32
-FLOPS_PER_UPDATE_1D = 5      # c + r*((l - 2c) + rt): 2 mul, 3 add/sub
+VALU_F32_PEAK = 157.3e12     # flop/s: 256 CU x 128 FP32 lanes/clk x 2 (FMA) x 2.4 GHz
+FLOPS_PER_UPDATE_1D = 3      # rescaled update w' = fma(b, l + rt, w): one add + one fma
+BYTES_PER_CELL_PASS = 8      # one fp32 read + one fp32 write per cell per pass
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                            "stencil1d_flat_2p28_fp32_traffic.md")
+KERNEL_SOURCES = ("paper_1810_11482_amd/csrc/hx_stencil1d.hip",
+                  "paper_1810_11482_amd/csrc/hx_internal.h")
 
 
 def log(msg):
@@ -62,9 +71,40 @@ def intersect_len(u1, u2):
     return tot
 
 
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    root = os.path.dirname(os.path.abspath(__file__))
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(root, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the headline kernel from the committed rocprofv3
+    counter summary, or None when the kernel sources changed since it was taken."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source_hash") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 class Partitioned:
-    """Device state of the partitioned workload: pinned host input, two
-    ping-pong buffer sets, and the step driver."""
+    """Device state of the partitioned workload: pinned host input, and two
+    ping-pong arenas (one allocation each) whose partitions are non-owning
+    buffer views, so the 64 partitions are laid out back to back in HBM."""
 
     def __init__(self, hx, ctx, n, parts, steps, r):
         self.hx, self.ctx = hx, ctx
@@ -78,8 +118,18 @@ class Partitioned:
         workloads.partitioned1d_u0(workloads.Partitioned1D(n=n, parts=parts, steps=steps, r=r),
                                    out=arr)
         self.u0 = arr
-        self.A = [hx.hx_buffer_create(ctx, s * 4) for s in self.sizes]
-        self.B = [hx.hx_buffer_create(ctx, s * 4) for s in self.sizes]
+        self.arena_a = hx.hx_buffer_create(ctx, n * 4)
+        self.arena_b = hx.hx_buffer_create(ctx, n * 4)
+        pa, _ = hx.hx_buffer_ptr(ctx, self.arena_a)
+        pb, _ = hx.hx_buffer_ptr(ctx, self.arena_b)
+        self.A = [hx.hx_buffer_wrap(ctx, pa + o * 4, s * 4) for o, s in self.bounds]
+        self.B = [hx.hx_buffer_wrap(ctx, pb + o * 4, s * 4) for o, s in self.bounds]
+        self.reset()
+        self.last = 0
+
+    def reset(self):
+        """Upload the initial state into arena A (partition by partition)."""
+        hx, ctx = self.hx, self.ctx
         evs = []
         for (o, s), b in zip(self.bounds, self.A):
             d = hx.hx_copy_desc(hx.HX_H2D, self.host_in + o * 4, b, 0, 0, 0, s * 4)
@@ -89,7 +139,6 @@ class Partitioned:
         for e in evs + [w]:
             hx.hx_event_release(ctx, e)
         self.cur_in_a = True
-        self.last = 0
 
     def step(self, mode, time_block, cpl=0, nodes=False):
         hx = self.hx
@@ -116,7 +165,7 @@ class Partitioned:
 
 def time_steps(P, k, mode, tb, cpl, nodes=False):
     import torch
-    P.wait()
+    P.wait() if P.last else None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     all_nodes = []
@@ -129,6 +178,47 @@ def time_steps(P, k, mode, tb, cpl, nodes=False):
     return (time.perf_counter() - t0) / k, all_nodes
 
 
+class BatchedPass:
+    """The partitioned run in its batched form: every pass of `tb` steps is one
+    node of the future graph, launched as one batched kernel over all
+    partitions (each partition's halos read from its neighbours' views), and
+    chained on the previous pass."""
+
+    def __init__(self, hx, ctx, P, tb, cpl):
+        self.hx, self.ctx, self.P, self.tb, self.cpl = hx, ctx, P, tb, cpl
+        self.plans = []
+        for src, dst in ((P.A, P.B), (P.B, P.A)):
+            segs = []
+            for p in range(P.parts):
+                lp, rp = (p - 1) % P.parts, (p + 1) % P.parts
+                segs.append(hx.segment(inp=src[p], out=dst[p], n=P.sizes[p], r=P.r,
+                                       bc_lo=hx.HX_BC_GHOST, bc_hi=hx.HX_BC_GHOST,
+                                       halo_lo=src[lp], halo_lo_offset=(P.sizes[lp] - tb) * 4,
+                                       halo_hi=src[rp], halo_width=tb))
+            self.plans.append(hx.hx_plan_create_batched(ctx, hx.HX_F32, tb, segs,
+                                                        hx.HX_BATCH_PERSISTENT, cells_per_lane=cpl,
+                                                        grid_waves_per_cu=-1))
+        self.passes = P.steps // tb
+        assert self.passes * tb == P.steps, "the time block must divide the step count"
+
+    def run(self, nsteps, keep=None):
+        """Queue nsteps bench steps; launch events go to `keep` when given."""
+        hx, P = self.hx, self.P
+        for _ in range(nsteps * self.passes):
+            plan = self.plans[0 if P.cur_in_a else 1]
+            ev = hx.hx_launch_batched(self.ctx, plan, deps=[P.last] if P.last else [])
+            if keep is not None:
+                keep.append(ev)
+            elif P.last:
+                hx.hx_event_release(self.ctx, P.last)
+            P.last = ev
+            P.cur_in_a = not P.cur_in_a
+
+    def close(self):
+        for pl in self.plans:
+            self.hx.hx_plan_destroy(self.ctx, pl)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -136,15 +226,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--log2n", type=int, default=28)
     ap.add_argument("--parts", type=int, default=64)
-    ap.add_argument("--time-block", type=int, default=0, help="0 = pick by a short sweep")
-    ap.add_argument("--cells-per-lane", type=int, default=0)
-    ap.add_argument("--streams", type=int, default=4)
-    ap.add_argument("--legs", default="graph,batched_pass,plain,pipeline,batched,fp64,2d,adjoint,cpu",
-                    help="comma list of legs: graph (the headline, always run), batched_pass, "
+    ap.add_argument("--cells-per-lane", type=int, default=0, help="0 = pick by a short sweep")
+    ap.add_argument("--streams", type=int, default=4,
+                    help="compute streams of the context (the per-partition graph spreads its "
+                         "nodes over them)")
+    ap.add_argument("--legs", default="graph,plain,pipeline,batched,fp64,2d,adjoint,copy,cpu",
+                    help="comma list of side legs: graph (the per-partition future graph), "
                          "plain, pipeline, batched, fp64 (2^20 fp64, 100 steps), 2d (16384^2, "
-                         "200 steps, 16 bands), adjoint (8192^2, 100 steps), cpu, copy (a "
-                         "zero-step pass: a plain device copy of known size, for counter "
-                         "calibration)")
+                         "200 steps, 16 bands), adjoint (8192^2, 100 steps), copy (a zero-step "
+                         "pass over the arena: a plain 1 GiB device copy, for counter "
+                         "calibration), cpu; 'none' runs the headline only")
     args = ap.parse_args()
     legs = set(args.legs.split(","))
 
@@ -162,54 +253,93 @@ def main():
     info = hx.hx_device_info(0)
     log(f"device {info.arch.decode()} CUs={info.compute_units}")
     P = Partitioned(hx, ctx, n, args.parts, T, r)
+    tb = T
 
-    # ---------------------------------------------------------- geometry sweep
+    # ------------------------------------------- geometry sweep (untimed)
+    cpls = [args.cells_per_lane] if args.cells_per_lane else [32, 16]
     cands = []
-    tbs = [args.time_block] if args.time_block else [10, 25, 50]
-    cpls = [args.cells_per_lane] if args.cells_per_lane else [32, 64]
-    for tb in tbs:
-        for cpl in cpls:
-            if 64 * cpl - 2 * ((tb + 3) // 4 * 4) < 64:
-                continue
-            time_steps(P, 1, hx.HX_PART_GRAPH, tb, cpl)
-            t, _ = time_steps(P, 2, hx.HX_PART_GRAPH, tb, cpl)
-            cands.append((t, tb, cpl))
-            log(f"sweep time_block={tb} cpl={cpl}: {t * 1e3:.3f} ms/step")
-    _, tb, cpl = min(cands)
+    for cpl in cpls:
+        bp = BatchedPass(hx, ctx, P, tb, cpl)
+        bp.run(2)
+        P.wait()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bp.run(3)
+        P.wait()
+        t = (time.perf_counter() - t0) / 3
+        hx.hx_event_release(ctx, P.last)
+        P.last = 0
+        bp.close()
+        cands.append((t, cpl))
+        log(f"sweep batched pass cpl={cpl}: {t * 1e3:.3f} ms/step")
+    _, cpl = min(cands)
 
     # ------------------------------------------------------------ timed region
-    time_steps(P, args.warmup, hx.HX_PART_GRAPH, tb, cpl)
-    sec, nodes = time_steps(P, args.steps, hx.HX_PART_GRAPH, tb, cpl, nodes=True)
+    P.reset()
+    bp = BatchedPass(hx, ctx, P, tb, cpl)
+    bp.run(args.warmup)
+    if P.last:
+        P.wait()
+    torch.cuda.synchronize()
+    launches = []
+    t0 = time.perf_counter()
+    bp.run(args.steps, keep=launches)
+    P.wait()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
     durs = []
-    for e in nodes:
+    for e in launches:
         a, b = hx.hx_event_span(ctx, e, e)
         durs.append(b - a)
+    for e in launches[:-1]:
         hx.hx_event_release(ctx, e)
+    bp.close()
     avg_ms = float(np.mean(durs))
     ms_per_step = sec * 1e3
-    updates = float(n) * T
-    value = updates / sec
-    launches_per_step = args.parts * -(-T // tb)
-    concurrency = float(np.sum(durs)) / (ms_per_step * args.steps)
-    cells_per_launch = n / args.parts
-    bytes_per_launch = cells_per_launch * 2 * 4
-    steps_per_launch = T / -(-T // tb)
+    value = float(n) * T / sec
+    # sampled correctness of the timed result against the oracle's light cone
+    import oracle
+    steps_done = (args.warmup + args.steps) * T
+    rng = np.random.default_rng(3)
+    idx = np.sort(rng.choice(n, 24, replace=False))
+    cur = P.current()
+    got = []
+    for i in idx:
+        p = int(i) // P.sizes[0] if n % args.parts == 0 else \
+            next(k for k, (o, s) in enumerate(P.bounds) if o <= i < o + s)
+        v = np.empty(1, np.float32)
+        e = hx.hx_copy_async(ctx, hx.hx_copy_desc(hx.HX_D2H, v.ctypes.data, cur[p],
+                                                  (int(i) - P.bounds[p][0]) * 4, 0, 0, 4))
+        assert hx.hx_wait(ctx, e) == hx.HX_OK
+        hx.hx_event_release(ctx, e)
+        got.append(float(v[0]))
+    u0 = np.asarray(P.u0, dtype=np.float64)
+    ref = oracle.heat1d_periodic_at(u0, r, steps_done, idx) if steps_done <= 4000 else None
+    sampled_err = (float(np.max(np.abs(np.array(got) - ref) / np.abs(ref)))
+                   if ref is not None else None)
+
+    cells_per_launch = float(n)
+    steps_per_launch = tb
+    bytes_per_launch = cells_per_launch * BYTES_PER_CELL_PASS
     flops_per_launch = cells_per_launch * steps_per_launch * FLOPS_PER_UPDATE_1D
     bw = bytes_per_launch / (avg_ms * 1e-3)
     fl = flops_per_launch / (avg_ms * 1e-3)
     hbm_frac, alu_frac = bw / HBM_PEAK, fl / VALU_F32_PEAK
+    traffic = measured_traffic()
     if alu_frac >= hbm_frac:
         roof = {"bound": "alu", "achieved": fl / 1e12, "peak": VALU_F32_PEAK / 1e12,
                 "unit": "TFLOP/s", "frac": alu_frac}
     else:
         roof = {"bound": "hbm", "achieved": bw / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                 "frac": hbm_frac}
-    roof.update({"traffic": None, "kernel": "k_stencil1d<float>", "avg_launch_ms": avg_ms,
-                 "launches": len(durs), "hbm_algorithmic_GBps": bw / 1e9,
-                 "hbm_frac": hbm_frac, "alu_frac": alu_frac,
-                 "alu_frac_vs_157TF_packed_peak": fl / 157.3e12,
-                 "kernel_concurrency": concurrency})
-    log(f"graph: {ms_per_step:.3f} ms/step, {value:.4e} cell-updates/s, kernel avg {avg_ms:.4f} ms")
+    roof.update({"traffic": traffic,
+                 "kernel": f"k_stencil1d_flat<float,{cpl}>", "avg_launch_ms": avg_ms,
+                 "launches": len(durs), "algorithmic_bytes_per_launch": bytes_per_launch,
+                 "algorithmic_flops_per_launch": flops_per_launch,
+                 "hbm_algorithmic_GBps": bw / 1e9, "hbm_frac": hbm_frac, "alu_frac": alu_frac,
+                 "kernel_source_hash": kernel_source_hash()})
+    log(f"headline: {ms_per_step:.3f} ms/step, {value:.4e} cell-updates/s, kernel avg "
+        f"{avg_ms:.4f} ms, sampled err {sampled_err}")
 
     result = {
         "metric": "stencil cell-updates/s + HBM GB/s vs roofline; % copy hidden; batched vs plain",
@@ -217,33 +347,37 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"1D periodic heat stencil, 2^{args.log2n} fp32 cells in "
-                               f"{args.parts} partitions, r=0.25, 50 steps, device-resident "
-                               f"future graph (halo dependencies)",
+                               f"{args.parts} partitions (one HBM arena), r=0.25, 50 steps, "
+                               f"device-resident future graph: one batched launch over all "
+                               f"partitions per {tb}-step pass, halos read from neighbour "
+                               f"partitions",
                    "cells": n, "parts": args.parts, "time_steps": T, "time_block": tb,
-                   "cells_per_lane": cpl, "compute_streams": args.streams,
-                   "launches_per_step": launches_per_step},
+                   "cells_per_lane": cpl, "launches_per_step": bp.passes,
+                   "sampled_max_rel_err_vs_oracle": sampled_err},
         "roofline": roof,
     }
+    hx.hx_event_release(ctx, P.last)
+    P.last = 0
 
-    # --------------------------------------------- batched-pass form of the graph
-    if "batched_pass" in legs:
-        bp = batched_pass_leg(hx, ctx, P, T, r)
-        result["graph_batched_pass"] = bp
-
-    # --------------------------------------------------------------- extra legs
+    # --------------------------------------------------------------- side legs
+    if "graph" in legs:
+        result["graph_per_partition"] = graph_leg(hx, ctx, P, T, r)
     if "plain" in legs:
         # plain comparator: one launch per partition per step, Algorithm 1 order
+        P.reset()
         time_steps(P, 1, hx.HX_PART_PLAIN, 1, 8)
         t_plain, _ = time_steps(P, 1, hx.HX_PART_PLAIN, 1, 8)
         result["plain"] = {"ms_per_step": t_plain * 1e3, "launches_per_step": args.parts * T,
-                           "speedup_graph_vs_plain": t_plain / sec}
+                           "speedup_headline_vs_plain": t_plain / sec}
         log(f"plain: {t_plain * 1e3:.3f} ms/step")
+        hx.hx_event_release(ctx, P.last)
+        P.last = 0
     if "pipeline" in legs:
         result["pipeline"] = pipeline_leg(hx, ctx, P, T, r, cpl)
-    if "batched" in legs:
-        result["batched"] = batched_leg(hx, ctx)
     if "copy" in legs:
         result["copy_calibration"] = copy_leg(hx, ctx, P)
+    if "batched" in legs:
+        result["batched"] = batched_leg(hx, ctx)
     if "fp64" in legs:
         result["periodic_fp64"] = fp64_leg(hx, ctx)
     if "2d" in legs:
@@ -256,58 +390,33 @@ def main():
         result["cpu_baseline"] = cpu_leg(r, T)
 
     print(json.dumps(result), flush=True)
-    hx.hx_event_release(ctx, P.last)
     hx.hx_ctx_destroy(ctx)
 
 
-def batched_pass_leg(hx, ctx, P, T, r, reps=10):
-    """The partitioned graph with one node per pass: each pass is one persistent
-    batched launch over all partitions (halos read from the neighbours'
-    buffers), chained on the previous pass."""
-    import torch
+def graph_leg(hx, ctx, P, T, r):
+    """The per-partition future graph: node (p, b) advances partition p by one
+    time block and depends on (p-1, b-1), (p, b-1), (p+1, b-1); nodes spread
+    over the context's compute streams and run concurrently."""
     best = None
-    for tb, cpl, grid in [(50, 32, 16), (50, 32, -1), (50, 16, -1), (25, 32, -1)]:
-        plans = []
-        for src, dst in ((P.A, P.B), (P.B, P.A)):
-            segs = []
-            for p in range(P.parts):
-                lp, rp = (p - 1) % P.parts, (p + 1) % P.parts
-                segs.append(hx.segment(inp=src[p], out=dst[p], n=P.sizes[p], r=r,
-                                       bc_lo=hx.HX_BC_GHOST, bc_hi=hx.HX_BC_GHOST,
-                                       halo_lo=src[lp], halo_lo_offset=(P.sizes[lp] - tb) * 4,
-                                       halo_hi=src[rp], halo_width=tb))
-            plans.append(hx.hx_plan_create_batched(ctx, hx.HX_F32, tb, segs,
-                                                   hx.HX_BATCH_PERSISTENT, cells_per_lane=cpl,
-                                                   grid_waves_per_cu=grid))
-        passes = T // tb
-        P.wait()
-        last = 0
-        k = 0
-
-        def run(nsteps):
-            nonlocal last, k
-            for _ in range(nsteps * passes):
-                ev = hx.hx_launch_batched(ctx, plans[k % 2], deps=[last] if last else [])
-                if last:
-                    hx.hx_event_release(ctx, last)
-                last = ev
-                k += 1
-            assert hx.hx_wait(ctx, last) == hx.HX_OK
-        run(2)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        run(reps)
-        torch.cuda.synchronize()
-        sec = (time.perf_counter() - t0) / reps
-        hx.hx_event_release(ctx, last)
-        for pl in plans:
-            hx.hx_plan_destroy(ctx, pl)
+    for tb, cpl in ((50, 32), (50, 16), (25, 32)):
+        P.reset()
+        time_steps(P, 2, hx.HX_PART_GRAPH, tb, cpl)
+        sec, nodes = time_steps(P, 5, hx.HX_PART_GRAPH, tb, cpl, nodes=True)
+        durs = []
+        for e in nodes:
+            a, b = hx.hx_event_span(ctx, e, e)
+            durs.append(b - a)
+            hx.hx_event_release(ctx, e)
+        log(f"per-partition graph tb={tb} cpl={cpl}: {sec * 1e3:.3f} ms/step, node avg "
+            f"{np.mean(durs) * 1e3:.1f} us")
         cand = {"ms_per_step": sec * 1e3, "cell_updates_per_s": P.n * T / sec, "time_block": tb,
-                "cells_per_lane": cpl, "grid_waves_per_cu": grid, "launches_per_step": passes}
-        log(f"batched-pass graph tb={tb} cpl={cpl} grid/CU={grid}: {sec * 1e3:.3f} ms/step")
+                "cells_per_lane": cpl, "launches_per_step": P.parts * -(-T // tb),
+                "node_avg_ms": float(np.mean(durs)),
+                "kernel_concurrency": float(np.sum(durs)) / (sec * 1e3 * 5)}
         if best is None or cand["ms_per_step"] < best["ms_per_step"]:
             best = cand
-    P.cur_in_a = True  # an even number of passes was run from A
+    hx.hx_event_release(ctx, P.last)
+    P.last = 0
     return best
 
 
@@ -516,18 +625,23 @@ def banded2d_leg(hx, ctx):
     spec = workloads.Banded2D()
     u0 = workloads.banded2d_u0(spec)
     bounds = workloads.band_bounds(spec.ny, spec.bands)
-    A = [hx.hx_buffer_create(ctx, s * spec.nx * 4) for _, s in bounds]
-    B = [hx.hx_buffer_create(ctx, s * spec.nx * 4) for _, s in bounds]
-    for (o, s), buf in zip(bounds, A):
-        chunk = np.ascontiguousarray(u0[o:o + s])
-        e = hx.hx_copy_async(ctx, hx.hx_copy_desc(hx.HX_H2D, chunk.ctypes.data, buf, 0, 0, 0,
-                                                  chunk.nbytes))
+    cells = spec.ny * spec.nx
+    arena_a = hx.hx_buffer_create(ctx, cells * 4)
+    arena_b = hx.hx_buffer_create(ctx, cells * 4)
+    pa, _ = hx.hx_buffer_ptr(ctx, arena_a)
+    pb, _ = hx.hx_buffer_ptr(ctx, arena_b)
+    row = spec.nx * 4
+    A = [hx.hx_buffer_wrap(ctx, pa + o * row, s * row) for o, s in bounds]
+    B = [hx.hx_buffer_wrap(ctx, pb + o * row, s * row) for o, s in bounds]
+
+    def upload():
+        e = hx.hx_copy_async(ctx, hx.hx_copy_desc(hx.HX_H2D, u0.ctypes.data, arena_a, 0, 0, 0,
+                                                  u0.nbytes))
         assert hx.hx_wait(ctx, e) == hx.HX_OK
         hx.hx_event_release(ctx, e)
-    cells = spec.ny * spec.nx
     best = None
-    for tb, cpl, rows in ((8, 4, 256), (8, 4, 128), (8, 8, 256), (10, 4, 256), (12, 4, 256),
-                          (16, 4, 256), (16, 4, 512), (4, 4, 256)):
+    for tb, cpl, rows in ((16, 4, 128), (12, 4, 128), (10, 4, 128), (8, 4, 64), (16, 4, 256)):
+        upload()
         d = hx.partitioned_desc(hx.HX_F32, [s for _, s in bounds], A, B, spec.steps, spec.r,
                                 periodic=False, time_block=tb, cells_per_lane=cpl, dims=2,
                                 nx=spec.nx, rows_per_block=rows)
@@ -549,7 +663,30 @@ def banded2d_leg(hx, ctx):
            "cell_updates_per_s": cells * spec.steps / sec, "time_block": tb, "cells_per_lane": cpl,
            "rows_per_block": rows,
            "hbm_algorithmic_GBps": cells * 8 * passes / sec / 1e9}
-    for b_ in A + B:
+    # sampled correctness of the best configuration against the oracle
+    import oracle
+    d = hx.partitioned_desc(hx.HX_F32, [s for _, s in bounds], A, B, spec.steps, spec.r,
+                            periodic=False, time_block=tb, cells_per_lane=cpl, dims=2,
+                            nx=spec.nx, rows_per_block=rows)
+    upload()
+    ev, in_b, _ = hx.hx_run_partitioned(ctx, d)
+    assert hx.hx_wait(ctx, ev) == hx.HX_OK
+    hx.hx_event_release(ctx, ev)
+    rng = np.random.default_rng(13)
+    pts = [(0, 0), (1023, 5000), (1024, 5000), (spec.ny - 1, spec.nx - 1)] + \
+        [(int(a), int(b)) for a, b in zip(rng.integers(0, spec.ny, 6), rng.integers(0, spec.nx, 6))]
+    ref = oracle.heat2d_dirichlet_at(u0, spec.r, spec.steps, pts)
+    errs = []
+    for (y, x), rv in zip(pts, ref):
+        v = np.empty(1, np.float32)
+        e = hx.hx_copy_async(ctx, hx.hx_copy_desc(hx.HX_D2H, v.ctypes.data,
+                                                  arena_b if in_b else arena_a,
+                                                  (y * spec.nx + x) * 4, 0, 0, 4))
+        assert hx.hx_wait(ctx, e) == hx.HX_OK
+        hx.hx_event_release(ctx, e)
+        errs.append(abs(float(v[0]) - rv) / max(abs(rv), 1e-3))
+    res["sampled_max_rel_err"] = float(max(errs))
+    for b_ in A + B + [arena_a, arena_b]:
         hx.hx_buffer_destroy(ctx, b_)
     return res
 
@@ -614,19 +751,21 @@ def adjoint_leg(hx, ctx):
 
 
 def copy_leg(hx, ctx, P, reps=5):
-    """Zero-step passes over the whole array in one launch: a plain device copy
+    """Zero-step passes over the whole arena in one launch: a plain device copy
     of 2^28 fp32 cells (1 GiB read, 1 GiB written), whose HBM counters scale
     the stencil's."""
-    a = hx.stencil_args(dims=1, dtype=hx.HX_F32, nx=P.sizes[0], steps=0, r=0.0, inp=P.A[0],
-                        out=P.B[0], cells_per_lane=32, time_block=1)
-    evs = [hx.hx_launch_stencil(ctx, a) for _ in range(reps)]
+    a = hx.stencil_args(dims=1, dtype=hx.HX_F32, nx=P.n, steps=0, r=0.0, inp=P.arena_a,
+                        out=P.arena_b, cells_per_lane=32, time_block=1)
+    evs = [hx.hx_launch_stencil(ctx, a)]
+    for _ in range(reps - 1):
+        evs.append(hx.hx_launch_stencil(ctx, a, deps=[evs[-1]]))
     assert hx.hx_wait(ctx, evs[-1]) == hx.HX_OK
     d = [b - s_ for s_, b in (hx.hx_event_span(ctx, e, e) for e in evs)]
     for e in evs:
         hx.hx_event_release(ctx, e)
     ms = float(np.median(d))
-    nbytes = P.sizes[0] * 8
-    return {"cells": P.sizes[0], "bytes_moved": nbytes, "avg_ms": ms,
+    nbytes = P.n * 8
+    return {"cells": P.n, "bytes_moved": nbytes, "avg_ms": ms,
             "GBps": nbytes / (ms * 1e-3) / 1e9}
 
 

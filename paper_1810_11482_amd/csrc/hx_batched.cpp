@@ -180,6 +180,10 @@ extern "C" hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* d, 
             }
         }
         bp->ntiles = (int64_t)tseg.size();
+        if (bp->ntiles >= (int64_t(1) << 31)) {
+            destroy_plan(bp);
+            return c->fail(HX_ERR_RANGE, "the batch has more than 2^31 tiles");
+        }
         const int64_t nt0 = tiles_1d(bp->segs[0], bp->g);
         bool uniform = true;
         for (const Seg1D& sg : bp->segs)
@@ -198,7 +202,9 @@ extern "C" hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* d, 
                                              : (tuned && tg.grid ? tg.grid : 0);
         hipDeviceProp_t prop;
         hipGetDeviceProperties(&prop, c->device);
-        bp->grid_waves = wpc <= 0 ? bp->ntiles
+        // one wave per tile needs 64 * ntiles work-items, under 2^32
+        const int64_t flat_max = (int64_t(1) << 32) / 64 - 1;
+        bp->grid_waves = wpc <= 0 ? std::min<int64_t>(bp->ntiles, flat_max)
                                   : std::min<int64_t>(bp->ntiles,
                                                       (int64_t)prop.multiProcessorCount * wpc);
         bool ok = hipMalloc(&bp->segs_dev, sizeof(Seg1D) * bp->segs.size()) == hipSuccess &&

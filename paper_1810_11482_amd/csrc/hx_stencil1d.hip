@@ -318,8 +318,9 @@ __global__ __launch_bounds__(256) void k_stencil1d_flat(const Seg1D* __restrict_
     if (t >= ntiles) return;
     uint32_t si, ti;
     if (per_seg > 0) {
-        si = (uint32_t)(t / per_seg);
-        ti = (uint32_t)(t - (int64_t)si * per_seg);
+        // the tile table is uint32-indexed, so 32-bit division suffices
+        si = (uint32_t)t / (uint32_t)per_seg;
+        ti = (uint32_t)t - si * (uint32_t)per_seg;
     } else {
         si = __builtin_amdgcn_readfirstlane(tseg[t]);
         ti = __builtin_amdgcn_readfirstlane(tidx[t]);
