@@ -300,8 +300,9 @@ typedef struct {
     int cells_per_lane;         /* 0 = tuned */
     int waves_per_group;        /* 0 = tuned */
     int grid_waves_per_cu;      /* PERSISTENT: > 0 = a persistent grid of that many waves per
-                                   CU striding over the tiles; < 0 = one wave per tile;
-                                   0 = tuned (one wave per tile if untuned) */
+                                   CU striding over the tiles, each wave prefetching its next
+                                   tile while it advances the current one; < 0 = one wave per
+                                   tile; 0 = tuned (one wave per tile if untuned) */
 } hx_batch_desc;
 
 /* Build a batch: `count` 1D segments, each with its own size, r, boundaries

@@ -37,6 +37,7 @@ struct BatchPlan {
     int64_t ntiles = 0;
     int64_t grid_waves = 0;
     int64_t per_seg = 0;  // tiles of every segment when all are equal (table unused)
+    bool scaled = true;    // every segment runs the rescaled update
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -161,6 +162,7 @@ extern "C" hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* d, 
         sg.hw = s.halo_width;
         sg.shift = tile_shift(pi, (int)es);
         set_rate_1d(sg, d->steps);
+        if (sg.period == 0) bp->scaled = false;
         bp->segs.push_back(sg);
         bp->tmps.push_back(pt);
     }
@@ -196,17 +198,19 @@ extern "C" hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* d, 
             }
             bp->per_seg = nt0;
         }
-        // Grid: `wpc` resident waves per CU striding over the tiles, or (the
-        // default, wpc <= 0 after tuning) one wave per tile.
+        // Grid: `wpc` > 0 persistent waves per CU striding over the tiles
+        // (software-pipelined), otherwise (the default after tuning) one wave
+        // per tile, the faster form measured on MI355X for fused passes.
         const int wpc = d->grid_waves_per_cu ? d->grid_waves_per_cu
                                              : (tuned && tg.grid ? tg.grid : 0);
         hipDeviceProp_t prop;
         hipGetDeviceProperties(&prop, c->device);
         // one wave per tile needs 64 * ntiles work-items, under 2^32
         const int64_t flat_max = (int64_t(1) << 32) / 64 - 1;
-        bp->grid_waves = wpc <= 0 ? std::min<int64_t>(bp->ntiles, flat_max)
-                                  : std::min<int64_t>(bp->ntiles,
-                                                      (int64_t)prop.multiProcessorCount * wpc);
+        if (wpc <= 0)
+            bp->grid_waves = std::min<int64_t>(bp->ntiles, flat_max);
+        else
+            bp->grid_waves = std::min<int64_t>(bp->ntiles, (int64_t)prop.multiProcessorCount * wpc);
         bool ok = hipMalloc(&bp->segs_dev, sizeof(Seg1D) * bp->segs.size()) == hipSuccess &&
                   hipMalloc(&bp->tseg_dev, 4 * tseg.size()) == hipSuccess &&
                   hipMalloc(&bp->tidx_dev, 4 * tidx.size()) == hipSuccess;
@@ -260,7 +264,7 @@ extern "C" hx_status hx_launch_batched(hx_ctx ctx, hx_plan plan, const hx_event*
             if (bp->mode == HX_BATCH_PERSISTENT)
                 return launch_stencil1d_batched(bp->dtype, bp->segs_dev, bp->tseg_dev,
                                                 bp->tidx_dev, bp->ntiles, bp->g, bp->grid_waves,
-                                                bp->per_seg, st);
+                                                bp->per_seg, bp->scaled, st);
             if (bp->mode == HX_BATCH_GRAPH) return hipGraphLaunch(bp->exec, st);
             // PLAIN: step by step, ping-pong so the last step lands in out
             const int S = bp->steps;

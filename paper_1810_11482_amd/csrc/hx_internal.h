@@ -81,12 +81,15 @@ hipError_t launch_stencil1d(int dtype, const Seg1D& seg, const Geom1D& g, hipStr
 
 // Batched 1D: segments described in device memory; `ntiles` entries of
 // (segment index, tile index within the segment) in device memory.  With
-// grid_waves >= ntiles every wave takes one tile, otherwise `grid_waves` waves
-// stride over the table.  per_seg > 0 means every segment has exactly per_seg
-// tiles in segment order, so the table need not be read.
+// grid_waves >= ntiles (or <= 0) every wave takes one tile, otherwise
+// `grid_waves` persistent waves stride over the table, each prefetching its
+// next tile while it advances the current one.  per_seg > 0 means every segment has exactly per_seg
+// tiles in segment order, so the table need not be read.  scaled: every
+// segment has period > 0 (set_rate_1d for g.steps), so the rescaled update runs.
 hipError_t launch_stencil1d_batched(int dtype, const Seg1D* segs_dev, const uint32_t* tile_seg,
                                     const uint32_t* tile_idx, int64_t ntiles, const Geom1D& g,
-                                    int64_t grid_waves, int64_t per_seg, hipStream_t stream);
+                                    int64_t grid_waves, int64_t per_seg, bool scaled,
+                                    hipStream_t stream);
 
 // One 2D band: ny rows of nx cells, row-major, advanced `steps` steps from in
 // into out.  Rows outside [0, ny) come from the top/bottom rule; columns

@@ -62,7 +62,10 @@ __device__ __forceinline__ T load_cell(const Seg1D& s, int64_t g) {
     if (g >= 0 && g < s.n) return in[g];
     if (g < 0) {
         if (s.bc_lo == BC_PERIODIC) {
-            int64_t m = g % s.n;
+            // 32-bit remainder where it fits (every segment under 2^31 cells)
+            int64_t m = (s.n < (int64_t(1) << 31) && g > -(int64_t(1) << 31))
+                            ? (int64_t)((int32_t)g % (int32_t)s.n)
+                            : g % s.n;
             if (m < 0) m += s.n;
             return in[m];
         }
@@ -70,7 +73,8 @@ __device__ __forceinline__ T load_cell(const Seg1D& s, int64_t g) {
             return static_cast<const T*>(s.halo_lo)[s.hw + g];
         return T(0);
     }
-    if (s.bc_hi == BC_PERIODIC) return in[g % s.n];
+    if (s.bc_hi == BC_PERIODIC)
+        return in[(g < (int64_t(1) << 31)) ? (int64_t)((uint32_t)g % (uint32_t)s.n) : g % s.n];
     if (s.bc_hi == BC_GHOST && g - s.n < (int64_t)s.hw)
         return static_cast<const T*>(s.halo_hi)[g - s.n];
     return T(0);
@@ -137,6 +141,20 @@ __device__ __forceinline__ void scale_tile(T (&a)[C], T f) {
     for (int j = 0; j < C; ++j) a[j] *= f;
 }
 
+// Segment pointers arrive as generic addresses; the tile's vector accesses go
+// through the global address space explicitly, so they compile to global
+// (not flat) instructions, which the LDS counters do not wait on.
+template <typename VT>
+__device__ __forceinline__ VT gload_nt(const VT* p, int64_t i) {
+    typedef __attribute__((address_space(1))) const VT GVT;
+    return __builtin_nontemporal_load((GVT*)p + i);
+}
+template <typename VT>
+__device__ __forceinline__ void gstore_nt(VT x, VT* p, int64_t i) {
+    typedef __attribute__((address_space(1))) VT GVT;
+    __builtin_nontemporal_store(x, (GVT*)p + i);
+}
+
 __device__ __forceinline__ bool aligned16(const void* p) {
     return (reinterpret_cast<uintptr_t>(p) & 15u) == 0;
 }
@@ -150,63 +168,112 @@ __device__ __forceinline__ int lds_pos(int i) {
     return (i / C) * (C + VN) + (i % C);
 }
 
-// Advance tile `tile` of segment `s` by `steps` steps (see the file comment).
-// HBM is touched only in coalesced order (lane l, cell l + 64 j or vector
-// l + 64 k); a wave-private LDS area transposes between that order and the
-// lane-contiguous register layout.  LDS accesses of one wave execute in order,
-// so the wave needs no barrier between writing and reading its own area.
+// A tile's pass is four phases, so that a persistent wave can overlap the
+// next tile's HBM reads with the current tile's steps:
+//   tile_fetch:  HBM -> registers, coalesced (lane l holds the vectors
+//                VN*(l + 64k), k = 0 .. C/VN-1, of the tile);
+//   tile_stage:  registers -> wave-private LDS -> lane-contiguous registers
+//                (lane l holds cells l*C .. l*C+C-1);
+//   tile_steps:  the time loop, registers only;
+//   tile_store:  registers -> LDS -> HBM, coalesced, inner cells only.
+// HBM is touched only in coalesced order.  LDS accesses of one wave execute in
+// order, so the wave needs no barrier between writing and reading its area.
+struct TileGeom {
+    int64_t o0, base;   // first output cell, first held cell
+    bool interior;      // the whole tile lies inside [0, n)
+};
+
+template <int C>
+__device__ __forceinline__ TileGeom tile_geom(const Seg1D& s, int64_t tile, int halo) {
+    TileGeom g;
+    const int64_t wout = 64LL * C - 2LL * halo;
+    g.o0 = tile * wout - s.shift;
+    g.base = g.o0 - halo;
+    g.interior = g.base >= 0 && g.base + 64LL * C <= s.n;
+    return g;
+}
+
+// Vector fetch of a tile that lies inside the segment with a 16-byte aligned
+// start (every tile but the segment's ends, given the grid shift).
+template <typename T>
+__device__ __forceinline__ bool tile_fast(const Seg1D& s, const TileGeom& tg) {
+    return tg.interior && aligned16(static_cast<const T*>(s.in) + tg.base);
+}
+
 template <typename T, int C>
-__device__ __forceinline__ void tile1d(const Seg1D& s, int64_t tile, int steps, int halo,
-                                       T* __restrict__ lds) {
+__device__ __forceinline__ void tile_fetch(const Seg1D& s, const TileGeom& tg, T (&pf)[C]) {
     typedef typename V16<T>::t VT;
     constexpr int VN = V16<T>::N;
-    constexpr int W = 64 * C;
-    static_assert(C % VN == 0, "cells per lane must be a multiple of the vector width");
     const int lane = threadIdx.x & 63;
-    const int64_t n = s.n;
-    const int64_t wout = (int64_t)W - 2LL * halo;
-    const int64_t o0 = tile * wout - s.shift;
-    const int64_t base = o0 - halo;
-    const T* in = static_cast<const T*>(s.in);
-    T* out = static_cast<T*>(s.out);
-    const bool interior = base >= 0 && base + W <= n;
-
-    // ---- load: HBM (coalesced) -> LDS
-    if (interior && aligned16(in + base)) {
-        const VT* src = reinterpret_cast<const VT*>(in + base);
+    const VT* src = reinterpret_cast<const VT*>(static_cast<const T*>(s.in) + tg.base);
 #pragma unroll
-        for (int k = 0; k < C / VN; ++k) {
-            const int i = VN * (lane + 64 * k);
-            const VT x = __builtin_nontemporal_load(src + lane + 64 * k);
-            *reinterpret_cast<VT*>(lds + lds_pos<T, C>(i)) = x;
-        }
-    } else if (interior) {
+    for (int k = 0; k < C / VN; ++k) {
+        const VT x = gload_nt(src, lane + 64 * k);
 #pragma unroll
-        for (int j = 0; j < C; ++j) {
-            const int i = lane + 64 * j;
-            lds[lds_pos<T, C>(i)] = in[base + i];
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < C; ++j) {
-            const int i = lane + 64 * j;
-            lds[lds_pos<T, C>(i)] = load_cell<T>(s, base + i);
-        }
+        for (int e = 0; e < VN; ++e) pf[k * VN + e] = x[e];
     }
-    __builtin_amdgcn_wave_barrier();
-    // ---- LDS -> registers, lane-contiguous
-    T v[C];
+}
+
+// Any other tile: cell by cell (boundary rules included) straight into the
+// wave's LDS area, in the same positions tile_stage writes.  Kept out of line:
+// it is rare and its boundary arithmetic would otherwise inflate the register
+// allocation of the whole tile loop.
+template <typename T, int C>
+__device__ __forceinline__ void tile_fill_slow(const Seg1D& s, int64_t base,
+                                                         bool interior, T* __restrict__ lds) {
+    const int lane = threadIdx.x & 63;
+    const T* in = static_cast<const T*>(s.in);
+    // a rolled loop: the path is rare, and unrolled its 64-bit addresses would
+    // set the register allocation of the whole kernel
+#pragma unroll 1
+    for (int j = 0; j < C; ++j) {
+        const int i = lane + 64 * j;
+        lds[lds_pos<T, C>(i)] = interior ? in[base + i] : load_cell<T>(s, base + i);
+    }
+}
+
+template <typename T, int C>
+__device__ __forceinline__ void tile_read(const T* __restrict__ lds, T (&v)[C]) {
+    typedef typename V16<T>::t VT;
+    constexpr int VN = V16<T>::N;
+    const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int q = 0; q < C / VN; ++q) {
         const VT x = *reinterpret_cast<const VT*>(lds + lane * (C + VN) + q * VN);
 #pragma unroll
         for (int e = 0; e < VN; ++e) v[q * VN + e] = x[e];
     }
+}
 
-    const int64_t lbase = base + (int64_t)lane * C;
-    const bool zero_lo = s.bc_lo == BC_DIRICHLET0 && base < 0;
-    const bool zero_hi = s.bc_hi == BC_DIRICHLET0 && base + W > n;
-    if (s.period > 0) {
+template <typename T, int C>
+__device__ __forceinline__ void tile_stage(const T (&pf)[C], T* __restrict__ lds, T (&v)[C]) {
+    typedef typename V16<T>::t VT;
+    constexpr int VN = V16<T>::N;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < C / VN; ++k) {
+        VT x;
+#pragma unroll
+        for (int e = 0; e < VN; ++e) x[e] = pf[k * VN + e];
+        *reinterpret_cast<VT*>(lds + lds_pos<T, C>(VN * (lane + 64 * k))) = x;
+    }
+    __builtin_amdgcn_wave_barrier();
+    tile_read<T, C>(lds, v);
+}
+
+// SC selects the rescaled update (every segment the kernel runs has
+// period > 0) or the direct one; the two are separate instantiations so that
+// each keeps its own, smaller register allocation.
+template <typename T, int C, bool SC>
+__device__ __forceinline__ void tile_steps(const Seg1D& s, const TileGeom& tg, int steps,
+                                           T (&v)[C]) {
+    constexpr int W = 64 * C;
+    const int lane = threadIdx.x & 63;
+    const int64_t n = s.n;
+    const int64_t lbase = tg.base + (int64_t)lane * C;
+    const bool zero_lo = s.bc_lo == BC_DIRICHLET0 && tg.base < 0;
+    const bool zero_hi = s.bc_hi == BC_DIRICHLET0 && tg.base + W > n;
+    if constexpr (SC) {
         const T b = static_cast<T>(s.beta);
         const T ap = static_cast<T>(s.alpha_p);
         int since = 0;
@@ -222,8 +289,35 @@ __device__ __forceinline__ void tile1d(const Seg1D& s, int64_t tile, int steps, 
         const T k = static_cast<T>(s.r);
         for (int t = 0; t < steps; ++t) step_tile<T, C>(v, k, zero_lo, zero_hi, lbase, n);
     }
+}
 
-    // ---- registers -> LDS -> HBM (coalesced), inner cells only
+// Cell-by-cell store of the inner cells of a boundary or unaligned tile from
+// the wave's LDS area.
+template <typename T, int C>
+__device__ __forceinline__ void tile_store_slow(const Seg1D& s, int64_t o0, int64_t base,
+                                                          int halo, const T* __restrict__ lds) {
+    const int lane = threadIdx.x & 63;
+    const int64_t n = s.n;
+    const int64_t wout = 64LL * C - 2LL * halo;
+    T* out = static_cast<T*>(s.out);
+    const int64_t ostart = o0 > 0 ? o0 : 0;
+    const int64_t oend = (o0 + wout < n) ? o0 + wout : n;
+#pragma unroll 1
+    for (int j = 0; j < C; ++j) {
+        const int i = lane + 64 * j;
+        const int64_t g = base + i;
+        if (g >= ostart && g < oend) out[g] = lds[lds_pos<T, C>(i)];
+    }
+}
+
+template <typename T, int C>
+__device__ __forceinline__ void tile_store(const Seg1D& s, const TileGeom& tg, int halo,
+                                           T* __restrict__ lds, const T (&v)[C]) {
+    typedef typename V16<T>::t VT;
+    constexpr int VN = V16<T>::N;
+    constexpr int W = 64 * C;
+    const int lane = threadIdx.x & 63;
+    T* out = static_cast<T*>(s.out);
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int q = 0; q < C / VN; ++q) {
@@ -233,25 +327,40 @@ __device__ __forceinline__ void tile1d(const Seg1D& s, int64_t tile, int steps, 
         *reinterpret_cast<VT*>(lds + lane * (C + VN) + q * VN) = x;
     }
     __builtin_amdgcn_wave_barrier();
-    const int64_t ostart = o0 > 0 ? o0 : 0;
-    const int64_t oend = (o0 + wout < n) ? o0 + wout : n;
-    if (interior && aligned16(out + base)) {
-        VT* dst = reinterpret_cast<VT*>(out + base);
+    if (tg.interior && aligned16(out + tg.base)) {
+        VT* dst = reinterpret_cast<VT*>(out + tg.base);
 #pragma unroll
         for (int kk = 0; kk < C / VN; ++kk) {
             const int i = VN * (lane + 64 * kk);
             if (i >= halo && i < W - halo)
-                __builtin_nontemporal_store(*reinterpret_cast<const VT*>(lds + lds_pos<T, C>(i)),
-                                            dst + lane + 64 * kk);
+                gstore_nt(*reinterpret_cast<const VT*>(lds + lds_pos<T, C>(i)), dst,
+                          lane + 64 * kk);
         }
     } else {
-#pragma unroll
-        for (int j = 0; j < C; ++j) {
-            const int i = lane + 64 * j;
-            const int64_t g = base + i;
-            if (g >= ostart && g < oend) out[g] = lds[lds_pos<T, C>(i)];
-        }
+        tile_store_slow<T, C>(s, tg.o0, tg.base, halo, lds);
     }
+    // the next tile's LDS writes must follow the reads above
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Advance tile `tile` of segment `s` by `steps` steps: the phases in a row.
+template <typename T, int C, bool SC>
+__device__ __forceinline__ void tile1d(const Seg1D& s, int64_t tile, int steps, int halo,
+                                       T* __restrict__ lds) {
+    static_assert(C % V16<T>::N == 0, "cells per lane must be a multiple of the vector width");
+    const TileGeom tg = tile_geom<C>(s, tile, halo);
+    T v[C];
+    if (tile_fast<T>(s, tg)) {
+        T pf[C];
+        tile_fetch<T, C>(s, tg, pf);
+        tile_stage<T, C>(pf, lds, v);
+    } else {
+        tile_fill_slow<T, C>(s, tg.base, tg.interior, lds);
+        __builtin_amdgcn_wave_barrier();
+        tile_read<T, C>(lds, v);
+    }
+    tile_steps<T, C, SC>(s, tg, steps, v);
+    tile_store<T, C>(s, tg, halo, lds, v);
 }
 
 // Dynamic LDS of the tile kernels: `wpg` wave areas of 64*(C + VN) cells.
@@ -264,35 +373,96 @@ __device__ __forceinline__ T* wave_lds() {
            __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * (64 * (C + VN));
 }
 
-template <typename T, int C>
+template <typename T, int C, bool SC>
 __global__ __launch_bounds__(256) void k_stencil1d(Seg1D s, int steps, int halo, int64_t ntiles) {
     const int wpg = blockDim.x >> 6;
     const int64_t tile = (int64_t)blockIdx.x * wpg + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (tile >= ntiles) return;
-    tile1d<T, C>(s, tile, steps, halo, wave_lds<T, C>());
+    tile1d<T, C, SC>(s, tile, steps, halo, wave_lds<T, C>());
 }
 
-// Out-of-line tile for the persistent loop: inlined into a loop, the tile's
-// code is allocated several times more registers than on its own.
-template <typename T, int C>
-__device__ __attribute__((noinline)) void tile1d_call(const Seg1D* __restrict__ segs, uint32_t si,
-                                                      uint32_t ti, int steps, int halo) {
-    tile1d<T, C>(segs[si], ti, steps, halo, wave_lds<T, C>());
+// Segment and tile of table entry t: computed when every segment has per_seg
+// tiles (the table is in segment order), else read from the table.
+__device__ __forceinline__ void locate_tile(const uint32_t* __restrict__ tseg,
+                                            const uint32_t* __restrict__ tidx, int64_t t,
+                                            int64_t per_seg, uint32_t& si, uint32_t& ti) {
+    if (per_seg > 0) {
+        // the tile table is uint32-indexed, so 32-bit division suffices
+        si = (uint32_t)t / (uint32_t)per_seg;
+        ti = (uint32_t)t - si * (uint32_t)per_seg;
+    } else {
+        si = __builtin_amdgcn_readfirstlane(tseg[t]);
+        ti = __builtin_amdgcn_readfirstlane(tidx[t]);
+    }
 }
 
-template <typename T, int C>
-__global__ __launch_bounds__(256) void k_stencil1d_batched(const Seg1D* __restrict__ segs,
-                                                           const uint32_t* __restrict__ tseg,
-                                                           const uint32_t* __restrict__ tidx,
-                                                           int64_t ntiles, int steps, int halo) {
+// Persistent, software-pipelined form: `gridDim.x * wpg` waves stride over the
+// tile table, and each wave issues the HBM reads of its next tile (into
+// registers) before running the current tile's steps, so the reads' latency
+// hides behind the arithmetic instead of behind other waves only.  `segs` is
+// the segment table (TAB), or unused for a single segment passed by value in
+// `s0` (!TAB); the two are separate instantiations so that the segment's fields
+// stay in scalar registers either way.
+template <typename T, int C, bool SC, bool TAB>
+__global__ __launch_bounds__(256) void k_stencil1d_pipe(Seg1D s0, const Seg1D* __restrict__ segs,
+                                                        const uint32_t* __restrict__ tseg,
+                                                        const uint32_t* __restrict__ tidx,
+                                                        int64_t ntiles, int steps, int halo,
+                                                        int64_t per_seg) {
     const int wpg = blockDim.x >> 6;
     const int64_t nwaves = (int64_t)gridDim.x * wpg;
+    int64_t t = (int64_t)blockIdx.x * wpg + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (t >= ntiles) return;
+    T* lds = wave_lds<T, C>();
+    // The segment and geometry of a tile are recomputed from its index where
+    // needed (scalar work), so that only the tile index, the prefetch flag and
+    // the prefetched registers are carried from one iteration to the next.
+    auto seg_of = [&](int64_t tt, uint32_t& ti) -> const Seg1D& {
+        uint32_t si = 0;
+        ti = (uint32_t)tt;
+        if constexpr (TAB) {
+            locate_tile(tseg, tidx, tt, per_seg, si, ti);
+            return segs[si];
+        } else {
+            return s0;
+        }
+    };
+    T pf[C], v[C];
+    bool fast;
+    {
+        uint32_t ti;
+        const Seg1D& s = seg_of(t, ti);
+        const TileGeom tg = tile_geom<C>(s, ti, halo);
+        fast = tile_fast<T>(s, tg);
+        if (fast) tile_fetch<T, C>(s, tg, pf);
+    }
 #pragma clang loop unroll(disable)
-    for (int64_t t = (int64_t)blockIdx.x * wpg + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-         t < ntiles; t += nwaves) {
-        const uint32_t si = __builtin_amdgcn_readfirstlane(tseg[t]);
-        const uint32_t ti = __builtin_amdgcn_readfirstlane(tidx[t]);
-        tile1d_call<T, C>(segs, si, ti, steps, halo);
+    for (;;) {
+        uint32_t ti;
+        const Seg1D& s = seg_of(t, ti);
+        const TileGeom tg = tile_geom<C>(s, ti, halo);
+        if (fast) {
+            tile_stage<T, C>(pf, lds, v);
+        } else {
+            tile_fill_slow<T, C>(s, tg.base, tg.interior, lds);
+            __builtin_amdgcn_wave_barrier();
+            tile_read<T, C>(lds, v);
+        }
+        const int64_t tn = t + nwaves;
+        const bool more = tn < ntiles;
+        bool fastn = false;
+        if (more) {
+            uint32_t tin;
+            const Seg1D& sn = seg_of(tn, tin);
+            const TileGeom tgn = tile_geom<C>(sn, tin, halo);
+            fastn = tile_fast<T>(sn, tgn);
+            if (fastn) tile_fetch<T, C>(sn, tgn, pf);  // overlaps the steps below
+        }
+        tile_steps<T, C, SC>(s, tg, steps, v);
+        tile_store<T, C>(s, tg, halo, lds, v);
+        if (!more) break;
+        t = tn;
+        fast = fastn;
     }
 }
 
@@ -307,7 +477,7 @@ size_t lds_bytes(const Geom1D& g) {
 // When every segment has the same tile count `per_seg` (a batch of equal
 // partitions), the tile's segment and index are computed instead of loaded, so
 // a wave's first HBM access does not wait behind two table lookups.
-template <typename T, int C>
+template <typename T, int C, bool SC>
 __global__ __launch_bounds__(256) void k_stencil1d_flat(const Seg1D* __restrict__ segs,
                                                         const uint32_t* __restrict__ tseg,
                                                         const uint32_t* __restrict__ tidx,
@@ -317,15 +487,44 @@ __global__ __launch_bounds__(256) void k_stencil1d_flat(const Seg1D* __restrict_
     const int64_t t = (int64_t)blockIdx.x * wpg + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (t >= ntiles) return;
     uint32_t si, ti;
-    if (per_seg > 0) {
-        // the tile table is uint32-indexed, so 32-bit division suffices
-        si = (uint32_t)t / (uint32_t)per_seg;
-        ti = (uint32_t)t - si * (uint32_t)per_seg;
-    } else {
-        si = __builtin_amdgcn_readfirstlane(tseg[t]);
-        ti = __builtin_amdgcn_readfirstlane(tidx[t]);
+    locate_tile(tseg, tidx, t, per_seg, si, ti);
+    tile1d<T, C, SC>(segs[si], ti, steps, halo, wave_lds<T, C>());
+}
+
+#define HX_CPL_SWITCH(KERNEL, ...)                                                    \
+    switch (g.cpl) {                                                                  \
+    case 8: hipLaunchKernelGGL((KERNEL<T, 8, SC>), __VA_ARGS__); break;                \
+    case 16: hipLaunchKernelGGL((KERNEL<T, 16, SC>), __VA_ARGS__); break;              \
+    case 32: hipLaunchKernelGGL((KERNEL<T, 32, SC>), __VA_ARGS__); break;              \
+    case 64: hipLaunchKernelGGL((KERNEL<T, 64, SC>), __VA_ARGS__); break;              \
+    default: return hipErrorInvalidValue;                                             \
     }
-    tile1d<T, C>(segs[si], ti, steps, halo, wave_lds<T, C>());
+
+template <typename T, bool SC>
+hipError_t launch_pipe(const Seg1D& s0, const Seg1D* segs, const uint32_t* tseg,
+                       const uint32_t* tidx, int64_t ntiles, const Geom1D& g, int64_t grid_waves,
+                       int64_t per_seg, hipStream_t st) {
+    const dim3 block(64 * g.wpg);
+    const dim3 grid((unsigned)((grid_waves + g.wpg - 1) / g.wpg));
+    const size_t sh = lds_bytes<T>(g);
+    if (segs) {
+        HX_CPL_SWITCH4(k_stencil1d_pipe, true, grid, block, sh, st, s0, segs, tseg, tidx, ntiles,
+                       g.steps, g.halo, per_seg)
+    } else {
+        HX_CPL_SWITCH4(k_stencil1d_pipe, false, grid, block, sh, st, s0, segs, tseg, tidx, ntiles,
+                       g.steps, g.halo, per_seg)
+    }
+    return hipGetLastError();
+}
+
+template <typename T, bool SC>
+hipError_t launch_single_sc(const Seg1D& s, const Geom1D& g, hipStream_t st) {
+    const int64_t ntiles = tiles_1d(s, g);
+    const dim3 block(64 * g.wpg);
+    const dim3 grid((unsigned)((ntiles + g.wpg - 1) / g.wpg));
+    const size_t sh = lds_bytes<T>(g);
+    HX_CPL_SWITCH(k_stencil1d, grid, block, sh, st, s, g.steps, g.halo, ntiles)
+    return hipGetLastError();
 }
 
 template <typename T>
@@ -333,47 +532,34 @@ hipError_t launch_single(const Seg1D& s0, const Geom1D& g, hipStream_t st) {
     Seg1D s = s0;
     s.shift = tile_shift(s.in, sizeof(T));
     set_rate_1d(s, g.steps);
-    const int64_t ntiles = tiles_1d(s, g);
+    return s.period > 0 ? launch_single_sc<T, true>(s, g, st) : launch_single_sc<T, false>(s, g, st);
+}
+
+template <typename T, bool SC>
+hipError_t launch_batched_sc(const Seg1D* segs, const uint32_t* tseg, const uint32_t* tidx,
+                             int64_t ntiles, const Geom1D& g, int64_t grid_waves, int64_t per_seg,
+                             hipStream_t st) {
+    if (grid_waves > 0 && grid_waves < ntiles)
+        return launch_pipe<T, SC>(Seg1D{}, segs, tseg, tidx, ntiles, g, grid_waves, per_seg, st);
     const dim3 block(64 * g.wpg);
-    const dim3 grid((unsigned)((ntiles + g.wpg - 1) / g.wpg));
     const size_t sh = lds_bytes<T>(g);
-    switch (g.cpl) {
-    case 8: hipLaunchKernelGGL((k_stencil1d<T, 8>), grid, block, sh, st, s, g.steps, g.halo, ntiles); break;
-    case 16: hipLaunchKernelGGL((k_stencil1d<T, 16>), grid, block, sh, st, s, g.steps, g.halo, ntiles); break;
-    case 32: hipLaunchKernelGGL((k_stencil1d<T, 32>), grid, block, sh, st, s, g.steps, g.halo, ntiles); break;
-    case 64: hipLaunchKernelGGL((k_stencil1d<T, 64>), grid, block, sh, st, s, g.steps, g.halo, ntiles); break;
-    default: return hipErrorInvalidValue;
-    }
+    const dim3 grid((unsigned)((ntiles + g.wpg - 1) / g.wpg));
+    HX_CPL_SWITCH(k_stencil1d_flat, grid, block, sh, st, segs, tseg, tidx, ntiles, g.steps,
+                  g.halo, per_seg)
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_batched(const Seg1D* segs, const uint32_t* tseg, const uint32_t* tidx,
                           int64_t ntiles, const Geom1D& g, int64_t grid_waves, int64_t per_seg,
-                          hipStream_t st) {
-    const dim3 block(64 * g.wpg);
-    const size_t sh = lds_bytes<T>(g);
-    if (grid_waves >= ntiles) {
-        const dim3 grid((unsigned)((ntiles + g.wpg - 1) / g.wpg));
-        switch (g.cpl) {
-        case 8: hipLaunchKernelGGL((k_stencil1d_flat<T, 8>), grid, block, sh, st, segs, tseg, tidx, ntiles, g.steps, g.halo, per_seg); break;
-        case 16: hipLaunchKernelGGL((k_stencil1d_flat<T, 16>), grid, block, sh, st, segs, tseg, tidx, ntiles, g.steps, g.halo, per_seg); break;
-        case 32: hipLaunchKernelGGL((k_stencil1d_flat<T, 32>), grid, block, sh, st, segs, tseg, tidx, ntiles, g.steps, g.halo, per_seg); break;
-        case 64: hipLaunchKernelGGL((k_stencil1d_flat<T, 64>), grid, block, sh, st, segs, tseg, tidx, ntiles, g.steps, g.halo, per_seg); break;
-        default: return hipErrorInvalidValue;
-        }
-        return hipGetLastError();
-    }
-    const dim3 grid((unsigned)((grid_waves + g.wpg - 1) / g.wpg));
-    switch (g.cpl) {
-    case 8: hipLaunchKernelGGL((k_stencil1d_batched<T, 8>), grid, block, sh, st, segs, tseg, tidx, ntiles, g.steps, g.halo); break;
-    case 16: hipLaunchKernelGGL((k_stencil1d_batched<T, 16>), grid, block, sh, st, segs, tseg, tidx, ntiles, g.steps, g.halo); break;
-    case 32: hipLaunchKernelGGL((k_stencil1d_batched<T, 32>), grid, block, sh, st, segs, tseg, tidx, ntiles, g.steps, g.halo); break;
-    case 64: hipLaunchKernelGGL((k_stencil1d_batched<T, 64>), grid, block, sh, st, segs, tseg, tidx, ntiles, g.steps, g.halo); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+                          bool scaled, hipStream_t st) {
+    return scaled ? launch_batched_sc<T, true>(segs, tseg, tidx, ntiles, g, grid_waves, per_seg, st)
+                  : launch_batched_sc<T, false>(segs, tseg, tidx, ntiles, g, grid_waves, per_seg,
+                                                st);
 }
+
+#undef HX_CPL_SWITCH
+#undef HX_CPL_SWITCH4
 
 }  // namespace
 
@@ -383,11 +569,12 @@ hipError_t launch_stencil1d(int dtype, const Seg1D& seg, const Geom1D& g, hipStr
 
 hipError_t launch_stencil1d_batched(int dtype, const Seg1D* segs_dev, const uint32_t* tile_seg,
                                     const uint32_t* tile_idx, int64_t ntiles, const Geom1D& g,
-                                    int64_t grid_waves, int64_t per_seg, hipStream_t stream) {
+                                    int64_t grid_waves, int64_t per_seg, bool scaled,
+                                    hipStream_t stream) {
     return dtype == 0 ? launch_batched<float>(segs_dev, tile_seg, tile_idx, ntiles, g, grid_waves,
-                                              per_seg, stream)
+                                              per_seg, scaled, stream)
                       : launch_batched<double>(segs_dev, tile_seg, tile_idx, ntiles, g,
-                                               grid_waves, per_seg, stream);
+                                               grid_waves, per_seg, scaled, stream);
 }
 
 }  // namespace hx

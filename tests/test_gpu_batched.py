@@ -34,7 +34,7 @@ def pack(sizes):
     return np.array(offs), o
 
 
-def run_batch(ctx, sizes, rs, steps, dtype, mode, cpl=0, sentinel=-7.0, seed=0):
+def run_batch(ctx, sizes, rs, steps, dtype, mode, cpl=0, sentinel=-7.0, seed=0, grid=0):
     offs, total = pack(sizes)
     u = np.full(total, sentinel, dtype=dtype)
     for k, (o, n) in enumerate(zip(offs, sizes)):
@@ -48,7 +48,8 @@ def run_batch(ctx, sizes, rs, steps, dtype, mode, cpl=0, sentinel=-7.0, seed=0):
                        tmp=btmp, tmp_offset=int(o) * es, n=int(n), r=float(r),
                        bc_lo=hx.HX_BC_PERIODIC, bc_hi=hx.HX_BC_PERIODIC)
             for o, n, r in zip(offs, sizes, rs)]
-    plan = hx.hx_plan_create_batched(ctx, code, steps, segs, mode, cells_per_lane=cpl)
+    plan = hx.hx_plan_create_batched(ctx, code, steps, segs, mode, cells_per_lane=cpl,
+                                     grid_waves_per_cu=grid)
     ev = hx.hx_launch_batched(ctx, plan)
     assert hx.hx_wait(ctx, ev) == hx.HX_OK, hx.hx_last_error(ctx)
     hx.hx_event_release(ctx, ev)
@@ -85,11 +86,15 @@ def test_uneven_batch_matches_oracle_all_modes(ctx, dtype, tol):
 
 
 @pytest.mark.parametrize("cpl", [8, 32, 64])
-def test_geometries_bitwise(ctx, cpl):
-    sizes = [1000, 50000, 7, 300000]
-    rs = [0.1, 0.25, 0.05, 0.2]
-    base = run_batch(ctx, sizes, rs, 20, np.float32, hx.HX_BATCH_PERSISTENT, cpl=16)[1]
-    got = run_batch(ctx, sizes, rs, 20, np.float32, hx.HX_BATCH_PERSISTENT, cpl=cpl)[1]
+@pytest.mark.parametrize("grid", [-1, 0, 1, 3])
+def test_geometries_bitwise(ctx, cpl, grid):
+    """Tile shapes and grid forms (one wave per tile, or persistent waves that
+    prefetch their next tile, with 1 or 3 waves per CU so that every wave
+    walks many tiles across segment boundaries) give identical bits."""
+    sizes = [1000, 50000, 7, 300000, 2000000, 65]
+    rs = [0.1, 0.25, 0.05, 0.2, 0.15, 0.45]
+    base = run_batch(ctx, sizes, rs, 20, np.float32, hx.HX_BATCH_PERSISTENT, cpl=16, grid=-1)[1]
+    got = run_batch(ctx, sizes, rs, 20, np.float32, hx.HX_BATCH_PERSISTENT, cpl=cpl, grid=grid)[1]
     assert np.array_equal(base, got)
 
 

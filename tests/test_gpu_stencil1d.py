@@ -96,6 +96,42 @@ def test_geometries_bitwise_equal(ctx, cpl, tb, wpg):
     assert rel_l2(got, ref) <= 1e-5
 
 
+@pytest.mark.parametrize("dtype,r", [(np.float32, 0.25), (np.float32, 0.45), (np.float64, 0.3)])
+def test_large_run_persistent_kernel(ctx, dtype, r):
+    """A long single run against the same pass as a one-segment batch run by
+    the persistent prefetching kernel (2 waves per CU, so every wave walks
+    dozens of tiles): bit-identical, and sampled cells against the oracle's
+    light cone."""
+    n = (1 << 25) + 12345
+    steps = 20
+    u0 = workloads.uniform(n, 205, int(r * 100), 0, 1, dtype)
+    code = hx.HX_F64 if dtype == np.float64 else hx.HX_F32
+    es = u0.itemsize
+    bin_ = upload(ctx, u0)
+    bout = hx.hx_buffer_create(ctx, n * es)
+    bref = hx.hx_buffer_create(ctx, n * es)
+    run(ctx, hx.stencil_args(dims=1, dtype=code, nx=n, steps=steps, r=r, inp=bin_, out=bout,
+                             cells_per_lane=8, time_block=steps))
+    plan = hx.hx_plan_create_batched(ctx, code, steps,
+                                     [hx.segment(inp=bin_, out=bref, n=n, r=r,
+                                                 bc_lo=hx.HX_BC_PERIODIC, bc_hi=hx.HX_BC_PERIODIC)],
+                                     hx.HX_BATCH_PERSISTENT, cells_per_lane=8,
+                                     grid_waves_per_cu=2)
+    ev = hx.hx_launch_batched(ctx, plan)
+    assert hx.hx_wait(ctx, ev) == hx.HX_OK
+    hx.hx_event_release(ctx, ev)
+    hx.hx_plan_destroy(ctx, plan)
+    got = download(ctx, bout, n, dtype)
+    ref_flat = download(ctx, bref, n, dtype)
+    assert np.array_equal(got, ref_flat)
+    rng = np.random.default_rng(21)
+    idx = np.sort(np.concatenate([rng.choice(n, 60, replace=False), [0, 1, n - 2, n - 1]]))
+    ref = oracle.heat1d_periodic_at(u0.astype(np.float64), r, steps, idx)
+    assert np.max(np.abs(got[idx] - ref) / np.abs(ref)) <= 10 * TOL[dtype]
+    for b in (bin_, bout, bref):
+        hx.hx_buffer_destroy(ctx, b)
+
+
 def test_paper_kernel_identity_on_gpu(ctx):
     """Sec. V-A.1's s(x) = 0.5 x_{i-1} + x_i + 0.5 x_{i+1} is 2 x one heat step at r = 1/4."""
     x = workloads.uniform(100003, 202, 0, -1, 1, np.float64)
