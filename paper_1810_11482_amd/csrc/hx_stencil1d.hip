@@ -500,6 +500,15 @@ __global__ __launch_bounds__(256) void k_stencil1d_flat(const Seg1D* __restrict_
     default: return hipErrorInvalidValue;                                             \
     }
 
+#define HX_CPL_SWITCH4(KERNEL, B, ...)                                                \
+    switch (g.cpl) {                                                                  \
+    case 8: hipLaunchKernelGGL((KERNEL<T, 8, SC, B>), __VA_ARGS__); break;             \
+    case 16: hipLaunchKernelGGL((KERNEL<T, 16, SC, B>), __VA_ARGS__); break;           \
+    case 32: hipLaunchKernelGGL((KERNEL<T, 32, SC, B>), __VA_ARGS__); break;           \
+    case 64: hipLaunchKernelGGL((KERNEL<T, 64, SC, B>), __VA_ARGS__); break;           \
+    default: return hipErrorInvalidValue;                                             \
+    }
+
 template <typename T, bool SC>
 hipError_t launch_pipe(const Seg1D& s0, const Seg1D* segs, const uint32_t* tseg,
                        const uint32_t* tidx, int64_t ntiles, const Geom1D& g, int64_t grid_waves,
