@@ -230,12 +230,15 @@ def main():
     ap.add_argument("--streams", type=int, default=4,
                     help="compute streams of the context (the per-partition graph spreads its "
                          "nodes over them)")
-    ap.add_argument("--legs", default="graph,plain,pipeline,batched,fp64,2d,adjoint,copy,cpu",
+    ap.add_argument("--legs",
+                    default="graph,plain,pipeline,batched,fp64,2d,adjoint,overhead,copy,cpu",
                     help="comma list of side legs: graph (the per-partition future graph), "
                          "plain, pipeline, batched, fp64 (2^20 fp64, 100 steps), 2d (16384^2, "
                          "200 steps, 16 bands), adjoint (8192^2, 100 steps), copy (a zero-step "
                          "pass over the arena: a plain 1 GiB device copy, for counter "
-                         "calibration), cpu; 'none' runs the headline only")
+                         "calibration), overhead (the partition benchmark of 2^21..2^28 "
+                         "doubles with a runtime-compiled kernel, hx futures against raw HIP "
+                         "streams), cpu; 'none' runs the headline only")
     args = ap.parse_args()
     legs = set(args.legs.split(","))
 
@@ -384,6 +387,8 @@ def main():
         result["banded_2d"] = banded2d_leg(hx, ctx)
     if "adjoint" in legs:
         result["adjoint"] = adjoint_leg(hx, ctx)
+    if "overhead" in legs:
+        result["overhead_vs_native"] = overhead_leg(hx)
 
     # --------------------------------------------------------------- CPU oracle
     if "cpu" in legs:
@@ -767,6 +772,130 @@ def copy_leg(hx, ctx, P, reps=5):
     nbytes = P.n * 8
     return {"cells": P.n, "bytes_moved": nbytes, "avg_ms": ms,
             "GBps": nbytes / (ms * 1e-3) / 1e9}
+
+
+OVERHEAD_SRC = r'''
+extern "C" __global__ void kmap(double* x, long n) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) { double v = x[i]; x[i] = sqrt(sin(v) * sin(v) + cos(v) * cos(v)); }
+}
+'''
+
+
+class NativeHip:
+    """The same partition benchmark written straight against the HIP runtime
+    (the one torch loaded): one stream per partition, async copies and a
+    module launch per partition, then a synchronize of every stream."""
+
+    def __init__(self, parts):
+        import ctypes
+        import torch
+        libdir = os.path.join(os.path.dirname(torch.__file__), "lib")
+        self.ct = ctypes
+        self.hip = ctypes.CDLL(os.path.join(libdir, "libamdhip64.so"))
+        self.streams = []
+        for _ in range(parts):
+            s = ctypes.c_void_p()
+            assert self.hip.hipStreamCreateWithFlags(ctypes.byref(s), 1) == 0
+            self.streams.append(s)
+        self.hip.hipMemcpyAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                            ctypes.c_int, ctypes.c_void_p]
+        self.hip.hipModuleLaunchKernel.argtypes = [ctypes.c_void_p] + [ctypes.c_uint] * 7 + [
+            ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p]
+        self.hip.hipStreamSynchronize.argtypes = [ctypes.c_void_p]
+        self.hip.hipStreamDestroy.argtypes = [ctypes.c_void_p]
+
+    def run(self, fn, host_in, host_out, dptrs, bounds):
+        ct = self.ct
+        keep = []
+        for (o, s), d, st in zip(bounds, dptrs, self.streams):
+            assert self.hip.hipMemcpyAsync(d, host_in + o * 8, s * 8, 1, st) == 0
+            a0, a1 = ct.c_void_p(d), ct.c_int64(s)
+            params = (ct.c_void_p * 2)(ct.cast(ct.byref(a0), ct.c_void_p),
+                                       ct.cast(ct.byref(a1), ct.c_void_p))
+            keep.append((a0, a1, params))
+            assert self.hip.hipModuleLaunchKernel(fn, (s + 255) // 256, 1, 1, 256, 1, 1, 0, st,
+                                                  params, None) == 0
+            assert self.hip.hipMemcpyAsync(host_out + o * 8, d, s * 8, 2, st) == 0
+        for st in self.streams:
+            assert self.hip.hipStreamSynchronize(st) == 0
+
+    def close(self):
+        for st in self.streams:
+            self.hip.hipStreamDestroy(st)
+
+
+def overhead_leg(hx, parts=4, iters=11):
+    """The paper's overhead experiment (Sec. V-A.2, Algorithm 1): a vector of
+    n = 2^m * 1024 * 256 * 4 doubles (m = 1..8) in `parts` partitions, each
+    copied in, mapped by k(x) = sqrt(sin^2 x + cos^2 x) (compiled at run time)
+    and copied out, all partitions in flight; the hx future graph against the
+    same work on raw HIP streams.  Each time is the mean of iterations 2..11,
+    the paper's method."""
+    import torch
+    ctx = hx.hx_ctx_create(0)
+    prog = hx.hx_program_create(ctx, OVERHEAD_SRC, "partition_kernel.hip")
+    hx.hx_program_build(ctx, prog)
+    fn = hx.hx_program_function(ctx, prog, "kmap")
+    nmax = (1 << 8) * 1024 * 256 * 4
+    hin = hx.hx_host_alloc(ctx, nmax * 8)
+    hout = hx.hx_host_alloc(ctx, nmax * 8)
+    arr = np.ctypeslib.as_array((np.ctypeslib.ctypes.c_double * nmax).from_address(hin))
+    arr[:] = np.arange(nmax, dtype=np.float64)
+    native = NativeHip(parts)
+    rows = []
+    for k, m in enumerate([1] + list(range(1, 9))):  # the first pass only warms up
+        n = (1 << m) * 1024 * 256 * 4
+        bounds = [(p * n // parts, (p + 1) * n // parts - p * n // parts) for p in range(parts)]
+        bufs = [hx.hx_buffer_create(ctx, s * 8) for _, s in bounds]
+        dptrs = [hx.hx_buffer_ptr(ctx, b)[0] for b in bufs]
+
+        def run_hx():
+            evs, keep = [], []
+            for (o, s), b in zip(bounds, bufs):
+                e1 = hx.hx_copy_async(ctx, hx.hx_copy_desc(hx.HX_H2D, hin + o * 8, b, 0, 0, 0,
+                                                           s * 8))
+                e2 = hx.hx_program_run(ctx, prog, "kmap",
+                                       [hx.karg_buffer(b), hx.karg_value(np.int64(s))],
+                                       ((s + 255) // 256,), (256,), deps=[e1])
+                e3 = hx.hx_copy_async(ctx, hx.hx_copy_desc(hx.HX_D2H, hout + o * 8, b, 0, 0, 0,
+                                                           s * 8), [e2])
+                evs.append(e3)
+                keep += [e1, e2]
+            w = hx.hx_when_all(ctx, evs)
+            assert hx.hx_wait(ctx, w) == hx.HX_OK, hx.hx_last_error(ctx)
+            for e in keep + evs + [w]:
+                hx.hx_event_release(ctx, e)
+
+        def run_native():
+            native.run(fn, hin, hout, dptrs, bounds)
+
+        res = {}
+        for name, f in (("hx", run_hx), ("native", run_native)):
+            ts = []
+            for _ in range(iters):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                f()
+                ts.append(time.perf_counter() - t0)
+            res[name] = float(np.mean(ts[1:])) * 1e3
+        out = np.ctypeslib.as_array((np.ctypeslib.ctypes.c_double * n).from_address(hout))
+        err = float(np.max(np.abs(out[:: max(1, n // 4096)] - 1.0)))
+        for b in bufs:
+            hx.hx_buffer_destroy(ctx, b)
+        if k == 0:
+            continue
+        rows.append({"m": m, "n": n, "hx_ms": res["hx"], "native_ms": res["native"],
+                     "hx_over_native": res["hx"] / res["native"],
+                     "host_link_GBps_hx": 2 * n * 8 / (res["hx"] * 1e-3) / 1e9,
+                     "max_abs_err_vs_1": err})
+        log(f"overhead m={m} n={n}: hx {res['hx']:.3f} ms, native {res['native']:.3f} ms")
+    native.close()
+    hx.hx_program_destroy(ctx, prog)
+    hx.hx_host_free(ctx, hin)
+    hx.hx_host_free(ctx, hout)
+    hx.hx_ctx_destroy(ctx)
+    return {"parts": parts, "dtype": "f64", "iterations": iters, "rows": rows}
 
 
 def cpu_leg(r, T):

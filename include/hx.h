@@ -496,6 +496,65 @@ hx_status hx_tune_cache_save(const char* path);
 /* Forget every tuned geometry (built-in defaults apply again). */
 hx_status hx_tune_cache_clear(void);
 
+/* ------------------------------------------------------------------ programs
+ * A kernel given as source text and compiled at run time for the context's
+ * GPU: the paper's program object (Sec. IV, Listing 2), which compiles CUDA
+ * source with NVRTC and runs a kernel with arguments, grid and block on the
+ * futures of its inputs.  Here hiprtc compiles HIP C++ for the device's
+ * architecture.  A program handle is an hx_plan-kind handle of the context. */
+typedef uint64_t hx_program;
+
+/* Copy `source` (NUL-terminated HIP C++; kernels declared
+ * extern "C" __global__) under the file name `name` (for diagnostics; null =
+ * "program.hip").  Nothing is compiled yet. */
+hx_status hx_program_create(hx_ctx ctx, const char* source, const char* name, hx_program* prog);
+
+/* Compile synchronously for the context's device (a host-only context
+ * compiles for gfx950 without loading the result), with the library's
+ * options (--offload-arch, -O3, packed FP32 instructions disabled) followed
+ * by the caller's `nopts` strings (null when nopts = 0).  HX_ERR_ARG when the
+ * source does not compile (the compiler's messages are in hx_program_log),
+ * HX_ERR_HIP when the code object does not load.  A program builds once. */
+hx_status hx_program_build(hx_ctx ctx, hx_program prog, const char* const* options, int nopts);
+
+/* The last build's compiler log, NUL-terminated and truncated to len;
+ * *needed (if non-null) receives the full length + 1. */
+hx_status hx_program_log(hx_ctx ctx, hx_program prog, char* buf, size_t len, size_t* needed);
+
+typedef enum { HX_ARG_BUFFER = 0, HX_ARG_VALUE = 1 } hx_arg_kind;
+enum { HX_ACCESS_READ = 1, HX_ACCESS_WRITE = 2 };
+
+/* One kernel argument.  HX_ARG_BUFFER: the device address of `buffer` +
+ * `offset`; `access` (HX_ACCESS_READ | HX_ACCESS_WRITE) declares how the
+ * kernel uses the bytes from `offset` to the end of the buffer, which the
+ * hazard checker and deferred frees rely on.  HX_ARG_VALUE: `size` bytes
+ * (1..16) from `value`, laid out as the kernel parameter's type. */
+typedef struct {
+    int32_t kind;
+    int32_t access;
+    hx_buffer buffer;
+    uint64_t offset;
+    uint32_t size;
+    uint32_t reserved;
+    uint8_t value[16];
+} hx_kernel_arg;
+
+/* Run `kernel` of a built program on grid[0..2] work-groups of
+ * block[0..2] work-items with `shared_bytes` of dynamic LDS, after `deps`;
+ * `args` are the kernel's parameters in order (not checked against its
+ * signature: a mismatch is the caller's error).  Argument errors return
+ * synchronously; launch errors complete the event with HX_ERR_HIP. */
+hx_status hx_program_run(hx_ctx ctx, hx_program prog, const char* kernel, const hx_kernel_arg* args,
+                         int nargs, const uint32_t grid[3], const uint32_t block[3],
+                         uint32_t shared_bytes, const hx_event* deps, int ndeps, hx_event* out);
+
+/* The hipFunction_t of a built program's kernel, for callers that launch it
+ * on streams of their own; valid until the program is destroyed. */
+hx_status hx_program_function(hx_ctx ctx, hx_program prog, const char* kernel, void** function);
+
+/* Wait for the context's streams, unload the code object, free the program. */
+hx_status hx_program_destroy(hx_ctx ctx, hx_program prog);
+
 #ifdef __cplusplus
 }
 #endif

@@ -123,6 +123,12 @@ class hx_vc_args(ctypes.Structure):
                 ("rows_per_block", ctypes.c_int)]
 
 
+class hx_kernel_arg(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("access", ctypes.c_int32), ("buffer", ctypes.c_uint64),
+                ("offset", ctypes.c_uint64), ("size", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("value", ctypes.c_uint8 * 16)]
+
+
 class hx_halo_desc(ctypes.Structure):
     _fields_ = [("src", _u64), ("src_offset", _sz), ("dst", _u64), ("dst_offset", _sz),
                 ("rows", _i64), ("row_bytes", _i64), ("src_pitch", _i64), ("dst_pitch", _i64)]
@@ -202,6 +208,15 @@ _PROTOS = {
     "hx_tune_batched": (_i32, [_vp, ctypes.POINTER(hx_batch_desc), ctypes.c_int,
                                ctypes.POINTER(hx_batch_desc)]),
     "hx_tune_cache_clear": (_i32, []),
+    "hx_program_create": (_i32, [_vp, ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(_u64)]),
+    "hx_program_build": (_i32, [_vp, _u64, ctypes.POINTER(ctypes.c_char_p), ctypes.c_int]),
+    "hx_program_log": (_i32, [_vp, _u64, ctypes.c_char_p, _sz, ctypes.POINTER(_sz)]),
+    "hx_program_run": (_i32, [_vp, _u64, ctypes.c_char_p, ctypes.POINTER(hx_kernel_arg),
+                              ctypes.c_int, ctypes.POINTER(ctypes.c_uint32),
+                              ctypes.POINTER(ctypes.c_uint32), ctypes.c_uint32,
+                              ctypes.POINTER(_u64), ctypes.c_int, ctypes.POINTER(_u64)]),
+    "hx_program_function": (_i32, [_vp, _u64, ctypes.c_char_p, ctypes.POINTER(_vp)]),
+    "hx_program_destroy": (_i32, [_vp, _u64]),
 }
 for _name, (_res, _args) in _PROTOS.items():
     _f = getattr(lib, _name)
@@ -400,6 +415,74 @@ def hx_launch_halo(ctx, plan: int, deps=()) -> int:
     ev = _u64()
     _ok(ctx, lib.hx_launch_halo(ctx, plan, arr, n, ctypes.byref(ev)))
     return ev.value
+
+
+HX_ARG_BUFFER, HX_ARG_VALUE = 0, 1
+HX_ACCESS_READ, HX_ACCESS_WRITE = 1, 2
+
+
+def karg_buffer(buf: int, offset: int = 0, access: int = HX_ACCESS_READ | HX_ACCESS_WRITE):
+    """A buffer kernel argument: the device address of buf + offset."""
+    a = hx_kernel_arg()
+    a.kind, a.access, a.buffer, a.offset = HX_ARG_BUFFER, access, buf, offset
+    return a
+
+
+def karg_value(x):
+    """A value kernel argument from a numpy scalar (its dtype is the parameter's type)."""
+    import numpy as np
+    x = np.asarray(x)
+    if x.ndim != 0 or x.nbytes > 16:
+        raise ValueError("a value argument is a numpy scalar of at most 16 bytes")
+    a = hx_kernel_arg()
+    a.kind, a.size = HX_ARG_VALUE, x.nbytes
+    ctypes.memmove(a.value, x.tobytes(), x.nbytes)
+    return a
+
+
+def hx_program_create(ctx, source: str, name: str = "program.hip") -> int:
+    h = _u64()
+    _ok(ctx, lib.hx_program_create(ctx, source.encode(), name.encode(), ctypes.byref(h)))
+    return h.value
+
+
+def hx_program_log(ctx, prog: int) -> str:
+    need = _sz()
+    _ok(ctx, lib.hx_program_log(ctx, prog, None, 0, ctypes.byref(need)))
+    buf = ctypes.create_string_buffer(max(1, need.value))
+    _ok(ctx, lib.hx_program_log(ctx, prog, buf, need.value, None))
+    return buf.value.decode(errors="replace")
+
+
+def hx_program_build(ctx, prog: int, options=()) -> None:
+    opts = [o.encode() for o in options]
+    arr = (ctypes.c_char_p * max(1, len(opts)))(*opts)
+    s = lib.hx_program_build(ctx, prog, arr, len(opts))
+    if s < 0:
+        raise HxError(s, hx_program_log(ctx, prog))
+
+
+def hx_program_run(ctx, prog: int, kernel: str, args, grid, block, shared_bytes: int = 0,
+                   deps=()) -> int:
+    """args: hx_kernel_arg values (karg_buffer / karg_value); grid, block: 1-3 ints."""
+    a = (hx_kernel_arg * max(1, len(args)))(*args)
+    g = (ctypes.c_uint32 * 3)(*(list(grid) + [1, 1, 1])[:3])
+    b = (ctypes.c_uint32 * 3)(*(list(block) + [1, 1, 1])[:3])
+    arr, n = _deps(deps)
+    ev = _u64()
+    _ok(ctx, lib.hx_program_run(ctx, prog, kernel.encode(), a, len(args), g, b, shared_bytes, arr,
+                                n, ctypes.byref(ev)))
+    return ev.value
+
+
+def hx_program_function(ctx, prog: int, kernel: str) -> int:
+    f = _vp()
+    _ok(ctx, lib.hx_program_function(ctx, prog, kernel.encode(), ctypes.byref(f)))
+    return f.value or 0
+
+
+def hx_program_destroy(ctx, prog: int) -> None:
+    _ok(ctx, lib.hx_program_destroy(ctx, prog))
 
 
 def segment(**kw) -> hx_segment:

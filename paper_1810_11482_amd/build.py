@@ -2,9 +2,10 @@
 
 Every HIP translation unit is compiled for gfx950 with hipcc; the host-only
 C++ files too (they use the HIP runtime API).  The library links the HIP
-runtime that the installed PyTorch ships (torch/lib/libamdhip64.so), so a
-process that uses torch for device memory and streams and this library for
-the kernels has exactly one HIP runtime loaded.
+runtime and runtime compiler that the installed PyTorch ships
+(torch/lib/libamdhip64.so, libhiprtc.so), so a process that uses torch for
+device memory and streams and this library for the kernels has exactly one HIP
+runtime loaded.
 
 Usage: python paper_1810_11482_amd/build.py  (run as a file: importing the package
 loads the library this script builds)
@@ -39,8 +40,9 @@ def _torch_lib_dir() -> str:
     if spec is None or not spec.submodule_search_locations:
         raise RuntimeError("torch is required: libhx links the HIP runtime torch ships")
     d = os.path.join(list(spec.submodule_search_locations)[0], "lib")
-    if not os.path.exists(os.path.join(d, "libamdhip64.so")):
-        raise RuntimeError(f"no libamdhip64.so in {d}")
+    for lib in ("libamdhip64.so", "libhiprtc.so"):
+        if not os.path.exists(os.path.join(d, lib)):
+            raise RuntimeError(f"no {lib} in {d}")
     return d
 
 
@@ -68,7 +70,8 @@ def build(verbose: bool = True) -> str:
     # Link with the host compiler against torch's runtime by full path, so the
     # library's NEEDED entry is the very libamdhip64.so torch loads.
     cmd = ["g++", "-shared", "-fPIC", "-o", tmp, *objs, "-Wl,--no-undefined",
-           os.path.join(tlib, "libamdhip64.so"), f"-Wl,-rpath,{tlib}", "-lpthread"]
+           os.path.join(tlib, "libamdhip64.so"), os.path.join(tlib, "libhiprtc.so"),
+           f"-Wl,-rpath,{tlib}", "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
