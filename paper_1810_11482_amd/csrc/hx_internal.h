@@ -104,7 +104,36 @@ struct Band2D {
     int32_t bc_top, bc_bot;
     int32_t hw;
     int32_t aligned;       // every row of in/out/halos starts 16-byte aligned
+    // Rescaled update (set_rate_2d for the pass's depth): period > 0 selects it.
+    int32_t period;        // levels between rescales
+    double beta;           // r / (1 - 4r)
+    double alpha_p;        // (1 - 4r)^period
+    double alpha_rem;      // (1 - 4r)^(steps mod period)
 };
+
+// The 2D analogue of set_rate_1d: u' = a u + r (u_n + u_s + u_w + u_e) with
+// a = 1 - 4r becomes w' = w + (r/a)(w_n + w_s + w_w + w_e) on w = u / a^k
+// (three adds and one fma per cell-level instead of five operations), with
+// rescales every `period` levels and at the end, so w never exceeds 2^16 u.
+// Used for 1/8 <= a <= 1 (0 <= r <= 7/32); other rates take the direct form.
+inline void set_rate_2d(Band2D& b, int steps) {
+    const double a = 1.0 - 4.0 * b.r;
+    b.period = 0;
+    b.beta = b.alpha_p = b.alpha_rem = 1.0;
+    if (!(a >= 0.125 && a <= 1.0)) return;
+    int p = 0;
+    double ap = 1.0;
+    while (p < 32 && ap * a >= 1.0 / 65536.0) {
+        ap *= a;
+        ++p;
+    }
+    double ar = 1.0;
+    for (int i = 0; i < (steps > 0 ? steps % p : 0); ++i) ar *= a;
+    b.period = p;
+    b.beta = b.r / a;
+    b.alpha_p = ap;
+    b.alpha_rem = ar;
+}
 
 struct Geom2D {
     int cpl;    // columns per lane: 4 (or 8 for f32 with steps <= 8)

@@ -19,8 +19,10 @@
 // barrier.  Outer context columns (H >= D per side) go stale one column per
 // level and are never stored.
 //
-// Per cell-step: a = n + s; b = w + e; t = a + b; d = fma(-4, c, t);
-// c' = fma(r, d, c) -- the same rounding in every geometry.
+// Per cell-step: t = (n + s) + (w + e), then for 0 <= r <= 7/32 the rescaled
+// update w' = fma(r/(1-4r), t, w) (set_rate_2d), otherwise d = fma(-4, c, t);
+// c' = fma(r, d, c).  A pass's result depends on its depth only, not on the
+// tile geometry.
 #include <hip/hip_runtime.h>
 
 #include "hx_internal.h"
@@ -52,6 +54,57 @@ __device__ __forceinline__ double dpp_move(double x) {
 
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// The per-cell update of one level: direct (k = r) or rescaled (SC: b =
+// r/(1-4r), and the level's row is multiplied by ap at every rescale level,
+// by arem at the last one when the depth is not a multiple of the period;
+// `mask` has bit l set for the levels l+1 that rescale).
+template <typename T>
+struct Rate2 {
+    T k, b, ap, arem;
+    uint32_t mask;
+    bool tail;
+};
+
+template <typename T, int D, bool SC>
+__device__ __forceinline__ Rate2<T> make_rate(const Band2D& band) {
+    Rate2<T> rt;
+    rt.k = static_cast<T>(band.r);
+    rt.b = static_cast<T>(band.beta);
+    rt.ap = static_cast<T>(band.alpha_p);
+    rt.arem = static_cast<T>(band.alpha_rem);
+    rt.mask = 0;
+    rt.tail = false;
+    if constexpr (SC) {
+        const int p = band.period;
+        for (int l = 0; l < D; ++l)
+            if ((l + 1) % p == 0) rt.mask |= 1u << l;
+        rt.tail = (D % p) != 0;
+        if (rt.tail) rt.mask |= 1u << (D - 1);
+    }
+    return rt;
+}
+
+template <typename T, bool SC>
+__device__ __forceinline__ T update(const Rate2<T>& rt, T c, T t) {
+    if constexpr (SC) {
+        return fmaT(rt.b, t, c);
+    } else {
+        const T d = fmaT(T(-4), c, t);
+        return fmaT(rt.k, d, c);
+    }
+}
+
+template <typename T, int C, int D, bool SC>
+__device__ __forceinline__ void rescale_level(const Rate2<T>& rt, int l, T* v) {
+    if constexpr (SC) {
+        if ((rt.mask >> l) & 1u) {
+            const T f = (l + 1 == D && rt.tail) ? rt.arem : rt.ap;
+#pragma unroll
+            for (int j = 0; j < C; ++j) v[j] *= f;
+        }
+    }
+}
 
 __device__ __forceinline__ bool aligned16(const void* p) {
     return (reinterpret_cast<uintptr_t>(p) & 15u) == 0;
@@ -134,10 +187,10 @@ constexpr int ring_rows() { return 6; }
 // none of the rows it produces is a zero-Dirichlet ghost, so no cell is masked
 // and each level is straight-line code (which also lets the compiler fold the
 // DPP shifts into the adds).
-template <typename T, int C, int D, int Q, int M, bool EDGE>
+template <typename T, int C, int D, int Q, int M, bool EDGE, bool SC>
 __device__ __forceinline__ void row_step(const Band2D& b, const Strip& w, int halo, int64_t yy,
                                          int64_t yend, T (&Z)[Q][C], T (&R)[D][3][C],
-                                         const bool (&colok)[C], T k) {
+                                         const bool (&colok)[C], const Rate2<T>& rt) {
     typedef typename V16<T>::t VT;
     constexpr int VN = V16<T>::N;
     constexpr int S = 64 * C;
@@ -159,8 +212,7 @@ __device__ __forceinline__ void row_step(const Band2D& b, const Strip& w, int ha
             const T we = (j > 0 ? cn[j - 1] : left) + (j + 1 < C ? cn[j + 1] : right);
             const T ns = no[j] + so[j];
             const T t = ns + we;
-            const T d = fmaT(T(-4), c, t);
-            nw[j] = fmaT(k, d, c);
+            nw[j] = update<T, SC>(rt, c, t);
         }
         if constexpr (EDGE) {
             if (zero_row(b, yo)) {
@@ -171,6 +223,7 @@ __device__ __forceinline__ void row_step(const Band2D& b, const Strip& w, int ha
                 for (int j = 0; j < C; ++j) nw[j] = colok[j] ? nw[j] : T(0);
             }
         }
+        rescale_level<T, C, D, SC>(rt, l, nw);
         if (l + 1 < D) {
 #pragma unroll
             for (int j = 0; j < C; ++j) R[l + 1 < D ? l + 1 : 0][M3][j] = nw[j];
@@ -282,9 +335,9 @@ __device__ __forceinline__ void store_fast(const FastIO<T, C>& io, int64_t y, co
     }
 }
 
-template <typename T, int C, int D, int Q, int M, bool STORE, bool EDGE>
+template <typename T, int C, int D, int Q, int M, bool STORE, bool EDGE, bool SC>
 __device__ __forceinline__ void row_step_fast(const FastIO<T, C>& io, int64_t yy, T (&Z)[Q][C],
-                                              T (&R)[D][3][C], T k) {
+                                              T (&R)[D][3][C], const Rate2<T>& rt) {
     constexpr int VN = V16<T>::N;
     constexpr int M3 = M % 3, OLD = (M3 + 1) % 3, NEW = (M3 + 2) % 3;
     load_fast<T, C, EDGE>(io, yy + Q - 3, Z[(M + Q - 3) % Q]);
@@ -304,48 +357,50 @@ __device__ __forceinline__ void row_step_fast(const FastIO<T, C>& io, int64_t yy
             const T we = (j > 0 ? cn[j - 1] : left) + (j + 1 < C ? cn[j + 1] : right);
             const T ns = no[j] + so[j];
             const T t = ns + we;
-            const T d = fmaT(T(-4), c, t);
-            const T v = fmaT(k, d, c);
+            const T v = update<T, SC>(rt, c, t);
             dst[j] = (EDGE && (zr || !io.colin[j / VN])) ? T(0) : v;
         }
+        rescale_level<T, C, D, SC>(rt, l, dst);
     }
     if constexpr (STORE) store_fast<T, C>(io, yy - D, last);
 }
 
 // N consecutive row steps starting at ring position M.  Steps that store
 // stop at the chunk's end.
-template <typename T, int C, int D, int Q, int M, int N, bool STORE, bool EDGE>
+template <typename T, int C, int D, int Q, int M, int N, bool STORE, bool EDGE, bool SC>
 __device__ __forceinline__ void steps_fast(const FastIO<T, C>& io, int64_t& yy, int64_t yend,
-                                           T (&Z)[Q][C], T (&R)[D][3][C], T k) {
+                                           T (&Z)[Q][C], T (&R)[D][3][C], const Rate2<T>& rt) {
     if constexpr (N > 0) {
         if (STORE && yy >= yend) return;
-        row_step_fast<T, C, D, Q, M, STORE, EDGE>(io, yy, Z, R, k);
+        row_step_fast<T, C, D, Q, M, STORE, EDGE, SC>(io, yy, Z, R, rt);
         ++yy;
-        steps_fast<T, C, D, Q, (M + 1) % Q, N - 1, STORE, EDGE>(io, yy, yend, Z, R, k);
+        steps_fast<T, C, D, Q, (M + 1) % Q, N - 1, STORE, EDGE, SC>(io, yy, yend, Z, R, rt);
     }
 }
 
 // Rows ystart .. ystart+2D-1 fill the pipeline (nothing to store yet); from
 // then on every row step stores row yy - D, an output row of the chunk.
-template <typename T, int C, int D, int Q, bool EDGE>
+template <typename T, int C, int D, int Q, bool EDGE, bool SC>
 __device__ __forceinline__ void stream_rows_fast(const FastIO<T, C>& io, int64_t ystart,
                                                  int64_t yend, T (&Z)[Q][C], T (&R)[D][3][C],
-                                                 T k) {
+                                                 const Rate2<T>& rt) {
     constexpr int W = 2 * D, WF = W / Q, WR = W % Q;
 #pragma unroll
     for (int m = 0; m < Q - 3; ++m) load_fast<T, C, EDGE>(io, ystart + m, Z[m]);
     int64_t yy = ystart;
-    for (int i = 0; i < WF; ++i) steps_fast<T, C, D, Q, 0, Q, false, EDGE>(io, yy, yend, Z, R, k);
-    steps_fast<T, C, D, Q, 0, WR, false, EDGE>(io, yy, yend, Z, R, k);
-    while (yy < yend) steps_fast<T, C, D, Q, WR, Q, true, EDGE>(io, yy, yend, Z, R, k);
+    for (int i = 0; i < WF; ++i)
+        steps_fast<T, C, D, Q, 0, Q, false, EDGE, SC>(io, yy, yend, Z, R, rt);
+    steps_fast<T, C, D, Q, 0, WR, false, EDGE, SC>(io, yy, yend, Z, R, rt);
+    while (yy < yend) steps_fast<T, C, D, Q, WR, Q, true, EDGE, SC>(io, yy, yend, Z, R, rt);
 }
 
 // The row loop of the general form, unrolled Q times so that every ring slot
 // index is a compile-time constant.
-template <typename T, int C, int D, int Q, bool EDGE>
+template <typename T, int C, int D, int Q, bool EDGE, bool SC>
 __device__ __forceinline__ void stream_rows(const Band2D& b, const Strip& w, int halo,
                                             int64_t ystart, int64_t yend, T (&Z)[Q][C],
-                                            T (&R)[D][3][C], const bool (&colok)[C], T k) {
+                                            T (&R)[D][3][C], const bool (&colok)[C],
+                                            const Rate2<T>& k) {
 #pragma unroll
     for (int m = 0; m < Q - 3; ++m) {
         if (ystart + m < yend) {
@@ -356,31 +411,31 @@ __device__ __forceinline__ void stream_rows(const Band2D& b, const Strip& w, int
         }
     }
     for (int64_t yy = ystart; yy < yend; yy += Q) {
-        row_step<T, C, D, Q, 0, EDGE>(b, w, halo, yy, yend, Z, R, colok, k);
+        row_step<T, C, D, Q, 0, EDGE, SC>(b, w, halo, yy, yend, Z, R, colok, k);
         if (yy + 1 >= yend) break;
-        row_step<T, C, D, Q, 1, EDGE>(b, w, halo, yy + 1, yend, Z, R, colok, k);
+        row_step<T, C, D, Q, 1, EDGE, SC>(b, w, halo, yy + 1, yend, Z, R, colok, k);
         if (yy + 2 >= yend) break;
-        row_step<T, C, D, Q, 2, EDGE>(b, w, halo, yy + 2, yend, Z, R, colok, k);
+        row_step<T, C, D, Q, 2, EDGE, SC>(b, w, halo, yy + 2, yend, Z, R, colok, k);
         if (yy + 3 >= yend) break;
-        row_step<T, C, D, Q, 3 % Q, EDGE>(b, w, halo, yy + 3, yend, Z, R, colok, k);
+        row_step<T, C, D, Q, 3 % Q, EDGE, SC>(b, w, halo, yy + 3, yend, Z, R, colok, k);
         if (yy + 4 >= yend) break;
-        row_step<T, C, D, Q, 4 % Q, EDGE>(b, w, halo, yy + 4, yend, Z, R, colok, k);
+        row_step<T, C, D, Q, 4 % Q, EDGE, SC>(b, w, halo, yy + 4, yend, Z, R, colok, k);
         if (yy + 5 >= yend) break;
-        row_step<T, C, D, Q, 5 % Q, EDGE>(b, w, halo, yy + 5, yend, Z, R, colok, k);
+        row_step<T, C, D, Q, 5 % Q, EDGE, SC>(b, w, halo, yy + 5, yend, Z, R, colok, k);
         if constexpr (Q > 6) {
             if (yy + 6 >= yend) break;
-            row_step<T, C, D, Q, 6 % Q, EDGE>(b, w, halo, yy + 6, yend, Z, R, colok, k);
+            row_step<T, C, D, Q, 6 % Q, EDGE, SC>(b, w, halo, yy + 6, yend, Z, R, colok, k);
             if (yy + 7 >= yend) break;
-            row_step<T, C, D, Q, 7 % Q, EDGE>(b, w, halo, yy + 7, yend, Z, R, colok, k);
+            row_step<T, C, D, Q, 7 % Q, EDGE, SC>(b, w, halo, yy + 7, yend, Z, R, colok, k);
             if (yy + 8 >= yend) break;
-            row_step<T, C, D, Q, 8 % Q, EDGE>(b, w, halo, yy + 8, yend, Z, R, colok, k);
+            row_step<T, C, D, Q, 8 % Q, EDGE, SC>(b, w, halo, yy + 8, yend, Z, R, colok, k);
         }
     }
 }
 
 // FAST = true: the static-count form (the host checks alignment and size);
 // FAST = false: the general form with per-row boundary handling.
-template <typename T, int C, int D, bool FAST>
+template <typename T, int C, int D, bool FAST, bool SC>
 __global__ __launch_bounds__(256) void k_stencil2d(Band2D b, int rows, int halo, int64_t nstrips,
                                                    int64_t nwaves) {
     constexpr int VN = V16<T>::N;
@@ -403,7 +458,7 @@ __global__ __launch_bounds__(256) void k_stencil2d(Band2D b, int rows, int halo,
     w.y1 = (w.y0 + rows < b.ny) ? w.y0 + rows : b.ny;
     w.xin = xb >= 0 && xb + S <= b.nx;
     w.vec = w.xin && b.aligned;
-    const T k = static_cast<T>(b.r);
+    const Rate2<T> k = make_rate<T, D, SC>(b);
 
     // Rows above the first streamed row only feed rows that are never stored;
     // they start as zeros so that no stale register value is ever read.
@@ -455,9 +510,9 @@ __global__ __launch_bounds__(256) void k_stencil2d(Band2D b, int rows, int halo,
                             : OOB_OFFSET;
         }
         if (edge) {
-            stream_rows_fast<T, C, D, Q, true>(io, ystart, yend, Z, R, k);
+            stream_rows_fast<T, C, D, Q, true, SC>(io, ystart, yend, Z, R, k);
         } else {
-            stream_rows_fast<T, C, D, Q, false>(io, ystart, yend, Z, R, k);
+            stream_rows_fast<T, C, D, Q, false, SC>(io, ystart, yend, Z, R, k);
         }
     } else {
         // column mask for edge strips (cells outside [0, nx) are zero ghosts)
@@ -465,9 +520,9 @@ __global__ __launch_bounds__(256) void k_stencil2d(Band2D b, int rows, int halo,
 #pragma unroll
         for (int j = 0; j < C; ++j) colok[j] = (w.xl + j >= 0) && (w.xl + j < b.nx);
         if (edge)
-            stream_rows<T, C, D, Q, true>(b, w, halo, ystart, yend, Z, R, colok, k);
+            stream_rows<T, C, D, Q, true, SC>(b, w, halo, ystart, yend, Z, R, colok, k);
         else
-            stream_rows<T, C, D, Q, false>(b, w, halo, ystart, yend, Z, R, colok, k);
+            stream_rows<T, C, D, Q, false, SC>(b, w, halo, ystart, yend, Z, R, colok, k);
     }
 }
 
@@ -482,12 +537,21 @@ hipError_t launch_cd(const Band2D& b, const Geom2D& g, hipStream_t st) {
     constexpr int VN = V16<T>::N;
     const bool fast = b.aligned && b.nx % VN == 0 && b.nx >= VN &&
                       b.ny * b.nx * (int64_t)sizeof(T) < (int64_t(1) << 31);
-    if (fast)
-        hipLaunchKernelGGL((k_stencil2d<T, C, D, true>), grid, block, 0, st, b, g.rows, g.halo,
-                           nstrips, nwaves);
+    Band2D bb = b;
+    set_rate_2d(bb, D);
+    const bool sc = bb.period > 0;
+    if (fast && sc)
+        hipLaunchKernelGGL((k_stencil2d<T, C, D, true, true>), grid, block, 0, st, bb, g.rows,
+                           g.halo, nstrips, nwaves);
+    else if (fast)
+        hipLaunchKernelGGL((k_stencil2d<T, C, D, true, false>), grid, block, 0, st, bb, g.rows,
+                           g.halo, nstrips, nwaves);
+    else if (sc)
+        hipLaunchKernelGGL((k_stencil2d<T, C, D, false, true>), grid, block, 0, st, bb, g.rows,
+                           g.halo, nstrips, nwaves);
     else
-        hipLaunchKernelGGL((k_stencil2d<T, C, D, false>), grid, block, 0, st, b, g.rows, g.halo,
-                           nstrips, nwaves);
+        hipLaunchKernelGGL((k_stencil2d<T, C, D, false, false>), grid, block, 0, st, bb, g.rows,
+                           g.halo, nstrips, nwaves);
     return hipGetLastError();
 }
 
