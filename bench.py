@@ -578,6 +578,7 @@ def pipeline_leg(hx, ctx0, P, T, r, cpl):
     res = {"wall_ms": W * 1e3, "copies_alone_ms": t_copy * 1e3, "kernels_alone_ms": t_kernel * 1e3,
            "pcie_inclusive_cell_updates_per_s": P.n * T / W,
            "copy_hidden_literal": lit, "overlap_efficiency_eta": eta,
+           "copy_bound_efficiency": t_copy / W,
            "host_link_GBps_during_overlap": bytes_copied / (measure_len(C) * 1e-3) / 1e9,
            "sampled_max_rel_err": err}
     log(f"pipeline: {res}")
