@@ -646,11 +646,14 @@ def banded2d_leg(hx, ctx):
         assert hx.hx_wait(ctx, e) == hx.HX_OK
         hx.hx_event_release(ctx, e)
     best = None
-    for tb, cpl, rows in ((16, 4, 128), (12, 4, 128), (10, 4, 128), (8, 4, 64), (16, 4, 256)):
+    per_mode = {}
+    cands = [(mode, tb, 4, rows) for mode in (hx.HX_PART_BATCHED, hx.HX_PART_GRAPH)
+             for tb, rows in ((16, 128), (12, 128), (8, 64))]
+    for mode, tb, cpl, rows in cands:
         upload()
         d = hx.partitioned_desc(hx.HX_F32, [s for _, s in bounds], A, B, spec.steps, spec.r,
                                 periodic=False, time_block=tb, cells_per_lane=cpl, dims=2,
-                                nx=spec.nx, rows_per_block=rows)
+                                nx=spec.nx, rows_per_block=rows, mode=mode)
         ts = []
         for it in range(2):
             torch.cuda.synchronize()
@@ -660,20 +663,26 @@ def banded2d_leg(hx, ctx):
             ts.append(time.perf_counter() - t0)
             hx.hx_event_release(ctx, ev)
         sec = ts[-1]
-        log(f"2D bands tb={tb} cpl={cpl} rows={rows}: {sec * 1e3:.2f} ms")
+        mname = "batched" if mode == hx.HX_PART_BATCHED else "graph"
+        log(f"2D bands {mname} tb={tb} cpl={cpl} rows={rows}: {sec * 1e3:.2f} ms")
         if best is None or sec < best[0]:
-            best = (sec, tb, cpl, rows)
-    sec, tb, cpl, rows = best
+            best = (sec, tb, cpl, rows, mode)
+        by_mode = per_mode.setdefault(mname, sec)
+        per_mode[mname] = min(by_mode, sec)
+    sec, tb, cpl, rows, mode = best
     passes = -(-spec.steps // tb)
     res = {"ny": spec.ny, "nx": spec.nx, "bands": spec.bands, "steps": spec.steps, "ms": sec * 1e3,
            "cell_updates_per_s": cells * spec.steps / sec, "time_block": tb, "cells_per_lane": cpl,
            "rows_per_block": rows,
+           "form": "one launch per pass over all bands" if mode == hx.HX_PART_BATCHED
+           else "one launch per band per pass",
+           "ms_by_form": {k: v * 1e3 for k, v in per_mode.items()},
            "hbm_algorithmic_GBps": cells * 8 * passes / sec / 1e9}
     # sampled correctness of the best configuration against the oracle
     import oracle
     d = hx.partitioned_desc(hx.HX_F32, [s for _, s in bounds], A, B, spec.steps, spec.r,
                             periodic=False, time_block=tb, cells_per_lane=cpl, dims=2,
-                            nx=spec.nx, rows_per_block=rows)
+                            nx=spec.nx, rows_per_block=rows, mode=mode)
     upload()
     ev, in_b, _ = hx.hx_run_partitioned(ctx, d)
     assert hx.hx_wait(ctx, ev) == hx.HX_OK

@@ -216,7 +216,7 @@ hx_status hx_launch_stencil(hx_ctx ctx, const hx_stencil_args* args, const hx_ev
                             int ndeps, hx_event* out);
 
 /* ------------------------------------------------------ partitioned arrays */
-typedef enum { HX_PART_GRAPH = 0, HX_PART_PLAIN = 1 } hx_part_mode;
+typedef enum { HX_PART_GRAPH = 0, HX_PART_PLAIN = 1, HX_PART_BATCHED = 2 } hx_part_mode;
 
 typedef struct {
     int dtype;                  /* hx_dtype */
@@ -248,7 +248,10 @@ typedef struct {
  * and depends on nodes (p-1, b-1),
  * (p, b-1) and (p+1, b-1); independent nodes run concurrently on the compute
  * streams.  HX_PART_PLAIN: the comparator: one step per launch, issued in
- * Algorithm 1's order and chained on one stream.  `deps` gate the first pass.
+ * Algorithm 1's order and chained on one stream.  HX_PART_BATCHED (2D bands
+ * only): every pass is one launch per group of up to 16 bands (one node per
+ * launch, depending on every node of the previous pass); 1D partitions batch
+ * through hx_plan_create_batched.  `deps` gate the first pass.
  * *out completes when the last pass has; the final state is in bufs_b if
  * *final_in_b is 1, else in bufs_a.  node_events (optional, parts x passes
  * entries, pass-major) receives every node's event; the caller releases them. */

@@ -96,7 +96,7 @@ class hx_pipeline_desc(ctypes.Structure):
     _fields_ = [("part", hx_partitioned_desc), ("host_in", _vp), ("host_out", _vp)]
 
 
-HX_PART_GRAPH, HX_PART_PLAIN = 0, 1
+HX_PART_GRAPH, HX_PART_PLAIN, HX_PART_BATCHED = 0, 1, 2
 HX_BATCH_PERSISTENT, HX_BATCH_GRAPH, HX_BATCH_PLAIN = 0, 1, 2
 
 

@@ -145,6 +145,10 @@ struct Geom2D {
 
 bool stencil2d_supported(int dtype, int cpl, int steps);
 hipError_t launch_stencil2d(int dtype, const Band2D& b, const Geom2D& g, hipStream_t stream);
+// Up to kMaxBands bands of one grid (same nx, r, depth g.steps) in one launch.
+constexpr int kMaxBands = 16;
+hipError_t launch_stencil2d_bands(int dtype, const Band2D* bands, int n, const Geom2D& g,
+                                  hipStream_t stream);
 
 // One variable-coefficient step (forward: out = A u; adjoint: out = A^T lam
 // and gacc += the step's conductivity gradient) on an ny x nx grid.

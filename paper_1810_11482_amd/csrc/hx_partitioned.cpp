@@ -20,6 +20,7 @@
 #include <string>
 #include <vector>
 
+#include "hx_internal.h"
 #include "hx_runtime.hpp"
 
 using namespace hx;
@@ -59,6 +60,133 @@ hx_status validate(Ctx* c, const hx_partitioned_desc* d) {
 
 }  // namespace
 
+namespace {
+
+// HX_PART_BATCHED for 2D bands: every pass advances all bands in launches of
+// up to kMaxBands bands each (one node per launch), each band reading its halo
+// rows from its neighbours' buffers of the previous pass.  A node depends on
+// every node of the previous pass.
+hx_status run_bands_batched(Ctx* c, const hx_partitioned_desc* d, hx_event gate, hx_event* out,
+                            int* final_in_b, hx_event* node_events) {
+    const int P = d->parts;
+    const int dt = d->dtype == HX_F64 ? 1 : 0;
+    const int64_t es = dt ? 8 : 4;
+    const int vn = dt ? 2 : 4;
+    Geom2D g;
+    g.cpl = d->cells_per_lane ? d->cells_per_lane : 4;
+    g.rows = d->rows_per_block ? d->rows_per_block : 128;
+    g.wpg = d->waves_per_group ? d->waves_per_group : 4;
+    if (g.wpg != 1 && g.wpg != 2 && g.wpg != 4)
+        return c->fail(HX_ERR_ARG, "waves_per_group must be 1, 2 or 4");
+    if (g.rows < 1) return c->fail(HX_ERR_ARG, "rows_per_block must be positive");
+    const int D = d->time_block > 0 ? d->time_block : std::min(d->steps, 8);
+    int64_t min_rows = d->sizes[0];
+    for (int p = 1; p < P; ++p) min_rows = std::min(min_rows, d->sizes[p]);
+    if (D > min_rows) return c->fail(HX_ERR_ARG, "time_block exceeds the smallest band");
+    // pass depths: D, D, ..., remainder; every depth must have a kernel
+    std::vector<int> plan;
+    for (int left = d->steps; left > 0; left -= std::min(D, left)) plan.push_back(std::min(D, left));
+    for (int depth : plan)
+        if (!stencil2d_supported(dt, g.cpl, depth))
+            return c->fail(HX_ERR_ARG, "unsupported 2D pass depth " + std::to_string(depth));
+    const int groups = (P + kMaxBands - 1) / kMaxBands;
+    std::vector<hx_event> prev, cur;
+    if (gate) {
+        hx_event gcopy = 0;
+        hx_status s = when_all_locked(c, &gate, 1, &gcopy);
+        if (s) return s;
+        prev.push_back(gcopy);
+    }
+    const bool give = node_events != nullptr;
+    int node = 0;
+    auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; };
+    for (size_t b = 0; b < plan.size(); ++b) {
+        const int depth = plan[b];
+        const bool src_a = (b % 2 == 0);
+        Geom2D gg = g;
+        gg.steps = depth;
+        gg.halo = std::max(vn, (depth + vn - 1) / vn * vn);
+        for (int gi = 0; gi < groups; ++gi) {
+            const int p0 = gi * kMaxBands, p1 = std::min(P, p0 + kMaxBands);
+            std::vector<Band2D> bands;
+            std::vector<Access> acc;
+            for (int p = p0; p < p1; ++p) {
+                const hx_buffer in = src_a ? d->bufs_a[p] : d->bufs_b[p];
+                const hx_buffer outb = src_a ? d->bufs_b[p] : d->bufs_a[p];
+                const int64_t band_bytes = d->sizes[p] * d->nx * es;
+                char *pin = nullptr, *pout = nullptr, *ptop = nullptr, *pbot = nullptr;
+                Access a{};
+                hx_status s = resolve_range(c, in, 0, (size_t)band_bytes, &pin, &a, false);
+                if (s) return s;
+                acc.push_back(a);
+                s = resolve_range(c, outb, 0, (size_t)band_bytes, &pout, &a, true);
+                if (s) return s;
+                acc.push_back(a);
+                Band2D bd{};
+                bd.nx = d->nx;
+                bd.ny = d->sizes[p];
+                bd.r = d->r;
+                bd.hw = depth;
+                bd.bc_top = p > 0 ? HX_BC_GHOST : HX_BC_DIRICHLET0;
+                bd.bc_bot = p < P - 1 ? HX_BC_GHOST : HX_BC_DIRICHLET0;
+                const size_t hb = (size_t)depth * d->nx * es;
+                if (p > 0) {
+                    const hx_buffer hbuf = src_a ? d->bufs_a[p - 1] : d->bufs_b[p - 1];
+                    s = resolve_range(c, hbuf, (size_t)(d->sizes[p - 1] - depth) * d->nx * es, hb,
+                                      &ptop, &a, false);
+                    if (s) return s;
+                    acc.push_back(a);
+                }
+                if (p < P - 1) {
+                    const hx_buffer hbuf = src_a ? d->bufs_a[p + 1] : d->bufs_b[p + 1];
+                    s = resolve_range(c, hbuf, 0, hb, &pbot, &a, false);
+                    if (s) return s;
+                    acc.push_back(a);
+                }
+                bd.in = pin;
+                bd.out = pout;
+                bd.halo_top = ptop;
+                bd.halo_bot = pbot;
+                bd.aligned = (d->nx % vn == 0) && al(pin) && al(pout) && (!ptop || al(ptop)) &&
+                             (!pbot || al(pbot));
+                bands.push_back(bd);
+            }
+            hx_event ev = 0;
+            const int dtype = dt;
+            hx_status s = c->submit(
+                SC_COMPUTE, prev.data(), (int)prev.size(), acc,
+                "stencil2d batched pass of " + std::to_string(bands.size()) + " bands",
+                [bands, gg, dtype](hipStream_t st) -> hipError_t {
+                    return launch_stencil2d_bands(dtype, bands.data(), (int)bands.size(), gg, st);
+                },
+                &ev);
+            if (s) return s;
+            cur.push_back(ev);
+            if (give) node_events[node++] = ev;
+        }
+        // prev holds the gate's copy (pass 0) or our own node events
+        if (!give || b == 0)
+            for (hx_event e : prev) release_locked(c, e);
+        prev.swap(cur);
+        cur.clear();
+    }
+    hx_status s;
+    if (plan.empty()) {
+        s = prev.empty() ? when_all_locked(c, nullptr, 0, out)
+                         : when_all_locked(c, prev.data(), (int)prev.size(), out);
+        for (hx_event e : prev) release_locked(c, e);
+        if (final_in_b) *final_in_b = 0;
+        return s;
+    }
+    s = when_all_locked(c, prev.data(), (int)prev.size(), out);
+    if (!give)
+        for (hx_event e : prev) release_locked(c, e);
+    if (final_in_b) *final_in_b = (plan.size() % 2 == 1);
+    return s;
+}
+
+}  // namespace
+
 extern "C" hx_status hx_run_partitioned(hx_ctx ctx, const hx_partitioned_desc* d,
                                         const hx_event* deps, int ndeps, hx_event* out,
                                         int* final_in_b, hx_event* node_events) {
@@ -68,6 +196,22 @@ extern "C" hx_status hx_run_partitioned(hx_ctx ctx, const hx_partitioned_desc* d
     if (!out) return c->fail(HX_ERR_ARG, "null output event");
     hx_status s = validate(c, d);
     if (s) return s;
+    if (d->mode == HX_PART_BATCHED) {
+        if (d->dims != 2)
+            return c->fail(HX_ERR_ARG, "HX_PART_BATCHED runs 2D bands; 1D batches use "
+                                       "hx_plan_create_batched");
+        if (c->host_only) return c->fail(HX_ERR_NO_DEVICE, "host-only context");
+        hx_event gate = 0;
+        if (ndeps > 0) {
+            s = when_all_locked(c, deps, ndeps, &gate);
+            if (s) return s;
+        }
+        s = run_bands_batched(c, d, gate, out, final_in_b, node_events);
+        release_locked(c, gate);
+        return s;
+    }
+    if (d->mode != HX_PART_GRAPH && d->mode != HX_PART_PLAIN)
+        return c->fail(HX_ERR_ARG, "bad mode");
     const int P = d->parts;
     const bool plain = d->mode == HX_PART_PLAIN;
     const int defD = d->dims == 2 ? 8 : 32;

@@ -435,9 +435,18 @@ __device__ __forceinline__ void stream_rows(const Band2D& b, const Strip& w, int
 
 // FAST = true: the static-count form (the host checks alignment and size);
 // FAST = false: the general form with per-row boundary handling.
+// One launch advances up to kMaxBands bands of one grid (same nx, r and
+// depth) by one pass: band k owns waves [first[k], first[k+1]), each wave a
+// (strip, chunk) of that band.  The set travels as the kernel argument.
+struct BandSet {
+    Band2D b[kMaxBands];
+    int64_t first[kMaxBands + 1];
+    int n;
+};
+
 template <typename T, int C, int D, bool FAST, bool SC>
-__global__ __launch_bounds__(256) void k_stencil2d(Band2D b, int rows, int halo, int64_t nstrips,
-                                                   int64_t nwaves) {
+__global__ __launch_bounds__(256) void k_stencil2d(BandSet set, int rows, int halo,
+                                                   int64_t nstrips) {
     constexpr int VN = V16<T>::N;
     constexpr int S = 64 * C;
     constexpr int Q = ring_rows();
@@ -445,11 +454,15 @@ __global__ __launch_bounds__(256) void k_stencil2d(Band2D b, int rows, int halo,
     static_assert(Q % 3 == 0 && Q >= 6, "the level-0 ring must be a multiple of 3 rows");
     const int wpg = blockDim.x >> 6;
     const int64_t wave = (int64_t)blockIdx.x * wpg + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (wave >= nwaves) return;
+    if (wave >= set.first[set.n]) return;
+    int kb = 0;
+    while (kb + 1 < set.n && wave >= set.first[kb + 1]) ++kb;
+    const Band2D& b = set.b[kb];
+    const int64_t wl = wave - set.first[kb];
     Strip w;
     w.lane = threadIdx.x & 63;
-    const int64_t strip = wave % nstrips;
-    const int64_t chunk = wave / nstrips;
+    const int64_t strip = wl % nstrips;
+    const int64_t chunk = wl / nstrips;
     w.wout = S - 2 * halo;
     w.x0 = strip * w.wout;
     const int64_t xb = w.x0 - halo;  // first column held by lane 0
@@ -527,53 +540,61 @@ __global__ __launch_bounds__(256) void k_stencil2d(Band2D b, int rows, int halo,
 }
 
 template <typename T, int C, int D>
-hipError_t launch_cd(const Band2D& b, const Geom2D& g, hipStream_t st) {
-    const int64_t wout = 64LL * C - 2LL * g.halo;
-    const int64_t nstrips = (b.nx + wout - 1) / wout;
-    const int64_t nchunks = (b.ny + g.rows - 1) / g.rows;
-    const int64_t nwaves = nstrips * nchunks;
-    const dim3 block(64 * g.wpg);
-    const dim3 grid((unsigned)((nwaves + g.wpg - 1) / g.wpg));
+hipError_t launch_cd(const Band2D* bands, int n, const Geom2D& g, hipStream_t st) {
     constexpr int VN = V16<T>::N;
-    const bool fast = b.aligned && b.nx % VN == 0 && b.nx >= VN &&
-                      b.ny * b.nx * (int64_t)sizeof(T) < (int64_t(1) << 31);
-    Band2D bb = b;
-    set_rate_2d(bb, D);
-    const bool sc = bb.period > 0;
+    const int64_t wout = 64LL * C - 2LL * g.halo;
+    const int64_t nstrips = (bands[0].nx + wout - 1) / wout;
+    BandSet set{};
+    set.n = n;
+    bool fast = true, sc = true;
+    int64_t total = 0;
+    for (int k = 0; k < n; ++k) {
+        Band2D bb = bands[k];
+        set_rate_2d(bb, D);
+        fast = fast && bb.aligned && bb.nx % VN == 0 && bb.nx >= VN &&
+               bb.ny * bb.nx * (int64_t)sizeof(T) < (int64_t(1) << 31);
+        sc = sc && bb.period > 0;
+        set.b[k] = bb;
+        set.first[k] = total;
+        total += nstrips * ((bb.ny + g.rows - 1) / g.rows);
+    }
+    set.first[n] = total;
+    const dim3 block(64 * g.wpg);
+    const dim3 grid((unsigned)((total + g.wpg - 1) / g.wpg));
     if (fast && sc)
-        hipLaunchKernelGGL((k_stencil2d<T, C, D, true, true>), grid, block, 0, st, bb, g.rows,
-                           g.halo, nstrips, nwaves);
+        hipLaunchKernelGGL((k_stencil2d<T, C, D, true, true>), grid, block, 0, st, set, g.rows,
+                           g.halo, nstrips);
     else if (fast)
-        hipLaunchKernelGGL((k_stencil2d<T, C, D, true, false>), grid, block, 0, st, bb, g.rows,
-                           g.halo, nstrips, nwaves);
+        hipLaunchKernelGGL((k_stencil2d<T, C, D, true, false>), grid, block, 0, st, set, g.rows,
+                           g.halo, nstrips);
     else if (sc)
-        hipLaunchKernelGGL((k_stencil2d<T, C, D, false, true>), grid, block, 0, st, bb, g.rows,
-                           g.halo, nstrips, nwaves);
+        hipLaunchKernelGGL((k_stencil2d<T, C, D, false, true>), grid, block, 0, st, set, g.rows,
+                           g.halo, nstrips);
     else
-        hipLaunchKernelGGL((k_stencil2d<T, C, D, false, false>), grid, block, 0, st, bb, g.rows,
-                           g.halo, nstrips, nwaves);
+        hipLaunchKernelGGL((k_stencil2d<T, C, D, false, false>), grid, block, 0, st, set, g.rows,
+                           g.halo, nstrips);
     return hipGetLastError();
 }
 
 template <typename T, int C, bool DEEP>
-hipError_t launch_c(const Band2D& b, const Geom2D& g, hipStream_t st) {
+hipError_t launch_c(const Band2D* b, int n, const Geom2D& g, hipStream_t st) {
     if constexpr (DEEP) {
         switch (g.steps) {
-        case 10: return launch_cd<T, C, 10>(b, g, st);
-        case 12: return launch_cd<T, C, 12>(b, g, st);
-        case 16: return launch_cd<T, C, 16>(b, g, st);
+        case 10: return launch_cd<T, C, 10>(b, n, g, st);
+        case 12: return launch_cd<T, C, 12>(b, n, g, st);
+        case 16: return launch_cd<T, C, 16>(b, n, g, st);
         default: break;
         }
     }
     switch (g.steps) {
-    case 1: return launch_cd<T, C, 1>(b, g, st);
-    case 2: return launch_cd<T, C, 2>(b, g, st);
-    case 3: return launch_cd<T, C, 3>(b, g, st);
-    case 4: return launch_cd<T, C, 4>(b, g, st);
-    case 5: return launch_cd<T, C, 5>(b, g, st);
-    case 6: return launch_cd<T, C, 6>(b, g, st);
-    case 7: return launch_cd<T, C, 7>(b, g, st);
-    case 8: return launch_cd<T, C, 8>(b, g, st);
+    case 1: return launch_cd<T, C, 1>(b, n, g, st);
+    case 2: return launch_cd<T, C, 2>(b, n, g, st);
+    case 3: return launch_cd<T, C, 3>(b, n, g, st);
+    case 4: return launch_cd<T, C, 4>(b, n, g, st);
+    case 5: return launch_cd<T, C, 5>(b, n, g, st);
+    case 6: return launch_cd<T, C, 6>(b, n, g, st);
+    case 7: return launch_cd<T, C, 7>(b, n, g, st);
+    case 8: return launch_cd<T, C, 8>(b, n, g, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -588,13 +609,21 @@ bool stencil2d_supported(int dtype, int cpl, int steps) {
     return dtype == 1 && cpl == 4 && small;
 }
 
-hipError_t launch_stencil2d(int dtype, const Band2D& b, const Geom2D& g, hipStream_t stream) {
-    if (!stencil2d_supported(dtype, g.cpl, g.steps)) return hipErrorInvalidValue;
+hipError_t launch_stencil2d_bands(int dtype, const Band2D* b, int n, const Geom2D& g,
+                                  hipStream_t stream) {
+    if (!stencil2d_supported(dtype, g.cpl, g.steps) || n < 1 || n > kMaxBands)
+        return hipErrorInvalidValue;
+    for (int k = 1; k < n; ++k)
+        if (b[k].nx != b[0].nx) return hipErrorInvalidValue;
     if (dtype == 0) {
-        if (g.cpl == 4) return launch_c<float, 4, true>(b, g, stream);
-        return launch_c<float, 8, false>(b, g, stream);
+        if (g.cpl == 4) return launch_c<float, 4, true>(b, n, g, stream);
+        return launch_c<float, 8, false>(b, n, g, stream);
     }
-    return launch_c<double, 4, false>(b, g, stream);
+    return launch_c<double, 4, false>(b, n, g, stream);
+}
+
+hipError_t launch_stencil2d(int dtype, const Band2D& b, const Geom2D& g, hipStream_t stream) {
+    return launch_stencil2d_bands(dtype, &b, 1, g, stream);
 }
 
 }  // namespace hx

@@ -201,3 +201,25 @@ def test_foreign_stream_interop(ctx):
     ref = oracle.heat1d_periodic(t.cpu().double().numpy(), 0.25, 3)
     assert abs(total.item() - ref.sum()) <= 1e-4 * abs(ref.sum())
     assert rel_l2(out.cpu().numpy(), ref) <= 1e-5
+
+
+def test_band_batches_are_hazard_free(ctx):
+    """2D bands in one launch per pass (two groups: 20 bands) and one launch
+    per band: every halo read is ordered after its write, every overwrite
+    after its reads."""
+    nx, bands = 512, 20
+    sizes = [9 + (p % 3) for p in range(bands)]
+    A = [upload(ctx, workloads.uniform(s * nx, 705, p, 0, 1, np.float32)) for p, s in
+         enumerate(sizes)]
+    B = [hx.hx_buffer_create(ctx, s * nx * 4) for s in sizes]
+    for mode in (hx.HX_PART_BATCHED, hx.HX_PART_GRAPH):
+        d = hx.partitioned_desc(hx.HX_F32, sizes, A, B, 20, 0.2, periodic=False, mode=mode,
+                                time_block=6, dims=2, nx=nx, rows_per_block=8)
+        ev, _, _ = hx.hx_run_partitioned(ctx, d)
+        assert hx.hx_wait(ctx, ev) == hx.HX_OK, hx.hx_last_error(ctx)
+        hx.hx_event_release(ctx, ev)
+    assert hx.hx_hazard_count(ctx) == 0, hx.hx_hazard_report(ctx)
+    d1 = hx.partitioned_desc(hx.HX_F32, [64, 64], A[:2], B[:2], 4, 0.2, mode=hx.HX_PART_BATCHED)
+    with pytest.raises(hx.HxError) as e:
+        hx.hx_run_partitioned(ctx, d1)
+    assert e.value.status == hx.HX_ERR_ARG

@@ -96,20 +96,20 @@ def test_fp64_multi_pass_closed_form_mode(ctx):
 
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
-@pytest.mark.parametrize("bands,steps,tb", [(4, 20, 5), (7, 24, 8), (3, 16, 16)])
+@pytest.mark.parametrize("bands,steps,tb", [(4, 20, 5), (7, 24, 8), (3, 16, 16), (20, 12, 4)])
 def test_band_graph(ctx, dtype, bands, steps, tb):
     """A grid split into row bands; every band reads its halo rows from its
     neighbours' buffers; future graph over (band, pass)."""
     if dtype == np.float64 and tb > 8:
         pytest.skip("fp64 fused depth is at most 8")
-    ny, nx = 211, 517
+    ny, nx = (211, 517) if bands < 16 else (260, 1024)
     u0 = workloads.uniform((ny, nx), 502, bands, 0, 1, dtype)
     bounds = workloads.band_bounds(ny, bands)
     code = hx.HX_F64 if dtype == np.float64 else hx.HX_F32
     A = [upload(ctx, u0[o:o + s]) for o, s in bounds]
     B = [hx.hx_buffer_create(ctx, s * nx * u0.itemsize) for _, s in bounds]
     outs = []
-    for mode in (hx.HX_PART_GRAPH, hx.HX_PART_PLAIN):
+    for mode in (hx.HX_PART_GRAPH, hx.HX_PART_PLAIN, hx.HX_PART_BATCHED):
         d = hx.partitioned_desc(code, [s for _, s in bounds], A, B, steps, 0.2, periodic=False,
                                 mode=mode, time_block=tb, dims=2, nx=nx, rows_per_block=64)
         ev, in_b, _ = hx.hx_run_partitioned(ctx, d)
@@ -128,6 +128,8 @@ def test_band_graph(ctx, dtype, bands, steps, tb):
         assert rel_l2(o, ref) <= TOL[dtype] and rel_max(o, ref) <= 20 * TOL[dtype]
     if tb == 1:  # one-step passes in both forms: the same arithmetic
         assert np.array_equal(outs[0], outs[1])
+    # one launch per band or one per group of bands: the same per-cell arithmetic
+    assert np.array_equal(outs[0], outs[2])
     for b in A + B:
         hx.hx_buffer_destroy(ctx, b)
 
