@@ -789,6 +789,13 @@ extern "C" __global__ void kmap(double* x, long n) {
     long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) { double v = x[i]; x[i] = sqrt(sin(v) * sin(v) + cos(v) * cos(v)); }
 }
+extern "C" __global__ void kprk(const double* x, double* y, long n) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        long il = i == 0 ? n - 1 : i - 1, ir = i == n - 1 ? 0 : i + 1;
+        y[i] = (0.5 * x[il] + x[i]) + 0.5 * x[ir];
+    }
+}
 '''
 
 
@@ -836,12 +843,14 @@ class NativeHip:
 
 
 def overhead_leg(hx, parts=4, iters=11):
-    """The paper's overhead experiment (Sec. V-A.2, Algorithm 1): a vector of
+    """The paper's overhead experiments.  E2 (Sec. V-A.2, Algorithm 1): a vector of
     n = 2^m * 1024 * 256 * 4 doubles (m = 1..8) in `parts` partitions, each
     copied in, mapped by k(x) = sqrt(sin^2 x + cos^2 x) (compiled at run time)
     and copied out, all partitions in flight; the hx future graph against the
-    same work on raw HIP streams.  Each time is the mean of iterations 2..11,
-    the paper's method."""
+    same work on raw HIP streams.  E1 (Sec. V-A.1): the 3-point stencil on one
+    vector of 2^21..2^26 doubles as a dependent copy-in, kernel, copy-out
+    chain, against the same chain on one raw HIP stream.  Each time is the mean
+    of iterations 2..11, the paper's method."""
     import torch
     ctx = hx.hx_ctx_create(0)
     prog = hx.hx_program_create(ctx, OVERHEAD_SRC, "partition_kernel.hip")
@@ -900,12 +909,63 @@ def overhead_leg(hx, parts=4, iters=11):
                      "host_link_GBps_hx": 2 * n * 8 / (res["hx"] * 1e-3) / 1e9,
                      "max_abs_err_vs_1": err})
         log(f"overhead m={m} n={n}: hx {res['hx']:.3f} ms, native {res['native']:.3f} ms")
+    # E1 (Sec. V-A.1): the 3-point stencil, one vector, copy in -> kernel ->
+    # copy out as a dependent chain, against the same chain with synchronous
+    # HIP calls.
+    kprk = hx.hx_program_function(ctx, prog, "kprk")
+    e1_rows = []
+    for k, m in enumerate([1] + list(range(1, 7))):
+        n = (1 << m) * 1024 * 256 * 4
+        bx = hx.hx_buffer_create(ctx, n * 8)
+        by = hx.hx_buffer_create(ctx, n * 8)
+        px, py = hx.hx_buffer_ptr(ctx, bx)[0], hx.hx_buffer_ptr(ctx, by)[0]
+
+        def run_hx():
+            e1 = hx.hx_copy_async(ctx, hx.hx_copy_desc(hx.HX_H2D, hin, bx, 0, 0, 0, n * 8))
+            e2 = hx.hx_program_run(ctx, prog, "kprk",
+                                   [hx.karg_buffer(bx, 0, hx.HX_ACCESS_READ),
+                                    hx.karg_buffer(by, 0, hx.HX_ACCESS_WRITE),
+                                    hx.karg_value(np.int64(n))], ((n + 255) // 256,), (256,),
+                                   deps=[e1])
+            e3 = hx.hx_copy_async(ctx, hx.hx_copy_desc(hx.HX_D2H, hout, by, 0, 0, 0, n * 8), [e2])
+            assert hx.hx_wait(ctx, e3) == hx.HX_OK
+            for e in (e1, e2, e3):
+                hx.hx_event_release(ctx, e)
+
+        def run_native():
+            ct = native.ct
+            st = native.streams[0]
+            assert native.hip.hipMemcpyAsync(px, hin, n * 8, 1, st) == 0
+            a0, a1, a2 = ct.c_void_p(px), ct.c_void_p(py), ct.c_int64(n)
+            params = (ct.c_void_p * 3)(*[ct.cast(ct.byref(v), ct.c_void_p) for v in (a0, a1, a2)])
+            assert native.hip.hipModuleLaunchKernel(kprk, (n + 255) // 256, 1, 1, 256, 1, 1, 0, st,
+                                                    params, None) == 0
+            assert native.hip.hipMemcpyAsync(hout, py, n * 8, 2, st) == 0
+            assert native.hip.hipStreamSynchronize(st) == 0
+
+        res = {}
+        for name, f in (("hx", run_hx), ("native", run_native)):
+            ts = []
+            for _ in range(iters):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                f()
+                ts.append(time.perf_counter() - t0)
+            res[name] = float(np.mean(ts[1:])) * 1e3
+        for b in (bx, by):
+            hx.hx_buffer_destroy(ctx, b)
+        if k == 0:
+            continue
+        e1_rows.append({"m": m, "n": n, "hx_ms": res["hx"], "native_ms": res["native"],
+                        "hx_over_native": res["hx"] / res["native"]})
+        log(f"overhead E1 m={m} n={n}: hx {res['hx']:.3f} ms, native {res['native']:.3f} ms")
     native.close()
     hx.hx_program_destroy(ctx, prog)
     hx.hx_host_free(ctx, hin)
     hx.hx_host_free(ctx, hout)
     hx.hx_ctx_destroy(ctx)
-    return {"parts": parts, "dtype": "f64", "iterations": iters, "rows": rows}
+    return {"parts": parts, "dtype": "f64", "iterations": iters, "rows": rows,
+            "e1_sequential_stencil": e1_rows}
 
 
 def cpu_leg(r, T):

@@ -137,3 +137,49 @@ def test_full_size_bench_configuration_sampled(ctx):
     for b in A + B:
         hx.hx_buffer_destroy(ctx, b)
     hx.hx_host_free(ctx, hin)
+
+
+@pytest.mark.parametrize("cpl", [32, 16])
+def test_full_size_batched_pass_arena_sampled(ctx, cpl):
+    """The bench's headline form: 2^28 fp32 cells as 64 partition views of one
+    HBM arena, r = 0.25, 50 steps as one batched launch over all partitions
+    (halos from the neighbour views); sampled cells against the oracle's light
+    cone, including every partition seam of a few partitions."""
+    n, parts, T, r = 1 << 28, 64, 50, 0.25
+    spec = workloads.Partitioned1D()
+    hin = hx.hx_host_alloc(ctx, n * 4)
+    u0 = np.ctypeslib.as_array((np.ctypeslib.ctypes.c_float * n).from_address(hin))
+    workloads.partitioned1d_u0(spec, out=u0)
+    bounds = workloads.partition_bounds(n, parts)
+    arena_a = hx.hx_buffer_create(ctx, n * 4)
+    arena_b = hx.hx_buffer_create(ctx, n * 4)
+    pa, pb = hx.hx_buffer_ptr(ctx, arena_a)[0], hx.hx_buffer_ptr(ctx, arena_b)[0]
+    A = [hx.hx_buffer_wrap(ctx, pa + o * 4, s * 4) for o, s in bounds]
+    B = [hx.hx_buffer_wrap(ctx, pb + o * 4, s * 4) for o, s in bounds]
+    e = hx.hx_copy_async(ctx, hx.hx_copy_desc(hx.HX_H2D, hin, arena_a, 0, 0, 0, n * 4))
+    assert hx.hx_wait(ctx, e) == hx.HX_OK
+    hx.hx_event_release(ctx, e)
+    segs = []
+    for p in range(parts):
+        lp, rp = (p - 1) % parts, (p + 1) % parts
+        segs.append(hx.segment(inp=A[p], out=B[p], n=bounds[p][1], r=r, bc_lo=hx.HX_BC_GHOST,
+                               bc_hi=hx.HX_BC_GHOST, halo_lo=A[lp],
+                               halo_lo_offset=(bounds[lp][1] - T) * 4, halo_hi=A[rp],
+                               halo_width=T))
+    plan = hx.hx_plan_create_batched(ctx, hx.HX_F32, T, segs, hx.HX_BATCH_PERSISTENT,
+                                     cells_per_lane=cpl, grid_waves_per_cu=-1)
+    ev = hx.hx_launch_batched(ctx, plan)
+    assert hx.hx_wait(ctx, ev) == hx.HX_OK, hx.hx_last_error(ctx)
+    hx.hx_event_release(ctx, ev)
+    hx.hx_plan_destroy(ctx, plan)
+    rng = np.random.default_rng(17)
+    seams = [k << 22 for k in (1, 17, 63)]
+    idx = np.sort(np.concatenate([rng.choice(n, 40, replace=False), [0, n - 1],
+                                  [s + d for s in seams for d in (-2, -1, 0, 1)]]))
+    ref = oracle.heat1d_periodic_at(u0.astype(np.float64), r, T, idx)
+    got = np.array([download(ctx, arena_b, 1, np.float32, offset=int(i) * 4)[0] for i in idx],
+                   dtype=np.float64)
+    assert np.max(np.abs(got - ref) / np.abs(ref)) <= 1e-5
+    for b in A + B + [arena_a, arena_b]:
+        hx.hx_buffer_destroy(ctx, b)
+    hx.hx_host_free(ctx, hin)

@@ -134,17 +134,21 @@ def test_band_graph(ctx, dtype, bands, steps, tb):
         hx.hx_buffer_destroy(ctx, b)
 
 
-def test_full_size_banded_sampled(ctx):
+@pytest.mark.parametrize("mode,tb,rows", [(hx.HX_PART_GRAPH, 8, 0),
+                                          (hx.HX_PART_BATCHED, 16, 128)])
+def test_full_size_banded_sampled(ctx, mode, tb, rows):
     """16384^2 fp32, r = 0.2, 200 steps, 16 row bands with halo-row futures,
-    Gaussian-bump initial field; 24 cells (corners, band edges, bump centres,
-    random) checked against the oracle's light cone."""
+    Gaussian-bump initial field, in the per-band graph and in the batched form
+    the bench times; 24 cells (corners, band edges, bump centres, random)
+    checked against the oracle's light cone."""
     spec = workloads.Banded2D()
     u0 = workloads.banded2d_u0(spec)
     bounds = workloads.band_bounds(spec.ny, spec.bands)
     A = [upload(ctx, u0[o:o + s]) for o, s in bounds]
     B = [hx.hx_buffer_create(ctx, s * spec.nx * 4) for _, s in bounds]
     d = hx.partitioned_desc(hx.HX_F32, [s for _, s in bounds], A, B, spec.steps, spec.r,
-                            periodic=False, time_block=8, dims=2, nx=spec.nx)
+                            periodic=False, time_block=tb, dims=2, nx=spec.nx, mode=mode,
+                            rows_per_block=rows)
     ev, in_b, _ = hx.hx_run_partitioned(ctx, d)
     assert hx.hx_wait(ctx, ev) == hx.HX_OK, hx.hx_last_error(ctx)
     hx.hx_event_release(ctx, ev)
