@@ -62,9 +62,35 @@ struct Raw {
     bool rowin;
 };
 
-template <typename T>
+// VEC (every row 16-byte aligned, nx a multiple of C): the same number of
+// loads for every row of every wave -- one vector per lane from a clamped
+// address plus one cell per lane for the strip edges, outside values replaced
+// by 0 afterwards -- so no load sits under a branch and the compiler's wait
+// counts cover only the row being consumed, not the one in flight.
+template <typename T, bool VEC>
 __device__ __forceinline__ void fetch_row(const T* __restrict__ f, int64_t y, int64_t ny, int64_t nx,
                                           int64_t x0, int64_t xl, int lane, bool vec, Raw<T>& r) {
+    if constexpr (VEC) {
+        typedef T V2 __attribute__((ext_vector_type(16 / sizeof(T))));
+        typedef __attribute__((address_space(1))) const V2 GV2;
+        typedef __attribute__((address_space(1))) const T GT;
+        constexpr int VN = 16 / sizeof(T);
+        r.rowin = y >= 0 && y < ny;
+        const T* row = f + (y < 0 ? 0 : (y >= ny ? ny - 1 : y)) * nx;
+        const bool lin = xl + C <= nx;  // the lane's cells are wholly inside or outside
+        const int64_t xv = lin ? xl : nx - C;
+#pragma unroll
+        for (int q = 0; q < C / VN; ++q) {
+            const V2 x = __builtin_nontemporal_load((GV2*)(row + xv) + q);
+#pragma unroll
+            for (int e = 0; e < VN; ++e) r.c[q * VN + e] = lin ? x[e] : T(0);
+        }
+        const int64_t xe = (lane == 0) ? x0 - 1 : (lane == 63 ? x0 + S : xv);
+        const bool ein = (lane == 0 || lane == 63) && xe >= 0 && xe < nx;
+        const T ev = *((GT*)row + (ein ? xe : xv));
+        r.edge = ein ? ev : T(0);
+        return;
+    }
     r.rowin = y >= 0 && y < ny;
     if (r.rowin && vec) {
         typedef T V2 __attribute__((ext_vector_type(16 / sizeof(T))));
@@ -141,7 +167,31 @@ __device__ __forceinline__ void face_sum(const Row<T>& fm, const Row<T>& f0, con
     }
 }
 
-template <typename T, bool ADJ>
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int BUF_DWORD3 = 0x00020000;  // raw 32-bit buffer (gfx9 family)
+constexpr uint32_t OOB_OFFSET = 0x7ffffff0u;
+
+// VEC stores of one lane's C cells of row y through a bounds-checked buffer
+// resource: a lane whose cells lie past nx stores at an out-of-range offset,
+// which the hardware drops, so the store is never under a branch.
+template <typename T>
+__device__ __forceinline__ void store_row(__amdgpu_buffer_rsrc_t rs, uint32_t lane_off, int64_t y,
+                                          int64_t nx, const T (&v)[C]) {
+    typedef T V2 __attribute__((ext_vector_type(16 / sizeof(T))));
+    constexpr int VN = 16 / sizeof(T);
+    const uint32_t row = (uint32_t)(y * nx * (int64_t)sizeof(T));
+#pragma unroll
+    for (int q = 0; q < C / VN; ++q) {
+        V2 x;
+#pragma unroll
+        for (int e = 0; e < VN; ++e) x[e] = v[q * VN + e];
+        u32x4 bits;
+        __builtin_memcpy(&bits, &x, sizeof(bits));
+        __builtin_amdgcn_raw_buffer_store_b128(bits, rs, (int)(lane_off + row + q * 16), 0, 0);
+    }
+}
+
+template <typename T, bool ADJ, bool VEC>
 __global__ __launch_bounds__(256) void k_vc_step(VCDev a, int64_t nstrips, int64_t nwaves) {
     const int wpg = blockDim.x >> 6;
     const int64_t wave = (int64_t)blockIdx.x * wpg + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -153,7 +203,7 @@ __global__ __launch_bounds__(256) void k_vc_step(VCDev a, int64_t nstrips, int64
     const int64_t xl = x0 + (int64_t)lane * C;
     const int64_t y0 = chunk * a.rows;
     const int64_t y1 = (y0 + a.rows < ny) ? y0 + a.rows : ny;
-    const bool vec = (x0 + S <= nx) && a.aligned;
+    const bool vec = VEC || ((x0 + S <= nx) && a.aligned);
     const T dt = static_cast<T>(a.dt);
     const T* U = static_cast<const T*>(a.u);
     const T* K = static_cast<const T*>(a.kappa);
@@ -163,35 +213,48 @@ __global__ __launch_bounds__(256) void k_vc_step(VCDev a, int64_t nstrips, int64
     const T zero[C] = {T(0), T(0), T(0), T(0)};
 
     Row<T> um, u0, up, km, k0, kp, lm, l0, lp;
-    Raw<T> rk, ru, rl;
+    Raw<T> rk, ru, rl, rg;
+    // (used by the VEC form only)
+    const int bytes = VEC ? (int)(ny * nx * (int64_t)sizeof(T)) : 0;
+    const __amdgpu_buffer_rsrc_t rso = __builtin_amdgcn_make_buffer_rsrc(O, (short)0, bytes, BUF_DWORD3);
+    const __amdgpu_buffer_rsrc_t rsg = __builtin_amdgcn_make_buffer_rsrc(G, (short)0, bytes, BUF_DWORD3);
+    const uint32_t lane_off = (xl + C <= nx) ? (uint32_t)(xl * (int64_t)sizeof(T)) : OOB_OFFSET;
     // rows y0 and y0-1 (kappa ghosts of row y0-1 are kappa of row y0)
-    fetch_row<T>(K, y0, ny, nx, x0, xl, lane, vec, rk);
+    fetch_row<T, VEC>(K, y0, ny, nx, x0, xl, lane, vec, rk);
     finish_row<T>(rk, zero, lane, k0);
-    fetch_row<T>(K, y0 - 1, ny, nx, x0, xl, lane, vec, rk);
+    fetch_row<T, VEC>(K, y0 - 1, ny, nx, x0, xl, lane, vec, rk);
     finish_row<T>(rk, k0.c, lane, km);
-    fetch_row<T>(U, y0 - 1, ny, nx, x0, xl, lane, vec, ru);
+    fetch_row<T, VEC>(U, y0 - 1, ny, nx, x0, xl, lane, vec, ru);
     finish_row<T>(ru, zero, lane, um);
-    fetch_row<T>(U, y0, ny, nx, x0, xl, lane, vec, ru);
+    fetch_row<T, VEC>(U, y0, ny, nx, x0, xl, lane, vec, ru);
     finish_row<T>(ru, zero, lane, u0);
     if (ADJ) {
-        fetch_row<T>(L, y0 - 1, ny, nx, x0, xl, lane, vec, rl);
+        fetch_row<T, VEC>(L, y0 - 1, ny, nx, x0, xl, lane, vec, rl);
         finish_row<T>(rl, zero, lane, lm);
-        fetch_row<T>(L, y0, ny, nx, x0, xl, lane, vec, rl);
+        fetch_row<T, VEC>(L, y0, ny, nx, x0, xl, lane, vec, rl);
         finish_row<T>(rl, zero, lane, l0);
     }
-    // row y0+1 in flight
-    fetch_row<T>(K, y0 + 1, ny, nx, x0, xl, lane, vec, rk);
-    fetch_row<T>(U, y0 + 1, ny, nx, x0, xl, lane, vec, ru);
-    if (ADJ) fetch_row<T>(L, y0 + 1, ny, nx, x0, xl, lane, vec, rl);
+    // the accumulator row y0 (adjoint, VEC) and the field rows y0+1 in flight
+    if (VEC && ADJ) fetch_row<T, VEC>(G, y0, ny, nx, x0, xl, lane, vec, rg);
+    fetch_row<T, VEC>(K, y0 + 1, ny, nx, x0, xl, lane, vec, rk);
+    fetch_row<T, VEC>(U, y0 + 1, ny, nx, x0, xl, lane, vec, ru);
+    if (ADJ) fetch_row<T, VEC>(L, y0 + 1, ny, nx, x0, xl, lane, vec, rl);
     for (int64_t y = y0; y < y1; ++y) {
-        // row y+1 arrives; row y+2 goes in flight
+        // row y+1 arrives; row y+2 goes in flight (VEC: unconditionally, the
+        // rows past the chunk are clamped reads of the last row)
         finish_row<T>(rk, k0.c, lane, kp);
         finish_row<T>(ru, zero, lane, up);
         if (ADJ) finish_row<T>(rl, zero, lane, lp);
-        if (y + 1 < y1) {
-            fetch_row<T>(K, y + 2, ny, nx, x0, xl, lane, vec, rk);
-            fetch_row<T>(U, y + 2, ny, nx, x0, xl, lane, vec, ru);
-            if (ADJ) fetch_row<T>(L, y + 2, ny, nx, x0, xl, lane, vec, rl);
+        T gr[C];
+        if (VEC && ADJ) {
+#pragma unroll
+            for (int j = 0; j < C; ++j) gr[j] = rg.c[j];
+        }
+        if (VEC || y + 1 < y1) {
+            if (VEC && ADJ) fetch_row<T, VEC>(G, y + 1, ny, nx, x0, xl, lane, vec, rg);
+            fetch_row<T, VEC>(K, y + 2, ny, nx, x0, xl, lane, vec, rk);
+            fetch_row<T, VEC>(U, y + 2, ny, nx, x0, xl, lane, vec, ru);
+            if (ADJ) fetch_row<T, VEC>(L, y + 2, ny, nx, x0, xl, lane, vec, rl);
         }
         // rows outside the domain carry ghost kappa = kappa of the row y cell
         if (y - 1 < 0) {
@@ -201,13 +264,21 @@ __global__ __launch_bounds__(256) void k_vc_step(VCDev a, int64_t nstrips, int64
         T acc[C];
         if (!ADJ) {
             face_sum<T>(um, u0, up, km, k0, kp, xl, nx, acc);
+            if constexpr (VEC) {
+                T o[C];
 #pragma unroll
-            for (int j = 0; j < C; ++j) {
-                const int64_t x = xl + j;
-                if (x < nx) O[y * nx + x] = fmaT(dt, acc[j], u0.c[j]);
+                for (int j = 0; j < C; ++j) o[j] = fmaT(dt, acc[j], u0.c[j]);
+                store_row<T>(rso, lane_off, y, nx, o);
+            } else {
+#pragma unroll
+                for (int j = 0; j < C; ++j) {
+                    const int64_t x = xl + j;
+                    if (x < nx) O[y * nx + x] = fmaT(dt, acc[j], u0.c[j]);
+                }
             }
         } else {
             face_sum<T>(lm, l0, lp, km, k0, kp, xl, nx, acc);
+            T o[C], gn[C];
 #pragma unroll
             for (int j = 0; j < C; ++j) {
                 const int64_t x = xl + j;
@@ -222,10 +293,17 @@ __global__ __launch_bounds__(256) void k_vc_step(VCDev a, int64_t nstrips, int64
                 const T hn = (y - 1 >= 0) ? (um.c[j] - uc) * (lm.c[j] - lc) * T(0.5) : prod;
                 const T hs = (y + 1 < ny) ? (up.c[j] - uc) * (lp.c[j] - lc) * T(0.5) : prod;
                 const T g = ((hw + he) + (hn + hs));
-                if (x < nx) {
+                if constexpr (VEC) {
+                    o[j] = fmaT(dt, acc[j], lc);
+                    gn[j] = fmaT(-dt, g, gr[j]);
+                } else if (x < nx) {
                     O[y * nx + x] = fmaT(dt, acc[j], lc);
                     G[y * nx + x] = fmaT(-dt, g, G[y * nx + x]);
                 }
+            }
+            if constexpr (VEC) {
+                store_row<T>(rso, lane_off, y, nx, o);
+                store_row<T>(rsg, lane_off, y, nx, gn);
             }
         }
         um = u0; u0 = up;
@@ -329,7 +407,11 @@ unsigned grid_for(int64_t n) {
 hipError_t launch_vc_step(int dtype, bool adjoint, const VCArgs& v, hipStream_t st) {
     auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; };
     const int es = dtype == 0 ? 4 : 8;
-    const bool aligned = ((v.nx * es) % 16 == 0) && al(v.u) && al(v.kappa) && (!v.lam || al(v.lam));
+    const bool aligned = ((v.nx * es) % 16 == 0) && al(v.u) && al(v.kappa) &&
+                         (!v.lam || al(v.lam)) && al(v.out) && (!v.gacc || al(v.gacc));
+    // VEC: aligned rows, whole lane chunks (nx a multiple of C) and a grid
+    // under 2 GiB (32-bit buffer offsets)
+    const bool vecform = aligned && v.nx % C == 0 && v.nx * v.ny * es < (int64_t(1) << 31);
     VCDev a{v.u, v.kappa, v.lam, v.out, v.gacc, v.nx, v.ny, v.dt, v.rows > 0 ? v.rows : 64,
             aligned ? 1 : 0};
     const int64_t nstrips = (v.nx + S - 1) / S;
@@ -337,13 +419,16 @@ hipError_t launch_vc_step(int dtype, bool adjoint, const VCArgs& v, hipStream_t 
     const int64_t nwaves = nstrips * nchunks;
     const int wpg = 4;
     const dim3 block(64 * wpg), grid((unsigned)((nwaves + wpg - 1) / wpg));
+#define HX_VC_LAUNCH(T, ADJ, VEC) \
+    hipLaunchKernelGGL((k_vc_step<T, ADJ, VEC>), grid, block, 0, st, a, nstrips, nwaves)
     if (dtype == 0) {
-        if (adjoint) hipLaunchKernelGGL((k_vc_step<float, true>), grid, block, 0, st, a, nstrips, nwaves);
-        else hipLaunchKernelGGL((k_vc_step<float, false>), grid, block, 0, st, a, nstrips, nwaves);
+        if (adjoint) { if (vecform) HX_VC_LAUNCH(float, true, true); else HX_VC_LAUNCH(float, true, false); }
+        else { if (vecform) HX_VC_LAUNCH(float, false, true); else HX_VC_LAUNCH(float, false, false); }
     } else {
-        if (adjoint) hipLaunchKernelGGL((k_vc_step<double, true>), grid, block, 0, st, a, nstrips, nwaves);
-        else hipLaunchKernelGGL((k_vc_step<double, false>), grid, block, 0, st, a, nstrips, nwaves);
+        if (adjoint) { if (vecform) HX_VC_LAUNCH(double, true, true); else HX_VC_LAUNCH(double, true, false); }
+        else { if (vecform) HX_VC_LAUNCH(double, false, true); else HX_VC_LAUNCH(double, false, false); }
     }
+#undef HX_VC_LAUNCH
     return hipGetLastError();
 }
 
