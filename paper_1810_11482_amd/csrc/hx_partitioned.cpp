@@ -100,6 +100,16 @@ hx_status run_bands_batched(Ctx* c, const hx_partitioned_desc* d, hx_event gate,
     const bool give = node_events != nullptr;
     int node = 0;
     auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; };
+    // On an error, drop our references (node events handed to the caller
+    // stay the caller's); what was already queued still runs.
+    bool first_pass = true;
+    auto unwind = [&](hx_status st) {
+        if (!give || first_pass)
+            for (hx_event e : prev) release_locked(c, e);
+        if (!give)
+            for (hx_event e : cur) release_locked(c, e);
+        return st;
+    };
     for (size_t b = 0; b < plan.size(); ++b) {
         const int depth = plan[b];
         const bool src_a = (b % 2 == 0);
@@ -117,10 +127,10 @@ hx_status run_bands_batched(Ctx* c, const hx_partitioned_desc* d, hx_event gate,
                 char *pin = nullptr, *pout = nullptr, *ptop = nullptr, *pbot = nullptr;
                 Access a{};
                 hx_status s = resolve_range(c, in, 0, (size_t)band_bytes, &pin, &a, false);
-                if (s) return s;
+                if (s) return unwind(s);
                 acc.push_back(a);
                 s = resolve_range(c, outb, 0, (size_t)band_bytes, &pout, &a, true);
-                if (s) return s;
+                if (s) return unwind(s);
                 acc.push_back(a);
                 Band2D bd{};
                 bd.nx = d->nx;
@@ -134,13 +144,13 @@ hx_status run_bands_batched(Ctx* c, const hx_partitioned_desc* d, hx_event gate,
                     const hx_buffer hbuf = src_a ? d->bufs_a[p - 1] : d->bufs_b[p - 1];
                     s = resolve_range(c, hbuf, (size_t)(d->sizes[p - 1] - depth) * d->nx * es, hb,
                                       &ptop, &a, false);
-                    if (s) return s;
+                    if (s) return unwind(s);
                     acc.push_back(a);
                 }
                 if (p < P - 1) {
                     const hx_buffer hbuf = src_a ? d->bufs_a[p + 1] : d->bufs_b[p + 1];
                     s = resolve_range(c, hbuf, 0, hb, &pbot, &a, false);
-                    if (s) return s;
+                    if (s) return unwind(s);
                     acc.push_back(a);
                 }
                 bd.in = pin;
@@ -160,15 +170,16 @@ hx_status run_bands_batched(Ctx* c, const hx_partitioned_desc* d, hx_event gate,
                     return launch_stencil2d_bands(dtype, bands.data(), (int)bands.size(), gg, st);
                 },
                 &ev);
-            if (s) return s;
+            if (s) return unwind(s);
             cur.push_back(ev);
             if (give) node_events[node++] = ev;
         }
         // prev holds the gate's copy (pass 0) or our own node events
-        if (!give || b == 0)
+        if (!give || first_pass)
             for (hx_event e : prev) release_locked(c, e);
         prev.swap(cur);
         cur.clear();
+        first_pass = false;
     }
     hx_status s;
     if (plan.empty()) {
