@@ -125,11 +125,12 @@ def test_halo_coupled_batch_is_one_pass_of_partitions(ctx):
         hx.hx_buffer_destroy(ctx, b)
 
 
-def test_full_size_batch_sampled(ctx):
+@pytest.mark.parametrize("cpl,grid", [(0, 0), (16, -1), (32, -1), (16, 64)])
+def test_full_size_batch_sampled(ctx, cpl, grid):
     """The full 4096-problem workload (sizes log-uniform in [1024, 2^20], r in
-    [0.05, 0.25], 20 steps, fp32) as one persistent launch: the 64 smallest
-    problems checked whole, cells of 64 other problems checked through their
-    light cones."""
+    [0.05, 0.25], 20 steps, fp32) as one launch, in the default geometry and in
+    the ones the bench sweeps: the 64 smallest problems checked whole, cells of
+    64 other problems checked through their light cones."""
     spec = workloads.Batched1D()
     sizes, rs, offs = workloads.batched1d_problems(spec)
     total = int(sizes.sum())
@@ -139,10 +140,12 @@ def test_full_size_batch_sampled(ctx):
     segs = [hx.segment(inp=bin_, in_offset=int(o) * 4, out=bout, out_offset=int(o) * 4,
                        n=int(n), r=float(r), bc_lo=hx.HX_BC_PERIODIC, bc_hi=hx.HX_BC_PERIODIC)
             for o, n, r in zip(offs, sizes, rs)]
-    plan = hx.hx_plan_create_batched(ctx, hx.HX_F32, spec.steps, segs, hx.HX_BATCH_PERSISTENT)
+    plan = hx.hx_plan_create_batched(ctx, hx.HX_F32, spec.steps, segs, hx.HX_BATCH_PERSISTENT,
+                                     cells_per_lane=cpl, grid_waves_per_cu=grid)
     ev = hx.hx_launch_batched(ctx, plan)
     assert hx.hx_wait(ctx, ev) == hx.HX_OK
     hx.hx_event_release(ctx, ev)
+    hx.hx_plan_destroy(ctx, plan)
     small = np.argsort(sizes)[:64]
     for k in small:
         o, n = int(offs[k]), int(sizes[k])
@@ -157,7 +160,6 @@ def test_full_size_batch_sampled(ctx):
         ref = oracle.heat1d_periodic_at(u0[o:o + n].astype(np.float64), float(rs[k]), spec.steps,
                                         [i])[0]
         assert abs(got - ref) <= 1e-5 * abs(ref)
-    hx.hx_plan_destroy(ctx, plan)
     hx.hx_buffer_destroy(ctx, bin_)
     hx.hx_buffer_destroy(ctx, bout)
 
