@@ -282,6 +282,16 @@ typedef enum {
     HX_BATCH_PLAIN = 2         /* comparator: one launch per segment per step */
 } hx_batch_mode;
 
+/* How a PERSISTENT batch evaluates its fused pass of `steps` steps. */
+typedef enum {
+    HX_FORM_DIRECT = 0,        /* step by step in registers (f32 and f64; any boundary) */
+    HX_FORM_PROPAGATOR = 1,    /* one convolution with the steps-step propagator on the matrix
+                                  cores (f32 only); the plan fails with HX_ERR_ARG unless every
+                                  segment qualifies, see hx_plan_create_batched */
+    HX_FORM_AUTO = 2           /* the tuned form, else PROPAGATOR where every segment qualifies,
+                                  else DIRECT */
+} hx_batch_form;
+
 typedef struct {
     hx_buffer in;  size_t in_offset;      /* n cells, byte offset */
     hx_buffer out; size_t out_offset;     /* n cells; must not overlap in */
@@ -306,6 +316,9 @@ typedef struct {
                                    CU striding over the tiles, each wave prefetching its next
                                    tile while it advances the current one; < 0 = one wave per
                                    tile; 0 = tuned (one wave per tile if untuned) */
+    int form;                   /* hx_batch_form; 0 = DIRECT */
+    int span_blocks;            /* PROPAGATOR: 1024-cell blocks per wave, 0 = chosen to fill the
+                                   device in whole rounds */
 } hx_batch_desc;
 
 /* Build a batch: `count` 1D segments, each with its own size, r, boundaries
@@ -315,9 +328,28 @@ typedef struct {
  * outlive the plan.  The work table is built and uploaded once. */
 hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* desc, hx_plan* plan);
 
+/* The PROPAGATOR form advances each segment by one convolution with the
+ * `steps`-step propagator of the 1D stencil (the steps-fold self-convolution of
+ * [r, 1-2r, r], see hx_propagator_coefficients), a banded Toeplitz product run
+ * as bf16 matrix-core tiles on an exact three-term bf16 split of every f32
+ * operand, accumulated in f32.  A segment qualifies when: dtype is HX_F32, the
+ * mode PERSISTENT, 1 <= steps <= 64; both ends PERIODIC (then n >= steps) or
+ * both GHOST with halo_width >= 4 * ceil(steps / 4); n is a multiple of 4; and
+ * in, out, the end of the left halo and the start of the right halo are
+ * 16-byte aligned.  Results agree with stepping to f32 rounding (not bit for
+ * bit); a non-finite input cell may also reach outputs up to steps + 46 cells
+ * away, not only steps (the zero taps of the tile multiply it). */
+
 /* Run a batch plan once after `deps`. */
 hx_status hx_launch_batched(hx_ctx ctx, hx_plan plan, const hx_event* deps, int ndeps,
                             hx_event* out);
+
+/* The `steps`-step propagator of the 1D heat stencil with diffusion number r:
+ * taps[steps + j] = p_j for -steps <= j <= steps (2*steps + 1 values), the
+ * steps-fold self-convolution of [r, 1 - 2r, r], computed in FP64.  One step
+ * is u'_i = u_i + r (u_{i-1} - 2 u_i + u_{i+1}), so steps steps on a periodic
+ * or halo-fed segment are u^(steps)_i = sum_j p_j u_{i+j}.  Needs no device. */
+hx_status hx_propagator_coefficients(double r, int steps, double* taps);
 
 /* Free a plan (waits for the context's queued work first). */
 hx_status hx_plan_destroy(hx_ctx ctx, hx_plan plan);

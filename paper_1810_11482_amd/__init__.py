@@ -98,6 +98,7 @@ class hx_pipeline_desc(ctypes.Structure):
 
 HX_PART_GRAPH, HX_PART_PLAIN, HX_PART_BATCHED = 0, 1, 2
 HX_BATCH_PERSISTENT, HX_BATCH_GRAPH, HX_BATCH_PLAIN = 0, 1, 2
+HX_FORM_DIRECT, HX_FORM_PROPAGATOR, HX_FORM_AUTO = 0, 1, 2
 
 
 class hx_segment(ctypes.Structure):
@@ -112,7 +113,8 @@ class hx_batch_desc(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int), ("steps", ctypes.c_int), ("count", ctypes.c_int),
                 ("segs", ctypes.POINTER(hx_segment)), ("mode", ctypes.c_int),
                 ("cells_per_lane", ctypes.c_int), ("waves_per_group", ctypes.c_int),
-                ("grid_waves_per_cu", ctypes.c_int)]
+                ("grid_waves_per_cu", ctypes.c_int), ("form", ctypes.c_int),
+                ("span_blocks", ctypes.c_int)]
 
 
 class hx_vc_args(ctypes.Structure):
@@ -155,6 +157,8 @@ _PROTOS = {
                                  ctypes.c_int, ctypes.POINTER(_u64)]),
     "hx_when_all": (_i32, [_vp, ctypes.POINTER(_u64), ctypes.c_int, ctypes.POINTER(_u64)]),
     "hx_plan_create_batched": (_i32, [_vp, ctypes.POINTER(hx_batch_desc), ctypes.POINTER(_u64)]),
+    "hx_propagator_coefficients": (_i32, [ctypes.c_double, ctypes.c_int,
+                                          ctypes.POINTER(ctypes.c_double)]),
     "hx_launch_batched": (_i32, [_vp, _u64, ctypes.POINTER(_u64), ctypes.c_int,
                                  ctypes.POINTER(_u64)]),
     "hx_plan_destroy": (_i32, [_vp, _u64]),
@@ -382,11 +386,12 @@ def hx_run_pipeline(ctx, desc: hx_pipeline_desc, deps=(), op_events=False):
 
 
 def hx_plan_create_batched(ctx, dtype, steps, segs, mode=HX_BATCH_PERSISTENT,
-                           cells_per_lane=0, waves_per_group=0, grid_waves_per_cu=0) -> int:
+                           cells_per_lane=0, waves_per_group=0, grid_waves_per_cu=0,
+                           form=HX_FORM_DIRECT, span_blocks=0) -> int:
     """segs: a list of hx_segment."""
     arr = (hx_segment * len(segs))(*segs)
     d = hx_batch_desc(dtype, steps, len(segs), arr, mode, cells_per_lane, waves_per_group,
-                      grid_waves_per_cu)
+                      grid_waves_per_cu, form, span_blocks)
     h = _u64()
     _ok(ctx, lib.hx_plan_create_batched(ctx, ctypes.byref(d), ctypes.byref(h)))
     return h.value
@@ -682,6 +687,16 @@ def hx_tune_batched(ctx, dtype, steps, segs, budget_ms: int = 2000) -> hx_batch_
     _ok(ctx, lib.hx_tune_batched(ctx, ctypes.byref(d), budget_ms, ctypes.byref(best)))
     best._keep = arr
     return best
+
+
+def hx_propagator_coefficients(r: float, steps: int) -> "np.ndarray":
+    """The steps-step propagator taps p_{-steps}..p_{steps} (FP64)."""
+    import numpy as np
+    out = np.empty(2 * steps + 1, dtype=np.float64)
+    st = lib.hx_propagator_coefficients(float(r), int(steps),
+                                        out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    _ok(None, st)
+    return out
 
 
 def hx_tune_cache_save(path: str) -> None:

@@ -9,7 +9,14 @@
 //  GRAPH       one kernel launch per segment, captured once into a hipGraph
 //              and replayed as a single graph launch.
 //  PLAIN       the comparator: one launch per segment per time step.
+//
+// A PERSISTENT plan evaluates its pass in one of two forms: DIRECT (the tile
+// kernels, step by step) or PROPAGATOR (one convolution with the D-step
+// propagator on the matrix cores, f32; see hx_prop1d.hip).  For the latter
+// the plan holds each distinct r's taps and a table of per-wave spans.
 #include <algorithm>
+#include <cmath>
+#include <map>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -38,6 +45,11 @@ struct BatchPlan {
     int64_t grid_waves = 0;
     int64_t per_seg = 0;  // tiles of every segment when all are equal (table unused)
     bool scaled = true;    // every segment runs the rescaled update
+    bool prop = false;     // PROPAGATOR form
+    PropSeg* psegs_dev = nullptr;
+    PropWave* pwaves_dev = nullptr;
+    float* taps_dev = nullptr;
+    int64_t pwaves = 0;
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -55,13 +67,78 @@ void destroy_plan(void* p) {
     if (b->segs_dev) hipFree(b->segs_dev);
     if (b->tseg_dev) hipFree(b->tseg_dev);
     if (b->tidx_dev) hipFree(b->tidx_dev);
+    if (b->psegs_dev) hipFree(b->psegs_dev);
+    if (b->pwaves_dev) hipFree(b->pwaves_dev);
+    if (b->taps_dev) hipFree(b->taps_dev);
     delete b;
 }
 
 size_t esz(int dt) { return dt == HX_F64 ? 8 : 4; }
 int vecn(int dt) { return dt == HX_F64 ? 2 : 4; }
 
+// The D-step propagator: [1] convolved D times with [r, 1 - 2r, r], in FP64.
+std::vector<double> propagator(double r, int D) {
+    std::vector<double> p(1, 1.0);
+    for (int t = 0; t < D; ++t) {
+        std::vector<double> q(p.size() + 2, 0.0);
+        for (size_t k = 0; k < p.size(); ++k) {
+            q[k] += r * p[k];
+            q[k + 1] += (1.0 - 2.0 * r) * p[k];
+            q[k + 2] += r * p[k];
+        }
+        p.swap(q);
+    }
+    return p;
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+// Why a segment cannot take the propagator form of a D-step pass (nullptr if
+// it can).
+const char* prop_unfit(const Seg1D& s, int D) {
+    int OD, NC;
+    if (!prop1d_geometry(D, &OD, &NC)) return "steps must be 1..64";
+    if (s.n % 4) return "n must be a multiple of 4";
+    if (!aligned16(s.in) || !aligned16(s.out)) return "in and out must be 16-byte aligned";
+    if (s.bc_lo == HX_BC_PERIODIC && s.bc_hi == HX_BC_PERIODIC) {
+        if (s.n < D) return "a periodic segment needs n >= steps";
+        return nullptr;
+    }
+    if (s.bc_lo != HX_BC_GHOST || s.bc_hi != HX_BC_GHOST)
+        return "both ends must be PERIODIC or both GHOST";
+    if (s.hw < 4 * ((D + 3) / 4)) return "halo_width must be at least 4 * ceil(steps / 4)";
+    const float* lo_end = static_cast<const float*>(s.halo_lo) + s.hw;
+    if (!aligned16(lo_end) || !aligned16(s.halo_hi))
+        return "the end of halo_lo and the start of halo_hi must be 16-byte aligned";
+    return nullptr;
+}
+
+// Blocks per wave: the span that fills the device in whole rounds of
+// `slots` concurrent waves at the least modelled cost (rounds x (span + a
+// start-up of about four iterations)).
+int choose_span(const std::vector<int64_t>& blocks, int64_t slots) {
+    int best = 32;
+    double best_cost = 1e300;
+    for (int ni = 8; ni <= 40; ++ni) {
+        int64_t w = 0;
+        for (int64_t b : blocks) w += (b + ni - 1) / ni;
+        const double cost = (double)((w + slots - 1) / slots) * (ni + 4);
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = ni;
+        }
+    }
+    return best;
+}
+
 }  // namespace
+
+extern "C" hx_status hx_propagator_coefficients(double r, int steps, double* taps) {
+    if (!taps || steps < 0 || steps > (1 << 20) || !std::isfinite(r)) return HX_ERR_ARG;
+    const std::vector<double> p = propagator(r, steps);
+    std::copy(p.begin(), p.end(), taps);
+    return HX_OK;
+}
 
 extern "C" hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* d, hx_plan* out) {
     Ctx* c = reinterpret_cast<Ctx*>(ctx);
@@ -74,6 +151,11 @@ extern "C" hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* d, 
     if (d->steps < 0) return c->fail(HX_ERR_ARG, "negative steps");
     if (d->mode != HX_BATCH_PERSISTENT && d->mode != HX_BATCH_GRAPH && d->mode != HX_BATCH_PLAIN)
         return c->fail(HX_ERR_ARG, "bad mode");
+    if (d->form != HX_FORM_DIRECT && d->form != HX_FORM_PROPAGATOR && d->form != HX_FORM_AUTO)
+        return c->fail(HX_ERR_ARG, "bad form");
+    if (d->form == HX_FORM_PROPAGATOR && (d->mode != HX_BATCH_PERSISTENT || d->dtype != HX_F32))
+        return c->fail(HX_ERR_ARG, "the propagator form needs a PERSISTENT f32 batch");
+    if (d->span_blocks < 0) return c->fail(HX_ERR_ARG, "span_blocks must be >= 0");
     hipSetDevice(c->device);
     const size_t es = esz(d->dtype);
     const int vn = vecn(d->dtype);
@@ -100,10 +182,6 @@ extern "C" hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* d, 
     const int fused = (d->mode == HX_BATCH_PLAIN) ? 1 : d->steps;
     bp->g.steps = fused;
     bp->g.halo = std::max(vn, (fused + vn - 1) / vn * vn);
-    if (fused > max_time_block_1d(d->dtype, bp->g.cpl)) {
-        delete bp;
-        return c->fail(HX_ERR_ARG, "steps exceed the fused-pass limit of the tile geometry");
-    }
 
     for (int i = 0; i < d->count; ++i) {
         const hx_segment& s = d->segs[i];
@@ -167,7 +245,100 @@ extern "C" hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* d, 
         bp->tmps.push_back(pt);
     }
 
-    if (d->mode == HX_BATCH_PERSISTENT) {
+    // form: PROPAGATOR when asked (every segment must qualify) or, for AUTO,
+    // when tuned so or untuned and every segment qualifies
+    if (d->mode == HX_BATCH_PERSISTENT && d->dtype == HX_F32 && d->form != HX_FORM_DIRECT) {
+        const char* why = nullptr;
+        int bad_seg = -1;
+        for (size_t i = 0; i < bp->segs.size() && !why; ++i) {
+            why = prop_unfit(bp->segs[i], d->steps);
+            if (why) bad_seg = (int)i;
+        }
+        if (d->form == HX_FORM_PROPAGATOR && why) {
+            delete bp;
+            return c->fail(HX_ERR_ARG, "propagator form: segment " + std::to_string(bad_seg) +
+                                           ": " + why);
+        }
+        const bool tuned_direct = tuned && tg.mode == 1 + HX_FORM_DIRECT;
+        bp->prop = !why && !(d->form == HX_FORM_AUTO && tuned_direct);
+    }
+    if (!bp->prop && fused > max_time_block_1d(d->dtype, bp->g.cpl)) {
+        delete bp;
+        return c->fail(HX_ERR_ARG, "steps exceed the fused-pass limit of the tile geometry");
+    }
+
+    if (bp->prop) {
+        // taps of each distinct r, then the segments and the per-wave spans
+        std::map<double, size_t> tap_at;
+        std::vector<float> taps;
+        const int D = d->steps;
+        for (const Seg1D& sg : bp->segs)
+            if (!tap_at.count(sg.r)) {
+                tap_at[sg.r] = taps.size();
+                for (double v : propagator(sg.r, D)) taps.push_back((float)v);
+            }
+        hipDeviceProp_t prop;
+        hipGetDeviceProperties(&prop, c->device);
+        int OD = 0, NC = 0;
+        prop1d_geometry(D, &OD, &NC);
+        // two waves per SIMD fit up to 9 chunks (18 KiB of LDS, <= 256 registers each)
+        const int64_t slots = (int64_t)prop.multiProcessorCount * (NC <= 9 ? 8 : 4);
+        std::vector<int64_t> blocks;
+        for (const Seg1D& sg : bp->segs) blocks.push_back((sg.n + 1023) / 1024);
+        const int ni = d->span_blocks > 0 ? d->span_blocks
+                       : (d->form == HX_FORM_AUTO && tuned && tg.rows > 0)
+                           ? tg.rows
+                           : choose_span(blocks, slots);
+        std::vector<PropWave> waves;
+        for (size_t i = 0; i < bp->segs.size(); ++i)
+            for (int64_t b0 = 0; b0 < blocks[i]; b0 += ni) {
+                PropWave w{};
+                w.seg = (uint32_t)i;
+                w.blk0 = (uint32_t)b0;
+                w.ni = (uint32_t)std::min<int64_t>(ni, blocks[i] - b0);
+                w.interior = (b0 >= 1 && 1024 * (b0 + w.ni + 1) <= bp->segs[i].n) ? 1u : 0u;
+                waves.push_back(w);
+            }
+        if ((int64_t)waves.size() >= (int64_t(1) << 31) || blocks.back() >= (int64_t(1) << 32)) {
+            destroy_plan(bp);
+            return c->fail(HX_ERR_RANGE, "the batch has too many propagator waves");
+        }
+        bp->pwaves = (int64_t)waves.size();
+        bool ok = hipMalloc(&bp->taps_dev, 4 * taps.size()) == hipSuccess &&
+                  hipMalloc(&bp->psegs_dev, sizeof(PropSeg) * bp->segs.size()) == hipSuccess &&
+                  hipMalloc(&bp->pwaves_dev, sizeof(PropWave) * waves.size()) == hipSuccess;
+        std::vector<PropSeg> ps;
+        if (ok) {
+            for (const Seg1D& sg : bp->segs) {
+                PropSeg q{};
+                q.in = static_cast<const float*>(sg.in);
+                q.out = static_cast<float*>(sg.out);
+                q.n = sg.n;
+                q.coef = bp->taps_dev + tap_at[sg.r];
+                if (sg.bc_lo == HX_BC_PERIODIC) {
+                    q.lo_base = q.in + sg.n;
+                    q.hi_base = q.in;
+                    q.lo_av = q.hi_av = sg.n;
+                } else {
+                    q.lo_base = static_cast<const float*>(sg.halo_lo) + sg.hw;
+                    q.hi_base = static_cast<const float*>(sg.halo_hi);
+                    q.lo_av = q.hi_av = 4 * (sg.hw / 4);
+                }
+                ps.push_back(q);
+            }
+            ok = hipMemcpy(bp->taps_dev, taps.data(), 4 * taps.size(), hipMemcpyHostToDevice) ==
+                     hipSuccess &&
+                 hipMemcpy(bp->psegs_dev, ps.data(), sizeof(PropSeg) * ps.size(),
+                           hipMemcpyHostToDevice) == hipSuccess &&
+                 hipMemcpy(bp->pwaves_dev, waves.data(), sizeof(PropWave) * waves.size(),
+                           hipMemcpyHostToDevice) == hipSuccess;
+        }
+        if (!ok) {
+            hipGetLastError();
+            destroy_plan(bp);
+            return c->fail(HX_ERR_OOM, "could not allocate the propagator tables");
+        }
+    } else if (d->mode == HX_BATCH_PERSISTENT) {
         // tile table, largest segments first
         std::vector<int> order(d->count);
         std::iota(order.begin(), order.end(), 0);
@@ -261,6 +432,8 @@ extern "C" hx_status hx_launch_batched(hx_ctx ctx, hx_plan plan, const hx_event*
     return c->submit(
         SC_COMPUTE, deps, ndeps, bp->acc, what,
         [bp](hipStream_t st) -> hipError_t {
+            if (bp->prop)
+                return launch_prop1d(bp->psegs_dev, bp->pwaves_dev, bp->pwaves, bp->steps, st);
             if (bp->mode == HX_BATCH_PERSISTENT)
                 return launch_stencil1d_batched(bp->dtype, bp->segs_dev, bp->tseg_dev,
                                                 bp->tidx_dev, bp->ntiles, bp->g, bp->grid_waves,

@@ -91,6 +91,41 @@ hipError_t launch_stencil1d_batched(int dtype, const Seg1D* segs_dev, const uint
                                     int64_t grid_waves, int64_t per_seg, bool scaled,
                                     hipStream_t stream);
 
+// Propagator form of a fused 1D pass (f32, MFMA): D steps as one convolution
+// with the D-step propagator.  A segment reads cell c < 0 at lo_base + c
+// (clamped to c >= -lo_av) and cell c >= n at hi_base + (c - n) (clamped to
+// c - n <= hi_av - 4): for a halo-fed segment these are the halos, for a
+// periodic one the segment itself.  n, lo_av and hi_av are multiples of 4 and
+// every base is 16-byte aligned.
+struct PropSeg {
+    const float* in;
+    float* out;
+    const float* lo_base;
+    const float* hi_base;
+    const float* coef;     // 2D+1 taps, coef[D + j] = p_j
+    int64_t n;
+    int64_t lo_av, hi_av;
+};
+
+// One wave's work: iterations blk0 .. blk0+ni-1 (1024 cells each) of segment
+// `seg`; interior = every cell it reads lies in [0, n).
+struct PropWave {
+    uint32_t seg, blk0, ni, interior;
+};
+
+// Window of the propagator kernel for depth D: offset OD (the window starts OD
+// cells before a stream, a multiple of 8 >= D) and NC 16-cell chunks.
+// Supported for 1 <= D <= 64.
+inline bool prop1d_geometry(int D, int* OD, int* NC) {
+    if (D < 1 || D > 64) return false;
+    *OD = 8 * ((D + 7) / 8);
+    *NC = (32 + D + *OD + 15) / 16;
+    return true;
+}
+
+hipError_t launch_prop1d(const PropSeg* segs_dev, const PropWave* waves_dev, int64_t nwaves, int D,
+                         hipStream_t stream);
+
 // One 2D band: ny rows of nx cells, row-major, advanced `steps` steps from in
 // into out.  Rows outside [0, ny) come from the top/bottom rule; columns
 // outside [0, nx) are zero-Dirichlet.

@@ -232,35 +232,50 @@ extern "C" hx_status hx_tune_batched(hx_ctx ctx, const hx_batch_desc* desc, int 
     const auto t_start = clk::now();
     double best_t = 1e30;
     bool found = false;
+    // candidates: the direct form over tile geometries, then (f32) the
+    // propagator form over a few spans; a candidate the plan rejects is skipped
+    std::vector<hx_batch_desc> cands;
     for (int cpl : {16, 32, 8, 64})
         for (int grid : {-1, 64, 16}) {
-            if (found && std::chrono::duration<double, std::milli>(clk::now() - t_start).count() >
-                             budget_ms)
-                break;
             hx_batch_desc d = *desc;
+            d.form = HX_FORM_DIRECT;
             d.cells_per_lane = cpl;
             d.grid_waves_per_cu = grid;
             d.waves_per_group = 4;
-            hx_plan plan = 0;
-            if (hx_plan_create_batched(ctx, &d, &plan) != HX_OK) continue;
-            double bt = 1e30;
-            for (int r = 0; r < 3; ++r) {
-                const auto t0 = clk::now();
-                hx_event ev = 0;
-                if (hx_launch_batched(ctx, plan, nullptr, 0, &ev) != HX_OK) break;
-                const hx_status st = hx_wait(ctx, ev, -1);
-                hx_event_release(ctx, ev);
-                if (st != HX_OK) break;
-                const double s = std::chrono::duration<double>(clk::now() - t0).count();
-                if (r > 0) bt = std::min(bt, s);
-            }
-            hx_plan_destroy(ctx, plan);
-            if (bt < best_t) {
-                best_t = bt;
-                *best = d;
-                found = true;
-            }
+            d.span_blocks = 0;
+            cands.push_back(d);
         }
+    if (desc->dtype == HX_F32)
+        for (int span : {0, 16, 24, 40}) {
+            hx_batch_desc d = *desc;
+            d.form = HX_FORM_PROPAGATOR;
+            d.span_blocks = span;
+            cands.insert(cands.begin() + (span == 0 ? 0 : (long)cands.size()), d);
+        }
+    for (const hx_batch_desc& d : cands) {
+        if (found &&
+            std::chrono::duration<double, std::milli>(clk::now() - t_start).count() > budget_ms)
+            break;
+        hx_plan plan = 0;
+        if (hx_plan_create_batched(ctx, &d, &plan) != HX_OK) continue;
+        double bt = 1e30;
+        for (int r = 0; r < 3; ++r) {
+            const auto t0 = clk::now();
+            hx_event ev = 0;
+            if (hx_launch_batched(ctx, plan, nullptr, 0, &ev) != HX_OK) break;
+            const hx_status st = hx_wait(ctx, ev, -1);
+            hx_event_release(ctx, ev);
+            if (st != HX_OK) break;
+            const double s = std::chrono::duration<double>(clk::now() - t0).count();
+            if (r > 0) bt = std::min(bt, s);
+        }
+        hx_plan_destroy(ctx, plan);
+        if (bt < best_t) {
+            best_t = bt;
+            *best = d;
+            found = true;
+        }
+    }
     if (!found) return HX_ERR_ARG;
     int64_t total = 0;
     for (int i = 0; i < desc->count; ++i) total += desc->segs[i].n;
@@ -268,6 +283,8 @@ extern "C" hx_status hx_tune_batched(hx_ctx ctx, const hx_batch_desc* desc, int 
     g.cpl = best->cells_per_lane;
     g.wpg = best->waves_per_group;
     g.grid = best->grid_waves_per_cu;
+    g.mode = 1 + best->form;
+    g.rows = best->form == HX_FORM_PROPAGATOR ? best->span_blocks : 0;
     tune_store(tune_key_batched(desc->dtype, total, desc->count, desc->steps), g);
     return HX_OK;
 }

@@ -22,7 +22,8 @@ struct TunedGeom {
     int wpg = 0;       // waves per group
     int rows = 0;      // 2D rows per wave
     int grid = 0;      // batched: waves per CU
-    int mode = 0;      // batched: chosen mode
+    int mode = 0;      // batched: chosen hx_batch_form + 1 (0 = none)
+                       // (a batched propagator keeps its span_blocks in `rows`)
 };
 
 TuneKey tune_key_1d(int dtype, int64_t n, int steps, bool ghost);

@@ -1,0 +1,229 @@
+"""GPU parity of the propagator form of a batched 1D pass against the oracle's
+stepping.  The form runs D steps as one convolution with the D-step propagator
+on the matrix cores.
+
+Covered:
+- periodic segments and halo-coupled partitions, depths 1..64, ragged sizes
+  and every span of blocks per wave;
+- identical bits for every span;
+- the plan rejects segments the form cannot take, and AUTO falls back to the
+  direct form for them;
+- the full-size headline form (2^28 cells, 64 partition views of one arena,
+  50 steps), sampled.
+
+The FP32 bar is the suite's: 1e-5 relative (L2 and per cell) against FP64."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from conftest import rel_l2, rel_max
+
+pytestmark = pytest.mark.gpu
+hx = pytest.importorskip("paper_1810_11482_amd")
+from hxutil import download, upload  # noqa: E402
+
+GUARD = 64  # guard cells between packed segments (a multiple of 4)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if hx.hx_device_count() == 0:
+        pytest.skip("no GPU")
+    c = hx.hx_ctx_create(0)
+    yield c
+    hx.hx_ctx_destroy(c)
+
+
+def periodic_batch(ctx, sizes, rs, steps, form, span=0, seed=0, sentinel=-7.0):
+    """Segments packed at 16-byte-aligned offsets of one buffer, run once;
+    returns (input, output, offsets)."""
+    offs, o = [], GUARD
+    for n in sizes:
+        offs.append(o)
+        o += -(-int(n) // 4) * 4 + GUARD
+    total = o
+    u = np.full(total, sentinel, dtype=np.float32)
+    for k, (o, n) in enumerate(zip(offs, sizes)):
+        u[o:o + n] = workloads.uniform(int(n), 500 + seed, k, 0, 1, np.float32)
+    bin_ = upload(ctx, u)
+    bout = upload(ctx, np.full(total, sentinel, dtype=np.float32))
+    segs = [hx.segment(inp=bin_, in_offset=o * 4, out=bout, out_offset=o * 4, n=int(n),
+                       r=float(r), bc_lo=hx.HX_BC_PERIODIC, bc_hi=hx.HX_BC_PERIODIC)
+            for o, n, r in zip(offs, sizes, rs)]
+    plan = hx.hx_plan_create_batched(ctx, hx.HX_F32, steps, segs, hx.HX_BATCH_PERSISTENT,
+                                     form=form, span_blocks=span)
+    ev = hx.hx_launch_batched(ctx, plan)
+    assert hx.hx_wait(ctx, ev) == hx.HX_OK, hx.hx_last_error(ctx)
+    hx.hx_event_release(ctx, ev)
+    hx.hx_plan_destroy(ctx, plan)
+    out = download(ctx, bout, total, np.float32)
+    hx.hx_buffer_destroy(ctx, bin_)
+    hx.hx_buffer_destroy(ctx, bout)
+    return u, out, offs
+
+
+def sizes_for(D):
+    """Ragged periodic sizes (multiples of 4, at least D) spanning the edge and
+    interior wave paths: tiny, just under and over a 1024-cell block, several
+    spans."""
+    m = -(-D // 4) * 4
+    return [m, max(m, 64), 1000, 1024, 1028, 4108, 30000, 262180]
+
+
+@pytest.mark.parametrize("D", [1, 3, 8, 20, 33, 50, 64])
+def test_periodic_segments_match_oracle(ctx, D):
+    sizes = sizes_for(D)
+    rs = [0.25, 0.05, 0.45, 0.2, 0.125, 0.3, 0.25, 0.1][:len(sizes)]
+    u, out, offs = periodic_batch(ctx, sizes, rs, D, hx.HX_FORM_PROPAGATOR, seed=D)
+    mask = np.ones(out.size, bool)
+    for k, (o, n, r) in enumerate(zip(offs, sizes, rs)):
+        mask[o:o + n] = False
+        ref = oracle.heat1d_periodic(u[o:o + n].astype(np.float64), float(r), D)
+        got = out[o:o + n]
+        e2, em = rel_l2(got, ref), rel_max(got, ref)
+        assert e2 <= 1e-5 and em <= 1e-5, (D, k, n, e2, em)
+    assert np.all(out[mask] == -7.0)  # guards untouched
+
+
+def test_spans_give_identical_bits(ctx):
+    """Every cell's taps meet the same window values in the same order,
+    whether its wave is an edge or an interior wave and however many blocks
+    a wave walks."""
+    sizes, rs = [4108, 30000, 262180, 64, 2052], [0.25, 0.1, 0.2, 0.3, 0.45]
+    base = periodic_batch(ctx, sizes, rs, 50, hx.HX_FORM_PROPAGATOR, span=0)[1]
+    for span in (1, 2, 3, 5, 6, 7, 13, 40):
+        got = periodic_batch(ctx, sizes, rs, 50, hx.HX_FORM_PROPAGATOR, span=span)[1]
+        assert np.array_equal(base, got), span
+
+
+@pytest.mark.parametrize("D,hw_extra", [(50, 0), (50, 6), (17, 3), (64, 0)])
+def test_halo_coupled_partitions(ctx, D, hw_extra):
+    """Partitions of one periodic array laid back to back in one buffer, halos
+    read from the neighbours' views: one pass equals the oracle on the whole
+    array, and agrees with the direct form within the tolerance."""
+    sizes = [4096, 1028, 70000, 8, 1024 * 37, 9000, 65536] if D <= 8 else \
+        [4096, 1028, 70000, 68, 1024 * 37, 9000, 65536]
+    n = sum(sizes)
+    offs = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+    u0 = workloads.uniform(n, 510, D, 0, 1, np.float32)
+    hw = 4 * (-(-D // 4)) + hw_extra
+    a = upload(ctx, u0)
+    results = []
+    for form in (hx.HX_FORM_PROPAGATOR, hx.HX_FORM_DIRECT):
+        b = hx.hx_buffer_create(ctx, n * 4)
+        segs = []
+        P = len(sizes)
+        for p in range(P):
+            lp, rp = (p - 1) % P, (p + 1) % P
+            segs.append(hx.segment(inp=a, in_offset=int(offs[p]) * 4, out=b,
+                                   out_offset=int(offs[p]) * 4, n=sizes[p], r=0.25,
+                                   bc_lo=hx.HX_BC_GHOST, bc_hi=hx.HX_BC_GHOST, halo_lo=a,
+                                   halo_lo_offset=int(offs[lp] + sizes[lp] - hw) * 4,
+                                   halo_hi=a, halo_hi_offset=int(offs[rp]) * 4, halo_width=hw))
+        plan = hx.hx_plan_create_batched(ctx, hx.HX_F32, D, segs, hx.HX_BATCH_PERSISTENT,
+                                         form=form)
+        ev = hx.hx_launch_batched(ctx, plan)
+        assert hx.hx_wait(ctx, ev) == hx.HX_OK, hx.hx_last_error(ctx)
+        hx.hx_event_release(ctx, ev)
+        hx.hx_plan_destroy(ctx, plan)
+        results.append(download(ctx, b, n, np.float32))
+        hx.hx_buffer_destroy(ctx, b)
+    hx.hx_buffer_destroy(ctx, a)
+    ref = oracle.heat1d_periodic(u0.astype(np.float64), 0.25, D)
+    prop, direct = results
+    assert rel_l2(prop, ref) <= 1e-5 and rel_max(prop, ref) <= 1e-5
+    assert rel_l2(prop, direct) <= 1e-5
+
+
+def test_unfit_segments_rejected_and_auto_falls_back(ctx):
+    b = hx.hx_buffer_create(ctx, 1 << 16)
+    c = hx.hx_buffer_create(ctx, 1 << 16)
+    per = dict(bc_lo=hx.HX_BC_PERIODIC, bc_hi=hx.HX_BC_PERIODIC)
+    ok = hx.segment(inp=b, out=c, n=1024, r=0.2, **per)
+    cases = [
+        (hx.HX_F64, 20, [ok], hx.HX_BATCH_PERSISTENT),                        # f64
+        (hx.HX_F32, 65, [ok], hx.HX_BATCH_PERSISTENT),                        # too deep
+        (hx.HX_F32, 20, [ok], hx.HX_BATCH_GRAPH),                             # not persistent
+        (hx.HX_F32, 20, [hx.segment(inp=b, out=c, n=1022, r=0.2, **per)],
+         hx.HX_BATCH_PERSISTENT),                                             # n % 4
+        (hx.HX_F32, 20, [hx.segment(inp=b, in_offset=4, out=c, n=1024, r=0.2, **per)],
+         hx.HX_BATCH_PERSISTENT),                                             # misaligned
+        (hx.HX_F32, 20, [hx.segment(inp=b, out=c, n=1024, r=0.2, bc_lo=hx.HX_BC_DIRICHLET0,
+                                    bc_hi=hx.HX_BC_DIRICHLET0)],
+         hx.HX_BATCH_PERSISTENT),                                             # Dirichlet
+        (hx.HX_F32, 18, [hx.segment(inp=b, out=c, n=1024, r=0.2, bc_lo=hx.HX_BC_GHOST,
+                                    bc_hi=hx.HX_BC_GHOST, halo_lo=b, halo_lo_offset=8192,
+                                    halo_hi=b, halo_hi_offset=12288, halo_width=18)],
+         hx.HX_BATCH_PERSISTENT),                                  # halo 18 < 4 ceil(18/4)
+        (hx.HX_F32, 20, [hx.segment(inp=b, out=c, n=16, r=0.2, **per)],
+         hx.HX_BATCH_PERSISTENT),                                             # n < steps
+    ]
+    for dt, steps, segs, mode in cases:
+        with pytest.raises(hx.HxError) as e:
+            hx.hx_plan_create_batched(ctx, dt, steps, segs, mode, form=hx.HX_FORM_PROPAGATOR)
+        assert e.value.status == hx.HX_ERR_ARG
+    with pytest.raises(hx.HxError) as e:
+        hx.hx_plan_create_batched(ctx, hx.HX_F32, 20, [ok], form=7)
+    assert e.value.status == hx.HX_ERR_ARG
+    # AUTO over an unfit (Dirichlet) segment runs the direct form
+    d = hx.segment(inp=b, out=c, n=1024, r=0.2, bc_lo=hx.HX_BC_DIRICHLET0,
+                   bc_hi=hx.HX_BC_DIRICHLET0)
+    plan = hx.hx_plan_create_batched(ctx, hx.HX_F32, 20, [d], form=hx.HX_FORM_AUTO)
+    hx.hx_plan_destroy(ctx, plan)
+    hx.hx_buffer_destroy(ctx, b)
+    hx.hx_buffer_destroy(ctx, c)
+
+
+def test_auto_takes_the_propagator_where_every_segment_fits(ctx):
+    sizes, rs = [4108, 30000, 64], [0.25, 0.1, 0.3]
+    prop = periodic_batch(ctx, sizes, rs, 30, hx.HX_FORM_PROPAGATOR)[1]
+    auto = periodic_batch(ctx, sizes, rs, 30, hx.HX_FORM_AUTO)[1]
+    direct = periodic_batch(ctx, sizes, rs, 30, hx.HX_FORM_DIRECT)[1]
+    assert np.array_equal(prop, auto)
+    assert not np.array_equal(prop, direct)  # a different evaluation, same result to f32
+
+
+def test_full_size_headline_form_sampled(ctx):
+    """2^28 fp32 cells as 64 partition views of one HBM arena, r = 0.25,
+    50 steps as one propagator launch (halos of 52 cells from the neighbour
+    views); sampled cells against the oracle's light cone, including the seams
+    of a few partitions."""
+    n, parts, T, r, hw = 1 << 28, 64, 50, 0.25, 52
+    spec = workloads.Partitioned1D()
+    hin = hx.hx_host_alloc(ctx, n * 4)
+    u0 = np.ctypeslib.as_array((np.ctypeslib.ctypes.c_float * n).from_address(hin))
+    workloads.partitioned1d_u0(spec, out=u0)
+    bounds = workloads.partition_bounds(n, parts)
+    arena_a = hx.hx_buffer_create(ctx, n * 4)
+    arena_b = hx.hx_buffer_create(ctx, n * 4)
+    pa, pb = hx.hx_buffer_ptr(ctx, arena_a)[0], hx.hx_buffer_ptr(ctx, arena_b)[0]
+    A = [hx.hx_buffer_wrap(ctx, pa + o * 4, s * 4) for o, s in bounds]
+    B = [hx.hx_buffer_wrap(ctx, pb + o * 4, s * 4) for o, s in bounds]
+    e = hx.hx_copy_async(ctx, hx.hx_copy_desc(hx.HX_H2D, hin, arena_a, 0, 0, 0, n * 4))
+    assert hx.hx_wait(ctx, e) == hx.HX_OK
+    hx.hx_event_release(ctx, e)
+    segs = []
+    for p in range(parts):
+        lp, rp = (p - 1) % parts, (p + 1) % parts
+        segs.append(hx.segment(inp=A[p], out=B[p], n=bounds[p][1], r=r, bc_lo=hx.HX_BC_GHOST,
+                               bc_hi=hx.HX_BC_GHOST, halo_lo=A[lp],
+                               halo_lo_offset=(bounds[lp][1] - hw) * 4, halo_hi=A[rp],
+                               halo_width=hw))
+    plan = hx.hx_plan_create_batched(ctx, hx.HX_F32, T, segs, hx.HX_BATCH_PERSISTENT,
+                                     form=hx.HX_FORM_PROPAGATOR)
+    ev = hx.hx_launch_batched(ctx, plan)
+    assert hx.hx_wait(ctx, ev) == hx.HX_OK, hx.hx_last_error(ctx)
+    hx.hx_event_release(ctx, ev)
+    hx.hx_plan_destroy(ctx, plan)
+    rng = np.random.default_rng(19)
+    seams = [k << 22 for k in (1, 17, 63)]
+    idx = np.sort(np.concatenate([rng.choice(n, 40, replace=False), [0, 1, n - 2, n - 1],
+                                  [s + d for s in seams for d in (-52, -2, -1, 0, 1, 51)]]))
+    ref = oracle.heat1d_periodic_at(u0.astype(np.float64), r, T, idx)
+    got = np.array([download(ctx, arena_b, 1, np.float32, offset=int(i) * 4)[0] for i in idx],
+                   dtype=np.float64)
+    assert np.max(np.abs(got - ref) / np.abs(ref)) <= 1e-5
+    for b in A + B + [arena_a, arena_b]:
+        hx.hx_buffer_destroy(ctx, b)
+    hx.hx_host_free(ctx, hin)
