@@ -692,6 +692,8 @@ def hx_tune_batched(ctx, dtype, steps, segs, budget_ms: int = 2000) -> hx_batch_
 def hx_propagator_coefficients(r: float, steps: int) -> "np.ndarray":
     """The steps-step propagator taps p_{-steps}..p_{steps} (FP64)."""
     import numpy as np
+    if int(steps) < 0:
+        raise HxError(HX_ERR_ARG, "steps must be >= 0")
     out = np.empty(2 * steps + 1, dtype=np.float64)
     st = lib.hx_propagator_coefficients(float(r), int(steps),
                                         out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))

@@ -114,15 +114,15 @@ const char* prop_unfit(const Seg1D& s, int D) {
 }
 
 // Blocks per wave: the span that fills the device in whole rounds of
-// `slots` concurrent waves at the least modelled cost (rounds x (span + a
-// start-up of about four iterations)).
+// `slots` concurrent waves at the least modelled cost, rounds x (span + a
+// start-up of about eight iterations: the taps, the first two blocks).
 int choose_span(const std::vector<int64_t>& blocks, int64_t slots) {
-    int best = 32;
+    int best = 64;
     double best_cost = 1e300;
-    for (int ni = 8; ni <= 40; ++ni) {
+    for (int ni = 8; ni <= 256; ++ni) {
         int64_t w = 0;
         for (int64_t b : blocks) w += (b + ni - 1) / ni;
-        const double cost = (double)((w + slots - 1) / slots) * (ni + 4);
+        const double cost = (double)((w + slots - 1) / slots) * (ni + 8);
         if (cost < best_cost) {
             best_cost = cost;
             best = ni;
