@@ -7,15 +7,22 @@ one HBM arena), r = 0.25, 50 steps, run as a device-resident future graph
 (Sec. V-A.2 / Algorithm 1 with the Sec. V-A.1 stencil): each pass of 50 fused
 steps is one node, launched as one batched kernel over all 64 partitions with
 every partition's halos read from its neighbours.  One bench "step" is the
-whole 50-step run over the whole array, with the data resident in HBM.
+whole 50-step run over the whole array, with the data resident in HBM.  The
+pass runs in the faster of the batched plan's two forms, chosen by a short
+untimed sweep: the direct form (the tile kernel stepping in registers) or the
+propagator form (the 50 steps as one convolution with the 50-step propagator
+on the bf16 matrix cores, operands split exactly into three bf16 terms,
+accumulated in f32).
 
 Printed: one JSON line with the throughput (cell-updates/s), the roofline of
 that kernel (per-launch durations from HIP events recorded on its stream in
-the timed region), the oracle's CPU throughput on a bounded sample, and the
-side measurements the metric names: the per-partition future graph (one node
-per partition per pass), the plain one-launch-per-partition-per-step form, the
-host-to-host pipeline with its copy overlap, the 4096-problem batched driver,
-the fp64, 2D and adjoint workloads, and a copy kernel for counter calibration.
+the timed region), the oracle's CPU throughput on the whole workload, and the
+side measurements the metric names: both forms of the pass, the per-partition
+future graph (one node per partition per pass), the plain
+one-launch-per-partition-per-step form, the host-to-host pipeline with its
+copy overlap, the 4096-problem batched driver, the fp64, 2D and adjoint
+workloads, the partition-benchmark overhead against raw HIP streams, and a
+copy kernel for counter calibration.
 """
 from __future__ import annotations
 
@@ -29,12 +36,20 @@ import numpy as np
 
 HBM_PEAK = 8.0e12            # bytes/s, MI355X HBM3E
 VALU_F32_PEAK = 157.3e12     # flop/s: 256 CU x 128 FP32 lanes/clk x 2 (FMA) x 2.4 GHz
+MFMA_BF16_PEAK = 2.5e15      # flop/s, dense bf16 matrix cores
 FLOPS_PER_UPDATE_1D = 3      # rescaled update w' = fma(b, l + rt, w): one add + one fma
 BYTES_PER_CELL_PASS = 8      # one fp32 read + one fp32 write per cell per pass
-TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                            "stencil1d_flat_2p28_fp32_traffic.md")
-KERNEL_SOURCES = ("paper_1810_11482_amd/csrc/hx_stencil1d.hip",
-                  "paper_1810_11482_amd/csrc/hx_internal.h")
+MFMA_FLOPS_PER_CHUNK = 6 * 32 * 32 * 16 * 2   # six 32x32x16 products per 16-cell window chunk
+ROOT = os.path.dirname(os.path.abspath(__file__))
+# per form: the committed counter summary of its kernel and the sources it is built from
+KERNELS = {
+    "direct": ("stencil1d_flat_2p28_fp32_traffic.md",
+               ("paper_1810_11482_amd/csrc/hx_stencil1d.hip",
+                "paper_1810_11482_amd/csrc/hx_internal.h")),
+    "propagator": ("prop1d_2p28_fp32_traffic.md",
+                   ("paper_1810_11482_amd/csrc/hx_prop1d.hip",
+                    "paper_1810_11482_amd/csrc/hx_internal.h")),
+}
 
 
 def log(msg):
@@ -71,21 +86,20 @@ def intersect_len(u1, u2):
     return tot
 
 
-def kernel_source_hash():
+def kernel_source_hash(form):
     import hashlib
     h = hashlib.sha256()
-    root = os.path.dirname(os.path.abspath(__file__))
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(root, f), "rb") as fh:
+    for f in KERNELS[form][1]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the headline kernel from the committed rocprofv3
+def measured_traffic(form):
+    """HBM bytes per launch of the form's kernel from the committed rocprofv3
     counter summary, or None when the kernel sources changed since it was taken."""
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(os.path.join(ROOT, "profiles", KERNELS[form][0])).read()
     except OSError:
         return None
     vals = {}
@@ -93,7 +107,7 @@ def measured_traffic():
         if ":" in line and line.startswith("- "):
             k, v = line[2:].split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
-    if vals.get("source_hash") != kernel_source_hash():
+    if vals.get("source_hash") != kernel_source_hash(form):
         return None
     try:
         return float(vals["traffic_bytes_per_launch"])
@@ -181,11 +195,14 @@ def time_steps(P, k, mode, tb, cpl, nodes=False):
 class BatchedPass:
     """The partitioned run in its batched form: every pass of `tb` steps is one
     node of the future graph, launched as one batched kernel over all
-    partitions (each partition's halos read from its neighbours' views), and
-    chained on the previous pass."""
+    partitions (each partition's halos, `hw` >= tb cells, read from its
+    neighbours' views), and chained on the previous pass.  form: the batched
+    plan's direct form (tile geometry `cpl`) or its propagator form (`span`
+    blocks per wave, 0 = the plan's choice)."""
 
-    def __init__(self, hx, ctx, P, tb, cpl):
+    def __init__(self, hx, ctx, P, tb, cpl, form=0, span=0, hw=None):
         self.hx, self.ctx, self.P, self.tb, self.cpl = hx, ctx, P, tb, cpl
+        hw = tb if hw is None else hw
         self.plans = []
         for src, dst in ((P.A, P.B), (P.B, P.A)):
             segs = []
@@ -193,11 +210,12 @@ class BatchedPass:
                 lp, rp = (p - 1) % P.parts, (p + 1) % P.parts
                 segs.append(hx.segment(inp=src[p], out=dst[p], n=P.sizes[p], r=P.r,
                                        bc_lo=hx.HX_BC_GHOST, bc_hi=hx.HX_BC_GHOST,
-                                       halo_lo=src[lp], halo_lo_offset=(P.sizes[lp] - tb) * 4,
-                                       halo_hi=src[rp], halo_width=tb))
+                                       halo_lo=src[lp], halo_lo_offset=(P.sizes[lp] - hw) * 4,
+                                       halo_hi=src[rp], halo_width=hw))
             self.plans.append(hx.hx_plan_create_batched(ctx, hx.HX_F32, tb, segs,
                                                         hx.HX_BATCH_PERSISTENT, cells_per_lane=cpl,
-                                                        grid_waves_per_cu=-1))
+                                                        grid_waves_per_cu=-1, form=form,
+                                                        span_blocks=span))
         self.passes = P.steps // tb
         assert self.passes * tb == P.steps, "the time block must divide the step count"
 
@@ -227,6 +245,10 @@ def main():
     ap.add_argument("--log2n", type=int, default=28)
     ap.add_argument("--parts", type=int, default=64)
     ap.add_argument("--cells-per-lane", type=int, default=0, help="0 = pick by a short sweep")
+    ap.add_argument("--form", choices=("auto", "direct", "propagator"), default="auto",
+                    help="form of the headline pass; auto = the faster in a short sweep")
+    ap.add_argument("--span-blocks", type=int, default=0,
+                    help="propagator form: 1024-cell blocks per wave, 0 = sweep")
     ap.add_argument("--streams", type=int, default=4,
                     help="compute streams of the context (the per-partition graph spreads its "
                          "nodes over them)")
@@ -258,11 +280,21 @@ def main():
     P = Partitioned(hx, ctx, n, args.parts, T, r)
     tb = T
 
-    # ------------------------------------------- geometry sweep (untimed)
-    cpls = [args.cells_per_lane] if args.cells_per_lane else [32, 16]
+    # ------------------------------------------- form / geometry sweep (untimed)
+    # halos of 52 cells: the 50 the pass reaches, rounded up to whole 16-byte
+    # vectors as the propagator form needs (the direct form reads its 50)
+    hw = 4 * ((tb + 3) // 4)
     cands = []
-    for cpl in cpls:
-        bp = BatchedPass(hx, ctx, P, tb, cpl)
+    if args.form in ("auto", "direct"):
+        cands += [("direct", c, 0) for c in ([args.cells_per_lane] if args.cells_per_lane
+                                            else [32, 16])]
+    if args.form in ("auto", "propagator"):
+        cands += [("propagator", 0, sp) for sp in ([args.span_blocks] if args.span_blocks
+                                                  else [0, 64])]
+    swept = []
+    for form, cpl_c, span_c in cands:
+        fcode = hx.HX_FORM_PROPAGATOR if form == "propagator" else hx.HX_FORM_DIRECT
+        bp = BatchedPass(hx, ctx, P, tb, cpl_c or 16, fcode, span_c, hw)
         bp.run(2)
         P.wait()
         torch.cuda.synchronize()
@@ -273,13 +305,18 @@ def main():
         hx.hx_event_release(ctx, P.last)
         P.last = 0
         bp.close()
-        cands.append((t, cpl))
-        log(f"sweep batched pass cpl={cpl}: {t * 1e3:.3f} ms/step")
-    _, cpl = min(cands)
+        swept.append((t, form, cpl_c or 16, span_c))
+        log(f"sweep batched pass form={form} cpl={cpl_c} span={span_c}: {t * 1e3:.3f} ms/step")
+    _, form, cpl, span = min(swept)
+    fcode = hx.HX_FORM_PROPAGATOR if form == "propagator" else hx.HX_FORM_DIRECT
+    by_form = {}
+    for t, f, c_, s_ in swept:
+        key = f"{f}_cpl{c_}" if f == "direct" else f"{f}_span{s_ or 'auto'}"
+        by_form[key] = t * 1e3
 
     # ------------------------------------------------------------ timed region
     P.reset()
-    bp = BatchedPass(hx, ctx, P, tb, cpl)
+    bp = BatchedPass(hx, ctx, P, tb, cpl, fcode, span, hw)
     bp.run(args.warmup)
     if P.last:
         P.wait()
@@ -322,27 +359,51 @@ def main():
                    if ref is not None else None)
 
     cells_per_launch = float(n)
-    steps_per_launch = tb
     bytes_per_launch = cells_per_launch * BYTES_PER_CELL_PASS
-    flops_per_launch = cells_per_launch * steps_per_launch * FLOPS_PER_UPDATE_1D
     bw = bytes_per_launch / (avg_ms * 1e-3)
-    fl = flops_per_launch / (avg_ms * 1e-3)
-    hbm_frac, alu_frac = bw / HBM_PEAK, fl / VALU_F32_PEAK
-    traffic = measured_traffic()
-    if alu_frac >= hbm_frac:
-        roof = {"bound": "alu", "achieved": fl / 1e12, "peak": VALU_F32_PEAK / 1e12,
-                "unit": "TFLOP/s", "frac": alu_frac}
+    hbm_frac = bw / HBM_PEAK
+    traffic = measured_traffic(form)
+    if form == "propagator":
+        # matrix-core work as issued: 1024-cell iterations x NC window chunks x
+        # six 32x32x16 bf16 products (NC = 9 at 50 steps)
+        od = 8 * ((tb + 7) // 8)
+        nc = (32 + tb + od + 15) // 16
+        mf_per_launch = cells_per_launch / 1024 * nc * MFMA_FLOPS_PER_CHUNK
+        mf = mf_per_launch / (avg_ms * 1e-3)
+        mfma_frac = mf / MFMA_BF16_PEAK
+        kname = f"k_prop1d<{nc}>"
+        if mfma_frac >= hbm_frac:
+            roof = {"bound": "mfma", "achieved": mf / 1e12, "peak": MFMA_BF16_PEAK / 1e12,
+                    "unit": "TFLOP/s", "frac": mfma_frac}
+        else:
+            roof = {"bound": "hbm", "achieved": bw / 1e9, "peak": HBM_PEAK / 1e9,
+                    "unit": "GB/s", "frac": hbm_frac}
+        roof.update({"mfma_bf16_flops_per_launch": mf_per_launch, "mfma_frac": mfma_frac})
     else:
-        roof = {"bound": "hbm", "achieved": bw / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                "frac": hbm_frac}
-    roof.update({"traffic": traffic,
-                 "kernel": f"k_stencil1d_flat<float,{cpl}>", "avg_launch_ms": avg_ms,
+        flops_per_launch = cells_per_launch * tb * FLOPS_PER_UPDATE_1D
+        fl = flops_per_launch / (avg_ms * 1e-3)
+        alu_frac = fl / VALU_F32_PEAK
+        kname = f"k_stencil1d_flat<float,{cpl}>"
+        if alu_frac >= hbm_frac:
+            roof = {"bound": "alu", "achieved": fl / 1e12, "peak": VALU_F32_PEAK / 1e12,
+                    "unit": "TFLOP/s", "frac": alu_frac}
+        else:
+            roof = {"bound": "hbm", "achieved": bw / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                    "frac": hbm_frac}
+        roof.update({"algorithmic_flops_per_launch": flops_per_launch, "alu_frac": alu_frac})
+    roof.update({"traffic": traffic, "kernel": kname, "avg_launch_ms": avg_ms,
                  "launches": len(durs), "algorithmic_bytes_per_launch": bytes_per_launch,
-                 "algorithmic_flops_per_launch": flops_per_launch,
-                 "hbm_algorithmic_GBps": bw / 1e9, "hbm_frac": hbm_frac, "alu_frac": alu_frac,
-                 "kernel_source_hash": kernel_source_hash()})
-    log(f"headline: {ms_per_step:.3f} ms/step, {value:.4e} cell-updates/s, kernel avg "
+                 "hbm_algorithmic_GBps": bw / 1e9, "hbm_frac": hbm_frac,
+                 "kernel_source_hash": kernel_source_hash(form)})
+    log(f"headline ({form}): {ms_per_step:.3f} ms/step, {value:.4e} cell-updates/s, kernel avg "
         f"{avg_ms:.4f} ms, sampled err {sampled_err}")
+    if form == "propagator":
+        form_desc = ("propagator: the 50 steps as one convolution with the 50-step propagator "
+                     "(101 taps, FP64 on the host, rounded to f32), a banded Toeplitz product on "
+                     "32x32x16 bf16 matrix-core tiles; every f32 operand split exactly into "
+                     "three bf16 terms, six products per pair accumulated in f32")
+    else:
+        form_desc = "direct: the tile kernel advancing the 50 steps in registers"
 
     result = {
         "metric": "stencil cell-updates/s + HBM GB/s vs roofline; % copy hidden; batched vs plain",
@@ -355,9 +416,13 @@ def main():
                                f"partitions per {tb}-step pass, halos read from neighbour "
                                f"partitions",
                    "cells": n, "parts": args.parts, "time_steps": T, "time_block": tb,
-                   "cells_per_lane": cpl, "launches_per_step": bp.passes,
+                   "update_form": form_desc,
+                   "cells_per_lane": cpl if form == "direct" else None,
+                   "span_blocks": (span or "plan's choice") if form == "propagator" else None,
+                   "halo_width": hw, "launches_per_step": bp.passes,
                    "sampled_max_rel_err_vs_oracle": sampled_err},
         "roofline": roof,
+        "pass_ms_by_form": by_form,
     }
     hx.hx_event_release(ctx, P.last)
     P.last = 0

@@ -50,6 +50,7 @@ struct BatchPlan {
     PropWave* pwaves_dev = nullptr;
     float* taps_dev = nullptr;
     int64_t pwaves = 0;
+    int pskip = 0;         // outer window chunks no segment multiplies
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -270,19 +271,32 @@ extern "C" hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* d, 
     if (bp->prop) {
         // taps of each distinct r, then the segments and the per-wave spans
         std::map<double, size_t> tap_at;
+        std::map<double, uint32_t> levels_of;
         std::vector<float> taps;
         const int D = d->steps;
         for (const Seg1D& sg : bp->segs)
             if (!tap_at.count(sg.r)) {
                 tap_at[sg.r] = taps.size();
-                for (double v : propagator(sg.r, D)) taps.push_back((float)v);
+                const std::vector<double> p = propagator(sg.r, D);
+                levels_of[sg.r] = prop1d_levels(p.data(), D);
+                for (double v : p) taps.push_back((float)v);
             }
         hipDeviceProp_t prop;
         hipGetDeviceProperties(&prop, c->device);
         int OD = 0, NC = 0;
         prop1d_geometry(D, &OD, &NC);
-        // two waves per SIMD fit up to 9 chunks (18 KiB of LDS, <= 256 registers each)
-        const int64_t slots = (int64_t)prop.multiProcessorCount * (NC <= 9 ? 8 : 4);
+        // outer chunks that every segment skips (level 0 on both sides)
+        int skip = NC;
+        for (const auto& kv : levels_of) {
+            int k = 0;
+            while (k < NC / 2 && ((kv.second >> (2 * k)) & 3) == 0 &&
+                   ((kv.second >> (2 * (NC - 1 - k))) & 3) == 0)
+                ++k;
+            skip = std::min(skip, k);
+        }
+        bp->pskip = std::min(skip, std::min(2, (NC - 1) / 2));
+        const int64_t slots =
+            (int64_t)prop.multiProcessorCount * prop1d_waves_per_cu(D, bp->pskip);
         std::vector<int64_t> blocks;
         for (const Seg1D& sg : bp->segs) blocks.push_back((sg.n + 1023) / 1024);
         const int ni = d->span_blocks > 0 ? d->span_blocks
@@ -315,6 +329,7 @@ extern "C" hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* d, 
                 q.out = static_cast<float*>(sg.out);
                 q.n = sg.n;
                 q.coef = bp->taps_dev + tap_at[sg.r];
+                q.levels = levels_of[sg.r];
                 if (sg.bc_lo == HX_BC_PERIODIC) {
                     q.lo_base = q.in + sg.n;
                     q.hi_base = q.in;
@@ -433,7 +448,8 @@ extern "C" hx_status hx_launch_batched(hx_ctx ctx, hx_plan plan, const hx_event*
         SC_COMPUTE, deps, ndeps, bp->acc, what,
         [bp](hipStream_t st) -> hipError_t {
             if (bp->prop)
-                return launch_prop1d(bp->psegs_dev, bp->pwaves_dev, bp->pwaves, bp->steps, st);
+                return launch_prop1d(bp->psegs_dev, bp->pwaves_dev, bp->pwaves, bp->steps,
+                                     bp->pskip, st);
             if (bp->mode == HX_BATCH_PERSISTENT)
                 return launch_stencil1d_batched(bp->dtype, bp->segs_dev, bp->tseg_dev,
                                                 bp->tidx_dev, bp->ntiles, bp->g, bp->grid_waves,

@@ -105,6 +105,11 @@ struct PropSeg {
     const float* coef;     // 2D+1 taps, coef[D + j] = p_j
     int64_t n;
     int64_t lo_av, hi_av;
+    // Bits 2c..2c+1: how many magnitude levels of the split products window
+    // chunk c takes: 0 none, 1 hi*hi, 2 also hi*mid and mid*hi, 3 all six.
+    // Chosen from the taps the chunk meets (prop1d_levels).
+    uint32_t levels;
+    uint32_t pad;
 };
 
 // One wave's work: iterations blk0 .. blk0+ni-1 (1024 cells each) of segment
@@ -123,8 +128,42 @@ inline bool prop1d_geometry(int D, int* OD, int* NC) {
     return true;
 }
 
+// Product levels per window chunk for taps p[0..2D] (p[D + j] = p_j): a chunk
+// keeps the levels whose omitted products stay below 2^-30 of the taps' total
+// magnitude.  The products of level k are about 2^-8k of the chunk's largest
+// tap t and there are at most three per level and 16 taps per row, so a chunk
+// is skipped when 16 t <= 2^-30 S, keeps hi*hi alone when 48 t 2^-8 <= 2^-30 S,
+// levels 0-1 when 48 t 2^-16 <= 2^-30 S, and all six products otherwise
+// (S = sum |p_j|).
+inline uint32_t prop1d_levels(const double* p, int D) {
+    int OD = 0, NC = 0;
+    if (!prop1d_geometry(D, &OD, &NC)) return 0;
+    double S = 0.0;
+    for (int j = 0; j <= 2 * D; ++j) S += p[j] < 0 ? -p[j] : p[j];
+    const double eps = S / 1073741824.0;  // 2^-30 S
+    uint32_t mask = 0;
+    for (int c = 0; c < NC; ++c) {
+        double t = 0.0;
+        for (int j = 16 * c - OD - 31; j <= 16 * c - OD + 15; ++j) {
+            if (j < -D || j > D) continue;
+            const double a = p[j + D] < 0 ? -p[j + D] : p[j + D];
+            if (a > t) t = a;
+        }
+        uint32_t L = 3;
+        if (16.0 * t <= eps) L = 0;
+        else if (48.0 * t / 256.0 <= eps) L = 1;
+        else if (48.0 * t / 65536.0 <= eps) L = 2;
+        mask |= L << (2 * c);
+    }
+    return mask;
+}
+
+// skip: window chunks on each side that no segment of the launch multiplies
+// (level 0 in every segment's mask); at most 2 are dropped from the kernel.
 hipError_t launch_prop1d(const PropSeg* segs_dev, const PropWave* waves_dev, int64_t nwaves, int D,
-                         hipStream_t stream);
+                         int skip, hipStream_t stream);
+// Waves of that kernel resident per CU (registers and LDS permitting).
+int prop1d_waves_per_cu(int D, int skip);
 
 // One 2D band: ny rows of nx cells, row-major, advanced `steps` steps from in
 // into out.  Rows outside [0, ny) come from the top/bottom rule; columns

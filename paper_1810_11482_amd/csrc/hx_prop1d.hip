@@ -22,7 +22,12 @@
 //     hi*lo, lo*hi, mid*mid are accumulated in f32: the dropped terms are
 //     below 2^-24 of each product, so the pass keeps f32 accuracy (measured
 //     within 4e-7 of the FP64 result, against about 3e-6 for 50 stepped f32
-//     updates).
+//     updates);
+//   * the taps fall off like a Gaussian of variance 2rD, so the outer chunks
+//     of the window meet taps far below f32 resolution: each chunk takes only
+//     the product levels whose omission would exceed 2^-30 of the taps' total
+//     magnitude (prop1d_levels), which skips 18 of the 54 products per
+//     iteration at r = 1/4, D = 50.
 // Data path per iteration: the wave loads the next 1024 cells with coalesced
 // 16-byte loads (two iterations ahead), splits them once into three bf16
 // planes in an LDS ring of three 1024-cell slots (64-byte rows, 16-byte units
@@ -116,14 +121,17 @@ __device__ __forceinline__ f32x4 load4(const PropSeg& s, int64_t c) {
     return gload(p);
 }
 
-template <int NC, bool INTERIOR>
+// Chunks [S0, NC - S0) of the window are materialised: the outer S0 chunks on
+// each side take no products for any segment of the launch.
+template <int NC, int S0, bool INTERIOR>
 __device__ __forceinline__ void prop_wave(const PropSeg& s, int64_t blk0, int ni, int D, int OD,
                                           char* lds) {
     const int l = threadIdx.x, i = l & 31, g = l >> 5;
+    const uint32_t lv = s.levels;
     // A operands: lane (m = i, g) holds taps for k = 8g..8g+7 of chunk c
     Split8 A[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
+    for (int c = S0; c < NC - S0; ++c) {
         float a[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
@@ -141,7 +149,7 @@ __device__ __forceinline__ void prop_wave(const PropSeg& s, int64_t blk0, int ni
 #pragma unroll
     for (int ph = 0; ph < 3; ++ph)
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
+        for (int c = S0; c < NC - S0; ++c) {
             const int X = 16 * c + 8 * g - OD;
             int t = 32 * ph + 32 + i + (X >> 5);
             t = t < 0 ? t + 96 : (t >= 96 ? t - 96 : t);
@@ -201,24 +209,31 @@ __device__ __forceinline__ void prop_wave(const PropSeg& s, int64_t blk0, int ni
             fetch(k + 3 < ni ? k + 3 : ni, St[sb]);
             __builtin_amdgcn_sched_barrier(0);
             f32x16 a0 = {}, a1 = {};
-            u32x4 bh = *reinterpret_cast<const u32x4*>(lds + roff[ph][0]);
-            u32x4 bm = *reinterpret_cast<const u32x4*>(lds + roff[ph][0] + kPlane);
-            u32x4 bl = *reinterpret_cast<const u32x4*>(lds + roff[ph][0] + 2 * kPlane);
+            // window chunks, each read one chunk ahead; a chunk multiplies only
+            // the product levels it takes (uniform per wave)
+            u32x4 bh = *reinterpret_cast<const u32x4*>(lds + roff[ph][S0]);
+            u32x4 bm = *reinterpret_cast<const u32x4*>(lds + roff[ph][S0] + kPlane);
+            u32x4 bl = *reinterpret_cast<const u32x4*>(lds + roff[ph][S0] + 2 * kPlane);
 #pragma unroll
-            for (int c = 0; c < NC; ++c) {
+            for (int c = S0; c < NC - S0; ++c) {
+                const int L = (lv >> (2 * c)) & 3;
                 u32x4 nh = bh, nm = bm, nl = bl;
-                if (c + 1 < NC) {
+                if (c + 1 < NC - S0) {
                     const char* p = lds + roff[ph][c + 1];
                     nh = *reinterpret_cast<const u32x4*>(p);
                     nm = *reinterpret_cast<const u32x4*>(p + kPlane);
                     nl = *reinterpret_cast<const u32x4*>(p + 2 * kPlane);
                 }
-                a0 = mfma(A[c].h, bm, a0);
-                a1 = mfma(A[c].m, bh, a1);
-                a0 = mfma(A[c].l, bh, a0);
-                a1 = mfma(A[c].h, bl, a1);
-                a0 = mfma(A[c].m, bm, a0);
-                a1 = mfma(A[c].h, bh, a1);
+                if (L >= 1) a1 = mfma(A[c].h, bh, a1);
+                if (L >= 2) {
+                    a0 = mfma(A[c].h, bm, a0);
+                    a1 = mfma(A[c].m, bh, a1);
+                }
+                if (L >= 3) {
+                    a0 = mfma(A[c].l, bh, a0);
+                    a1 = mfma(A[c].h, bl, a1);
+                    a0 = mfma(A[c].m, bm, a0);
+                }
                 bh = nh;
                 bm = nm;
                 bl = nl;
@@ -231,44 +246,65 @@ __device__ __forceinline__ void prop_wave(const PropSeg& s, int64_t blk0, int ni
     store(yprev, oprev);
 }
 
-template <int NC>
+template <int NC, int S0>
 __global__ __launch_bounds__(64) void k_prop1d(const PropSeg* __restrict__ segs,
                                                const PropWave* __restrict__ waves, int D, int OD) {
     __shared__ __attribute__((aligned(16))) char lds[3 * kPlane];
     const PropWave w = waves[blockIdx.x];
     const PropSeg s = segs[w.seg];
     if (w.interior)
-        prop_wave<NC, true>(s, w.blk0, (int)w.ni, D, OD, lds);
+        prop_wave<NC, S0, true>(s, w.blk0, (int)w.ni, D, OD, lds);
     else
-        prop_wave<NC, false>(s, w.blk0, (int)w.ni, D, OD, lds);
+        prop_wave<NC, S0, false>(s, w.blk0, (int)w.ni, D, OD, lds);
 }
 
 }  // namespace
 
-hipError_t launch_prop1d(const PropSeg* segs_dev, const PropWave* waves_dev, int64_t nwaves, int D,
-                         hipStream_t stream) {
+// The kernel instantiation for depth D and `skip` dropped chunks per side
+// (nullptr when there is none).
+static const void* prop1d_kernel(int D, int skip) {
     int OD = 0, NC = 0;
-    if (!prop1d_geometry(D, &OD, &NC) || nwaves <= 0 || nwaves >= (int64_t(1) << 31))
-        return hipErrorInvalidValue;
-    const dim3 grid((unsigned)nwaves), block(64);
-    switch (NC) {
-#define HX_PROP_CASE(N)                                                                        \
-    case N:                                                                                    \
-        hipLaunchKernelGGL(k_prop1d<N>, grid, block, 0, stream, segs_dev, waves_dev, D, OD); \
-        break;
-        HX_PROP_CASE(3)
-        HX_PROP_CASE(4)
-        HX_PROP_CASE(5)
-        HX_PROP_CASE(6)
-        HX_PROP_CASE(7)
-        HX_PROP_CASE(8)
-        HX_PROP_CASE(9)
-        HX_PROP_CASE(10)
+    if (!prop1d_geometry(D, &OD, &NC) || skip < 0 || NC - 2 * skip < 1) return nullptr;
+    switch (NC * 4 + (skip > 2 ? 2 : skip)) {
+#define HX_PROP_CASE(N, S) \
+    case N * 4 + S:        \
+        return reinterpret_cast<const void*>(&k_prop1d<N, S>);
+#define HX_PROP_CASES(N) HX_PROP_CASE(N, 0) HX_PROP_CASE(N, 1) HX_PROP_CASE(N, 2)
+        HX_PROP_CASE(3, 0)
+        HX_PROP_CASE(3, 1)
+        HX_PROP_CASE(4, 0)
+        HX_PROP_CASE(4, 1)
+        HX_PROP_CASES(5)
+        HX_PROP_CASES(6)
+        HX_PROP_CASES(7)
+        HX_PROP_CASES(8)
+        HX_PROP_CASES(9)
+        HX_PROP_CASES(10)
+#undef HX_PROP_CASES
 #undef HX_PROP_CASE
     default:
-        return hipErrorInvalidValue;
+        return nullptr;
     }
-    return hipGetLastError();
+}
+
+int prop1d_waves_per_cu(int D, int skip) {
+    const void* k = prop1d_kernel(D, skip);
+    int blocks = 0;
+    if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k, 64, 0) != hipSuccess) {
+        hipGetLastError();
+        return 4;
+    }
+    return blocks > 0 ? blocks : 1;
+}
+
+hipError_t launch_prop1d(const PropSeg* segs_dev, const PropWave* waves_dev, int64_t nwaves, int D,
+                         int skip, hipStream_t stream) {
+    int OD = 0, NC = 0;
+    const void* k = prop1d_kernel(D, skip);
+    if (!k || !prop1d_geometry(D, &OD, &NC) || nwaves <= 0 || nwaves >= (int64_t(1) << 31))
+        return hipErrorInvalidValue;
+    void* args[] = {&segs_dev, &waves_dev, &D, &OD};
+    return hipLaunchKernel(k, dim3((unsigned)nwaves), dim3(64), args, 0, stream);
 }
 
 }  // namespace hx
