@@ -248,7 +248,8 @@ def main():
     ap.add_argument("--form", choices=("auto", "direct", "propagator"), default="auto",
                     help="form of the headline pass; auto = the faster in a short sweep")
     ap.add_argument("--span-blocks", type=int, default=0,
-                    help="propagator form: 1024-cell blocks per wave, 0 = sweep")
+                    help="propagator form: 1024-cell blocks per wave, -1 = the interleaved "
+                         "walk, 0 = sweep both walks")
     ap.add_argument("--streams", type=int, default=4,
                     help="compute streams of the context (the per-partition graph spreads its "
                          "nodes over them)")
@@ -289,8 +290,10 @@ def main():
         cands += [("direct", c, 0) for c in ([args.cells_per_lane] if args.cells_per_lane
                                             else [32, 16])]
     if args.form in ("auto", "propagator"):
+        # the interleaved walk (-1, the plan's choice for equal partitions) and
+        # contiguous spans of 128 blocks per wave
         cands += [("propagator", 0, sp) for sp in ([args.span_blocks] if args.span_blocks
-                                                  else [0, 64])]
+                                                  else [-1, 128])]
     swept = []
     for form, cpl_c, span_c in cands:
         fcode = hx.HX_FORM_PROPAGATOR if form == "propagator" else hx.HX_FORM_DIRECT
@@ -311,7 +314,8 @@ def main():
     fcode = hx.HX_FORM_PROPAGATOR if form == "propagator" else hx.HX_FORM_DIRECT
     by_form = {}
     for t, f, c_, s_ in swept:
-        key = f"{f}_cpl{c_}" if f == "direct" else f"{f}_span{s_ or 'auto'}"
+        key = (f"{f}_cpl{c_}" if f == "direct" else
+               f"{f}_interleaved" if s_ == -1 else f"{f}_span{s_ or 'auto'}")
         by_form[key] = t * 1e3
 
     # ------------------------------------------------------------ timed region
@@ -334,6 +338,7 @@ def main():
     for e in launches[:-1]:
         hx.hx_event_release(ctx, e)
     bp.close()
+    log("timed launches, ms: " + " ".join(f"{d:.4f}" for d in durs))
     avg_ms = float(np.mean(durs))
     ms_per_step = sec * 1e3
     value = float(n) * T / sec
@@ -371,7 +376,7 @@ def main():
         mf_per_launch = cells_per_launch / 1024 * nc * MFMA_FLOPS_PER_CHUNK
         mf = mf_per_launch / (avg_ms * 1e-3)
         mfma_frac = mf / MFMA_BF16_PEAK
-        kname = f"k_prop1d<{nc}>"
+        kname = f"k_prop1d_il<{nc}>" if span == -1 else f"k_prop1d<{nc}>"
         if mfma_frac >= hbm_frac:
             roof = {"bound": "mfma", "achieved": mf / 1e12, "peak": MFMA_BF16_PEAK / 1e12,
                     "unit": "TFLOP/s", "frac": mfma_frac}
@@ -418,7 +423,8 @@ def main():
                    "cells": n, "parts": args.parts, "time_steps": T, "time_block": tb,
                    "update_form": form_desc,
                    "cells_per_lane": cpl if form == "direct" else None,
-                   "span_blocks": (span or "plan's choice") if form == "propagator" else None,
+                   "span_blocks": ("interleaved walk" if span == -1 else span or "plan's choice")
+                   if form == "propagator" else None,
                    "halo_width": hw, "launches_per_step": bp.passes,
                    "sampled_max_rel_err_vs_oracle": sampled_err},
         "roofline": roof,

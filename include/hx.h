@@ -317,8 +317,13 @@ typedef struct {
                                    tile while it advances the current one; < 0 = one wave per
                                    tile; 0 = tuned (one wave per tile if untuned) */
     int form;                   /* hx_batch_form; 0 = DIRECT */
-    int span_blocks;            /* PROPAGATOR: 1024-cell blocks per wave, 0 = chosen to fill the
-                                   device in whole rounds */
+    int span_blocks;            /* PROPAGATOR: how waves walk the blocks of 1024 cells.  > 0 =
+                                   contiguous spans of that many blocks per wave; -1 = the
+                                   interleaved walk (a persistent grid, wave w taking blocks
+                                   w, w + grid, ... of all segments numbered back to back;
+                                   HX_ERR_ARG unless every segment has the same n and r);
+                                   0 = the tuned walk, else interleaved where allowed, else
+                                   spans chosen to fill the device in whole rounds */
 } hx_batch_desc;
 
 /* Build a batch: `count` 1D segments, each with its own size, r, boundaries

@@ -13,7 +13,9 @@
 // A PERSISTENT plan evaluates its pass in one of two forms: DIRECT (the tile
 // kernels, step by step) or PROPAGATOR (one convolution with the D-step
 // propagator on the matrix cores, f32; see hx_prop1d.hip).  For the latter
-// the plan holds each distinct r's taps and a table of per-wave spans.
+// the plan holds each distinct r's taps and, for contiguous spans, a table of
+// per-wave spans; the interleaved walk (segments of one size and one rate)
+// needs only the segment table.
 #include <algorithm>
 #include <cmath>
 #include <map>
@@ -51,6 +53,9 @@ struct BatchPlan {
     float* taps_dev = nullptr;
     int64_t pwaves = 0;
     int pskip = 0;         // outer window chunks no segment multiplies
+    bool pil = false;      // interleaved walk (segments of one size and one rate)
+    int64_t pblocks = 0;   // interleaved: 1024-cell blocks in all, and per segment
+    int64_t pbps = 0;
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -156,7 +161,7 @@ extern "C" hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* d, 
         return c->fail(HX_ERR_ARG, "bad form");
     if (d->form == HX_FORM_PROPAGATOR && (d->mode != HX_BATCH_PERSISTENT || d->dtype != HX_F32))
         return c->fail(HX_ERR_ARG, "the propagator form needs a PERSISTENT f32 batch");
-    if (d->span_blocks < 0) return c->fail(HX_ERR_ARG, "span_blocks must be >= 0");
+    if (d->span_blocks < -1) return c->fail(HX_ERR_ARG, "span_blocks must be >= -1");
     hipSetDevice(c->device);
     const size_t es = esz(d->dtype);
     const int vn = vecn(d->dtype);
@@ -271,7 +276,8 @@ extern "C" hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* d, 
     if (bp->prop) {
         // taps of each distinct r, then the segments and the per-wave spans
         std::map<double, size_t> tap_at;
-        std::map<double, uint32_t> levels_of;
+        std::map<double, uint32_t> levels_of, levels16_of;
+        std::map<double, int32_t> texp_of;
         std::vector<float> taps;
         const int D = d->steps;
         for (const Seg1D& sg : bp->segs)
@@ -279,6 +285,8 @@ extern "C" hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* d, 
                 tap_at[sg.r] = taps.size();
                 const std::vector<double> p = propagator(sg.r, D);
                 levels_of[sg.r] = prop1d_levels(p.data(), D);
+                levels16_of[sg.r] = prop1d_levels16(p.data(), D);
+                texp_of[sg.r] = prop1d_tap_exp(p.data(), D);
                 for (double v : p) taps.push_back((float)v);
             }
         hipDeviceProp_t prop;
@@ -295,16 +303,45 @@ extern "C" hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* d, 
             skip = std::min(skip, k);
         }
         bp->pskip = std::min(skip, std::min(2, (NC - 1) / 2));
+        // the walk: interleaved when asked (span_blocks = -1) or, with no span
+        // given or tuned, whenever every segment has the same size and rate;
+        // otherwise contiguous spans
+        bool il_ok = levels_of.size() == 1;
+        for (const Seg1D& sg : bp->segs) il_ok = il_ok && sg.n == bp->segs[0].n;
+        const int64_t bps = (bp->segs[0].n + 1023) / 1024;
+        il_ok = il_ok && bps * (int64_t)bp->segs.size() < (int64_t(1) << 32);
+        if (d->span_blocks == -1 && !il_ok) {
+            destroy_plan(bp);
+            return c->fail(HX_ERR_ARG, "span_blocks = -1 (the interleaved walk) needs segments "
+                                       "of one size and one rate");
+        }
+        const bool tuned_span = d->form == HX_FORM_AUTO && tuned && tg.rows != 0;
+        bp->pil = il_ok && (d->span_blocks == -1 ||
+                            (d->span_blocks == 0 && (!tuned_span || tg.rows == -1)));
+        if (bp->pil) {
+            // the interleaved walk's fp16 levels decide its dropped chunks
+            const uint32_t m = levels16_of.begin()->second;
+            int k = 0;
+            while (k < NC / 2 && ((m >> (2 * k)) & 3) == 0 && ((m >> (2 * (NC - 1 - k))) & 3) == 0)
+                ++k;
+            bp->pskip = std::min(k, std::min(2, (NC - 1) / 2));
+        }
         const int64_t slots =
-            (int64_t)prop.multiProcessorCount * prop1d_waves_per_cu(D, bp->pskip);
+            (int64_t)prop.multiProcessorCount * prop1d_waves_per_cu(D, bp->pskip, bp->pil);
         std::vector<int64_t> blocks;
         for (const Seg1D& sg : bp->segs) blocks.push_back((sg.n + 1023) / 1024);
-        const int ni = d->span_blocks > 0 ? d->span_blocks
-                       : (d->form == HX_FORM_AUTO && tuned && tg.rows > 0)
+        const int ni = bp->pil               ? 0
+                       : d->span_blocks > 0 ? d->span_blocks
+                       : (tuned_span && tg.rows > 0)
                            ? tg.rows
                            : choose_span(blocks, slots);
         std::vector<PropWave> waves;
-        for (size_t i = 0; i < bp->segs.size(); ++i)
+        if (bp->pil) {
+            bp->pbps = bps;
+            bp->pblocks = bps * (int64_t)bp->segs.size();
+            bp->pwaves = std::min<int64_t>(bp->pblocks, slots);
+        }
+        for (size_t i = 0; i < bp->segs.size() && !bp->pil; ++i)
             for (int64_t b0 = 0; b0 < blocks[i]; b0 += ni) {
                 PropWave w{};
                 w.seg = (uint32_t)i;
@@ -317,10 +354,11 @@ extern "C" hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* d, 
             destroy_plan(bp);
             return c->fail(HX_ERR_RANGE, "the batch has too many propagator waves");
         }
-        bp->pwaves = (int64_t)waves.size();
+        if (!bp->pil) bp->pwaves = (int64_t)waves.size();
         bool ok = hipMalloc(&bp->taps_dev, 4 * taps.size()) == hipSuccess &&
                   hipMalloc(&bp->psegs_dev, sizeof(PropSeg) * bp->segs.size()) == hipSuccess &&
-                  hipMalloc(&bp->pwaves_dev, sizeof(PropWave) * waves.size()) == hipSuccess;
+                  (bp->pil ||
+                   hipMalloc(&bp->pwaves_dev, sizeof(PropWave) * waves.size()) == hipSuccess);
         std::vector<PropSeg> ps;
         if (ok) {
             for (const Seg1D& sg : bp->segs) {
@@ -330,6 +368,8 @@ extern "C" hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* d, 
                 q.n = sg.n;
                 q.coef = bp->taps_dev + tap_at[sg.r];
                 q.levels = levels_of[sg.r];
+                q.levels16 = levels16_of[sg.r];
+                q.texp = texp_of[sg.r];
                 if (sg.bc_lo == HX_BC_PERIODIC) {
                     q.lo_base = q.in + sg.n;
                     q.hi_base = q.in;
@@ -345,8 +385,9 @@ extern "C" hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* d, 
                      hipSuccess &&
                  hipMemcpy(bp->psegs_dev, ps.data(), sizeof(PropSeg) * ps.size(),
                            hipMemcpyHostToDevice) == hipSuccess &&
-                 hipMemcpy(bp->pwaves_dev, waves.data(), sizeof(PropWave) * waves.size(),
-                           hipMemcpyHostToDevice) == hipSuccess;
+                 (bp->pil || hipMemcpy(bp->pwaves_dev, waves.data(),
+                                       sizeof(PropWave) * waves.size(),
+                                       hipMemcpyHostToDevice) == hipSuccess);
         }
         if (!ok) {
             hipGetLastError();
@@ -447,6 +488,9 @@ extern "C" hx_status hx_launch_batched(hx_ctx ctx, hx_plan plan, const hx_event*
     return c->submit(
         SC_COMPUTE, deps, ndeps, bp->acc, what,
         [bp](hipStream_t st) -> hipError_t {
+            if (bp->prop && bp->pil)
+                return launch_prop1d_il(bp->psegs_dev, bp->pblocks, bp->pbps, bp->pwaves,
+                                        bp->steps, bp->pskip, st);
             if (bp->prop)
                 return launch_prop1d(bp->psegs_dev, bp->pwaves_dev, bp->pwaves, bp->steps,
                                      bp->pskip, st);

@@ -109,7 +109,13 @@ struct PropSeg {
     // chunk c takes: 0 none, 1 hi*hi, 2 also hi*mid and mid*hi, 3 all six.
     // Chosen from the taps the chunk meets (prop1d_levels).
     uint32_t levels;
-    uint32_t pad;
+    // The same for the two-term fp16 split of the interleaved walk: 0 none,
+    // 1 hi*hi, 2 also hi*lo and lo*hi (prop1d_levels16).
+    uint32_t levels16;
+    // fp16 split: the taps are scaled by 2^texp so that the largest lies in
+    // [2^14, 2^15).
+    int32_t texp;
+    int32_t pad;
 };
 
 // One wave's work: iterations blk0 .. blk0+ni-1 (1024 cells each) of segment
@@ -158,12 +164,58 @@ inline uint32_t prop1d_levels(const double* p, int D) {
     return mask;
 }
 
+// Product levels per window chunk for the interleaved walk's two-term fp16
+// split (each operand x = hi + lo to 22 bits, the product keeping hi*hi, hi*lo
+// and lo*hi, so it carries a relative error of about 3 * 2^-22 of itself).
+// The pruning bound is set below that: a chunk is skipped when its omission,
+// at most 16 t per row, is within 2^-26 S, and keeps hi*hi alone when the two
+// cross terms, at most 2 * 16 t 2^-11, are (t: the chunk's largest |tap|,
+// S = sum |p_j|).
+inline uint32_t prop1d_levels16(const double* p, int D) {
+    int OD = 0, NC = 0;
+    if (!prop1d_geometry(D, &OD, &NC)) return 0;
+    double S = 0.0;
+    for (int j = 0; j <= 2 * D; ++j) S += p[j] < 0 ? -p[j] : p[j];
+    const double eps = S / 67108864.0;  // 2^-26 S
+    uint32_t mask = 0;
+    for (int c = 0; c < NC; ++c) {
+        double t = 0.0;
+        for (int j = 16 * c - OD - 31; j <= 16 * c - OD + 15; ++j) {
+            if (j < -D || j > D) continue;
+            const double a = p[j + D] < 0 ? -p[j + D] : p[j + D];
+            if (a > t) t = a;
+        }
+        uint32_t L = 2;
+        if (16.0 * t <= eps) L = 0;
+        else if (32.0 * t / 2048.0 <= eps) L = 1;
+        mask |= L << (2 * c);
+    }
+    return mask;
+}
+
+// Exponent e with max|p_j| 2^e in [2^14, 2^15) (0 for all-zero taps).
+inline int32_t prop1d_tap_exp(const double* p, int D) {
+    double t = 0.0;
+    for (int j = 0; j <= 2 * D; ++j) t = (p[j] < 0 ? -p[j] : p[j]) > t ? (p[j] < 0 ? -p[j] : p[j]) : t;
+    if (!(t > 0.0)) return 0;
+    int e = 0;
+    while (t * __builtin_ldexp(1.0, e) >= 32768.0) --e;
+    while (t * __builtin_ldexp(1.0, e) < 16384.0) ++e;
+    return e;
+}
+
 // skip: window chunks on each side that no segment of the launch multiplies
 // (level 0 in every segment's mask); at most 2 are dropped from the kernel.
 hipError_t launch_prop1d(const PropSeg* segs_dev, const PropWave* waves_dev, int64_t nwaves, int D,
                          int skip, hipStream_t stream);
 // Waves of that kernel resident per CU (registers and LDS permitting).
-int prop1d_waves_per_cu(int D, int skip);
+int prop1d_waves_per_cu(int D, int skip, bool il = false);
+// Interleaved walk of the same pass: `nblocks` 1024-cell blocks, bps per
+// segment (every segment has the same n and the same taps, those of segs[0]);
+// a persistent grid of nwaves <= nblocks waves, wave w taking blocks w,
+// w + nwaves, ...  nblocks < 2^32 and a multiple of bps.
+hipError_t launch_prop1d_il(const PropSeg* segs_dev, int64_t nblocks, int64_t bps, int64_t nwaves,
+                            int D, int skip, hipStream_t stream);
 
 // One 2D band: ny rows of nx cells, row-major, advanced `steps` steps from in
 // into out.  Rows outside [0, ny) come from the top/bottom rule; columns

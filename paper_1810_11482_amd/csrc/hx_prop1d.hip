@@ -101,28 +101,52 @@ __device__ __forceinline__ int swz(int row, int unit) {
     return row * 64 + ((unit ^ ((row >> 1) & 3)) << 4);
 }
 
+template <bool NT = false>
 __device__ __forceinline__ f32x4 gload(const float* p) {
     typedef __attribute__((address_space(1))) const f32x4 G;
+    if (NT) return __builtin_nontemporal_load((G*)p);
     return *(G*)p;
 }
 
+template <bool NT = false>
 __device__ __forceinline__ void gstore(f32x4 v, float* p) {
     typedef __attribute__((address_space(1))) f32x4 G;
-    *(G*)p = v;
+    if (NT)
+        __builtin_nontemporal_store(v, (G*)p);
+    else
+        *(G*)p = v;
 }
 
 // Four cells starting at segment cell c (a multiple of 4): from the segment,
 // the left source (halo or wrap) or the right source, clamped into what each
 // holds.  Cells beyond the sources' reach only meet zero taps; clamping keeps
 // their reads in bounds and finite.
-template <bool INTERIOR>
+template <bool INTERIOR, bool NT = false>
 __device__ __forceinline__ f32x4 load4(const PropSeg& s, int64_t c) {
-    if (INTERIOR) return gload(s.in + c);
+    if (INTERIOR) return gload<NT>(s.in + c);
     const bool lo = c < 0, hi = c >= s.n;
     const int64_t cl = c < -s.lo_av ? -s.lo_av : c;
     const int64_t ch = c - s.n > s.hi_av - 4 ? s.hi_av - 4 : c - s.n;
     const float* p = lo ? s.lo_base + cl : (hi ? s.hi_base + ch : s.in + c);
-    return gload(p);
+    return gload<NT>(p);
+}
+
+// The A operands of window chunks [S0, NC - S0): lane (m = i, g) holds the
+// taps of k = 8g .. 8g+7, split into three bf16 levels.
+template <int NC, int S0>
+__device__ __forceinline__ void prop_taps(const float* coef, int D, int OD, Split8 (&A)[NC]) {
+    const int l = threadIdx.x, i = l & 31, g = l >> 5;
+#pragma unroll
+    for (int c = S0; c < NC - S0; ++c) {
+        float a[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int j = 16 * c + 8 * g + e - OD - i;
+            const float v = coef[j < -D ? 0 : (j > D ? 2 * D : j + D)];
+            a[e] = (j >= -D && j <= D) ? v : 0.f;
+        }
+        A[c] = split8(a);
+    }
 }
 
 // Chunks [S0, NC - S0) of the window are materialised: the outer S0 chunks on
@@ -132,19 +156,8 @@ __device__ __forceinline__ void prop_wave(const PropSeg& s, int64_t blk0, int ni
                                           char* lds) {
     const int l = threadIdx.x, i = l & 31, g = l >> 5;
     const uint32_t lv = s.levels;
-    // A operands: lane (m = i, g) holds taps for k = 8g..8g+7 of chunk c
     Split8 A[NC];
-#pragma unroll
-    for (int c = S0; c < NC - S0; ++c) {
-        float a[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int j = 16 * c + 8 * g + e - OD - i;
-            const float v = s.coef[j < -D ? 0 : (j > D ? 2 * D : j + D)];
-            a[e] = (j >= -D && j <= D) ? v : 0.f;
-        }
-        A[c] = split8(a);
-    }
+    prop_taps<NC, S0>(s.coef, D, OD, A);
     // Ring: segment m (relative to the span) lives in slot (m + 1) % 3.  At
     // iteration k (ring phase ph = k % 3) the window of stream i, chunk c,
     // starts X = 16c + 8g - OD cells from the stream, i.e. ring row
@@ -284,17 +297,241 @@ __global__ __launch_bounds__(64) void k_prop1d(const PropSeg* __restrict__ segs,
         prop_wave<NC, S0, false>(s, w.blk0, (int)w.ni, D, OD, lds);
 }
 
+// Interleaved walk (every segment of the launch has the same n and the same
+// taps).  The blocks of all segments are numbered back to back, block b of
+// the launch being block b mod bps of segment b / bps (bps = blocks per
+// segment), and wave w of a persistent grid of nw waves takes blocks w,
+// w + nw, w + 2 nw, ...: at any moment the grid reads and writes one narrow
+// band of the arrays instead of nw bands far apart, which measured 9 % more
+// HBM bandwidth for the same bytes than contiguous spans.  A block is read
+// with the 64 cells on each side that its windows reach (12.5 % more read
+// requests, mostly served by the caches, since the neighbouring blocks are in
+// flight on neighbouring waves); loads and stores are nontemporal.
+//
+// Because a block's whole window (1152 cells) is loaded at once, it can share
+// one scale: the window's largest finite |x| is brought into [2^14, 2^15) by
+// an exact power of two 2^ex, and every cell is split into two fp16 terms,
+// x 2^ex = hi + lo (round to nearest each, so the pair holds x to 2^-22 of
+// itself; cells far below the largest keep an absolute error within 2^-38 of
+// it).  The taps are split the same way at their own scale 2^texp.  A product
+// then takes three 32x32x16 fp16 MFMAs (hi*hi, hi*lo, lo*hi; the dropped
+// lo*lo is below 2^-22 of it) instead of the six of the bf16 split, which
+// halves the matrix-core work (17 instead of 36 products per block at
+// r = 1/4, D = 50, with the fp16 levels' pruning) and the power it draws on
+// high-entropy data, where the six-product form ran into the card's power
+// limit.  The result is scaled back by 2^-(ex + texp).  A non-finite cell is
+// left out of the scale and reaches every output whose window holds it.
+constexpr int kWPlane = 36 * 64;  // bytes of one fp16 plane of the 1152-cell window
+
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ f32x16 mfma16(u32x4 a, u32x4 b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a),
+                                                  __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+}
+
+__device__ __forceinline__ uint32_t hbits(_Float16 x) {
+    return (uint32_t)__builtin_bit_cast(uint16_t, x);
+}
+
+// Two f32 values scaled by 2^e (exact) and split into packed fp16 pairs
+// (element 0 in the low half): x 2^e = hi + lo, both rounded to nearest.
+__device__ __forceinline__ void split16_pair(float x0, float x1, int e, uint32_t& h,
+                                             uint32_t& l) {
+    const float s0 = ldexpf(x0, e), s1 = ldexpf(x1, e);
+    const _Float16 h0 = (_Float16)s0, h1 = (_Float16)s1;
+    const _Float16 l0 = (_Float16)(s0 - (float)h0), l1 = (_Float16)(s1 - (float)h1);
+    h = hbits(h0) | (hbits(h1) << 16);
+    l = hbits(l0) | (hbits(l1) << 16);
+}
+
+struct Split8h {
+    u32x4 h, l;
+};
+
+__device__ __forceinline__ float wave_max(float x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = fmaxf(x, __shfl_xor(x, o));
+    return x;
+}
+
+template <int NC, int S0>
+__global__ __launch_bounds__(64) void k_prop1d_il(const PropSeg* __restrict__ segs,
+                                                  uint32_t nblocks, uint32_t bps, int D, int OD) {
+    __shared__ __attribute__((aligned(16))) char lds[2 * kWPlane];
+    const int l = threadIdx.x, i = l & 31, g = l >> 5;
+    const uint32_t w = blockIdx.x, nw = gridDim.x;
+    if (w >= nblocks) return;
+    const int nk = (int)((nblocks - 1 - w) / nw) + 1;
+    const uint32_t lv = segs[0].levels16;
+    const int texp = segs[0].texp;
+    // A operands: lane (m = i, g) holds the taps of k = 8g .. 8g+7, scaled by
+    // 2^texp and split into two fp16 terms
+    Split8h A[NC];
+    {
+        const float* coef = segs[0].coef;
+#pragma unroll
+        for (int c = S0; c < NC - S0; ++c) {
+            float a[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int j = 16 * c + 8 * g + e - OD - i;
+                const float v = coef[j < -D ? 0 : (j > D ? 2 * D : j + D)];
+                a[e] = (j >= -D && j <= D) ? v : 0.f;
+            }
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                uint32_t h, lo;
+                split16_pair(a[2 * p], a[2 * p + 1], texp, h, lo);
+                A[c].h[p] = h;
+                A[c].l[p] = lo;
+            }
+        }
+    }
+    // Window row r holds cells 32 (r - 2) .. +31 of the block.  The window of
+    // stream i, chunk c, starts X = 16c + 8g - OD cells from the stream: row
+    // 2 + i + floor(X / 32), 16-byte unit (X mod 32) / 8.
+    int roff[NC];
+#pragma unroll
+    for (int c = S0; c < NC - S0; ++c) {
+        const int X = 16 * c + 8 * g - OD;
+        roff[c] = swz(2 + i + (X >> 5), (X & 31) >> 3);
+    }
+    // This lane's 8-byte pieces of the window: block cells 256 j + 4 l .. +3
+    // (j = 0..3) and context cells 4 q .. +3 (q = l mod 16) of the left 64
+    // (lanes with l mod 32 < 16) or the right 64 (the others).
+    int woff[5];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) woff[j] = swz(2 + 8 * j + (l >> 3), (l & 7) >> 1) + 8 * (l & 1);
+    const int q = l & 15;
+    const bool left = (l & 31) < 16;
+    woff[4] = swz((left ? 0 : 34) + (q >> 3), (q & 7) >> 1) + 8 * (q & 1);
+    // split the window into the two planes at the window's own scale;
+    // returns that scale's exponent
+    auto put = [&](const f32x4 v[5]) -> int {
+        float mx = 0.f;
+#pragma unroll
+        for (int j = 0; j < 5; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float a = fabsf(v[j][e]);
+                mx = (a <= 3.402823466e38f && a > mx) ? a : mx;  // finite only
+            }
+        mx = wave_max(mx);
+        const int ex = __builtin_amdgcn_readfirstlane(
+            mx > 0.f ? 15 - __builtin_amdgcn_frexp_expf(mx) : 0);
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            uint32_t h0, l0, h1, l1;
+            split16_pair(v[j][0], v[j][1], ex, h0, l0);
+            split16_pair(v[j][2], v[j][3], ex, h1, l1);
+            char* p = lds + woff[j];
+            *reinterpret_cast<u32x2*>(p) = u32x2{h0, h1};
+            *reinterpret_cast<u32x2*>(p + kWPlane) = u32x2{l0, l1};
+        }
+        return ex;
+    };
+    auto fetch = [&](int k, f32x4 v[5]) {
+        const uint32_t b = w + (uint32_t)k * nw;
+        const uint32_t sg = b / bps;
+        const PropSeg& s = segs[sg];
+        const int64_t c0 = 1024 * (int64_t)(b - sg * bps);
+        const int64_t cx = (left ? c0 - 64 : c0 + 1024) + 4 * q;
+        if (c0 >= 1024 && c0 + 1024 + 64 <= s.n) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[j] = gload<true>(s.in + c0 + 256 * j + 4 * l);
+            v[4] = gload<true>(s.in + cx);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[j] = load4<false, true>(s, c0 + 256 * j + 4 * l);
+            v[4] = load4<false, true>(s, cx);
+        }
+    };
+    // Output transposition, as in the span walk, through the two planes of
+    // the window (32 rows of 128 bytes, 16-byte units XOR-swizzled by row).
+    auto tpos = [](int row, int unit) {
+        return (row < 16 ? 0 : kWPlane) + (row & 15) * 128 + ((unit ^ (row & 7)) << 4);
+    };
+    int wt[4], rd[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) wt[e] = tpos(i, 2 * e + g);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) rd[j] = tpos(8 * j + (l >> 3), l & 7);
+    auto store = [&](int k, const f32x16& y, int ex) {
+        const int sc = -(ex + texp);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            *reinterpret_cast<f32x4*>(lds + wt[e]) =
+                f32x4{ldexpf(y[4 * e], sc), ldexpf(y[4 * e + 1], sc), ldexpf(y[4 * e + 2], sc),
+                      ldexpf(y[4 * e + 3], sc)};
+        f32x4 v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = *reinterpret_cast<const f32x4*>(lds + rd[j]);
+        const uint32_t b = w + (uint32_t)k * nw;
+        const uint32_t sg = b / bps;
+        const PropSeg& s = segs[sg];
+        const int64_t o = 1024 * (int64_t)(b - sg * bps) + 4 * l;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (o + 256 * j < s.n) gstore<true>(v[j], s.out + o + 256 * j);
+    };
+    f32x4 St[2][5];
+    fetch(0, St[0]);
+    fetch(nk > 1 ? 1 : 0, St[1]);
+    f32x16 yprev = {};
+    int exprev = 0;
+    for (int k0 = 0; k0 < nk; k0 += 2) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int k = k0 + u;
+            if (k >= nk) break;
+            // the previous block's outputs leave through its dead window, then
+            // block k (fetched two iterations ago) takes the window
+            if (k > 0) store(k - 1, yprev, exprev);
+            __builtin_amdgcn_sched_barrier(0);
+            const int ex = put(St[u]);
+            __builtin_amdgcn_sched_barrier(0);
+            fetch(k + 2 < nk ? k + 2 : nk - 1, St[u]);
+            __builtin_amdgcn_sched_barrier(0);
+            f32x16 a0 = {}, a1 = {};
+            u32x4 bh = *reinterpret_cast<const u32x4*>(lds + roff[S0]);
+            u32x4 bl = *reinterpret_cast<const u32x4*>(lds + roff[S0] + kWPlane);
+#pragma unroll
+            for (int c = S0; c < NC - S0; ++c) {
+                const int L = (lv >> (2 * c)) & 3;
+                u32x4 nh = bh, nl = bl;
+                if (c + 1 < NC - S0) {
+                    const char* p = lds + roff[c + 1];
+                    nh = *reinterpret_cast<const u32x4*>(p);
+                    nl = *reinterpret_cast<const u32x4*>(p + kWPlane);
+                }
+                if (L >= 1) a1 = mfma16(A[c].h, bh, a1);
+                if (L >= 2) {
+                    a0 = mfma16(A[c].h, bl, a0);
+                    a1 = mfma16(A[c].l, bh, a1);
+                }
+                bh = nh;
+                bl = nl;
+            }
+            yprev = a0 + a1;
+            exprev = ex;
+        }
+    }
+    store(nk - 1, yprev, exprev);
+}
+
 }  // namespace
 
 // The kernel instantiation for depth D and `skip` dropped chunks per side
-// (nullptr when there is none).
-static const void* prop1d_kernel(int D, int skip) {
+// (nullptr when there is none); `il` selects the interleaved walk.
+static const void* prop1d_kernel(int D, int skip, bool il = false) {
     int OD = 0, NC = 0;
     if (!prop1d_geometry(D, &OD, &NC) || skip < 0 || NC - 2 * skip < 1) return nullptr;
     switch (NC * 4 + (skip > 2 ? 2 : skip)) {
-#define HX_PROP_CASE(N, S) \
-    case N * 4 + S:        \
-        return reinterpret_cast<const void*>(&k_prop1d<N, S>);
+#define HX_PROP_CASE(N, S)                                                      \
+    case N * 4 + S:                                                             \
+        return il ? reinterpret_cast<const void*>(&k_prop1d_il<N, S>)         \
+                  : reinterpret_cast<const void*>(&k_prop1d<N, S>);
 #define HX_PROP_CASES(N) HX_PROP_CASE(N, 0) HX_PROP_CASE(N, 1) HX_PROP_CASE(N, 2)
         HX_PROP_CASE(3, 0)
         HX_PROP_CASE(3, 1)
@@ -313,8 +550,8 @@ static const void* prop1d_kernel(int D, int skip) {
     }
 }
 
-int prop1d_waves_per_cu(int D, int skip) {
-    const void* k = prop1d_kernel(D, skip);
+int prop1d_waves_per_cu(int D, int skip, bool il) {
+    const void* k = prop1d_kernel(D, skip, il);
     int blocks = 0;
     if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k, 64, 0) != hipSuccess) {
         hipGetLastError();
@@ -330,6 +567,18 @@ hipError_t launch_prop1d(const PropSeg* segs_dev, const PropWave* waves_dev, int
     if (!k || !prop1d_geometry(D, &OD, &NC) || nwaves <= 0 || nwaves >= (int64_t(1) << 31))
         return hipErrorInvalidValue;
     void* args[] = {&segs_dev, &waves_dev, &D, &OD};
+    return hipLaunchKernel(k, dim3((unsigned)nwaves), dim3(64), args, 0, stream);
+}
+
+hipError_t launch_prop1d_il(const PropSeg* segs_dev, int64_t nblocks, int64_t bps, int64_t nwaves,
+                            int D, int skip, hipStream_t stream) {
+    int OD = 0, NC = 0;
+    const void* k = prop1d_kernel(D, skip, true);
+    if (!k || !prop1d_geometry(D, &OD, &NC) || nblocks <= 0 || nblocks >= (int64_t(1) << 32) ||
+        bps <= 0 || nblocks % bps != 0 || nwaves <= 0 || nwaves > nblocks)
+        return hipErrorInvalidValue;
+    uint32_t nb = (uint32_t)nblocks, bp = (uint32_t)bps;
+    void* args[] = {&segs_dev, &nb, &bp, &D, &OD};
     return hipLaunchKernel(k, dim3((unsigned)nwaves), dim3(64), args, 0, stream);
 }
 

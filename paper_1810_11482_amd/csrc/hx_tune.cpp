@@ -246,7 +246,7 @@ extern "C" hx_status hx_tune_batched(hx_ctx ctx, const hx_batch_desc* desc, int 
             cands.push_back(d);
         }
     if (desc->dtype == HX_F32)
-        for (int span : {0, 16, 24, 40}) {
+        for (int span : {0, -1, 16, 24, 40}) {
             hx_batch_desc d = *desc;
             d.form = HX_FORM_PROPAGATOR;
             d.span_blocks = span;

@@ -6,6 +6,10 @@ Covered:
 - periodic segments and halo-coupled partitions, depths 1..64, ragged sizes
   and every span of blocks per wave;
 - identical bits for every span;
+- the interleaved walk (segments of one size and one rate, fp16 two-term
+  split at a per-window scale): the oracle, the span walk within the
+  tolerance, waves of one and of several blocks, halo-coupled partitions,
+  extreme and mixed magnitudes, and the plan's rejections;
 - the plan rejects segments the form cannot take, and AUTO falls back to the
   direct form for them;
 - the full-size headline form (2^28 cells, 64 partition views of one arena,
@@ -227,3 +231,124 @@ def test_full_size_headline_form_sampled(ctx):
     for b in A + B + [arena_a, arena_b]:
         hx.hx_buffer_destroy(ctx, b)
     hx.hx_host_free(ctx, hin)
+
+
+@pytest.mark.parametrize("D,n,count", [(1, 1028, 5), (20, 4108, 7), (50, 30000, 3),
+                                       (64, 1000, 4), (50, 1000000, 3), (33, 64, 9)])
+def test_interleaved_walk_matches_oracle_and_spans(ctx, D, n, count):
+    """Segments of one size and one rate, walked interleaved (span_blocks = -1):
+    the oracle on every segment, the span walk within the tolerance, and the
+    same bits as the plan's own choice (which is this walk).  With
+    3 x 10^6 cells the launch has more blocks than the persistent grid has
+    waves, so waves take several blocks; n = 1000 and 1028 leave a partial
+    last block, n = 64 a segment of one partial block."""
+    sizes, rs = [n] * count, [0.2] * count
+    u, il, offs = periodic_batch(ctx, sizes, rs, D, hx.HX_FORM_PROPAGATOR, span=-1, seed=D + 7)
+    span = periodic_batch(ctx, sizes, rs, D, hx.HX_FORM_PROPAGATOR, span=5, seed=D + 7)[1]
+    auto = periodic_batch(ctx, sizes, rs, D, hx.HX_FORM_PROPAGATOR, span=0, seed=D + 7)[1]
+    assert np.array_equal(il, auto)
+    mask = np.ones(il.size, bool)
+    for k, o in enumerate(offs):
+        mask[o:o + n] = False
+        ref = oracle.heat1d_periodic(u[o:o + n].astype(np.float64), 0.2, D)
+        got = il[o:o + n]
+        assert rel_l2(got, ref) <= 1e-5 and rel_max(got, ref) <= 1e-5, (D, n, k)
+        assert rel_l2(got, span[o:o + n]) <= 1e-5
+    assert np.all(il[mask] == -7.0)  # guards untouched
+
+
+@pytest.mark.parametrize("D,hw", [(50, 52), (17, 23), (8, 8)])
+def test_interleaved_halo_coupled_partitions(ctx, D, hw):
+    """Equal partitions of one periodic array, halos from the neighbours'
+    views, walked interleaved: the oracle on the whole array, and the span
+    walk within the tolerance."""
+    P, m = 9, 70004
+    n = P * m
+    u0 = workloads.uniform(n, 511, D, 0, 1, np.float32)
+    a = upload(ctx, u0)
+    results = []
+    for span in (-1, 3):
+        b = hx.hx_buffer_create(ctx, n * 4)
+        segs = []
+        for p in range(P):
+            lp, rp = (p - 1) % P, (p + 1) % P
+            segs.append(hx.segment(inp=a, in_offset=p * m * 4, out=b, out_offset=p * m * 4,
+                                   n=m, r=0.25, bc_lo=hx.HX_BC_GHOST, bc_hi=hx.HX_BC_GHOST,
+                                   halo_lo=a, halo_lo_offset=(lp * m + m - hw) * 4, halo_hi=a,
+                                   halo_hi_offset=rp * m * 4, halo_width=hw))
+        plan = hx.hx_plan_create_batched(ctx, hx.HX_F32, D, segs, hx.HX_BATCH_PERSISTENT,
+                                         form=hx.HX_FORM_PROPAGATOR, span_blocks=span)
+        ev = hx.hx_launch_batched(ctx, plan)
+        assert hx.hx_wait(ctx, ev) == hx.HX_OK, hx.hx_last_error(ctx)
+        hx.hx_event_release(ctx, ev)
+        hx.hx_plan_destroy(ctx, plan)
+        results.append(download(ctx, b, n, np.float32))
+        hx.hx_buffer_destroy(ctx, b)
+    hx.hx_buffer_destroy(ctx, a)
+    ref = oracle.heat1d_periodic(u0.astype(np.float64), 0.25, D)
+    il, span = results
+    assert rel_l2(il, ref) <= 1e-5 and rel_max(il, ref) <= 1e-5
+    assert rel_l2(il, span) <= 1e-5
+
+
+def test_interleaved_walk_rejections(ctx):
+    """span_blocks = -1 needs segments of one size and one rate; below -1 is
+    invalid; unequal segments with span_blocks = 0 take the span walk."""
+    b = hx.hx_buffer_create(ctx, 1 << 16)
+    c = hx.hx_buffer_create(ctx, 1 << 16)
+    per = dict(bc_lo=hx.HX_BC_PERIODIC, bc_hi=hx.HX_BC_PERIODIC)
+    s1 = hx.segment(inp=b, out=c, n=1024, r=0.2, **per)
+    s2 = hx.segment(inp=b, in_offset=4096, out=c, out_offset=4096, n=2048, r=0.2, **per)
+    s3 = hx.segment(inp=b, in_offset=4096, out=c, out_offset=4096, n=1024, r=0.1, **per)
+    for segs, span in (([s1, s2], -1), ([s1, s3], -1), ([s1], -2)):
+        with pytest.raises(hx.HxError) as e:
+            hx.hx_plan_create_batched(ctx, hx.HX_F32, 20, segs, hx.HX_BATCH_PERSISTENT,
+                                      form=hx.HX_FORM_PROPAGATOR, span_blocks=span)
+        assert e.value.status == hx.HX_ERR_ARG
+    for segs in ([s1, s2], [s1, s3]):
+        plan = hx.hx_plan_create_batched(ctx, hx.HX_F32, 20, segs, hx.HX_BATCH_PERSISTENT,
+                                         form=hx.HX_FORM_PROPAGATOR, span_blocks=0)
+        hx.hx_plan_destroy(ctx, plan)
+    hx.hx_buffer_destroy(ctx, b)
+    hx.hx_buffer_destroy(ctx, c)
+
+
+def test_interleaved_scaling_extreme_magnitudes(ctx):
+    """Every window of the interleaved walk takes its own power-of-two scale:
+    segments of U[0,1] times 1e-30, 1, 1e30, a segment with a spike of 1e6 on
+    a U[0,1] background, one of zeros and one of negative values all match the
+    oracle (each against its own magnitude), and zeros stay exact zeros."""
+    n, D, r = 8192, 50, 0.25
+    base = [workloads.uniform(n, 512, k, 0, 1, np.float64) for k in range(6)]
+    vals = [base[0] * 1e-30, base[1], base[2] * 1e30, base[3].copy(), np.zeros(n),
+            -base[5]]
+    vals[3][4000] = 1e6
+    offs, o = [], GUARD
+    for _ in vals:
+        offs.append(o)
+        o += n + GUARD
+    u = np.full(o, -7.0, dtype=np.float32)
+    for v, o in zip(vals, offs):
+        u[o:o + n] = v.astype(np.float32)
+    bin_ = upload(ctx, u)
+    bout = upload(ctx, np.full(u.size, -7.0, dtype=np.float32))
+    segs = [hx.segment(inp=bin_, in_offset=o * 4, out=bout, out_offset=o * 4, n=n, r=r,
+                       bc_lo=hx.HX_BC_PERIODIC, bc_hi=hx.HX_BC_PERIODIC) for o in offs]
+    plan = hx.hx_plan_create_batched(ctx, hx.HX_F32, D, segs, hx.HX_BATCH_PERSISTENT,
+                                     form=hx.HX_FORM_PROPAGATOR, span_blocks=-1)
+    ev = hx.hx_launch_batched(ctx, plan)
+    assert hx.hx_wait(ctx, ev) == hx.HX_OK, hx.hx_last_error(ctx)
+    hx.hx_event_release(ctx, ev)
+    hx.hx_plan_destroy(ctx, plan)
+    out = download(ctx, bout, u.size, np.float32)
+    hx.hx_buffer_destroy(ctx, bin_)
+    hx.hx_buffer_destroy(ctx, bout)
+    for k, o in enumerate(offs):
+        got = out[o:o + n].astype(np.float64)
+        ref = oracle.heat1d_periodic(u[o:o + n].astype(np.float64), r, D)
+        if k == 4:
+            assert np.all(got == 0.0)
+            continue
+        assert rel_l2(got, ref) <= 1e-5 and rel_max(got, ref) <= 1e-5, k
+        if k != 3:  # homogeneous magnitudes: every cell to 1e-5 of itself
+            assert np.max(np.abs(got - ref) / np.abs(ref)) <= 1e-5, k
