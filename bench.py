@@ -36,10 +36,11 @@ import numpy as np
 
 HBM_PEAK = 8.0e12            # bytes/s, MI355X HBM3E
 VALU_F32_PEAK = 157.3e12     # flop/s: 256 CU x 128 FP32 lanes/clk x 2 (FMA) x 2.4 GHz
-MFMA_BF16_PEAK = 2.5e15      # flop/s, dense bf16 matrix cores
+MFMA_BF16_PEAK = 2.5e15      # flop/s, dense bf16 (and fp16) matrix cores
 FLOPS_PER_UPDATE_1D = 3      # rescaled update w' = fma(b, l + rt, w): one add + one fma
 BYTES_PER_CELL_PASS = 8      # one fp32 read + one fp32 write per cell per pass
 MFMA_FLOPS_PER_CHUNK = 6 * 32 * 32 * 16 * 2   # six 32x32x16 products per 16-cell window chunk
+MFMA_FLOPS_PER_CHUNK_IL = 3 * 32 * 32 * 16 * 2  # interleaved walk: three fp16 products
 ROOT = os.path.dirname(os.path.abspath(__file__))
 # per form: the committed counter summary of its kernel and the sources it is built from
 KERNELS = {
@@ -373,11 +374,13 @@ def main():
     kform = "propagator_il" if form == "propagator" and span == -1 else form
     traffic = measured_traffic(kform)
     if form == "propagator":
-        # matrix-core work as issued: 1024-cell iterations x NC window chunks x
-        # six 32x32x16 bf16 products (NC = 9 at 50 steps)
+        # matrix-core work, unpruned: 1024-cell iterations x NC window chunks x
+        # six 32x32x16 bf16 products (span walk) or three fp16 ones (interleaved
+        # walk); NC = 9 at 50 steps
         od = 8 * ((tb + 7) // 8)
         nc = (32 + tb + od + 15) // 16
-        mf_per_launch = cells_per_launch / 1024 * nc * MFMA_FLOPS_PER_CHUNK
+        mf_per_launch = cells_per_launch / 1024 * nc * (MFMA_FLOPS_PER_CHUNK_IL if span == -1
+                                                        else MFMA_FLOPS_PER_CHUNK)
         mf = mf_per_launch / (avg_ms * 1e-3)
         mfma_frac = mf / MFMA_BF16_PEAK
         kname = f"k_prop1d_il<{nc}>" if span == -1 else f"k_prop1d<{nc}>"
