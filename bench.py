@@ -258,9 +258,11 @@ def main():
                     help="compute streams of the context (the per-partition graph spreads its "
                          "nodes over them)")
     ap.add_argument("--legs",
-                    default="graph,plain,pipeline,batched,fp64,2d,adjoint,overhead,copy,cpu",
+                    default="graph,plain,pipeline,pipeline2d,batched,fp64,2d,adjoint,overhead,copy,"
+                            "cpu",
                     help="comma list of side legs: graph (the per-partition future graph), "
-                         "plain, pipeline, batched, fp64 (2^20 fp64, 100 steps), 2d (16384^2, "
+                         "plain, pipeline, pipeline2d (16384^2 bands host to host, 200 steps), "
+                         "batched, fp64 (2^20 fp64, 100 steps), 2d (16384^2, "
                          "200 steps, 16 bands), adjoint (8192^2, 100 steps), copy (a zero-step "
                          "pass over the arena: a plain 1 GiB device copy, for counter "
                          "calibration), overhead (the partition benchmark of 2^21..2^28 "
@@ -455,6 +457,8 @@ def main():
         P.last = 0
     if "pipeline" in legs:
         result["pipeline"] = pipeline_leg(hx, ctx, P, T, r, cpl)
+    if "pipeline2d" in legs:
+        result["pipeline_2d"] = pipeline2d_leg(hx)
     if "copy" in legs:
         result["copy_calibration"] = copy_leg(hx, ctx, P)
     if "batched" in legs:
@@ -660,6 +664,86 @@ def pipeline_leg(hx, ctx0, P, T, r, cpl):
            "host_link_GBps_during_overlap": bytes_copied / (measure_len(C) * 1e-3) / 1e9,
            "sampled_max_rel_err": err}
     log(f"pipeline: {res}")
+    return res
+
+
+def pipeline2d_leg(hx):
+    """Host-to-host 2D run: 16384^2 fp32, zero-Dirichlet, r = 0.2, 200 steps, 16
+    row bands, each copied in, advanced on its extended rows (own rows plus the
+    200-row light cone from each neighbour, by device copies) and copied out,
+    so that copies of some bands overlap the kernels of others; the overlap
+    measures as in the 1D pipeline."""
+    import torch
+    import oracle
+    import workloads
+    from paper_1810_11482_amd.pipeline2d import Pipeline2D
+    spec = workloads.Banded2D()
+    u0 = workloads.banded2d_u0(spec)
+    ny, nx, T, r = spec.ny, spec.nx, spec.steps, spec.r
+    cells = ny * nx
+    ctx = hx.hx_ctx_create(0, timing=True)
+    hin = hx.hx_host_alloc(ctx, cells * 4)
+    hout = hx.hx_host_alloc(ctx, cells * 4)
+    np.ctypeslib.as_array((np.ctypeslib.ctypes.c_float * cells).from_address(hin))[:] = \
+        u0.ravel()
+    out = np.ctypeslib.as_array((np.ctypeslib.ctypes.c_float * cells).from_address(hout))
+    hx_ctx = ctx
+    pl = Pipeline2D(ctx, ny, nx, workloads.band_bounds(ny, spec.bands), T, r, time_block=16,
+                    cells_per_lane=4, rows_per_block=128)
+
+    def timed(fn, reps=3):
+        walls, last = [], None
+        for it in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = fn()
+            assert hx.hx_wait(hx_ctx, res[0]) == hx.HX_OK, hx.hx_last_error(hx_ctx)
+            walls.append(time.perf_counter() - t0)
+            if last:
+                for e in [x for grp in last for x in (grp if isinstance(grp, list) else [grp])]:
+                    hx.hx_event_release(hx_ctx, e)
+            last = res
+        return float(np.mean(walls[1:])), last
+
+    W, res = timed(lambda: pl.run(hin, hout))
+    _, h2d, ker, d2h = res
+    ref0 = h2d[0]
+    spans = {"h2d": [hx.hx_event_span(ctx, e, ref0) for e in h2d],
+             "kernel": [hx.hx_event_span(ctx, e, ref0) for e in ker],
+             "d2h": [hx.hx_event_span(ctx, e, ref0) for e in d2h]}
+    for e in [res[0]] + h2d + ker + d2h:
+        hx.hx_event_release(ctx, e)
+    # sampled correctness before anything else touches host_out
+    rng = np.random.default_rng(14)
+    pts = [(0, 0), (1023, 5000), (1024, 5000), (ny - 1, nx - 1)] + \
+        [(int(a), int(b)) for a, b in zip(rng.integers(0, ny, 6), rng.integers(0, nx, 6))]
+    ref = oracle.heat2d_dirichlet_at(u0, r, T, pts)
+    got = np.array([out[y * nx + x] for y, x in pts], dtype=np.float64)
+    err = float(np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1e-30)))
+    t_copy, res = timed(lambda: pl.run(hin, hout, kernels=False))
+    for e in [res[0]] + res[1] + res[3]:
+        hx.hx_event_release(ctx, e)
+    t_kernel, res = timed(lambda: pl.kernels_only())
+    for e in [res[0]] + res[1]:
+        hx.hx_event_release(ctx, e)
+    C = intervals_union([tuple(x) for x in spans["h2d"] + spans["d2h"]])
+    K = intervals_union([tuple(x) for x in spans["kernel"]])
+    lit = intersect_len(C, K) / measure_len(C)
+    eta = (t_copy + t_kernel - W) / min(t_copy, t_kernel)
+    ext = sum(pl.ext_rows) / ny
+    pl.close()
+    hx.hx_host_free(ctx, hin)
+    hx.hx_host_free(ctx, hout)
+    hx.hx_ctx_destroy(ctx)
+    res = {"ny": ny, "nx": nx, "bands": spec.bands, "steps": T,
+           "wall_ms": W * 1e3, "copies_alone_ms": t_copy * 1e3, "kernels_alone_ms": t_kernel * 1e3,
+           "pcie_inclusive_cell_updates_per_s": cells * T / W,
+           "recomputed_rows_factor": ext,
+           "copy_hidden_literal": lit, "overlap_efficiency_eta": eta,
+           "copy_bound_efficiency": t_copy / W,
+           "host_link_GBps_during_overlap": 2 * cells * 4 / (measure_len(C) * 1e-3) / 1e9,
+           "sampled_max_rel_err": err}
+    log(f"pipeline 2D: {res}")
     return res
 
 
