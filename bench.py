@@ -688,8 +688,9 @@ def pipeline2d_leg(hx):
         u0.ravel()
     out = np.ctypeslib.as_array((np.ctypeslib.ctypes.c_float * cells).from_address(hout))
     hx_ctx = ctx
+    # 64 rows per wave: two bands' kernels share the GPU at a time here
     pl = Pipeline2D(ctx, ny, nx, workloads.band_bounds(ny, spec.bands), T, r, time_block=16,
-                    cells_per_lane=4, rows_per_block=128)
+                    cells_per_lane=4, rows_per_block=64)
 
     def timed(fn, reps=3):
         walls, last = [], None

@@ -80,12 +80,17 @@ class Pipeline2D:
                                                              self.ext[q], src, self.top[p] * rb),
                                            [h2d[q]]))
             if kernels and self.bot[p]:
+                # chained on the top halo's copy: the runtime continues the
+                # compute stream whose last operation is a dependency, so a
+                # band's halo copies and kernel share one stream and the next
+                # band starts on the other, instead of a halo copy queueing
+                # behind the previous band's kernel
                 q = p + 1
                 dst = (self.top[p] + s) * rb
                 halos.append(hx_copy_async(ctx, hx_copy_desc(HX_D2D, 0, self.ext[p], dst,
                                                              self.ext[q], self.top[q] * rb,
                                                              self.bot[p] * rb),
-                                           [h2d[q]]))
+                                           [h2d[q]] + halos[-1:]))
             if kernels:
                 k = hx_launch_stencil(ctx, self._kernel_args(p), [h2d[p]] + halos)
                 ker.append(k)
