@@ -603,16 +603,18 @@ def pipeline_leg(hx, ctx0, P, T, r, cpl):
     base = hx.partitioned_desc(hx.HX_F32, P.sizes, P.A, P.B, T, r, periodic=True,
                                time_block=T, cells_per_lane=cpl)
     pd = hx.hx_pipeline_desc(base, P.host_in, P.host_out)
+    # the host link's rate drifts between runs: every time is the median of
+    # five runs after a warm-up
     walls = []
     spans = None
-    for it in range(3):
+    for it in range(6):
         P.wait()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ev, h2d, ker, d2h = hx.hx_run_pipeline(ctx, pd, op_events=(it == 2))
+        ev, h2d, ker, d2h = hx.hx_run_pipeline(ctx, pd, op_events=(it == 5))
         assert hx.hx_wait(ctx, ev) == hx.HX_OK, hx.hx_last_error(ctx)
         walls.append(time.perf_counter() - t0)
-        if it == 2:
+        if it == 5:
             ref = h2d[0]
             spans = {"h2d": [hx.hx_event_span(ctx, e, ref) for e in h2d],
                      "kernel": [hx.hx_event_span(ctx, e, ref) for e in ker],
@@ -620,7 +622,7 @@ def pipeline_leg(hx, ctx0, P, T, r, cpl):
             for e in h2d + ker + d2h:
                 hx.hx_event_release(ctx, e)
         hx.hx_event_release(ctx, ev)
-    W = float(np.mean(walls[1:]))
+    W = float(np.median(walls[1:]))
     # correctness of the pipeline output on sampled cells, before anything else
     # touches host_out
     import oracle
@@ -635,14 +637,14 @@ def pipeline_leg(hx, ctx0, P, T, r, cpl):
                                                   periodic=True, cells_per_lane=cpl),
                               P.host_in, P.host_out)
     cw = []
-    for it in range(3):
+    for it in range(6):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ev, _, _, _ = hx.hx_run_pipeline(ctx, pd0)
         assert hx.hx_wait(ctx, ev) == hx.HX_OK
         cw.append(time.perf_counter() - t0)
         hx.hx_event_release(ctx, ev)
-    t_copy = float(np.mean(cw[1:]))
+    t_copy = float(np.median(cw[1:]))
     # kernels alone: the single-pass device-resident graph
     P.cur_in_a = True
     t_kernel, _ = time_steps(P, 2, hx.HX_PART_GRAPH, T, cpl)
@@ -693,6 +695,9 @@ def pipeline2d_leg(hx):
                     cells_per_lane=4, rows_per_block=64)
 
     def timed(fn, reps=3):
+        """Wall time of fn() to its final event: the mean after the first of
+        `reps` runs (the only run when reps is 1); returns it and the last
+        run's events (earlier runs' are released)."""
         walls, last = [], None
         for it in range(reps):
             torch.cuda.synchronize()
@@ -704,9 +709,28 @@ def pipeline2d_leg(hx):
                 for e in [x for grp in last for x in (grp if isinstance(grp, list) else [grp])]:
                     hx.hx_event_release(hx_ctx, e)
             last = res
-        return float(np.mean(walls[1:])), last
+        return float(np.mean(walls[1:] if reps > 1 else walls)), last
 
-    W, res = timed(lambda: pl.run(hin, hout))
+    # the host link's rate drifts between runs: full runs and copies-only runs
+    # alternate, and each time is the median of five after a warm-up
+    walls, cwalls, res = [], [], None
+    for it in range(6):
+        w_, res_ = timed(lambda: pl.run(hin, hout), reps=1)
+        if res:
+            for e in [res[0]] + res[1] + res[2] + res[3]:
+                hx.hx_event_release(ctx, e)
+        res = res_
+        walls.append(w_)
+        c_, cres = timed(lambda: pl.run(hin, hout, kernels=False), reps=1)
+        for e in [cres[0]] + cres[1] + cres[3]:
+            hx.hx_event_release(ctx, e)
+        cwalls.append(c_)
+    W, t_copy = float(np.median(walls[1:])), float(np.median(cwalls[1:]))
+    # the last full run's output and spans
+    w_, res_ = timed(lambda: pl.run(hin, hout), reps=1)
+    for e in [res[0]] + res[1] + res[2] + res[3]:
+        hx.hx_event_release(ctx, e)
+    res = res_
     _, h2d, ker, d2h = res
     ref0 = h2d[0]
     spans = {"h2d": [hx.hx_event_span(ctx, e, ref0) for e in h2d],
@@ -721,9 +745,6 @@ def pipeline2d_leg(hx):
     ref = oracle.heat2d_dirichlet_at(u0, r, T, pts)
     got = np.array([out[y * nx + x] for y, x in pts], dtype=np.float64)
     err = float(np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1e-30)))
-    t_copy, res = timed(lambda: pl.run(hin, hout, kernels=False))
-    for e in [res[0]] + res[1] + res[3]:
-        hx.hx_event_release(ctx, e)
     t_kernel, res = timed(lambda: pl.kernels_only())
     for e in [res[0]] + res[1]:
         hx.hx_event_release(ctx, e)

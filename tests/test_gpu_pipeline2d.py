@@ -73,3 +73,29 @@ def test_pipeline2d_matches_oracle(ctx, ny, nx, bands, steps, tb):
 def test_pipeline2d_rejects_thin_bands(ctx):
     with pytest.raises(ValueError):
         Pipeline2D(ctx, 100, 64, workloads.band_bounds(100, 4), 30, 0.2)
+
+
+def test_pipeline2d_full_size_sampled(ctx):
+    """The benchmark's configuration: 16384^2 fp32, 16 bands, r = 0.2, 200
+    steps, Gaussian bumps, 64 rows per wave; sampled cells (band seams, grid
+    edges, random points) against the oracle's light cones."""
+    spec = workloads.Banded2D()
+    u0 = workloads.banded2d_u0(spec)
+    ny, nx, T, r = spec.ny, spec.nx, spec.steps, spec.r
+    hin, _ = host_grid(ctx, u0)
+    hout, out = host_grid(ctx, np.zeros(ny * nx, np.float32))
+    pl = Pipeline2D(ctx, ny, nx, workloads.band_bounds(ny, spec.bands), T, r, time_block=16,
+                    cells_per_lane=4, rows_per_block=64)
+    ev, h2d, ker, d2h = pl.run(hin, hout)
+    assert hx.hx_wait(ctx, ev) == hx.HX_OK, hx.hx_last_error(ctx)
+    for e in [ev] + h2d + ker + d2h:
+        hx.hx_event_release(ctx, e)
+    rng = np.random.default_rng(23)
+    pts = [(0, 0), (ny - 1, nx - 1), (1023, 7000), (1024, 7000), (8191, 100), (8192, 100)] + \
+        [(int(a), int(b)) for a, b in zip(rng.integers(0, ny, 6), rng.integers(0, nx, 6))]
+    ref = oracle.heat2d_dirichlet_at(u0, r, T, pts)
+    got = np.array([out[y * nx + x] for y, x in pts], dtype=np.float64)
+    assert np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1e-30)) <= 1e-5
+    pl.close()
+    hx.hx_host_free(ctx, hin)
+    hx.hx_host_free(ctx, hout)
