@@ -234,14 +234,14 @@ def test_full_size_headline_form_sampled(ctx):
 
 
 @pytest.mark.parametrize("D,n,count", [(1, 1028, 5), (20, 4108, 7), (50, 30000, 3),
-                                       (64, 1000, 4), (50, 1000000, 3), (33, 64, 9)])
+                                       (64, 1000, 4), (50, 4000000, 3), (33, 64, 9)])
 def test_interleaved_walk_matches_oracle_and_spans(ctx, D, n, count):
     """Segments of one size and one rate, walked interleaved (span_blocks = -1):
     the oracle on every segment, the span walk within the tolerance, and the
     same bits as the plan's own choice (which is this walk).  With
-    3 x 10^6 cells the launch has more blocks than the persistent grid has
-    waves, so waves take several blocks; n = 1000 and 1028 leave a partial
-    last block, n = 64 a segment of one partial block."""
+    1.2 x 10^7 cells the launch has about four times as many blocks as the
+    persistent grid has waves, so waves take several blocks; n = 1000 and
+    1028 leave a partial last block, n = 64 a segment of one partial block."""
     sizes, rs = [n] * count, [0.2] * count
     u, il, offs = periodic_batch(ctx, sizes, rs, D, hx.HX_FORM_PROPAGATOR, span=-1, seed=D + 7)
     span = periodic_batch(ctx, sizes, rs, D, hx.HX_FORM_PROPAGATOR, span=5, seed=D + 7)[1]
@@ -352,3 +352,34 @@ def test_interleaved_scaling_extreme_magnitudes(ctx):
         assert rel_l2(got, ref) <= 1e-5 and rel_max(got, ref) <= 1e-5, k
         if k != 3:  # homogeneous magnitudes: every cell to 1e-5 of itself
             assert np.max(np.abs(got - ref) / np.abs(ref)) <= 1e-5, k
+
+
+def test_interleaved_non_finite_cell_stays_in_its_windows(ctx):
+    """A NaN input cell is left out of its window's scale: it reaches outputs
+    within the windows that hold it (at most 64 + 32 cells away at D = 50)
+    and no others; every other cell of the segment matches the oracle run on
+    the same input with that cell set to zero, outside the reach."""
+    n, D, r, bad = 16384, 50, 0.25, 5000
+    u, _, offs = periodic_batch(ctx, [n], [r], D, hx.HX_FORM_PROPAGATOR, span=-1, seed=71)
+    o = offs[0]
+    u[o + bad] = np.nan
+    bin_ = upload(ctx, u)
+    bout = upload(ctx, np.full(u.size, -7.0, dtype=np.float32))
+    seg = hx.segment(inp=bin_, in_offset=o * 4, out=bout, out_offset=o * 4, n=n, r=r,
+                     bc_lo=hx.HX_BC_PERIODIC, bc_hi=hx.HX_BC_PERIODIC)
+    plan = hx.hx_plan_create_batched(ctx, hx.HX_F32, D, [seg], hx.HX_BATCH_PERSISTENT,
+                                     form=hx.HX_FORM_PROPAGATOR, span_blocks=-1)
+    ev = hx.hx_launch_batched(ctx, plan)
+    assert hx.hx_wait(ctx, ev) == hx.HX_OK, hx.hx_last_error(ctx)
+    hx.hx_event_release(ctx, ev)
+    hx.hx_plan_destroy(ctx, plan)
+    got = download(ctx, bout, u.size, np.float32)[o:o + n]
+    hx.hx_buffer_destroy(ctx, bin_)
+    hx.hx_buffer_destroy(ctx, bout)
+    clean = u[o:o + n].astype(np.float64)
+    clean[bad] = 0.0
+    ref = oracle.heat1d_periodic(clean, r, D)
+    far = np.abs(np.arange(n) - bad) > 64 + 32
+    assert np.all(np.isfinite(got[far]))
+    assert rel_max(got[far], ref[far]) <= 1e-5
+    assert np.isnan(got[bad])
