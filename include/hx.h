@@ -336,14 +336,20 @@ hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* desc, hx_plan*
 /* The PROPAGATOR form advances each segment by one convolution with the
  * `steps`-step propagator of the 1D stencil (the steps-fold self-convolution of
  * [r, 1-2r, r], see hx_propagator_coefficients), a banded Toeplitz product run
- * as bf16 matrix-core tiles on an exact three-term bf16 split of every f32
- * operand, accumulated in f32.  A segment qualifies when: dtype is HX_F32, the
- * mode PERSISTENT, 1 <= steps <= 64; both ends PERIODIC (then n >= steps) or
- * both GHOST with halo_width >= 4 * ceil(steps / 4); n is a multiple of 4; and
- * in, out, the end of the left halo and the start of the right halo are
- * 16-byte aligned.  Results agree with stepping to f32 rounding (not bit for
- * bit); a non-finite input cell may also reach outputs up to steps + 46 cells
- * away, not only steps (the zero taps of the tile multiply it). */
+ * on matrix-core tiles and accumulated in f32.  Walked in spans, every f32
+ * operand takes an exact three-term bf16 split (six products per pair);
+ * walked interleaved (segments of one size and one rate), each 1152-cell
+ * window is scaled by a power of two and split into two fp16 terms (three
+ * products per pair; each product within about 3 * 2^-22 of itself, cells far
+ * below their window's largest within 2^-38 of it).  A segment qualifies
+ * when: dtype is HX_F32, the mode PERSISTENT, 1 <= steps <= 64; both ends
+ * PERIODIC (then n >= steps) or both GHOST with halo_width >=
+ * 4 * ceil(steps / 4); n is a multiple of 4; and in, out, the end of the left
+ * halo and the start of the right halo are 16-byte aligned.  Results agree
+ * with stepping to f32 rounding (not bit for bit, and not between the two
+ * walks); a non-finite input cell may also reach outputs up to steps + 46
+ * cells away, not only steps (the zero taps of the tile multiply it); in the
+ * interleaved walk it is left out of its window's scale. */
 
 /* Run a batch plan once after `deps`. */
 hx_status hx_launch_batched(hx_ctx ctx, hx_plan plan, const hx_event* deps, int ndeps,
