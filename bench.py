@@ -1,28 +1,35 @@
 #!/usr/bin/env python3
 """Benchmark of the hx hot path on one MI355X.
 
-Workload (the headline configuration): a 1D periodic heat stencil over 2^28
-fp32 cells split into 64 partitions of 4 Mi cells (laid out back to back in
-one HBM arena), r = 0.25, 50 steps, run as a device-resident future graph
-(Sec. V-A.2 / Algorithm 1 with the Sec. V-A.1 stencil): each pass of 50 fused
-steps is one node, launched as one batched kernel over all 64 partitions with
-every partition's halos read from its neighbours.  One bench "step" is the
-whole 50-step run over the whole array, with the data resident in HBM.  The
-pass runs in the faster of the batched plan's two forms, chosen by a short
-untimed sweep: the direct form (the tile kernel stepping in registers) or the
-propagator form (the 50 steps as one convolution with the 50-step propagator
-on the bf16 matrix cores, operands split exactly into three bf16 terms,
-accumulated in f32).
+Workload: a 1D periodic heat stencil over 2^28 fp32 cells split into 64
+partitions of 4 Mi cells, r = 0.25, 50 steps (Sec. V-A.2 / Algorithm 1 with
+the Sec. V-A.1 stencil).
 
-Printed: one JSON line with the throughput (cell-updates/s), the roofline of
-that kernel (per-launch durations from HIP events recorded on its stream in
-the timed region), the oracle's CPU throughput on the whole workload, and the
-side measurements the metric names: both forms of the pass, the per-partition
-future graph (one node per partition per pass), the plain
-one-launch-per-partition-per-step form, the host-to-host pipeline with its
-copy overlap, the 4096-problem batched driver, the fp64, 2D and adjoint
-workloads, the partition-benchmark overhead against raw HIP streams, and a
-copy kernel for counter calibration.
+`value` is the throughput of the whole 50-step run with the partitions
+resident in HBM (laid out back to back in one arena): each pass of 50 fused
+steps is one node of the future graph, launched as one batched kernel over
+all 64 partitions with every partition's halos read from its neighbours.  One
+bench "step" is the whole 50-step run over the whole array.  The pass runs in
+the faster of the batched plan's two forms, chosen by a short untimed sweep:
+the direct form (the tile kernel stepping in registers, vector ALUs only) or
+the propagator form (the 50 steps as one convolution with the 50-step
+propagator on the matrix cores; see `config.update_form`).
+
+The same configuration host to host (pinned host partitions, per-partition
+H2D -> 50-step kernel -> D2H, overlapped) is `host_to_host`, with the copy
+overlap it reaches and the host link's own rates (`host_link`: H2D alone, D2H
+alone, both together).  The PCIe-inclusive throughput is never `value`.
+
+Printed: one JSON line with the throughput, the roofline of the timed kernel
+(per-launch durations from HIP events recorded on its stream in the timed
+region), the error of one pass against the oracle on every cell, the oracle's
+CPU throughput (the headline workload, and a bounded sample of every other
+workload), and the side measurements the metric names: both forms of the
+pass, the per-partition future graph, the plain one-launch-per-partition-
+per-step form, the 2D host-to-host pipeline, the 4096-problem batched driver,
+the fp64, 2D and adjoint workloads, the partition-benchmark overhead against
+raw HIP streams, and a one-pass device copy (the copy ceiling, and the
+calibration of the HBM counters).
 """
 from __future__ import annotations
 
@@ -36,10 +43,10 @@ import numpy as np
 
 HBM_PEAK = 8.0e12            # bytes/s, MI355X HBM3E
 VALU_F32_PEAK = 157.3e12     # flop/s: 256 CU x 128 FP32 lanes/clk x 2 (FMA) x 2.4 GHz
-MFMA_BF16_PEAK = 2.5e15      # flop/s, dense bf16 (and fp16) matrix cores
+MFMA_16BIT_PEAK = 2.5e15     # flop/s, dense bf16 and fp16 matrix cores
 FLOPS_PER_UPDATE_1D = 3      # rescaled update w' = fma(b, l + rt, w): one add + one fma
 BYTES_PER_CELL_PASS = 8      # one fp32 read + one fp32 write per cell per pass
-MFMA_FLOPS_PER_CHUNK = 6 * 32 * 32 * 16 * 2   # six 32x32x16 products per 16-cell window chunk
+MFMA_FLOPS_PER_CHUNK = 6 * 32 * 32 * 16 * 2   # span walk: six bf16 32x32x16 products per chunk
 MFMA_FLOPS_PER_CHUNK_IL = 3 * 32 * 32 * 16 * 2  # interleaved walk: three fp16 products
 ROOT = os.path.dirname(os.path.abspath(__file__))
 # per form: the committed counter summary of its kernel and the sources it is built from
@@ -384,10 +391,10 @@ def main():
         mf_per_launch = cells_per_launch / 1024 * nc * (MFMA_FLOPS_PER_CHUNK_IL if span == -1
                                                         else MFMA_FLOPS_PER_CHUNK)
         mf = mf_per_launch / (avg_ms * 1e-3)
-        mfma_frac = mf / MFMA_BF16_PEAK
+        mfma_frac = mf / MFMA_16BIT_PEAK
         kname = f"k_prop1d_il<{nc}>" if span == -1 else f"k_prop1d<{nc}>"
         if mfma_frac >= hbm_frac:
-            roof = {"bound": "mfma", "achieved": mf / 1e12, "peak": MFMA_BF16_PEAK / 1e12,
+            roof = {"bound": "mfma", "achieved": mf / 1e12, "peak": MFMA_16BIT_PEAK / 1e12,
                     "unit": "TFLOP/s", "frac": mfma_frac}
         else:
             roof = {"bound": "hbm", "achieved": bw / 1e9, "peak": HBM_PEAK / 1e9,

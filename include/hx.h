@@ -163,8 +163,12 @@ typedef struct {
 /* Asynchronous copy (the paper's enqueue_write / enqueue_read, Sec. IV and
  * Listing 2; cudaMemcpyAsync in Algorithm 1).  H2D copies run on the
  * context's host-to-device stream, D2H copies on its device-to-host stream, so
- * the two directions and the kernels of other partitions overlap.  Ranges are
- * checked against the buffer (HX_ERR_RANGE). */
+ * the two directions and the kernels of other partitions overlap.  D2D copies
+ * run on a compute stream: ranges whose ends and length are multiples of 16
+ * bytes take the library's one-pass vector copy kernel (one 16-byte
+ * nontemporal load and store per thread), others hipMemcpyAsync.  Ranges are
+ * checked against the buffer (HX_ERR_RANGE); overlapping D2D ranges of one
+ * buffer are rejected (HX_ERR_ARG). */
 hx_status hx_copy_async(hx_ctx ctx, const hx_copy_desc* desc, const hx_event* deps, int ndeps,
                         hx_event* out);
 
@@ -337,19 +341,28 @@ hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* desc, hx_plan*
  * `steps`-step propagator of the 1D stencil (the steps-fold self-convolution of
  * [r, 1-2r, r], see hx_propagator_coefficients), a banded Toeplitz product run
  * on matrix-core tiles and accumulated in f32.  Walked in spans, every f32
- * operand takes an exact three-term bf16 split (six products per pair);
- * walked interleaved (segments of one size and one rate), each 1152-cell
- * window is scaled by a power of two and split into two fp16 terms (three
- * products per pair; each product within about 3 * 2^-22 of itself, cells far
- * below their window's largest within 2^-38 of it).  A segment qualifies
- * when: dtype is HX_F32, the mode PERSISTENT, 1 <= steps <= 64; both ends
- * PERIODIC (then n >= steps) or both GHOST with halo_width >=
- * 4 * ceil(steps / 4); n is a multiple of 4; and in, out, the end of the left
- * halo and the start of the right halo are 16-byte aligned.  Results agree
- * with stepping to f32 rounding (not bit for bit, and not between the two
- * walks); a non-finite input cell may also reach outputs up to steps + 46
- * cells away, not only steps (the zero taps of the tile multiply it); in the
- * interleaved walk it is left out of its window's scale. */
+ * operand takes an exact three-term bf16 split (six products per pair, each
+ * within 2^-20 of itself); walked interleaved (segments of one size and one
+ * rate), each 1152-cell window is scaled by a power of two and split into two
+ * fp16 terms (three products per pair, each within about 3 * 2^-22 of
+ * itself).  Both walks prune product levels whose taps are tiny, and the fp16
+ * split has absolute floors; so every 1024-cell block checks its outputs
+ * against the bound E of those absolute terms: unless every output is finite
+ * and at least 2^21 E times the largest finite |x| of the block's window (E
+ * is a few 2^-32 of the tap mass at r = 1/4, steps = 50), the block is
+ * recomputed by f32 stepping in a second kernel of the same launch.  Each
+ * output is then either within a few 2^-22 of sum_j |p_j u_{i+j}| plus 2^-21
+ * of itself, or the stepped f32 result: f32 accuracy cell by cell, also next
+ * to cells many orders of magnitude larger, and a non-finite input cell
+ * reaches exactly the outputs within `steps` of it, as stepping does.  A
+ * segment qualifies when: dtype is HX_F32, the mode PERSISTENT,
+ * 1 <= steps <= 64; both ends PERIODIC (then n >= steps) or both GHOST with
+ * halo_width >= 4 * ceil(steps / 4); n is a multiple of 4; and in, out, the
+ * end of the left halo and the start of the right halo are 16-byte aligned.
+ * Results agree with stepping to f32 rounding (not bit for bit, and not
+ * between the two walks).  The plan keeps a list of the blocks to recompute
+ * in device memory, so its launches are serialised on the GPU (each waits for
+ * the previous one); two plans never share it. */
 
 /* Run a batch plan once after `deps`. */
 hx_status hx_launch_batched(hx_ctx ctx, hx_plan plan, const hx_event* deps, int ndeps,

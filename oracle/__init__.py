@@ -234,6 +234,36 @@ def heatvc_grad(u0, kappa, target, dt: float, steps: int, ckpt: int = 0):
     return loss.value, lam0, gk
 
 
+def heatvc_grad_window(u0, kappa, target, dt: float, steps: int, y0: int, x0: int, hy: int,
+                       hx: int):
+    """dL/du0 and dL/dkappa of the whole grid's loss, on the cells of the window
+    [y0, y0 + hy) x [x0, x0 + hx) (clipped to the grid) that lie at least
+    2 * steps cells inside every side where the window cuts the grid.
+
+    The window is run as a grid of its own (heatvc_grad), whose boundary rule
+    is wrong only along those cuts.  One step carries that error one cell
+    inward; the forward sweep takes `steps` steps and the adjoint sweep
+    `steps` more, and the conductivity gradient of a cell also reads its
+    neighbours, so cells 2 * steps or more inside every cut get exactly the
+    whole grid's values.  Returns (rows, cols, lam0, gk): the index ranges of
+    those cells in the grid and their values."""
+    uu, kk, yy = _in(u0), _in(kappa), _in(target)
+    ny, nx = uu.shape
+    a0, a1 = max(y0, 0), min(y0 + hy, ny)
+    b0, b1 = max(x0, 0), min(x0 + hx, nx)
+    m = 2 * steps
+    r0 = a0 if a0 == 0 else a0 + m
+    r1 = a1 if a1 == ny else a1 - m
+    c0 = b0 if b0 == 0 else b0 + m
+    c1 = b1 if b1 == nx else b1 - m
+    if r1 <= r0 or c1 <= c0:
+        raise ValueError("the window holds no cell 2 * steps inside its cuts")
+    sl = (slice(a0, a1), slice(b0, b1))
+    _, lam0, gk = heatvc_grad(uu[sl], kk[sl], yy[sl], dt, steps, 0)
+    keep = (slice(r0 - a0, r1 - a0), slice(c0 - b0, c1 - b0))
+    return (r0, r1), (c0, c1), lam0[keep], gk[keep]
+
+
 def loss(u, y) -> float:
     uu, yy = _in(u), _in(y)
     return _load().orc_loss(_p(uu), _p(yy), uu.size)

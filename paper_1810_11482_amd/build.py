@@ -46,8 +46,20 @@ def _torch_lib_dir() -> str:
     return d
 
 
-def _compile(src: str) -> str:
+def _up_to_date(src: str, obj: str) -> bool:
+    """The object is newer than its source and every header it may include."""
+    if not os.path.exists(obj):
+        return False
+    deps = [src] + glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(CSRC, "*.hpp")) \
+        + glob.glob(os.path.join(INCLUDE, "*.h"))
+    t = os.path.getmtime(obj)
+    return all(os.path.getmtime(d) < t for d in deps)
+
+
+def _compile(src: str, incremental: bool = False) -> str:
     obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
+    if incremental and _up_to_date(src, obj):
+        return obj
     if src.endswith(".hip"):
         cmd = [HIPCC, *COMMON, *DEVICE, "-c", src, "-o", obj]
     else:
@@ -59,12 +71,16 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = True) -> str:
+def build(verbose: bool = True, incremental: bool = False) -> str:
+    """Compile every source (or, with incremental, only those whose object is
+    older than the source or a header) and link libhx.so."""
     os.makedirs(OBJDIR, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
     jobs = min(len(srcs), max(1, min(8, os.cpu_count() or 1)))
+    # the slowest translation units first, so they do not start last
+    srcs.sort(key=lambda f: -os.path.getsize(f))
     with ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda f: _compile(f, incremental), srcs))
     tlib = _torch_lib_dir()
     tmp = LIB + f".tmp{os.getpid()}"
     # Link with the host compiler against torch's runtime by full path, so the
@@ -82,4 +98,4 @@ def build(verbose: bool = True) -> str:
 
 
 if __name__ == "__main__":
-    build()
+    build(incremental="--incremental" in sys.argv)

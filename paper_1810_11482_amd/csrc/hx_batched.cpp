@@ -51,6 +51,10 @@ struct BatchPlan {
     PropSeg* psegs_dev = nullptr;
     PropWave* pwaves_dev = nullptr;
     float* taps_dev = nullptr;
+    uint32_t* fix_dev = nullptr;   // fix list of the propagator form (launch_prop1d)
+    // recorded after each propagator launch and waited on by the next one, so
+    // that launches of the plan never overlap on its fix list
+    hipEvent_t order_ev = nullptr;
     int64_t pwaves = 0;
     int pskip = 0;         // outer window chunks no segment multiplies
     bool pil = false;      // interleaved walk (segments of one size and one rate)
@@ -76,6 +80,8 @@ void destroy_plan(void* p) {
     if (b->psegs_dev) hipFree(b->psegs_dev);
     if (b->pwaves_dev) hipFree(b->pwaves_dev);
     if (b->taps_dev) hipFree(b->taps_dev);
+    if (b->fix_dev) hipFree(b->fix_dev);
+    if (b->order_ev) hipEventDestroy(b->order_ev);
     delete b;
 }
 
@@ -278,6 +284,7 @@ extern "C" hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* d, 
         std::map<double, size_t> tap_at;
         std::map<double, uint32_t> levels_of, levels16_of;
         std::map<double, int32_t> texp_of;
+        std::map<double, double> err_of, err16_of;
         std::vector<float> taps;
         const int D = d->steps;
         for (const Seg1D& sg : bp->segs)
@@ -287,6 +294,9 @@ extern "C" hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* d, 
                 levels_of[sg.r] = prop1d_levels(p.data(), D);
                 levels16_of[sg.r] = prop1d_levels16(p.data(), D);
                 texp_of[sg.r] = prop1d_tap_exp(p.data(), D);
+                err_of[sg.r] = prop1d_err_bound(p.data(), D, levels_of[sg.r], false, 0);
+                err16_of[sg.r] =
+                    prop1d_err_bound(p.data(), D, levels16_of[sg.r], true, texp_of[sg.r]);
                 for (double v : p) taps.push_back((float)v);
             }
         hipDeviceProp_t prop;
@@ -355,7 +365,13 @@ extern "C" hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* d, 
             return c->fail(HX_ERR_RANGE, "the batch has too many propagator waves");
         }
         if (!bp->pil) bp->pwaves = (int64_t)waves.size();
+        int64_t nblk = 0;
+        for (int64_t b : blocks) nblk += b;
+        const size_t fix_bytes = 4 * (size_t)(2 + 2 * nblk);
         bool ok = hipMalloc(&bp->taps_dev, 4 * taps.size()) == hipSuccess &&
+                  hipMalloc(&bp->fix_dev, fix_bytes) == hipSuccess &&
+                  hipMemset(bp->fix_dev, 0, fix_bytes) == hipSuccess &&
+                  hipEventCreateWithFlags(&bp->order_ev, hipEventDisableTiming) == hipSuccess &&
                   hipMalloc(&bp->psegs_dev, sizeof(PropSeg) * bp->segs.size()) == hipSuccess &&
                   (bp->pil ||
                    hipMalloc(&bp->pwaves_dev, sizeof(PropWave) * waves.size()) == hipSuccess);
@@ -370,6 +386,10 @@ extern "C" hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* d, 
                 q.levels = levels_of[sg.r];
                 q.levels16 = levels16_of[sg.r];
                 q.texp = texp_of[sg.r];
+                q.r = (float)sg.r;
+                // the accuracy check's threshold for the walk this plan runs
+                q.chk = bp->pil ? (float)std::ldexp(err16_of[sg.r], 21 + 15 + q.texp)
+                                : (float)std::ldexp(err_of[sg.r], 21);
                 if (sg.bc_lo == HX_BC_PERIODIC) {
                     q.lo_base = q.in + sg.n;
                     q.hi_base = q.in;
@@ -488,12 +508,15 @@ extern "C" hx_status hx_launch_batched(hx_ctx ctx, hx_plan plan, const hx_event*
     return c->submit(
         SC_COMPUTE, deps, ndeps, bp->acc, what,
         [bp](hipStream_t st) -> hipError_t {
-            if (bp->prop && bp->pil)
-                return launch_prop1d_il(bp->psegs_dev, bp->pblocks, bp->pbps, bp->pwaves,
-                                        bp->steps, bp->pskip, st);
-            if (bp->prop)
-                return launch_prop1d(bp->psegs_dev, bp->pwaves_dev, bp->pwaves, bp->steps,
-                                     bp->pskip, st);
+            if (bp->prop) {
+                hipError_t e = hipStreamWaitEvent(st, bp->order_ev, 0);
+                if (e != hipSuccess) return e;
+                e = bp->pil ? launch_prop1d_il(bp->psegs_dev, bp->pblocks, bp->pbps, bp->pwaves,
+                                               bp->steps, bp->pskip, bp->fix_dev, st)
+                            : launch_prop1d(bp->psegs_dev, bp->pwaves_dev, bp->pwaves,
+                                            bp->steps, bp->pskip, bp->fix_dev, st);
+                return e != hipSuccess ? e : hipEventRecord(bp->order_ev, st);
+            }
             if (bp->mode == HX_BATCH_PERSISTENT)
                 return launch_stencil1d_batched(bp->dtype, bp->segs_dev, bp->tseg_dev,
                                                 bp->tidx_dev, bp->ntiles, bp->g, bp->grid_waves,

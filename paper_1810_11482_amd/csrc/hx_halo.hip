@@ -1,3 +1,5 @@
+// Halo pack/unpack, and the device-to-device copy kernel.
+//
 // Halo pack/unpack: one launch copies every descriptor's runs (a run is a
 // contiguous byte range; descriptors with a pitch gather or scatter columns),
 // so all partitions' halos move between state buffers and ghost slots in a
@@ -41,7 +43,32 @@ __global__ __launch_bounds__(256) void k_halo(const HaloDev* __restrict__ d,
     }
 }
 
+// Device-to-device copy of a 16-byte-aligned range: every thread moves one
+// 16-byte vector with a nontemporal load and store, 256 threads (4 KiB) per
+// workgroup, one pass (no loop): the pattern that measured the highest copy
+// bandwidth on MI355X; the grid's tail workgroup checks the bound.
+__global__ __launch_bounds__(256) void k_copy16(const u32x4* __restrict__ src,
+                                                u32x4* __restrict__ dst, int64_t nvec) {
+    typedef __attribute__((address_space(1))) const u32x4 G;
+    typedef __attribute__((address_space(1))) u32x4 GW;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < nvec) __builtin_nontemporal_store(__builtin_nontemporal_load((G*)(src + i)),
+                                              (GW*)(dst + i));
+}
+
 }  // namespace
+
+hipError_t launch_copy16(void* dst, const void* src, size_t bytes, hipStream_t st) {
+    if (bytes == 0) return hipSuccess;
+    if (((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst) | bytes) & 15u) ||
+        bytes / 16 / 256 >= (size_t(1) << 31))
+        return hipErrorInvalidValue;
+    const int64_t nvec = (int64_t)(bytes / 16);
+    const dim3 block(256), grid((unsigned)((nvec + 255) / 256));
+    hipLaunchKernelGGL(k_copy16, grid, block, 0, st, static_cast<const u32x4*>(src),
+                       static_cast<u32x4*>(dst), nvec);
+    return hipGetLastError();
+}
 
 hipError_t launch_halo(const HaloDev* descs, const int64_t* first_run, int nd, int64_t total_runs,
                        hipStream_t st) {

@@ -115,6 +115,16 @@ struct PropSeg {
     // fp16 split: the taps are scaled by 2^texp so that the largest lies in
     // [2^14, 2^15).
     int32_t texp;
+    float r;               // the segment's rate (the stepping path of a block)
+    // Accuracy check of a block's products (prop1d_err_bound): the absolute
+    // error the split and the pruning can add is at most E times the largest
+    // finite |x| of the block's window; a block whose every output y has
+    // |y| >= 2^21 E M keeps those terms within 2^-21 |y|, any other block
+    // (or one with a non-finite output) is recomputed by stepping.  Span
+    // walk: chk = 2^21 E (times the window's M in the kernel); interleaved
+    // walk: chk = 2^21 E 2^(15 + texp), the same bound in the scaled units of
+    // its products (where M < 2^15).
+    float chk;
     int32_t pad;
 };
 
@@ -193,6 +203,43 @@ inline uint32_t prop1d_levels16(const double* p, int D) {
     return mask;
 }
 
+// Bound E on the absolute error that the operand split and the level pruning
+// add to an output, in units of the largest finite |x| of the block's window
+// (the relative parts, at most a few 2^-22 of each product, are not counted
+// here).  Per output row m of a stream, a chunk at level 0 omits its products
+// entirely; at the fp16 split (fp16 = true), level 1 omits the two cross terms
+// (at most 2^-10 of |p_j x_j|); at the bf16 split, level 1 omits all but
+// hi*hi (below 2^-5 of it) and level 2 the terms of order 2^-14 and smaller
+// (below 2^-12).  The fp16 split adds two absolute floors: a data term below
+// fp16's subnormal spacing (2^-25 at a scale that puts the window's largest in
+// [2^14, 2^15), i.e. 2^-39 of it, per unit of tap mass) and a tap term below
+// 2^-25 at the taps' scale 2^texp, per tap.
+inline double prop1d_err_bound(const double* p, int D, uint32_t levels, bool fp16, int texp) {
+    int OD = 0, NC = 0;
+    if (!prop1d_geometry(D, &OD, &NC)) return 0.0;
+    double S = 0.0;
+    for (int j = 0; j <= 2 * D; ++j) S += p[j] < 0 ? -p[j] : p[j];
+    double E = 0.0;
+    for (int m = 0; m < 32; ++m) {
+        double e = 0.0;
+        for (int c = 0; c < NC; ++c) {
+            const uint32_t L = (levels >> (2 * c)) & 3;
+            const double f = L == 0 ? 1.0
+                             : fp16 ? (L == 1 ? 1.0 / 1024.0 : 0.0)
+                                    : (L == 1 ? 1.0 / 32.0 : (L == 2 ? 1.0 / 4096.0 : 0.0));
+            if (f == 0.0) continue;
+            for (int k = 0; k < 16; ++k) {
+                const int j = 16 * c + k - OD - m;
+                if (j < -D || j > D) continue;
+                e += f * (p[j + D] < 0 ? -p[j + D] : p[j + D]);
+            }
+        }
+        E = e > E ? e : E;
+    }
+    if (fp16) E += S * __builtin_ldexp(1.0, -39) + (2 * D + 1) * __builtin_ldexp(1.0, -25 - texp);
+    return E;
+}
+
 // Exponent e with max|p_j| 2^e in [2^14, 2^15) (0 for all-zero taps).
 inline int32_t prop1d_tap_exp(const double* p, int D) {
     double t = 0.0;
@@ -204,10 +251,18 @@ inline int32_t prop1d_tap_exp(const double* p, int D) {
     return e;
 }
 
+// Waves of the fix-up pass that follows every propagator launch.
+constexpr int kPropFixWaves = 1024;
+
 // skip: window chunks on each side that no segment of the launch multiplies
 // (level 0 in every segment's mask); at most 2 are dropped from the kernel.
+// fix: the plan's fix list in device memory, 2 + 2 x (blocks of the launch)
+// words, zero before the first launch: blocks whose products fail the
+// accuracy check are listed there and stepped by a second kernel on the same
+// stream, which leaves the list cleared.  Launches sharing a list must not
+// overlap.
 hipError_t launch_prop1d(const PropSeg* segs_dev, const PropWave* waves_dev, int64_t nwaves, int D,
-                         int skip, hipStream_t stream);
+                         int skip, uint32_t* fix, hipStream_t stream);
 // Waves of that kernel resident per CU (registers and LDS permitting).
 int prop1d_waves_per_cu(int D, int skip, bool il = false);
 // Interleaved walk of the same pass: `nblocks` 1024-cell blocks, bps per
@@ -215,7 +270,7 @@ int prop1d_waves_per_cu(int D, int skip, bool il = false);
 // a persistent grid of nwaves <= nblocks waves, wave w taking blocks w,
 // w + nwaves, ...  nblocks < 2^32 and a multiple of bps.
 hipError_t launch_prop1d_il(const PropSeg* segs_dev, int64_t nblocks, int64_t bps, int64_t nwaves,
-                            int D, int skip, hipStream_t stream);
+                            int D, int skip, uint32_t* fix, hipStream_t stream);
 
 // One 2D band: ny rows of nx cells, row-major, advanced `steps` steps from in
 // into out.  Rows outside [0, ny) come from the top/bottom rule; columns
@@ -307,6 +362,11 @@ struct HaloDev {
     void* dst;
     int64_t rows, row_bytes, src_pitch, dst_pitch;
 };
+
+// Device-to-device copy of `bytes` (a multiple of 16, both ends 16-byte
+// aligned, under 2^43 bytes): one 16-byte nontemporal vector per thread.
+// hipErrorInvalidValue for anything else (the caller then uses hipMemcpyAsync).
+hipError_t launch_copy16(void* dst, const void* src, size_t bytes, hipStream_t stream);
 
 // first_run[i] = runs of descriptors 0..i-1 (device arrays of nd entries).
 hipError_t launch_halo(const HaloDev* descs, const int64_t* first_run, int nd, int64_t total_runs,

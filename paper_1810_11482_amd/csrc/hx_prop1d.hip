@@ -20,14 +20,24 @@
 //   * every f32 operand is split exactly into three bf16 terms
 //     (x = hi + mid + lo, below), and the six products hi*hi, hi*mid, mid*hi,
 //     hi*lo, lo*hi, mid*mid are accumulated in f32: the dropped terms are
-//     below 2^-24 of each product, so the pass keeps f32 accuracy (measured
-//     within 4e-7 of the FP64 result, against about 3e-6 for 50 stepped f32
-//     updates);
+//     below 2^-20 of each product (|mid| < 2^-7 |x|, |lo| < 2^-14 |x|), so the
+//     pass keeps f32 accuracy (measured within 4e-7 of the FP64 result,
+//     against about 3e-6 for 50 stepped f32 updates);
 //   * the taps fall off like a Gaussian of variance 2rD, so the outer chunks
 //     of the window meet taps far below f32 resolution: each chunk takes only
 //     the product levels whose omission would exceed 2^-30 of the taps' total
 //     magnitude (prop1d_levels), which skips 18 of the 54 products per
-//     iteration at r = 1/4, D = 50.
+//     iteration at r = 1/4, D = 50;
+//   * that pruning adds an absolute error, at most E (prop1d_err_bound) times
+//     the largest |x| of the block's window, which is not small against an
+//     output far below that largest value (a cell next to a spike, or a zero
+//     crossing).  So every block checks its outputs: unless each is finite
+//     and at least 2^21 E times the window's largest finite |x|, its products
+//     are not stored and the block goes on a fix list; a second kernel
+//     (k_prop1d_fix) then advances those blocks by plain f32 stepping.  Every
+//     output therefore carries only relative errors of f32 size, or is the
+//     stepped result, and a non-finite input reaches exactly the outputs that
+//     stepping reaches.
 // Data path per iteration: the wave loads the next 1024 cells with coalesced
 // 16-byte loads (two iterations ahead), splits them once into three bf16
 // planes in an LDS ring of three 1024-cell slots (64-byte rows, 16-byte units
@@ -131,6 +141,79 @@ __device__ __forceinline__ f32x4 load4(const PropSeg& s, int64_t c) {
     return gload<NT>(p);
 }
 
+// One cell c of a segment from the same sources as load4, clamped cell by
+// cell (the stepping path below).
+__device__ __forceinline__ float load1(const PropSeg& s, int64_t c) {
+    if (c < 0) return s.lo_base[c < -s.lo_av ? -s.lo_av : c];
+    if (c >= s.n) {
+        const int64_t h = c - s.n;
+        return s.hi_base[h > s.hi_av - 1 ? s.hi_av - 1 : h];
+    }
+    return s.in[c];
+}
+
+// The stepping path of one block: its 1024 cells from c0 advanced D steps of
+// u' = u + r ((u_{i-1} - 2 u_i) + u_{i+1}) in f32, over the block's window of
+// 64 cells each side (D <= 64).  Lane l holds window cells 18 l .. 18 l + 17;
+// the neighbours across lanes come by shuffles, and the cells within D of the
+// window's ends, which go stale, are never stored.  It serves the blocks whose
+// products fail the accuracy check, so it is rare and kept simple: every cell
+// is one 4-byte load and one 4-byte store.
+__device__ __forceinline__ void step_block(const PropSeg& s, int64_t c0, int D) {
+    const int l = threadIdx.x;
+    const float r = s.r;
+    const int64_t b = c0 - 64 + 18 * l;
+    float w[18];
+#pragma unroll
+    for (int t = 0; t < 18; ++t) w[t] = load1(s, b + t);
+    for (int k = 0; k < D; ++k) {
+        const float lf = __shfl_up(w[17], 1);
+        const float rt = __shfl_down(w[0], 1);
+        float prev = lf;
+#pragma unroll
+        for (int t = 0; t < 18; ++t) {
+            const float nx = t < 17 ? w[t + 1] : rt;
+            const float v = w[t] + r * ((prev - 2.f * w[t]) + nx);
+            prev = w[t];
+            w[t] = v;
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 18; ++t) {
+        const int64_t c = b + t;
+        if (c >= c0 && c < c0 + 1024 && c < s.n) s.out[c] = w[t];
+    }
+}
+
+// True on every lane when some output of the block fails the accuracy check:
+// non-finite (including NaN), or below thr in magnitude.
+__device__ __forceinline__ bool block_fails(const f32x16& y, float thr) {
+    bool bad = false;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const float a = fabsf(y[e]);
+        bad = bad || !(a <= 3.402823466e38f) || a < thr;
+    }
+    return __ballot(bad) != 0;
+}
+
+// Fix list of a launch: fix[0] = entries, fix[1] = finished fix-up waves,
+// then (segment, block) pairs.  A block that fails the check is appended
+// (its products are not stored) and k_prop1d_fix steps it afterwards.
+__device__ __forceinline__ void fix_append(uint32_t* fix, uint32_t seg, uint32_t blk) {
+    if (threadIdx.x == 0) {
+        const uint32_t k = atomicAdd(fix, 1u);
+        fix[2 + 2 * k] = seg;
+        fix[3 + 2 * k] = blk;
+    }
+}
+
+__device__ __forceinline__ float wave_max(float x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = fmaxf(x, __shfl_xor(x, o));
+    return x;
+}
+
 // The A operands of window chunks [S0, NC - S0): lane (m = i, g) holds the
 // taps of k = 8g .. 8g+7, split into three bf16 levels.
 template <int NC, int S0>
@@ -152,8 +235,8 @@ __device__ __forceinline__ void prop_taps(const float* coef, int D, int OD, Spli
 // Chunks [S0, NC - S0) of the window are materialised: the outer S0 chunks on
 // each side take no products for any segment of the launch.
 template <int NC, int S0, bool INTERIOR>
-__device__ __forceinline__ void prop_wave(const PropSeg& s, int64_t blk0, int ni, int D, int OD,
-                                          char* lds) {
+__device__ __forceinline__ void prop_wave(const PropSeg& s, uint32_t seg, int64_t blk0, int ni,
+                                          int D, int OD, char* lds, uint32_t* fix) {
     const int l = threadIdx.x, i = l & 31, g = l >> 5;
     const uint32_t lv = s.levels;
     Split8 A[NC];
@@ -176,7 +259,19 @@ __device__ __forceinline__ void prop_wave(const PropSeg& s, int64_t blk0, int ni
     int woff[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) woff[j] = swz(8 * j + (l >> 3), (l & 7) >> 1) + 8 * (l & 1);
+    // smx[slot]: the largest finite |x| of the slot's 1024 cells
+    float smx[3] = {0.f, 0.f, 0.f};
     auto put = [&](int slot, const f32x4 v[4]) {
+        float mx = 0.f;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float a = fabsf(v[j][e]);
+                mx = (a <= 3.402823466e38f && a > mx) ? a : mx;
+            }
+        smx[slot] = __builtin_bit_cast(
+            float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, wave_max(mx))));
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             uint32_t h0, m0, l0, h1, m1, l1;
@@ -234,6 +329,16 @@ __device__ __forceinline__ void prop_wave(const PropSeg& s, int64_t blk0, int ni
         for (int j = 0; j < 4; ++j)
             if (o + 256 * j < s.n) gstore(v[j], s.out + o + 256 * j);
     };
+    // The block's window lies in the three slots of the ring (segments kb - 1,
+    // kb, kb + 1): its outputs pass the check against their largest finite
+    // |x|, or the block is stepped instead.
+    auto emit = [&](int slot, const f32x16& y, int kb) {
+        const float M = fmaxf(fmaxf(smx[0], smx[1]), smx[2]);
+        if (block_fails(y, s.chk * M))
+            fix_append(fix, seg, (uint32_t)(blk0 + kb));
+        else
+            store(slot, y, kb);
+    };
     for (int k0 = 0; k0 < ni; k0 += 6) {
 #pragma unroll
         for (int u = 0; u < 6; ++u) {
@@ -242,7 +347,7 @@ __device__ __forceinline__ void prop_wave(const PropSeg& s, int64_t blk0, int ni
             // the previous block's outputs go out through slot (k + 2) % 3 (its
             // segment, k - 2, is dead); then segment k+1, fetched two
             // iterations ago, goes into the same slot
-            if (k > 0) store((ph + 2) % 3, yprev, k - 1);
+            if (k > 0) emit((ph + 2) % 3, yprev, k - 1);
             __builtin_amdgcn_sched_barrier(0);
             put((ph + 2) % 3, St[sb]);
             __builtin_amdgcn_sched_barrier(0);
@@ -282,19 +387,35 @@ __device__ __forceinline__ void prop_wave(const PropSeg& s, int64_t blk0, int ni
         }
     }
     // the last block, through the slot that iteration ni would have refilled
-    store((ni + 2) % 3, yprev, ni - 1);
+    emit((ni + 2) % 3, yprev, ni - 1);
 }
 
 template <int NC, int S0>
 __global__ __launch_bounds__(64) void k_prop1d(const PropSeg* __restrict__ segs,
-                                               const PropWave* __restrict__ waves, int D, int OD) {
+                                               const PropWave* __restrict__ waves, int D, int OD,
+                                               uint32_t* fix) {
     __shared__ __attribute__((aligned(16))) char lds[3 * kPlane];
     const PropWave w = waves[blockIdx.x];
     const PropSeg s = segs[w.seg];
     if (w.interior)
-        prop_wave<NC, S0, true>(s, w.blk0, (int)w.ni, D, OD, lds);
+        prop_wave<NC, S0, true>(s, w.seg, w.blk0, (int)w.ni, D, OD, lds, fix);
     else
-        prop_wave<NC, S0, false>(s, w.blk0, (int)w.ni, D, OD, lds);
+        prop_wave<NC, S0, false>(s, w.seg, w.blk0, (int)w.ni, D, OD, lds, fix);
+}
+
+// The fix-up pass after either walk: `gridDim.x` waves step the listed
+// blocks (wave w takes entries w, w + grid, ...); the last wave to finish
+// clears the list for the next launch.
+__global__ __launch_bounds__(64) void k_prop1d_fix(const PropSeg* __restrict__ segs,
+                                                   uint32_t* fix, int D) {
+    const uint32_t n = __atomic_load_n(fix, __ATOMIC_RELAXED);
+    for (uint32_t k = blockIdx.x; k < n; k += gridDim.x)
+        step_block(segs[fix[2 + 2 * k]], 1024 * (int64_t)fix[3 + 2 * k], D);
+    __threadfence();
+    if (threadIdx.x == 0 && atomicAdd(fix + 1, 1u) == gridDim.x - 1) {
+        atomicExch(fix, 0u);
+        atomicExch(fix + 1, 0u);
+    }
 }
 
 // Interleaved walk (every segment of the launch has the same n and the same
@@ -312,15 +433,20 @@ __global__ __launch_bounds__(64) void k_prop1d(const PropSeg* __restrict__ segs,
 // one scale: the window's largest finite |x| is brought into [2^14, 2^15) by
 // an exact power of two 2^ex, and every cell is split into two fp16 terms,
 // x 2^ex = hi + lo (round to nearest each, so the pair holds x to 2^-22 of
-// itself; cells far below the largest keep an absolute error within 2^-38 of
-// it).  The taps are split the same way at their own scale 2^texp.  A product
+// itself, or, below fp16's normal range, to an absolute 2^-25 at that scale,
+// i.e. 2^-39 of the largest).  The taps are split the same way at their own
+// scale 2^texp.  These absolute floors and the pruning of product levels are
+// what the check after the products bounds (as in the span walk: a block
+// whose outputs are not all finite and at least 2^21 E times the window's
+// largest is stepped by k_prop1d_fix instead).  A product
 // then takes three 32x32x16 fp16 MFMAs (hi*hi, hi*lo, lo*hi; the dropped
 // lo*lo is below 2^-22 of it) instead of the six of the bf16 split, which
 // halves the matrix-core work (17 instead of 36 products per block at
 // r = 1/4, D = 50, with the fp16 levels' pruning) and the power it draws on
 // high-entropy data, where the six-product form ran into the card's power
 // limit.  The result is scaled back by 2^-(ex + texp).  A non-finite cell is
-// left out of the scale and reaches every output whose window holds it.
+// left out of the scale; the outputs it reaches through the products fail the
+// check.
 constexpr int kWPlane = 36 * 64;  // bytes of one fp16 plane of the 1152-cell window
 
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
@@ -349,12 +475,6 @@ struct Split8h {
     u32x4 h, l;
 };
 
-__device__ __forceinline__ float wave_max(float x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x = fmaxf(x, __shfl_xor(x, o));
-    return x;
-}
-
 // Up to 7 materialised window chunks the kernel fits three waves per SIMD
 // (168 registers): one accumulator, and each block's outputs leave at the end
 // of its own iteration, so no result is held across iterations.  Measured at
@@ -363,7 +483,8 @@ __device__ __forceinline__ float wave_max(float x) {
 // milliseconds into sustained launches.
 template <int NC, int S0>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NC - 2 * S0 <= 7 ? 3 : 1, 8)))
-void k_prop1d_il(const PropSeg* __restrict__ segs, uint32_t nblocks, uint32_t bps, int D, int OD) {
+void k_prop1d_il(const PropSeg* __restrict__ segs, uint32_t nblocks, uint32_t bps, int D, int OD,
+                 uint32_t* fix) {
     __shared__ __attribute__((aligned(16))) char lds[2 * kWPlane];
     const int l = threadIdx.x, i = l & 31, g = l >> 5;
     const uint32_t w = blockIdx.x, nw = gridDim.x;
@@ -371,6 +492,7 @@ void k_prop1d_il(const PropSeg* __restrict__ segs, uint32_t nblocks, uint32_t bp
     const int nk = (int)((nblocks - 1 - w) / nw) + 1;
     const uint32_t lv = segs[0].levels16;
     const int texp = segs[0].texp;
+    const float chk = segs[0].chk;
     // A operands: lane (m = i, g) holds the taps of k = 8g .. 8g+7, scaled by
     // 2^texp and split into two fp16 terms
     Split8h A[NC];
@@ -412,9 +534,10 @@ void k_prop1d_il(const PropSeg* __restrict__ segs, uint32_t nblocks, uint32_t bp
     const int q = l & 15;
     const bool left = (l & 31) < 16;
     woff[4] = swz((left ? 0 : 34) + (q >> 3), (q & 7) >> 1) + 8 * (q & 1);
-    // split the window into the two planes at the window's own scale;
-    // returns that scale's exponent
-    auto put = [&](const f32x4 v[5]) -> int {
+    // split the window into the two planes at the window's own scale; sets
+    // that scale's exponent and the check's threshold (zero for a window with
+    // no nonzero finite cell, whose outputs are exact)
+    auto put = [&](const f32x4 v[5], int& ex_out, float& thr) {
         float mx = 0.f;
 #pragma unroll
         for (int j = 0; j < 5; ++j)
@@ -435,7 +558,8 @@ void k_prop1d_il(const PropSeg* __restrict__ segs, uint32_t nblocks, uint32_t bp
             *reinterpret_cast<u32x2*>(p) = u32x2{h0, h1};
             *reinterpret_cast<u32x2*>(p + kWPlane) = u32x2{l0, l1};
         }
-        return ex;
+        ex_out = ex;
+        thr = mx > 0.f ? chk : 0.f;
     };
     auto fetch = [&](int k, f32x4 v[5]) {
         const uint32_t b = w + (uint32_t)k * nw;
@@ -493,7 +617,9 @@ void k_prop1d_il(const PropSeg* __restrict__ segs, uint32_t nblocks, uint32_t bp
             if (k >= nk) break;
             // block k (fetched two iterations ago) takes the window, then
             // block k + 2 is fetched into the registers it leaves
-            const int ex = put(St[u]);
+            int ex;
+            float thr;
+            put(St[u], ex, thr);
             __builtin_amdgcn_sched_barrier(0);
             fetch(k + 2 < nk ? k + 2 : nk - 1, St[u]);
             __builtin_amdgcn_sched_barrier(0);
@@ -517,9 +643,16 @@ void k_prop1d_il(const PropSeg* __restrict__ segs, uint32_t nblocks, uint32_t bp
                 bh = nh;
                 bl = nl;
             }
-            // the outputs leave through the window, whose reads are all issued
+            // the outputs leave through the window, whose reads are all issued;
+            // a block that fails the check is stepped instead
             __builtin_amdgcn_sched_barrier(0);
-            store(k, acc, ex);
+            if (block_fails(acc, thr)) {
+                const uint32_t b = w + (uint32_t)k * nw;
+                const uint32_t sg = b / bps;
+                fix_append(fix, sg, b - sg * bps);
+            } else {
+                store(k, acc, ex);
+            }
         }
     }
 }
@@ -564,26 +697,36 @@ int prop1d_waves_per_cu(int D, int skip, bool il) {
     return blocks > 0 ? blocks : 1;
 }
 
+static hipError_t launch_fix(const PropSeg* segs_dev, uint32_t* fix, int D, hipStream_t stream) {
+    void* args[] = {&segs_dev, &fix, &D};
+    return hipLaunchKernel(reinterpret_cast<const void*>(&k_prop1d_fix), dim3(kPropFixWaves),
+                           dim3(64), args, 0, stream);
+}
+
 hipError_t launch_prop1d(const PropSeg* segs_dev, const PropWave* waves_dev, int64_t nwaves, int D,
-                         int skip, hipStream_t stream) {
+                         int skip, uint32_t* fix, hipStream_t stream) {
     int OD = 0, NC = 0;
     const void* k = prop1d_kernel(D, skip);
-    if (!k || !prop1d_geometry(D, &OD, &NC) || nwaves <= 0 || nwaves >= (int64_t(1) << 31))
+    if (!k || !fix || !prop1d_geometry(D, &OD, &NC) || nwaves <= 0 ||
+        nwaves >= (int64_t(1) << 31))
         return hipErrorInvalidValue;
-    void* args[] = {&segs_dev, &waves_dev, &D, &OD};
-    return hipLaunchKernel(k, dim3((unsigned)nwaves), dim3(64), args, 0, stream);
+    void* args[] = {&segs_dev, &waves_dev, &D, &OD, &fix};
+    hipError_t e = hipLaunchKernel(k, dim3((unsigned)nwaves), dim3(64), args, 0, stream);
+    return e != hipSuccess ? e : launch_fix(segs_dev, fix, D, stream);
 }
 
 hipError_t launch_prop1d_il(const PropSeg* segs_dev, int64_t nblocks, int64_t bps, int64_t nwaves,
-                            int D, int skip, hipStream_t stream) {
+                            int D, int skip, uint32_t* fix, hipStream_t stream) {
     int OD = 0, NC = 0;
     const void* k = prop1d_kernel(D, skip, true);
-    if (!k || !prop1d_geometry(D, &OD, &NC) || nblocks <= 0 || nblocks >= (int64_t(1) << 32) ||
-        bps <= 0 || nblocks % bps != 0 || nwaves <= 0 || nwaves > nblocks)
+    if (!k || !fix || !prop1d_geometry(D, &OD, &NC) || nblocks <= 0 ||
+        nblocks >= (int64_t(1) << 32) || bps <= 0 || nblocks % bps != 0 || nwaves <= 0 ||
+        nwaves > nblocks)
         return hipErrorInvalidValue;
     uint32_t nb = (uint32_t)nblocks, bp = (uint32_t)bps;
-    void* args[] = {&segs_dev, &nb, &bp, &D, &OD};
-    return hipLaunchKernel(k, dim3((unsigned)nwaves), dim3(64), args, 0, stream);
+    void* args[] = {&segs_dev, &nb, &bp, &D, &OD, &fix};
+    hipError_t e = hipLaunchKernel(k, dim3((unsigned)nwaves), dim3(64), args, 0, stream);
+    return e != hipSuccess ? e : launch_fix(segs_dev, fix, D, stream);
 }
 
 }  // namespace hx

@@ -815,11 +815,15 @@ hx_status hx::copy_async_locked(Ctx* c, const hx_copy_desc* d, const hx_event* d
             return c->fail(HX_ERR_ARG, "overlapping D2D ranges");
         acc.push_back(a);
         acc.push_back(b);
+        // aligned ranges take the library's one-pass vector copy kernel, the
+        // rest hipMemcpyAsync
+        const bool vec = ((reinterpret_cast<uintptr_t>(dev) | reinterpret_cast<uintptr_t>(src) |
+                           bytes) & 15u) == 0;
         return c->submit(SC_COMPUTE, deps, ndeps, acc, "copy D2D",
                          [=](hipStream_t st) {
-                             return bytes ? hipMemcpyAsync(dev, src, bytes,
-                                                           hipMemcpyDeviceToDevice, st)
-                                          : hipSuccess;
+                             if (!bytes) return hipSuccess;
+                             if (vec) return launch_copy16(dev, src, bytes, st);
+                             return hipMemcpyAsync(dev, src, bytes, hipMemcpyDeviceToDevice, st);
                          },
                          out);
     }

@@ -212,18 +212,74 @@ def test_autograd_function(ctx):
         assert rel_l2(k.grad.cpu().double().numpy(), ref[2]) <= tol
 
 
-def test_full_size_fp32_against_fp64(ctx):
+def full_size_windows(ny, nx, T):
+    """Oracle windows over the 8192^2 grid (a cell is exact 2T inside every cut:
+    T forward and T adjoint steps): the four corners (a (4T+1)^2 window each,
+    whose (2T+1)^2 corner block is exact), the four edge midpoints (2T+1 cells
+    each), four cells where the kernel's 64-row chunks and 256-column strips
+    meet, and four seeded interior cells (a (4T+21)^2 window each: its 21 x 21
+    centre)."""
+    m = 4 * T + 1
+    h = 2 * T
+    wins = [(0, 0, m, m), (0, nx - m, m, m), (ny - m, 0, m, m), (ny - m, nx - m, m, m),
+            (0, nx // 2 - h, m, m), (ny - m, nx // 2 - h, m, m), (ny // 2 - h, 0, m, m),
+            (ny // 2 - h, nx - m, m, m)]
+    c = 4 * T + 21
+    centres = [(64 * 37, 256 * 5), (64 * 100, 256 * 17), (64 * 7 + 1, 256 * 29 - 1),
+               (64 * 120 - 1, 256 * 3 + 1)]
+    rng = np.random.default_rng(23)
+    centres += [(int(rng.integers(c, ny - c)), int(rng.integers(c, nx - c))) for _ in range(4)]
+    wins += [(y - c // 2, x - c // 2, c, c) for y, x in centres]
+    return wins
+
+
+def test_full_size_against_oracle_windows(ctx):
     """8192^2, 100 steps, dt = 0.2, log-normal kappa clipped at 1, S = 10: the
-    FP32 gradients against the FP64 GPU path (pinned to the oracle at small
-    sizes), and the FP64 path's directional finite difference."""
+    FP32 and FP64 gradients of the full run against the FP64 oracle cell by
+    cell, on the oracle's light-cone windows (each window is an exact
+    sub-problem for its cells 2T inside its cuts): corners, edges, the
+    kernel's row-chunk and strip seams and random cells.  Also the FP32 run
+    against the FP64 run on the whole grid, and the FP64 run's directional
+    finite difference (exact in u0 for this quadratic loss, O(eps^2) in
+    kappa)."""
     spec = workloads.VarCoef2D()
     u0, kappa, y = workloads.varcoef2d_inputs(spec)
+    u0, kappa, y = u0.astype(np.float64), kappa.astype(np.float64), y.astype(np.float64)
+    T = spec.steps
     res = {}
     for dt_ in (np.float64, np.float32):
-        res[dt_] = gpu_grad(ctx, u0.astype(np.float64), kappa.astype(np.float64),
-                            y.astype(np.float64), spec.dt, spec.steps, spec.ckpt, dt_)
+        res[dt_] = gpu_grad(ctx, u0, kappa, y, spec.dt, T, spec.ckpt, dt_)
+    refs_l, refs_g = [], []
+    got = {dt_: ([], []) for dt_ in res}
+    for w in full_size_windows(spec.ny, spec.nx, T):
+        (r0, r1), (c0, c1), wl, wg = oracle.heatvc_grad_window(u0, kappa, y, spec.dt, T, *w)
+        refs_l.append(wl.ravel())
+        refs_g.append(wg.ravel())
+        for dt_, (_, lam, gk) in res.items():
+            got[dt_][0].append(lam[r0:r1, c0:c1].ravel())
+            got[dt_][1].append(gk[r0:r1, c0:c1].ravel())
+    rl, rg = np.concatenate(refs_l), np.concatenate(refs_g)
+    for dt_ in res:
+        gl, gg = np.concatenate(got[dt_][0]), np.concatenate(got[dt_][1])
+        e = (rel_l2(gl, rl), rel_max(gl, rl), rel_l2(gg, rg), rel_max(gg, rg))
+        print(f"full size {dt_.__name__} vs oracle windows ({rl.size} cells): lam0 rel L2 "
+              f"{e[0]:.2e} max {e[1]:.2e}, dL/dkappa rel L2 {e[2]:.2e} max {e[3]:.2e}")
+        assert e[0] <= TOL[dt_] and e[2] <= TOL[dt_], e
+        assert e[1] <= 10 * TOL[dt_] and e[3] <= 10 * TOL[dt_], e
     l64, lam64, gk64 = res[np.float64]
     l32, lam32, gk32 = res[np.float32]
     e = (abs(l32 - l64) / l64, rel_l2(lam32, lam64), rel_l2(gk32, gk64))
     print(f"full size fp32 vs fp64: loss {e[0]:.2e} lam0 {e[1]:.2e} gk {e[2]:.2e}")
     assert max(e) <= 1e-5
+    # directional finite difference of the FP64 run
+    du = workloads.uniform(u0.shape, 615, 0, -1, 1)
+    dk = workloads.uniform(u0.shape, 615, 1, -1, 1) * 0.01
+    eps = 1e-4
+    lp = gpu_grad(ctx, u0 + eps * du, kappa + eps * dk, y, spec.dt, T, spec.ckpt,
+                  np.float64)[0]
+    lm = gpu_grad(ctx, u0 - eps * du, kappa - eps * dk, y, spec.dt, T, spec.ckpt,
+                  np.float64)[0]
+    fd = (lp - lm) / (2 * eps)
+    an = float(np.sum(lam64 * du) + np.sum(gk64 * dk))
+    print(f"full size fp64 directional derivative: analytic {an:.10e} fd {fd:.10e}")
+    assert abs(fd - an) <= 1e-6 * abs(an)

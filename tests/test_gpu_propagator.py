@@ -13,7 +13,11 @@ Covered:
 - the plan rejects segments the form cannot take, and AUTO falls back to the
   direct form for them;
 - the full-size headline form (2^28 cells, 64 partition views of one arena,
-  50 steps), sampled.
+  50 steps), every cell against the oracle;
+- the accuracy check after the products: spikes up to 1e30 on U[0,1],
+  windows spanning 20 orders of magnitude, zero crossings and NaN/inf input
+  cells, each cell against the oracle (blocks that fail the check are
+  stepped).
 
 The FP32 bar is the suite's: 1e-5 relative (L2 and per cell) against FP64."""
 import numpy as np
@@ -188,11 +192,11 @@ def test_auto_takes_the_propagator_where_every_segment_fits(ctx):
     assert not np.array_equal(prop, direct)  # a different evaluation, same result to f32
 
 
-def test_full_size_headline_form_sampled(ctx):
+def test_full_size_headline_form_every_cell(ctx):
     """2^28 fp32 cells as 64 partition views of one HBM arena, r = 0.25,
     50 steps as one propagator launch (halos of 52 cells from the neighbour
-    views); sampled cells against the oracle's light cone, including the seams
-    of a few partitions."""
+    views): the whole array against the oracle's serial FP64 run (about 8 s on
+    one core), 1e-5 relative L2 and 1e-5 of itself in every cell."""
     n, parts, T, r, hw = 1 << 28, 64, 50, 0.25, 52
     spec = workloads.Partitioned1D()
     hin = hx.hx_host_alloc(ctx, n * 4)
@@ -220,17 +224,15 @@ def test_full_size_headline_form_sampled(ctx):
     assert hx.hx_wait(ctx, ev) == hx.HX_OK, hx.hx_last_error(ctx)
     hx.hx_event_release(ctx, ev)
     hx.hx_plan_destroy(ctx, plan)
-    rng = np.random.default_rng(19)
-    seams = [k << 22 for k in (1, 17, 63)]
-    idx = np.sort(np.concatenate([rng.choice(n, 40, replace=False), [0, 1, n - 2, n - 1],
-                                  [s + d for s in seams for d in (-52, -2, -1, 0, 1, 51)]]))
-    ref = oracle.heat1d_periodic_at(u0.astype(np.float64), r, T, idx)
-    got = np.array([download(ctx, arena_b, 1, np.float32, offset=int(i) * 4)[0] for i in idx],
-                   dtype=np.float64)
-    assert np.max(np.abs(got - ref) / np.abs(ref)) <= 1e-5
+    got = download(ctx, arena_b, n, np.float32)
+    ref = oracle.heat1d_periodic(u0.astype(np.float64), r, T)
     for b in A + B + [arena_a, arena_b]:
         hx.hx_buffer_destroy(ctx, b)
     hx.hx_host_free(ctx, hin)
+    err2 = rel_l2(got, ref)
+    errc = float(np.max(np.abs(got - ref) / np.abs(ref)))
+    print(f"full 2^28 array vs oracle: rel L2 {err2:.3e}, max per cell {errc:.3e}")
+    assert err2 <= 1e-5 and errc <= 1e-5
 
 
 @pytest.mark.parametrize("D,n,count", [(1, 1028, 5), (20, 4108, 7), (50, 30000, 3),
@@ -313,29 +315,24 @@ def test_interleaved_walk_rejections(ctx):
     hx.hx_buffer_destroy(ctx, c)
 
 
-def test_interleaved_scaling_extreme_magnitudes(ctx):
-    """Every window of the interleaved walk takes its own power-of-two scale:
-    segments of U[0,1] times 1e-30, 1, 1e30, a segment with a spike of 1e6 on
-    a U[0,1] background, one of zeros and one of negative values all match the
-    oracle (each against its own magnitude), and zeros stay exact zeros."""
-    n, D, r = 8192, 50, 0.25
-    base = [workloads.uniform(n, 512, k, 0, 1, np.float64) for k in range(6)]
-    vals = [base[0] * 1e-30, base[1], base[2] * 1e30, base[3].copy(), np.zeros(n),
-            -base[5]]
-    vals[3][4000] = 1e6
+def run_segments(ctx, vals, r, D, span):
+    """Periodic segments holding `vals` (f32), one propagator pass walked
+    interleaved (span = -1, segments of one size) or in spans; returns the
+    f32 inputs and outputs per segment."""
+    n = len(vals[0])
     offs, o = [], GUARD
     for _ in vals:
         offs.append(o)
         o += n + GUARD
     u = np.full(o, -7.0, dtype=np.float32)
     for v, o in zip(vals, offs):
-        u[o:o + n] = v.astype(np.float32)
+        u[o:o + n] = np.asarray(v).astype(np.float32)
     bin_ = upload(ctx, u)
     bout = upload(ctx, np.full(u.size, -7.0, dtype=np.float32))
     segs = [hx.segment(inp=bin_, in_offset=o * 4, out=bout, out_offset=o * 4, n=n, r=r,
                        bc_lo=hx.HX_BC_PERIODIC, bc_hi=hx.HX_BC_PERIODIC) for o in offs]
     plan = hx.hx_plan_create_batched(ctx, hx.HX_F32, D, segs, hx.HX_BATCH_PERSISTENT,
-                                     form=hx.HX_FORM_PROPAGATOR, span_blocks=-1)
+                                     form=hx.HX_FORM_PROPAGATOR, span_blocks=span)
     ev = hx.hx_launch_batched(ctx, plan)
     assert hx.hx_wait(ctx, ev) == hx.HX_OK, hx.hx_last_error(ctx)
     hx.hx_event_release(ctx, ev)
@@ -343,43 +340,108 @@ def test_interleaved_scaling_extreme_magnitudes(ctx):
     out = download(ctx, bout, u.size, np.float32)
     hx.hx_buffer_destroy(ctx, bin_)
     hx.hx_buffer_destroy(ctx, bout)
-    for k, o in enumerate(offs):
-        got = out[o:o + n].astype(np.float64)
-        ref = oracle.heat1d_periodic(u[o:o + n].astype(np.float64), r, D)
+    mask = np.ones(u.size, bool)
+    for o in offs:
+        mask[o:o + n] = False
+    assert np.all(out[mask] == -7.0)  # guards untouched
+    return [u[o:o + n] for o in offs], [out[o:o + n] for o in offs]
+
+
+def envelope(u, r, D):
+    """sum_j |p_j| |u_{i+j}| on a periodic segment: the scale of f32 rounding in
+    an output, which stepping and the propagator form both keep to."""
+    taps = np.asarray(hx.hx_propagator_coefficients(r, D), np.float64)
+    a = np.abs(np.asarray(u, np.float64))
+    env = np.zeros(a.size)
+    for j in range(-D, D + 1):
+        env += abs(taps[j + D]) * np.roll(a, -j)
+    return env
+
+
+def per_cell(got, ref):
+    """Largest per-cell relative error |got - ref| / |ref| (cells with ref = 0
+    must be exact)."""
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    nz = ref != 0
+    assert np.all(got[~nz] == 0.0)
+    return float(np.max(np.abs(got[nz] - ref[nz]) / np.abs(ref[nz]))) if nz.any() else 0.0
+
+
+@pytest.mark.parametrize("span", [-1, 5])
+@pytest.mark.parametrize("spike", [1e6, 1e8, 1e10, 1e30])
+def test_spikes_keep_every_cell_to_f32(ctx, span, spike):
+    """U[0,1] segments with spikes many orders of magnitude above the
+    background: every cell, near the spike or not, matches the oracle to 1e-5
+    of itself (of the magnitude envelope sum_j |p_j u_{i+j}| next to a negative
+    spike, where the outputs cross zero and stepping in f32 is no closer).  The spikes sit inside a block, at a block boundary (so two
+    windows hold them) and next to the periodic seam; without the accuracy
+    check, cells more than D away from a 1e8 spike lost up to 1e-4 of
+    themselves to the fp16 split's window scale, and 1e10 about 1e-2."""
+    n, D, r = 8192, 50, 0.25
+    vals = [workloads.uniform(n, 513, k, 0, 1, np.float64) for k in range(4)]
+    vals[0][3000] = spike
+    vals[1][1024] = spike
+    vals[1][1023] = spike / 3
+    vals[2][n - 2] = spike
+    vals[3][5000] = -spike
+    u, out = run_segments(ctx, vals, r, D, span)
+    for k in range(4):
+        ref = oracle.heat1d_periodic(u[k].astype(np.float64), r, D)
+        if k < 3:
+            err = per_cell(out[k], ref)
+        else:  # a negative spike on positive data: outputs cross zero near it
+            err = np.max(np.abs(out[k] - ref) / envelope(u[k], r, D))
+        assert err <= 1e-5, (k, spike, span, err)
+
+
+@pytest.mark.parametrize("span", [-1, 5])
+def test_wide_dynamic_range_and_mixed_signs(ctx, span):
+    """A steep exponential (e^-i/24 down to about 1e-37, so each window spans
+    about 20 orders of magnitude), U[0,1] times 1e-30, 1 and 1e30, zeros, and
+    a sign-alternating field: every cell matches the oracle to 1e-5 of
+    sum_j |p_j u_{i+j}| (of itself where the data are of one sign), and zeros
+    stay exact zeros."""
+    n, D, r = 2048, 50, 0.25
+    i = np.arange(n, dtype=np.float64)
+    base = [workloads.uniform(n, 514, k, 0, 1, np.float64) for k in range(6)]
+    vals = [np.exp(-i / 24.0), base[0] * 1e-30, base[1], base[2] * 1e30, np.zeros(n),
+            base[5] * np.where(i % 2 == 0, 1.0, -1.0)]
+    u, out = run_segments(ctx, vals, r, D, span)
+    for k in range(len(vals)):
+        ref = oracle.heat1d_periodic(u[k].astype(np.float64), r, D)
         if k == 4:
-            assert np.all(got == 0.0)
+            assert np.all(out[k] == 0.0)
             continue
-        assert rel_l2(got, ref) <= 1e-5 and rel_max(got, ref) <= 1e-5, k
-        if k != 3:  # homogeneous magnitudes: every cell to 1e-5 of itself
-            assert np.max(np.abs(got - ref) / np.abs(ref)) <= 1e-5, k
+        env = envelope(u[k], r, D)
+        got = out[k].astype(np.float64)
+        big = env > 1e-35  # clear of f32's subnormal range
+        err = np.max(np.abs(got[big] - ref[big]) / env[big])
+        assert err <= 1e-5, (k, span, err)
+        if k < 4:
+            assert per_cell(got[big], ref[big]) <= 1e-5, k
 
 
-def test_interleaved_non_finite_cell_stays_in_its_windows(ctx):
-    """A NaN input cell is left out of its window's scale: it reaches outputs
-    within the windows that hold it (at most 64 + 32 cells away at D = 50)
-    and no others; every other cell of the segment matches the oracle run on
-    the same input with that cell set to zero, outside the reach."""
-    n, D, r, bad = 16384, 50, 0.25, 5000
-    u, _, offs = periodic_batch(ctx, [n], [r], D, hx.HX_FORM_PROPAGATOR, span=-1, seed=71)
-    o = offs[0]
-    u[o + bad] = np.nan
-    bin_ = upload(ctx, u)
-    bout = upload(ctx, np.full(u.size, -7.0, dtype=np.float32))
-    seg = hx.segment(inp=bin_, in_offset=o * 4, out=bout, out_offset=o * 4, n=n, r=r,
-                     bc_lo=hx.HX_BC_PERIODIC, bc_hi=hx.HX_BC_PERIODIC)
-    plan = hx.hx_plan_create_batched(ctx, hx.HX_F32, D, [seg], hx.HX_BATCH_PERSISTENT,
-                                     form=hx.HX_FORM_PROPAGATOR, span_blocks=-1)
-    ev = hx.hx_launch_batched(ctx, plan)
-    assert hx.hx_wait(ctx, ev) == hx.HX_OK, hx.hx_last_error(ctx)
-    hx.hx_event_release(ctx, ev)
-    hx.hx_plan_destroy(ctx, plan)
-    got = download(ctx, bout, u.size, np.float32)[o:o + n]
-    hx.hx_buffer_destroy(ctx, bin_)
-    hx.hx_buffer_destroy(ctx, bout)
-    clean = u[o:o + n].astype(np.float64)
-    clean[bad] = 0.0
-    ref = oracle.heat1d_periodic(clean, r, D)
-    far = np.abs(np.arange(n) - bad) > 64 + 32
-    assert np.all(np.isfinite(got[far]))
-    assert rel_max(got[far], ref[far]) <= 1e-5
-    assert np.isnan(got[bad])
+@pytest.mark.parametrize("span", [-1, 5])
+def test_non_finite_cells_reach_what_stepping_reaches(ctx, span):
+    """NaN, +inf and -inf input cells: the outputs that are NaN, +inf or -inf
+    are exactly those of the oracle's stepping (within D cells of each such
+    cell), and every finite output matches the oracle to 1e-5 of itself,
+    right up to the edge of that reach."""
+    n, D, r = 16384, 50, 0.25
+    vals = [workloads.uniform(n, 515, k, 0, 1, np.float64) for k in range(3)]
+    vals[0][5000] = np.nan
+    vals[1][1024] = np.inf
+    vals[1][9000] = -np.inf
+    vals[2][30] = np.nan
+    vals[2][n - 1] = np.inf
+    u, out = run_segments(ctx, vals, r, D, span)
+    for k in range(3):
+        ref = oracle.heat1d_periodic(u[k].astype(np.float64), r, D)
+        got = out[k].astype(np.float64)
+        assert np.array_equal(np.isnan(got), np.isnan(ref)), k
+        assert np.array_equal(np.isposinf(got), np.isposinf(ref)), k
+        assert np.array_equal(np.isneginf(got), np.isneginf(ref)), k
+        fin = np.isfinite(ref)
+        assert np.isfinite(ref).sum() < n  # the reach is not empty
+        assert per_cell(got[fin], ref[fin]) <= 1e-5, k

@@ -103,3 +103,28 @@ def test_zero_steps():
     loss, lam0, gk = oracle.heatvc_grad(u0, np.ones((4, 5)) * 0.1, y, 0.2, 0)
     assert loss == oracle.loss(u0, y)
     assert np.array_equal(lam0, u0 - y) and not gk.any()
+
+
+@pytest.mark.parametrize("win", [(0, 0, 40, 40), (20, 25, 37, 37), (50, 0, 60, 45),
+                                 (-5, 60, 50, 40), (10, 10, 45, 38)])
+def test_window_equals_whole_grid_inside_its_cone(win):
+    """The light-cone window of the gradient (used to check full-size runs
+    cell by cell): on its cells 2T inside every cut it returns the whole
+    grid's lam0 and dL/dkappa bit for bit; the cells just outside that band
+    differ, so the band is not wider than it must be."""
+    ny, nx, dt, T = 90, 100, 0.2, 6
+    kappa = _kappa(ny, nx, 5)
+    u0 = workloads.gaussian_bumps(ny, nx, 5, 8.0, 112, np.float64)
+    y = workloads.uniform((ny, nx), 112, 1)
+    _, lam, gk = oracle.heatvc_grad(u0, kappa, y, dt, T)
+    (r0, r1), (c0, c1), wl, wg = oracle.heatvc_grad_window(u0, kappa, y, dt, T, *win)
+    assert wl.shape == (r1 - r0, c1 - c0) and wl.size > 0
+    assert np.array_equal(wl, lam[r0:r1, c0:c1])
+    assert np.array_equal(wg, gk[r0:r1, c0:c1])
+    y0, x0, hy, hx = win
+    if y0 > 0:  # one row closer to the top cut than allowed is wrong
+        big = oracle.heatvc_grad(u0[y0:y0 + hy, max(x0, 0):x0 + hx],
+                                 kappa[y0:y0 + hy, max(x0, 0):x0 + hx],
+                                 y[y0:y0 + hy, max(x0, 0):x0 + hx], dt, T)[1]
+        row = r0 - y0 - 1
+        assert not np.array_equal(big[row], lam[r0 - 1, max(x0, 0):x0 + hx])
