@@ -265,14 +265,15 @@ def main():
                     help="compute streams of the context (the per-partition graph spreads its "
                          "nodes over them)")
     ap.add_argument("--legs",
-                    default="graph,plain,pipeline,pipeline2d,batched,fp64,2d,adjoint,overhead,copy,"
+                    default="graph,plain,pipeline2d,batched,fp64,2d,adjoint,overhead,copy,"
                             "cpu",
-                    help="comma list of side legs: graph (the per-partition future graph), "
-                         "plain, pipeline, pipeline2d (16384^2 bands host to host, 200 steps), "
+                    help="comma list of side legs (the host-to-host run and the host-link "
+                         "rates always run): graph (the per-partition future graph), "
+                         "plain, pipeline2d (16384^2 bands host to host, 200 steps), "
                          "batched, fp64 (2^20 fp64, 100 steps), 2d (16384^2, "
-                         "200 steps, 16 bands), adjoint (8192^2, 100 steps), copy (a zero-step "
-                         "pass over the arena: a plain 1 GiB device copy, for counter "
-                         "calibration), overhead (the partition benchmark of 2^21..2^28 "
+                         "200 steps, 16 bands), adjoint (8192^2, 100 steps), copy (a one-pass "
+                         "1 GiB device copy: the copy ceiling and the counter calibration), "
+                         "overhead (the partition benchmark of 2^21..2^28 "
                          "doubles with a runtime-compiled kernel, hx futures against raw HIP "
                          "streams), cpu; 'none' runs the headline only")
     args = ap.parse_args()
@@ -355,26 +356,33 @@ def main():
     avg_ms = float(np.mean(durs))
     ms_per_step = sec * 1e3
     value = float(n) * T / sec
-    # sampled correctness of the timed result against the oracle's light cone
-    import oracle
-    steps_done = (args.warmup + args.steps) * T
-    rng = np.random.default_rng(3)
-    idx = np.sort(rng.choice(n, 24, replace=False))
+    # one pass from the initial state, every cell against the oracle (the same
+    # serial FP64 run the CPU baseline times)
+    P.reset()
+    bp = BatchedPass(hx, ctx, P, tb, cpl, fcode, span, hw)
+    bp.run(1)
+    P.wait()
+    bp.close()
     cur = P.current()
-    got = []
-    for i in idx:
-        p = int(i) // P.sizes[0] if n % args.parts == 0 else \
-            next(k for k, (o, s) in enumerate(P.bounds) if o <= i < o + s)
-        v = np.empty(1, np.float32)
-        e = hx.hx_copy_async(ctx, hx.hx_copy_desc(hx.HX_D2H, v.ctypes.data, cur[p],
-                                                  (int(i) - P.bounds[p][0]) * 4, 0, 0, 4))
+    got = np.empty(n, np.float32)
+    evs = [hx.hx_copy_async(ctx, hx.hx_copy_desc(hx.HX_D2H, got[o:].ctypes.data, b, 0, 0, 0,
+                                                 s_ * 4), [P.last])
+           for (o, s_), b in zip(P.bounds, cur)]
+    for e in evs:
         assert hx.hx_wait(ctx, e) == hx.HX_OK
         hx.hx_event_release(ctx, e)
-        got.append(float(v[0]))
+    import oracle
     u0 = np.asarray(P.u0, dtype=np.float64)
-    ref = oracle.heat1d_periodic_at(u0, r, steps_done, idx) if steps_done <= 4000 else None
-    sampled_err = (float(np.max(np.abs(np.array(got) - ref) / np.abs(ref)))
-                   if ref is not None else None)
+    t_or = time.perf_counter()
+    ref = oracle.heat1d_periodic(u0, r, T)
+    t_or = time.perf_counter() - t_or
+    del u0
+    g64 = got.astype(np.float64)
+    full_err = {"rel_l2": float(np.linalg.norm(g64 - ref) / np.linalg.norm(ref)),
+                "max_rel_per_cell": float(np.max(np.abs(g64 - ref) / np.abs(ref))),
+                "cells": n}
+    del g64, got
+    log(f"one pass against the oracle, every cell: {full_err} (oracle {t_or:.2f} s)")
 
     cells_per_launch = float(n)
     bytes_per_launch = cells_per_launch * BYTES_PER_CELL_PASS
@@ -399,7 +407,10 @@ def main():
         else:
             roof = {"bound": "hbm", "achieved": bw / 1e9, "peak": HBM_PEAK / 1e9,
                     "unit": "GB/s", "frac": hbm_frac}
-        roof.update({"mfma_bf16_flops_per_launch": mf_per_launch, "mfma_frac": mfma_frac})
+        mkey = "mfma_fp16_flops_per_launch" if span == -1 else "mfma_bf16_flops_per_launch"
+        roof.update({mkey: mf_per_launch, "mfma_frac": mfma_frac,
+                     "fixup_kernel": "k_prop1d_fix (steps the blocks that fail the accuracy "
+                                     "check; inside the launch's HIP-event span)"})
     else:
         flops_per_launch = cells_per_launch * tb * FLOPS_PER_UPDATE_1D
         fl = flops_per_launch / (avg_ms * 1e-3)
@@ -417,14 +428,31 @@ def main():
                  "hbm_algorithmic_GBps": bw / 1e9, "hbm_frac": hbm_frac,
                  "kernel_source_hash": kernel_source_hash(kform)})
     log(f"headline ({form}): {ms_per_step:.3f} ms/step, {value:.4e} cell-updates/s, kernel avg "
-        f"{avg_ms:.4f} ms, sampled err {sampled_err}")
-    if form == "propagator":
-        form_desc = ("propagator: the 50 steps as one convolution with the 50-step propagator "
-                     "(101 taps, FP64 on the host, rounded to f32), a banded Toeplitz product on "
+        f"{avg_ms:.4f} ms")
+    check = ("; every 1024-cell block checks its outputs against the split's and the "
+             "pruning's absolute error bound and is stepped in f32 by a fix-up kernel when "
+             "an output is non-finite or too small for that bound")
+    if form == "propagator" and span == -1:
+        form_desc = ("propagator, interleaved walk: the 50 steps as one convolution with the "
+                     "50-step propagator (101 taps, FP64 on the host), a banded Toeplitz product "
+                     "on 32x32x16 fp16 matrix-core tiles; each 1152-cell window scaled by a "
+                     "power of two and split into two fp16 terms (hi + lo), the taps likewise, "
+                     "three products per pair (hi*hi, hi*lo, lo*hi) accumulated in f32" + check)
+    elif form == "propagator":
+        form_desc = ("propagator, span walk: the 50 steps as one convolution with the 50-step "
+                     "propagator (101 taps, FP64 on the host), a banded Toeplitz product on "
                      "32x32x16 bf16 matrix-core tiles; every f32 operand split exactly into "
-                     "three bf16 terms, six products per pair accumulated in f32")
+                     "three bf16 terms, six products per pair accumulated in f32" + check)
     else:
-        form_desc = "direct: the tile kernel advancing the 50 steps in registers"
+        form_desc = ("direct: the tile kernel advancing the 50 steps in registers on the vector "
+                     "ALUs (no matrix cores)")
+    # the form without the matrix cores, from the sweep
+    direct_ms = min((v for k_, v in by_form.items() if k_.startswith("direct")), default=None)
+    no_mfma = None if direct_ms is None else {
+        "form": "direct (vector ALUs only)", "ms_per_step": direct_ms,
+        "cell_updates_per_s": float(n) * T / (direct_ms * 1e-3),
+        "hbm_algorithmic_frac": float(n) * BYTES_PER_CELL_PASS / (direct_ms * 1e-3) / HBM_PEAK,
+        "note": "host wall time per 50-step run in the untimed sweep"}
 
     result = {
         "metric": "stencil cell-updates/s + HBM GB/s vs roofline; % copy hidden; batched vs plain",
@@ -432,19 +460,22 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"1D periodic heat stencil, 2^{args.log2n} fp32 cells in "
-                               f"{args.parts} partitions (one HBM arena), r=0.25, 50 steps, "
-                               f"device-resident future graph: one batched launch over all "
+                               f"{args.parts} partitions of 4 Mi cells, r=0.25, 50 steps, "
+                               f"seeded U[0,1] input, with the partitions resident in HBM (one "
+                               f"arena): a future graph of one batched launch over all "
                                f"partitions per {tb}-step pass, halos read from neighbour "
-                               f"partitions",
+                               f"partitions; the same configuration host to host (pinned "
+                               f"partitions, H2D -> kernel -> D2H overlapped) is host_to_host",
                    "cells": n, "parts": args.parts, "time_steps": T, "time_block": tb,
                    "update_form": form_desc,
                    "cells_per_lane": cpl if form == "direct" else None,
                    "span_blocks": ("interleaved walk" if span == -1 else span or "plan's choice")
                    if form == "propagator" else None,
                    "halo_width": hw, "launches_per_step": bp.passes,
-                   "sampled_max_rel_err_vs_oracle": sampled_err},
+                   "error_vs_oracle_every_cell": full_err},
         "roofline": roof,
         "pass_ms_by_form": by_form,
+        "no_mfma": no_mfma,
     }
     hx.hx_event_release(ctx, P.last)
     P.last = 0
@@ -462,8 +493,9 @@ def main():
         log(f"plain: {t_plain * 1e3:.3f} ms/step")
         hx.hx_event_release(ctx, P.last)
         P.last = 0
-    if "pipeline" in legs:
-        result["pipeline"] = pipeline_leg(hx, ctx, P, T, r, cpl)
+    result["host_to_host"] = pipeline_leg(hx, ctx, P, T, r, cpl, ref)
+    del ref
+    result["host_link"] = host_link_leg(hx, P)
     if "pipeline2d" in legs:
         result["pipeline_2d"] = pipeline2d_leg(hx)
     if "copy" in legs:
@@ -481,7 +513,8 @@ def main():
 
     # --------------------------------------------------------------- CPU oracle
     if "cpu" in legs:
-        result["cpu_baseline"] = cpu_leg(r, T)
+        result["cpu_baseline"] = cpu_baseline(n * T / t_or, t_or, n, T)
+        result["oracle_timings"] = oracle_timings()
 
     print(json.dumps(result), flush=True)
     hx.hx_ctx_destroy(ctx)
@@ -596,9 +629,16 @@ def batched_leg(hx, ctx, reps=5):
     return res
 
 
-def pipeline_leg(hx, ctx0, P, T, r, cpl):
-    """Host-to-host run (H2D -> kernel -> D2H per partition) and its overlap, on a
-    context whose default stream set leaves each copy stream a hardware queue."""
+def pipeline_leg(hx, ctx0, P, T, r, cpl, ref):
+    """The headline configuration host to host: the pinned 2^28-cell input is
+    copied in partition by partition, each partition's 50-step kernel waits for
+    its own and its neighbours' copies, and its copy out for its kernel
+    (hx_run_pipeline), on a context whose default stream set leaves each copy
+    stream a hardware queue.  Full runs and copies-only runs (the same graph
+    with zero-step kernels, i.e. 16 MiB device copies) alternate, because the
+    host link's rate drifts by a few percent between runs; every time is a
+    median of nine after a warm-up.  ref: the oracle's result (FP64), against
+    which every cell of the host output is checked."""
     import torch
     ctx = hx.hx_ctx_create(0, timing=True)
     P.wait()
@@ -610,54 +650,46 @@ def pipeline_leg(hx, ctx0, P, T, r, cpl):
     base = hx.partitioned_desc(hx.HX_F32, P.sizes, P.A, P.B, T, r, periodic=True,
                                time_block=T, cells_per_lane=cpl)
     pd = hx.hx_pipeline_desc(base, P.host_in, P.host_out)
-    # the host link's rate drifts between runs: every time is the median of
-    # five runs after a warm-up
-    walls = []
-    spans = None
-    for it in range(6):
-        P.wait()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ev, h2d, ker, d2h = hx.hx_run_pipeline(ctx, pd, op_events=(it == 5))
-        assert hx.hx_wait(ctx, ev) == hx.HX_OK, hx.hx_last_error(ctx)
-        walls.append(time.perf_counter() - t0)
-        if it == 5:
-            ref = h2d[0]
-            spans = {"h2d": [hx.hx_event_span(ctx, e, ref) for e in h2d],
-                     "kernel": [hx.hx_event_span(ctx, e, ref) for e in ker],
-                     "d2h": [hx.hx_event_span(ctx, e, ref) for e in d2h]}
-            for e in h2d + ker + d2h:
-                hx.hx_event_release(ctx, e)
-        hx.hx_event_release(ctx, ev)
-    W = float(np.median(walls[1:]))
-    # correctness of the pipeline output on sampled cells, before anything else
-    # touches host_out
-    import oracle
-    rng = np.random.default_rng(11)
-    idx = np.sort(rng.choice(P.n, 64, replace=False))
-    out = np.ctypeslib.as_array((np.ctypeslib.ctypes.c_float * P.n).from_address(P.host_out))
-    ref = oracle.heat1d_periodic_at(np.asarray(P.u0, dtype=np.float64), r, T, idx)
-    err = float(np.max(np.abs(out[idx] - ref) / np.maximum(np.abs(ref), 1e-30)))
-    # copies alone: the same pipeline with zero steps (its kernels are plain
-    # 16 MiB device copies)
     pd0 = hx.hx_pipeline_desc(hx.partitioned_desc(hx.HX_F32, P.sizes, P.A, P.B, 0, r,
                                                   periodic=True, cells_per_lane=cpl),
                               P.host_in, P.host_out)
-    cw = []
-    for it in range(6):
+
+    def once(desc, spans=False):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ev, _, _, _ = hx.hx_run_pipeline(ctx, pd0)
-        assert hx.hx_wait(ctx, ev) == hx.HX_OK
-        cw.append(time.perf_counter() - t0)
+        ev, h2d, ker, d2h = hx.hx_run_pipeline(ctx, desc, op_events=spans)
+        assert hx.hx_wait(ctx, ev) == hx.HX_OK, hx.hx_last_error(ctx)
+        w = time.perf_counter() - t0
+        sp = None
+        if spans:
+            ref = h2d[0]
+            sp = {"h2d": [hx.hx_event_span(ctx, e, ref) for e in h2d],
+                  "kernel": [hx.hx_event_span(ctx, e, ref) for e in ker],
+                  "d2h": [hx.hx_event_span(ctx, e, ref) for e in d2h]}
+            for e in h2d + ker + d2h:
+                hx.hx_event_release(ctx, e)
         hx.hx_event_release(ctx, ev)
-    t_copy = float(np.median(cw[1:]))
+        return w, sp
+
+    walls, cw = [], []
+    for it in range(10):
+        walls.append(once(pd)[0])
+        cw.append(once(pd0)[0])
+    W, t_copy = float(np.median(walls[1:])), float(np.median(cw[1:]))
+    # the timeline of one more full run, and its output: every cell against the
+    # oracle
+    w_last, spans = once(pd, spans=True)
+    out = np.ctypeslib.as_array((np.ctypeslib.ctypes.c_float * P.n).from_address(P.host_out))
+    o64 = out.astype(np.float64)
+    err = {"rel_l2": float(np.linalg.norm(o64 - ref) / np.linalg.norm(ref)),
+           "max_rel_per_cell": float(np.max(np.abs(o64 - ref) / np.abs(ref))), "cells": P.n}
+    del o64
     # kernels alone: the single-pass device-resident graph
     P.cur_in_a = True
-    t_kernel, _ = time_steps(P, 2, hx.HX_PART_GRAPH, T, cpl)
+    t_kernel, _ = time_steps(P, 3, hx.HX_PART_GRAPH, T, cpl)
     C = intervals_union([tuple(x) for x in spans["h2d"] + spans["d2h"]])
     K = intervals_union([tuple(x) for x in spans["kernel"]])
-    lit = intersect_len(C, K) / measure_len(C)
+    CK = intersect_len(C, K)
     eta = (t_copy + t_kernel - W) / min(t_copy, t_kernel)
     bytes_copied = 2 * P.n * 4
     P.wait()
@@ -666,13 +698,65 @@ def pipeline_leg(hx, ctx0, P, T, r, cpl):
     hx.hx_ctx_destroy(ctx)
     P.ctx, P.A, P.B, P.last = saved
     P.cur_in_a = True
-    res = {"wall_ms": W * 1e3, "copies_alone_ms": t_copy * 1e3, "kernels_alone_ms": t_kernel * 1e3,
-           "pcie_inclusive_cell_updates_per_s": P.n * T / W,
-           "copy_hidden_literal": lit, "overlap_efficiency_eta": eta,
-           "copy_bound_efficiency": t_copy / W,
+    res = {"value": P.n * T / W, "unit": "cell-updates/s (PCIe-inclusive, host to host)",
+           "wall_ms": W * 1e3, "copies_alone_ms": t_copy * 1e3,
+           "kernels_alone_ms": t_kernel * 1e3,
+           "wall_over_copies_alone": W / t_copy,
+           "copy_hidden_literal": CK / measure_len(C),
+           "copy_hidden_literal_bound": min(1.0, measure_len(K) / measure_len(C)),
+           "kernel_time_under_copies": CK / measure_len(K),
+           "overlap_efficiency_eta": eta,
            "host_link_GBps_during_overlap": bytes_copied / (measure_len(C) * 1e-3) / 1e9,
-           "sampled_max_rel_err": err}
-    log(f"pipeline: {res}")
+           "host_link_GBps_whole_run": bytes_copied / W / 1e9,
+           "error_vs_oracle_every_cell": err,
+           "timeline_run_ms": w_last * 1e3,
+           "method": "wall times: host clock around each run, medians of 9 (full and "
+                     "copies-only runs alternating); spans: HIP events of every copy and kernel "
+                     "of the last run (timing context)"}
+    log(f"host to host: {res}")
+    return res
+
+
+def host_link_leg(hx, P, reps=7):
+    """The host link alone: 1 GiB host to device, 1 GiB device to host, and
+    both at once, each as 64 copies of 16 MiB between the pinned arrays and
+    device buffers on the context's copy streams (medians of `reps` after a
+    warm-up)."""
+    import torch
+    ctx = hx.hx_ctx_create(0, timing=True)
+    A = [hx.hx_buffer_create(ctx, s * 4) for s in P.sizes]
+    B = [hx.hx_buffer_create(ctx, s * 4) for s in P.sizes]
+
+    def run(h2d, d2h):
+        evs = []
+        for (o, s_), a, b in zip(P.bounds, A, B):
+            if h2d:
+                evs.append(hx.hx_copy_async(ctx, hx.hx_copy_desc(hx.HX_H2D, P.host_in + o * 4,
+                                                                 a, 0, 0, 0, s_ * 4)))
+            if d2h:
+                evs.append(hx.hx_copy_async(ctx, hx.hx_copy_desc(hx.HX_D2H, P.host_out + o * 4,
+                                                                 b, 0, 0, 0, s_ * 4)))
+        torch.cuda.synchronize()
+        w = hx.hx_when_all(ctx, evs)
+        assert hx.hx_wait(ctx, w) == hx.HX_OK, hx.hx_last_error(ctx)
+        spans = [hx.hx_event_span(ctx, e, evs[0]) for e in evs]
+        for e in evs + [w]:
+            hx.hx_event_release(ctx, e)
+        return max(b_ for _, b_ in spans) - min(a_ for a_, _ in spans)
+
+    res = {}
+    nbytes = P.n * 4
+    for key, h, d in (("h2d_alone", True, False), ("d2h_alone", False, True),
+                      ("both", True, True)):
+        ms = float(np.median([run(h, d) for _ in range(reps + 1)][1:]))
+        moved = nbytes * (2 if key == "both" else 1)
+        res[key] = {"ms": ms, "GBps": moved / (ms * 1e-3) / 1e9}
+    for b in A + B:
+        hx.hx_buffer_destroy(ctx, b)
+    hx.hx_ctx_destroy(ctx)
+    res["method"] = ("HIP events of the copies (first start to last end), 64 x 16 MiB per "
+                     "direction, pinned host memory from hx_host_alloc")
+    log(f"host link: {res}")
     return res
 
 
@@ -957,22 +1041,23 @@ def adjoint_leg(hx, ctx):
 
 
 def copy_leg(hx, ctx, P, reps=5):
-    """Zero-step passes over the whole arena in one launch: a plain device copy
-    of 2^28 fp32 cells (1 GiB read, 1 GiB written), whose HBM counters scale
-    the stencil's."""
-    a = hx.stencil_args(dims=1, dtype=hx.HX_F32, nx=P.n, steps=0, r=0.0, inp=P.arena_a,
-                        out=P.arena_b, cells_per_lane=32, time_block=1)
-    evs = [hx.hx_launch_stencil(ctx, a)]
-    for _ in range(reps - 1):
-        evs.append(hx.hx_launch_stencil(ctx, a, deps=[evs[-1]]))
-    assert hx.hx_wait(ctx, evs[-1]) == hx.HX_OK
-    d = [b - s_ for s_, b in (hx.hx_event_span(ctx, e, e) for e in evs)]
+    """A one-pass device copy of the whole arena (hx_copy_async D2D: the
+    library's vector copy kernel, one 16-byte nontemporal load and store per
+    thread, 4 KiB per workgroup): 1 GiB read and 1 GiB written.  It is the
+    practical HBM ceiling the stencil kernels are held against, and the kernel
+    whose HBM counters scale the stencil's."""
+    d = hx.hx_copy_desc(hx.HX_D2D, 0, P.arena_b, 0, P.arena_a, 0, P.n * 4)
+    evs = [hx.hx_copy_async(ctx, d)]
+    for _ in range(reps):
+        evs.append(hx.hx_copy_async(ctx, d, deps=[evs[-1]]))
+    assert hx.hx_wait(ctx, evs[-1]) == hx.HX_OK, hx.hx_last_error(ctx)
+    dur = [b - s_ for s_, b in (hx.hx_event_span(ctx, e, e) for e in evs)]
     for e in evs:
         hx.hx_event_release(ctx, e)
-    ms = float(np.median(d))
+    ms = float(np.median(dur[1:]))
     nbytes = P.n * 8
-    return {"cells": P.n, "bytes_moved": nbytes, "avg_ms": ms,
-            "GBps": nbytes / (ms * 1e-3) / 1e9}
+    return {"kernel": "k_copy16", "cells": P.n, "bytes_moved": nbytes, "avg_ms": ms,
+            "GBps": nbytes / (ms * 1e-3) / 1e9, "frac_of_peak": nbytes / (ms * 1e-3) / HBM_PEAK}
 
 
 OVERHEAD_SRC = r'''
@@ -1159,21 +1244,82 @@ def overhead_leg(hx, parts=4, iters=11):
             "e1_sequential_stencil": e1_rows}
 
 
-def cpu_leg(r, T):
-    """The oracle, untuned, on one host core over the whole headline workload:
-    a periodic vector of 2^28 cells (the 64 partitions joined) for the full 50
-    steps (about 5-15 s of serial FP64 work)."""
+def host_cpu():
+    """The host's processor model and the CPU counts this process sees."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"cpu_model": model, "nproc": avail, "logical_cpus": os.cpu_count()}
+
+
+def cpu_baseline(value, seconds, n, T):
+    """The oracle, untuned, on one host core over the whole headline workload
+    (timed in main while it checks every cell of one GPU pass)."""
+    return {"value": value, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"the whole workload: periodic vector of {n} cells (the 64 partitions "
+                      f"joined), {T} steps, serial FP64 C oracle, {seconds:.2f} s",
+            **host_cpu()}
+
+
+def oracle_timings():
+    """The serial FP64 oracle on one core over a bounded sample of each of the
+    other workloads (the per-cell work does not depend on the sample's size),
+    in cell-updates/s."""
     import oracle
     import workloads
-    n = 1 << 28
-    u = workloads.partitioned1d_u0(workloads.Partitioned1D(n=n)).astype(np.float64)
-    t0 = time.perf_counter()
-    oracle.heat1d_periodic(u, r, T)
-    dt = time.perf_counter() - t0
-    del u
-    return {"value": n * T / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"the whole workload: periodic vector of 2^28 cells (the 64 partitions "
-                      f"joined), 50 steps, serial FP64 C oracle, {dt:.2f} s"}
+    res = {}
+
+    def timed(fn):
+        t0 = time.perf_counter()
+        fn()
+        return time.perf_counter() - t0
+
+    s1 = workloads.Periodic1D()
+    u = workloads.periodic1d_u0(s1).astype(np.float64)
+    t = timed(lambda: oracle.heat1d_periodic(u, s1.r, s1.steps))
+    res["periodic_fp64"] = {"value": s1.n * s1.steps / t, "seconds": t,
+                            "sample": f"the whole workload: 2^20 cells, {s1.steps} steps"}
+    s3 = workloads.Batched1D()
+    sizes, rs, _ = workloads.batched1d_problems(s3)
+    k = int(np.searchsorted(np.cumsum(sizes), 1 << 26)) + 1
+    u = workloads.batched1d_u0(s3, total=int(sizes[:k].sum())).astype(np.float64)
+    t = timed(lambda: oracle.heat1d_batched(sizes[:k], rs[:k], u, s3.steps))
+    res["batched"] = {"value": float(sizes[:k].sum()) * s3.steps / t, "seconds": t,
+                      "sample": f"the first {k} of {s3.count} problems "
+                                f"({int(sizes[:k].sum())} cells), {s3.steps} steps"}
+    s4 = workloads.Banded2D()
+    rows = 1024
+    u = workloads.gaussian_bumps(rows, s4.nx, 4, s4.sigma, 4, np.float64)
+    st4 = 16
+    t = timed(lambda: oracle.heat2d_dirichlet(u, s4.r, st4))
+    res["banded_2d"] = {"value": rows * s4.nx * st4 / t, "seconds": t,
+                        "sample": f"one band of {rows} x {s4.nx} cells, {st4} steps"}
+    s5 = workloads.VarCoef2D()
+    m = 1024
+    z = workloads.rng(5, 0).standard_normal((m, m))
+    kap = np.minimum(np.exp(s5.mu + s5.sigma_log * z), s5.kappa_max)
+    u0 = workloads.gaussian_bumps(m, m, 4, s5.sigma, 5, np.float64)
+    y = workloads.rng(5, 1).random((m, m))
+    t = timed(lambda: oracle.heatvc_grad(u0, kap, y, s5.dt, s5.steps, s5.ckpt))
+    res["adjoint"] = {"value": m * m * s5.steps / t, "seconds": t,
+                      "unit_note": "forward steps per second of the whole gradient (forward, "
+                                   "checkpointed recompute and adjoint sweep)",
+                      "sample": f"{m} x {m} cells, {s5.steps} steps, checkpoints every "
+                                f"{s5.ckpt}"}
+    res["cores"] = 1
+    res["unit"] = "cell-updates/s"
+    log(f"oracle timings: {res}")
+    return res
 
 
 if __name__ == "__main__":

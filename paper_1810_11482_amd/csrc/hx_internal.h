@@ -252,7 +252,7 @@ inline int32_t prop1d_tap_exp(const double* p, int D) {
 }
 
 // Waves of the fix-up pass that follows every propagator launch.
-constexpr int kPropFixWaves = 1024;
+constexpr int kPropFixWaves = 512;
 
 // skip: window chunks on each side that no segment of the launch multiplies
 // (level 0 in every segment's mask); at most 2 are dropped from the kernel.

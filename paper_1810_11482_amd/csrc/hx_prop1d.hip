@@ -405,10 +405,13 @@ __global__ __launch_bounds__(64) void k_prop1d(const PropSeg* __restrict__ segs,
 
 // The fix-up pass after either walk: `gridDim.x` waves step the listed
 // blocks (wave w takes entries w, w + grid, ...); the last wave to finish
-// clears the list for the next launch.
+// clears the list for the next launch.  An empty list (the usual case) leaves
+// at once, with no atomic: the waves' completion count is only kept, and the
+// list only cleared, when there was something to step.
 __global__ __launch_bounds__(64) void k_prop1d_fix(const PropSeg* __restrict__ segs,
                                                    uint32_t* fix, int D) {
     const uint32_t n = __atomic_load_n(fix, __ATOMIC_RELAXED);
+    if (n == 0) return;
     for (uint32_t k = blockIdx.x; k < n; k += gridDim.x)
         step_block(segs[fix[2 + 2 * k]], 1024 * (int64_t)fix[3 + 2 * k], D);
     __threadfence();

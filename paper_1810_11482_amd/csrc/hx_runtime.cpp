@@ -11,6 +11,7 @@
 // operation: it is kept on the host and queued from hx_user_event_set.  Failures
 // travel with the events: an operation with a failed dependency never runs and
 // completes with HX_ERR_DEP_FAILED.
+#include "hx_internal.h"
 #include "hx_runtime.hpp"
 
 #include <algorithm>
