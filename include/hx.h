@@ -461,6 +461,23 @@ hx_status hx_launch_dot(hx_ctx ctx, int dtype, int64_t n, hx_buffer a, hx_buffer
                         hx_buffer out64, hx_buffer work, const hx_event* deps, int ndeps,
                         hx_event* out);
 
+/* hx_launch_loss without the `work` buffer, for callers that cannot allocate
+ * device memory (code under graph capture, tight serving loops): it calls no
+ * hipMalloc, hipFree or other allocating routine.  The partial sums go to a
+ * static device array of 4096 doubles (32 KiB) that every GPU the library
+ * runs on holds until the process ends; its device address is looked up once
+ * per device when a context is created.  Same kernels, same result bit for
+ * bit as hx_launch_loss.  Every call on one GPU shares that array: calls that
+ * overlap on one GPU (on different streams, with no event ordering them) race
+ * and give wrong losses, so order them through deps.  Nothing needs clearing
+ * between calls (each call writes every partial it reads).  HX_ERR_RANGE if a
+ * reduction would need more than 4096 partials (never with the library's
+ * grid, capped at 4096 workgroups), HX_ERR_HIP if the array's address could
+ * not be looked up on this device; otherwise as hx_launch_loss. */
+hx_status hx_launch_loss_noalloc(hx_ctx ctx, int dtype, int64_t n, hx_buffer u, hx_buffer y,
+                                 hx_buffer resid, hx_buffer out64, const hx_event* deps,
+                                 int ndeps, hx_event* out);
+
 /* y = x * s with s an FP64 scalar in device memory (out64 of a reduction, or a
  * gradient), and dst = (dtype) src64. */
 hx_status hx_launch_scale(hx_ctx ctx, int dtype, int64_t n, hx_buffer x, hx_buffer s64,

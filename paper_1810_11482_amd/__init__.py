@@ -179,6 +179,9 @@ _PROTOS = {
                                    ctypes.c_int, ctypes.POINTER(_u64)]),
     "hx_launch_loss": (_i32, [_vp, ctypes.c_int, _i64, _u64, _u64, _u64, _u64, _u64,
                               ctypes.POINTER(_u64), ctypes.c_int, ctypes.POINTER(_u64)]),
+    "hx_launch_loss_noalloc": (_i32, [_vp, ctypes.c_int, _i64, _u64, _u64, _u64, _u64,
+                                      ctypes.POINTER(_u64), ctypes.c_int,
+                                      ctypes.POINTER(_u64)]),
     "hx_launch_dot": (_i32, [_vp, ctypes.c_int, _i64, _u64, _u64, _u64, _u64,
                              ctypes.POINTER(_u64), ctypes.c_int, ctypes.POINTER(_u64)]),
     "hx_launch_scale": (_i32, [_vp, ctypes.c_int, _i64, _u64, _u64, _u64,
@@ -540,6 +543,10 @@ def hx_heat_vc_backward(ctx, args: hx_vc_args, deps=()) -> int:
 
 def hx_launch_loss(ctx, dtype, n, u, y, resid, out64, work, deps=()) -> int:
     return _op(ctx, lib.hx_launch_loss, dtype, n, u, y, resid, out64, work, deps=deps)
+
+
+def hx_launch_loss_noalloc(ctx, dtype, n, u, y, resid, out64, deps=()) -> int:
+    return _op(ctx, lib.hx_launch_loss_noalloc, dtype, n, u, y, resid, out64, deps=deps)
 
 
 def hx_launch_dot(ctx, dtype, n, a, b, out64, work, deps=()) -> int:

@@ -234,6 +234,33 @@ hx_status hx_launch_loss(hx_ctx ctx, int dtype, int64_t n, hx_buffer u, hx_buffe
                      out);
 }
 
+hx_status hx_launch_loss_noalloc(hx_ctx ctx, int dtype, int64_t n, hx_buffer u, hx_buffer y,
+                                 hx_buffer resid, hx_buffer out64, const hx_event* deps,
+                                 int ndeps, hx_event* out) {
+    LOCK_CTX(ctx);
+    if (!out) return c->fail(HX_ERR_ARG, "null output event");
+    hx_status s = check_common(c, dtype, n, 1);
+    if (s) return s;
+    if (reduce_blocks(n) > kLossScratch)
+        return c->fail(HX_ERR_RANGE, "the reduction needs more partial sums than the scratch "
+                                     "holds (" + std::to_string(kLossScratch) + ")");
+    double* pw = scratch_of(c->device);
+    if (!pw) return c->fail(HX_ERR_HIP, "the device address of the loss scratch is unknown");
+    const size_t bytes = (size_t)n * esz(dtype);
+    std::vector<Access> acc;
+    char *pu, *py, *pr = nullptr, *po;
+    if ((s = state_range(c, u, bytes, 1, false, &pu, acc))) return s;
+    if ((s = state_range(c, y, bytes, 1, false, &py, acc))) return s;
+    if (resid && (s = state_range(c, resid, bytes, 1, true, &pr, acc))) return s;
+    if ((s = state_range(c, out64, 8, 1, true, &po, acc))) return s;
+    return c->submit(SC_COMPUTE, deps, ndeps, acc, "loss (no allocation)",
+                     [=](hipStream_t st) {
+                         return launch_reduce(dtype, 0, pu, py, pr, n, pw,
+                                              reinterpret_cast<double*>(po), st);
+                     },
+                     out);
+}
+
 hx_status hx_launch_dot(hx_ctx ctx, int dtype, int64_t n, hx_buffer a, hx_buffer b,
                         hx_buffer out64, hx_buffer work, const hx_event* deps, int ndeps,
                         hx_event* out) {

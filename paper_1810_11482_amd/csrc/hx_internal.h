@@ -351,6 +351,14 @@ hipError_t launch_cast64(int dtype, const double* src, void* dst, int64_t n, hip
 hipError_t launch_scale(int dtype, const void* x, const double* s, void* out, int64_t n,
                         hipStream_t stream);
 int reduce_blocks(int64_t n);
+// The allocation-free loss's scratch: kLossScratch doubles per device in a
+// static device array.  scratch_init (with `device` current; once per device,
+// from hx_ctx_create) looks up its device address; scratch_of returns it, or
+// nullptr before scratch_init succeeded on that device.
+constexpr int kLossScratch = 4096;
+constexpr int kMaxDevices = 64;
+hipError_t scratch_init(int device);
+double* scratch_of(int device);
 // mode 0: out = 0.5 sum (a-b)^2 (resid = a - b if non-null); mode 1: out = sum a*b.
 hipError_t launch_reduce(int dtype, int mode, const void* a, const void* b, void* resid, int64_t n,
                          double* partial, double* out, hipStream_t stream);

@@ -601,6 +601,9 @@ hx_status hx_ctx_create(int dev, const hx_ctx_opts* opts, hx_ctx* out) {
         c->h2d = c->ncompute;
         c->d2h = c->ncompute + 1;
         c->stream_tail.assign(c->streams.size(), 0);
+        // the device address of the allocation-free loss's scratch (an error
+        // here only disables that entry point, which then reports it)
+        if (hx::scratch_init(dev) != hipSuccess) hipGetLastError();
     }
     *out = reinterpret_cast<hx_ctx>(c);
     return HX_OK;

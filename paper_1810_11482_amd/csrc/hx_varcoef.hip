@@ -20,6 +20,8 @@
 // cells just outside the strip are loaded per row by lanes 0 and 63.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "hx_internal.h"
 
 namespace hx {
@@ -458,6 +460,36 @@ hipError_t launch_scale(int dtype, const void* x, const double* s, void* out, in
 }
 
 int reduce_blocks(int64_t n) { return (int)grid_for(n); }
+
+// Scratch of the allocation-free loss (hx_launch_loss_noalloc): the partial
+// sums of one reduction, one per workgroup (grid_for caps the grid at
+// kLossScratch).  Every GPU the library runs on holds its own copy until the
+// process ends.  Host code never uses the array's name as an address: it uses
+// the device address that hipGetSymbolAddress returns, once per device, with
+// that device current (scratch_init, from hx_ctx_create).
+static __device__ __align__(256) double scratch[kLossScratch];
+
+namespace {
+std::mutex scratch_mu;
+double* scratch_dev[kMaxDevices];  // per device: the address of `scratch` there
+}  // namespace
+
+hipError_t scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (scratch_dev[device]) return hipSuccess;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return e != hipSuccess ? e : hipErrorInvalidSymbol;
+    scratch_dev[device] = static_cast<double*>(p);
+    return hipSuccess;
+}
+
+double* scratch_of(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    return scratch_dev[device];
+}
 
 hipError_t launch_reduce(int dtype, int mode, const void* a, const void* b, void* resid, int64_t n,
                          double* partial, double* out, hipStream_t st) {
