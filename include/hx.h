@@ -322,7 +322,8 @@ typedef struct {
                                    tile; 0 = tuned (one wave per tile if untuned) */
     int form;                   /* hx_batch_form; 0 = DIRECT */
     int span_blocks;            /* PROPAGATOR: how waves walk the blocks of 1024 cells.  > 0 =
-                                   contiguous spans of that many blocks per wave; -1 = the
+                                   contiguous spans of that many blocks per wave (at most
+                                   256, else HX_ERR_ARG); -1 = the
                                    interleaved walk (a persistent grid, wave w taking blocks
                                    w, w + grid, ... of all segments numbered back to back;
                                    HX_ERR_ARG unless every segment has the same n and r);
@@ -350,7 +351,8 @@ hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* desc, hx_plan*
  * against the bound E of those absolute terms: unless every output is finite
  * and at least 2^21 E times the largest finite |x| of the block's window (E
  * is a few 2^-32 of the tap mass at r = 1/4, steps = 50), the block is
- * recomputed by f32 stepping in a second kernel of the same launch.  Each
+ * advanced by f32 stepping instead, in the same launch (by its wave, after
+ * the wave's other blocks).  Each
  * output is then either within a few 2^-22 of sum_j |p_j u_{i+j}| plus 2^-21
  * of itself, or the stepped f32 result: f32 accuracy cell by cell, also next
  * to cells many orders of magnitude larger, and a non-finite input cell
@@ -360,9 +362,7 @@ hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* desc, hx_plan*
  * halo_width >= 4 * ceil(steps / 4); n is a multiple of 4; and in, out, the
  * end of the left halo and the start of the right halo are 16-byte aligned.
  * Results agree with stepping to f32 rounding (not bit for bit, and not
- * between the two walks).  The plan keeps a list of the blocks to recompute
- * in device memory, so its launches are serialised on the GPU (each waits for
- * the previous one); two plans never share it. */
+ * between the two walks). */
 
 /* Run a batch plan once after `deps`. */
 hx_status hx_launch_batched(hx_ctx ctx, hx_plan plan, const hx_event* deps, int ndeps,

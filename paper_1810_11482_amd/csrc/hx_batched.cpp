@@ -51,10 +51,6 @@ struct BatchPlan {
     PropSeg* psegs_dev = nullptr;
     PropWave* pwaves_dev = nullptr;
     float* taps_dev = nullptr;
-    uint32_t* fix_dev = nullptr;   // fix list of the propagator form (launch_prop1d)
-    // recorded after each propagator launch and waited on by the next one, so
-    // that launches of the plan never overlap on its fix list
-    hipEvent_t order_ev = nullptr;
     int64_t pwaves = 0;
     int pskip = 0;         // outer window chunks no segment multiplies
     bool pil = false;      // interleaved walk (segments of one size and one rate)
@@ -80,8 +76,6 @@ void destroy_plan(void* p) {
     if (b->psegs_dev) hipFree(b->psegs_dev);
     if (b->pwaves_dev) hipFree(b->pwaves_dev);
     if (b->taps_dev) hipFree(b->taps_dev);
-    if (b->fix_dev) hipFree(b->fix_dev);
-    if (b->order_ev) hipEventDestroy(b->order_ev);
     delete b;
 }
 
@@ -167,7 +161,8 @@ extern "C" hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* d, 
         return c->fail(HX_ERR_ARG, "bad form");
     if (d->form == HX_FORM_PROPAGATOR && (d->mode != HX_BATCH_PERSISTENT || d->dtype != HX_F32))
         return c->fail(HX_ERR_ARG, "the propagator form needs a PERSISTENT f32 batch");
-    if (d->span_blocks < -1) return c->fail(HX_ERR_ARG, "span_blocks must be >= -1");
+    if (d->span_blocks < -1 || d->span_blocks > kSpanMax)
+        return c->fail(HX_ERR_ARG, "span_blocks must be -1 .. " + std::to_string(kSpanMax));
     hipSetDevice(c->device);
     const size_t es = esz(d->dtype);
     const int vn = vecn(d->dtype);
@@ -349,7 +344,10 @@ extern "C" hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* d, 
         if (bp->pil) {
             bp->pbps = bps;
             bp->pblocks = bps * (int64_t)bp->segs.size();
-            bp->pwaves = std::min<int64_t>(bp->pblocks, slots);
+            // one round of resident waves, unless a wave would then take more
+            // blocks than it can list for stepping
+            bp->pwaves = std::max(std::min<int64_t>(bp->pblocks, slots),
+                                  (bp->pblocks + kIlMax - 1) / kIlMax);
         }
         for (size_t i = 0; i < bp->segs.size() && !bp->pil; ++i)
             for (int64_t b0 = 0; b0 < blocks[i]; b0 += ni) {
@@ -365,13 +363,7 @@ extern "C" hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* d, 
             return c->fail(HX_ERR_RANGE, "the batch has too many propagator waves");
         }
         if (!bp->pil) bp->pwaves = (int64_t)waves.size();
-        int64_t nblk = 0;
-        for (int64_t b : blocks) nblk += b;
-        const size_t fix_bytes = 4 * (size_t)(2 + 2 * nblk);
         bool ok = hipMalloc(&bp->taps_dev, 4 * taps.size()) == hipSuccess &&
-                  hipMalloc(&bp->fix_dev, fix_bytes) == hipSuccess &&
-                  hipMemset(bp->fix_dev, 0, fix_bytes) == hipSuccess &&
-                  hipEventCreateWithFlags(&bp->order_ev, hipEventDisableTiming) == hipSuccess &&
                   hipMalloc(&bp->psegs_dev, sizeof(PropSeg) * bp->segs.size()) == hipSuccess &&
                   (bp->pil ||
                    hipMalloc(&bp->pwaves_dev, sizeof(PropWave) * waves.size()) == hipSuccess);
@@ -508,15 +500,12 @@ extern "C" hx_status hx_launch_batched(hx_ctx ctx, hx_plan plan, const hx_event*
     return c->submit(
         SC_COMPUTE, deps, ndeps, bp->acc, what,
         [bp](hipStream_t st) -> hipError_t {
-            if (bp->prop) {
-                hipError_t e = hipStreamWaitEvent(st, bp->order_ev, 0);
-                if (e != hipSuccess) return e;
-                e = bp->pil ? launch_prop1d_il(bp->psegs_dev, bp->pblocks, bp->pbps, bp->pwaves,
-                                               bp->steps, bp->pskip, bp->fix_dev, st)
-                            : launch_prop1d(bp->psegs_dev, bp->pwaves_dev, bp->pwaves,
-                                            bp->steps, bp->pskip, bp->fix_dev, st);
-                return e != hipSuccess ? e : hipEventRecord(bp->order_ev, st);
-            }
+            if (bp->prop && bp->pil)
+                return launch_prop1d_il(bp->psegs_dev, bp->pblocks, bp->pbps, bp->pwaves,
+                                        bp->steps, bp->pskip, st);
+            if (bp->prop)
+                return launch_prop1d(bp->psegs_dev, bp->pwaves_dev, bp->pwaves, bp->steps,
+                                     bp->pskip, st);
             if (bp->mode == HX_BATCH_PERSISTENT)
                 return launch_stencil1d_batched(bp->dtype, bp->segs_dev, bp->tseg_dev,
                                                 bp->tidx_dev, bp->ntiles, bp->g, bp->grid_waves,

@@ -120,7 +120,7 @@ struct PropSeg {
     // error the split and the pruning can add is at most E times the largest
     // finite |x| of the block's window; a block whose every output y has
     // |y| >= 2^21 E M keeps those terms within 2^-21 |y|, any other block
-    // (or one with a non-finite output) is recomputed by stepping.  Span
+    // (or one with a non-finite output) is advanced by stepping instead.  Span
     // walk: chk = 2^21 E (times the window's M in the kernel); interleaved
     // walk: chk = 2^21 E 2^(15 + texp), the same bound in the scaled units of
     // its products (where M < 2^15).
@@ -251,18 +251,17 @@ inline int32_t prop1d_tap_exp(const double* p, int D) {
     return e;
 }
 
-// Waves of the fix-up pass that follows every propagator launch.
-constexpr int kPropFixWaves = 512;
-
 // skip: window chunks on each side that no segment of the launch multiplies
 // (level 0 in every segment's mask); at most 2 are dropped from the kernel.
-// fix: the plan's fix list in device memory, 2 + 2 x (blocks of the launch)
-// words, zero before the first launch: blocks whose products fail the
-// accuracy check are listed there and stepped by a second kernel on the same
-// stream, which leaves the list cleared.  Launches sharing a list must not
-// overlap.
+// A block whose products fail the accuracy check (PropSeg::chk) is advanced
+// by f32 stepping in the same launch, by its wave after the wave's other
+// blocks: a wave lists at most kSpanMax blocks (span walk: the most blocks a
+// wave walks) or kIlMax (interleaved walk: the grid must have at least
+// ceil(nblocks / kIlMax) waves).
+constexpr int kSpanMax = 256;
+constexpr int kIlMax = 128;
 hipError_t launch_prop1d(const PropSeg* segs_dev, const PropWave* waves_dev, int64_t nwaves, int D,
-                         int skip, uint32_t* fix, hipStream_t stream);
+                         int skip, hipStream_t stream);
 // Waves of that kernel resident per CU (registers and LDS permitting).
 int prop1d_waves_per_cu(int D, int skip, bool il = false);
 // Interleaved walk of the same pass: `nblocks` 1024-cell blocks, bps per
@@ -270,7 +269,7 @@ int prop1d_waves_per_cu(int D, int skip, bool il = false);
 // a persistent grid of nwaves <= nblocks waves, wave w taking blocks w,
 // w + nwaves, ...  nblocks < 2^32 and a multiple of bps.
 hipError_t launch_prop1d_il(const PropSeg* segs_dev, int64_t nblocks, int64_t bps, int64_t nwaves,
-                            int D, int skip, uint32_t* fix, hipStream_t stream);
+                            int D, int skip, hipStream_t stream);
 
 // One 2D band: ny rows of nx cells, row-major, advanced `steps` steps from in
 // into out.  Rows outside [0, ny) come from the top/bottom rule; columns

@@ -33,11 +33,10 @@
 //     output far below that largest value (a cell next to a spike, or a zero
 //     crossing).  So every block checks its outputs: unless each is finite
 //     and at least 2^21 E times the window's largest finite |x|, its products
-//     are not stored and the block goes on a fix list; a second kernel
-//     (k_prop1d_fix) then advances those blocks by plain f32 stepping.  Every
-//     output therefore carries only relative errors of f32 size, or is the
-//     stepped result, and a non-finite input reaches exactly the outputs that
-//     stepping reaches.
+//     are not stored and the wave advances the block by plain f32 stepping
+//     instead, after its other blocks (step_block, in LDS).  Every output therefore carries only
+//     relative errors of f32 size, or is the stepped result, and a non-finite
+//     input reaches exactly the outputs that stepping reaches.
 // Data path per iteration: the wave loads the next 1024 cells with coalesced
 // 16-byte loads (two iterations ahead), splits them once into three bf16
 // planes in an LDS ring of three 1024-cell slots (64-byte rows, 16-byte units
@@ -154,35 +153,43 @@ __device__ __forceinline__ float load1(const PropSeg& s, int64_t c) {
 
 // The stepping path of one block: its 1024 cells from c0 advanced D steps of
 // u' = u + r ((u_{i-1} - 2 u_i) + u_{i+1}) in f32, over the block's window of
-// 64 cells each side (D <= 64).  Lane l holds window cells 18 l .. 18 l + 17;
-// the neighbours across lanes come by shuffles, and the cells within D of the
-// window's ends, which go stale, are never stored.  It serves the blocks whose
-// products fail the accuracy check, so it is rare and kept simple: every cell
+// 64 cells each side (D <= 64), held in 1152 floats of LDS that the caller no
+// longer needs (`cell(i)` is window cell i).  Lane l steps window cells
+// 18 l .. 18 l + 17 in place: each step reads the two neighbours across its
+// ends first, then updates its cells in order carrying the old left value; the
+// cells within D of the window's ends go stale and are never stored.  It
+// serves the blocks whose products fail the accuracy check, after the wave's
+// other blocks, so it is rare and kept simple (loops not unrolled): every cell
 // is one 4-byte load and one 4-byte store.
-__device__ __forceinline__ void step_block(const PropSeg& s, int64_t c0, int D) {
+template <typename Cell>
+__device__ __forceinline__ void step_block(const PropSeg& s, int64_t c0, int D, Cell cell) {
     const int l = threadIdx.x;
     const float r = s.r;
-    const int64_t b = c0 - 64 + 18 * l;
-    float w[18];
-#pragma unroll
-    for (int t = 0; t < 18; ++t) w[t] = load1(s, b + t);
+    const int b = 18 * l;
+    __syncthreads();
+#pragma unroll 1
+    for (int t = 0; t < 18; ++t) cell(b + t) = load1(s, c0 - 64 + b + t);
+    __syncthreads();
     for (int k = 0; k < D; ++k) {
-        const float lf = __shfl_up(w[17], 1);
-        const float rt = __shfl_down(w[0], 1);
-        float prev = lf;
-#pragma unroll
+        const float lf = l > 0 ? cell(b - 1) : 0.f;
+        const float rt = l < 63 ? cell(b + 18) : 0.f;
+        __syncthreads();
+        float prev = lf, cur = cell(b);
+#pragma unroll 1
         for (int t = 0; t < 18; ++t) {
-            const float nx = t < 17 ? w[t + 1] : rt;
-            const float v = w[t] + r * ((prev - 2.f * w[t]) + nx);
-            prev = w[t];
-            w[t] = v;
+            const float nx = t < 17 ? cell(b + t + 1) : rt;
+            cell(b + t) = cur + r * ((prev - 2.f * cur) + nx);
+            prev = cur;
+            cur = nx;
         }
+        __syncthreads();
     }
-#pragma unroll
+#pragma unroll 1
     for (int t = 0; t < 18; ++t) {
-        const int64_t c = b + t;
-        if (c >= c0 && c < c0 + 1024 && c < s.n) s.out[c] = w[t];
+        const int64_t c = c0 - 64 + b + t;
+        if (c >= c0 && c < c0 + 1024 && c < s.n) s.out[c] = cell(b + t);
     }
+    __syncthreads();
 }
 
 // True on every lane when some output of the block fails the accuracy check:
@@ -195,17 +202,6 @@ __device__ __forceinline__ bool block_fails(const f32x16& y, float thr) {
         bad = bad || !(a <= 3.402823466e38f) || a < thr;
     }
     return __ballot(bad) != 0;
-}
-
-// Fix list of a launch: fix[0] = entries, fix[1] = finished fix-up waves,
-// then (segment, block) pairs.  A block that fails the check is appended
-// (its products are not stored) and k_prop1d_fix steps it afterwards.
-__device__ __forceinline__ void fix_append(uint32_t* fix, uint32_t seg, uint32_t blk) {
-    if (threadIdx.x == 0) {
-        const uint32_t k = atomicAdd(fix, 1u);
-        fix[2 + 2 * k] = seg;
-        fix[3 + 2 * k] = blk;
-    }
 }
 
 __device__ __forceinline__ float wave_max(float x) {
@@ -235,8 +231,8 @@ __device__ __forceinline__ void prop_taps(const float* coef, int D, int OD, Spli
 // Chunks [S0, NC - S0) of the window are materialised: the outer S0 chunks on
 // each side take no products for any segment of the launch.
 template <int NC, int S0, bool INTERIOR>
-__device__ __forceinline__ void prop_wave(const PropSeg& s, uint32_t seg, int64_t blk0, int ni,
-                                          int D, int OD, char* lds, uint32_t* fix) {
+__device__ __forceinline__ void prop_wave(const PropSeg& s, int64_t blk0, int ni, int D, int OD,
+                                          char* lds, uint16_t* fails) {
     const int l = threadIdx.x, i = l & 31, g = l >> 5;
     const uint32_t lv = s.levels;
     Split8 A[NC];
@@ -331,13 +327,18 @@ __device__ __forceinline__ void prop_wave(const PropSeg& s, uint32_t seg, int64_
     };
     // The block's window lies in the three slots of the ring (segments kb - 1,
     // kb, kb + 1): its outputs pass the check against their largest finite
-    // |x|, or the block is stepped instead.
+    // |x|, or the block goes on the wave's list (`fails`, at most 256 entries:
+    // a span has at most 256 blocks) and is stepped after the span, when the
+    // registers of the pipeline are free.
+    int nfail = 0;
     auto emit = [&](int slot, const f32x16& y, int kb) {
         const float M = fmaxf(fmaxf(smx[0], smx[1]), smx[2]);
-        if (block_fails(y, s.chk * M))
-            fix_append(fix, seg, (uint32_t)(blk0 + kb));
-        else
+        if (block_fails(y, s.chk * M)) {
+            if (l == 0) fails[nfail] = (uint16_t)kb;
+            ++nfail;
+        } else {
             store(slot, y, kb);
+        }
     };
     for (int k0 = 0; k0 < ni; k0 += 6) {
 #pragma unroll
@@ -388,37 +389,24 @@ __device__ __forceinline__ void prop_wave(const PropSeg& s, uint32_t seg, int64_
     }
     // the last block, through the slot that iteration ni would have refilled
     emit((ni + 2) % 3, yprev, ni - 1);
+    // the listed blocks, stepped in plane 0 of the ring (4.5 of its 6 KiB)
+    __syncthreads();
+    for (int f = 0; f < nfail; ++f)
+        step_block(s, c_span + 1024 * (int64_t)fails[f], D,
+                   [&](int i) -> float& { return reinterpret_cast<float*>(lds)[i]; });
 }
 
 template <int NC, int S0>
 __global__ __launch_bounds__(64) void k_prop1d(const PropSeg* __restrict__ segs,
-                                               const PropWave* __restrict__ waves, int D, int OD,
-                                               uint32_t* fix) {
+                                               const PropWave* __restrict__ waves, int D, int OD) {
     __shared__ __attribute__((aligned(16))) char lds[3 * kPlane];
+    __shared__ uint16_t fails[kSpanMax];
     const PropWave w = waves[blockIdx.x];
     const PropSeg s = segs[w.seg];
     if (w.interior)
-        prop_wave<NC, S0, true>(s, w.seg, w.blk0, (int)w.ni, D, OD, lds, fix);
+        prop_wave<NC, S0, true>(s, w.blk0, (int)w.ni, D, OD, lds, fails);
     else
-        prop_wave<NC, S0, false>(s, w.seg, w.blk0, (int)w.ni, D, OD, lds, fix);
-}
-
-// The fix-up pass after either walk: `gridDim.x` waves step the listed
-// blocks (wave w takes entries w, w + grid, ...); the last wave to finish
-// clears the list for the next launch.  An empty list (the usual case) leaves
-// at once, with no atomic: the waves' completion count is only kept, and the
-// list only cleared, when there was something to step.
-__global__ __launch_bounds__(64) void k_prop1d_fix(const PropSeg* __restrict__ segs,
-                                                   uint32_t* fix, int D) {
-    const uint32_t n = __atomic_load_n(fix, __ATOMIC_RELAXED);
-    if (n == 0) return;
-    for (uint32_t k = blockIdx.x; k < n; k += gridDim.x)
-        step_block(segs[fix[2 + 2 * k]], 1024 * (int64_t)fix[3 + 2 * k], D);
-    __threadfence();
-    if (threadIdx.x == 0 && atomicAdd(fix + 1, 1u) == gridDim.x - 1) {
-        atomicExch(fix, 0u);
-        atomicExch(fix + 1, 0u);
-    }
+        prop_wave<NC, S0, false>(s, w.blk0, (int)w.ni, D, OD, lds, fails);
 }
 
 // Interleaved walk (every segment of the launch has the same n and the same
@@ -441,7 +429,7 @@ __global__ __launch_bounds__(64) void k_prop1d_fix(const PropSeg* __restrict__ s
 // scale 2^texp.  These absolute floors and the pruning of product levels are
 // what the check after the products bounds (as in the span walk: a block
 // whose outputs are not all finite and at least 2^21 E times the window's
-// largest is stepped by k_prop1d_fix instead).  A product
+// largest is stepped instead, in the window's LDS).  A product
 // then takes three 32x32x16 fp16 MFMAs (hi*hi, hi*lo, lo*hi; the dropped
 // lo*lo is below 2^-22 of it) instead of the six of the bf16 split, which
 // halves the matrix-core work (17 instead of 36 products per block at
@@ -486,13 +474,14 @@ struct Split8h {
 // milliseconds into sustained launches.
 template <int NC, int S0>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NC - 2 * S0 <= 7 ? 3 : 1, 8)))
-void k_prop1d_il(const PropSeg* __restrict__ segs, uint32_t nblocks, uint32_t bps, int D, int OD,
-                 uint32_t* fix) {
+void k_prop1d_il(const PropSeg* __restrict__ segs, uint32_t nblocks, uint32_t bps, int D, int OD) {
     __shared__ __attribute__((aligned(16))) char lds[2 * kWPlane];
+    __shared__ uint16_t fails[kIlMax];  // this wave's blocks that failed the check
     const int l = threadIdx.x, i = l & 31, g = l >> 5;
     const uint32_t w = blockIdx.x, nw = gridDim.x;
     if (w >= nblocks) return;
-    const int nk = (int)((nblocks - 1 - w) / nw) + 1;
+    const int nk = (int)((nblocks - 1 - w) / nw) + 1;  // at most kIlMax (the host's grid)
+    int nfail = 0;
     const uint32_t lv = segs[0].levels16;
     const int texp = segs[0].texp;
     const float chk = segs[0].chk;
@@ -650,13 +639,20 @@ void k_prop1d_il(const PropSeg* __restrict__ segs, uint32_t nblocks, uint32_t bp
             // a block that fails the check is stepped instead
             __builtin_amdgcn_sched_barrier(0);
             if (block_fails(acc, thr)) {
-                const uint32_t b = w + (uint32_t)k * nw;
-                const uint32_t sg = b / bps;
-                fix_append(fix, sg, b - sg * bps);
+                if (l == 0) fails[nfail] = (uint16_t)k;
+                ++nfail;
             } else {
                 store(k, acc, ex);
             }
         }
+    }
+    // the listed blocks, stepped now that the pipeline's registers are free
+    __syncthreads();
+    for (int f = 0; f < nfail; ++f) {
+        const uint32_t b = w + (uint32_t)fails[f] * nw;
+        const uint32_t sg = b / bps;
+        step_block(segs[sg], 1024 * (int64_t)(b - sg * bps), D,
+                   [&](int c) -> float& { return reinterpret_cast<float*>(lds)[c]; });
     }
 }
 
@@ -700,36 +696,27 @@ int prop1d_waves_per_cu(int D, int skip, bool il) {
     return blocks > 0 ? blocks : 1;
 }
 
-static hipError_t launch_fix(const PropSeg* segs_dev, uint32_t* fix, int D, hipStream_t stream) {
-    void* args[] = {&segs_dev, &fix, &D};
-    return hipLaunchKernel(reinterpret_cast<const void*>(&k_prop1d_fix), dim3(kPropFixWaves),
-                           dim3(64), args, 0, stream);
-}
-
 hipError_t launch_prop1d(const PropSeg* segs_dev, const PropWave* waves_dev, int64_t nwaves, int D,
-                         int skip, uint32_t* fix, hipStream_t stream) {
+                         int skip, hipStream_t stream) {
     int OD = 0, NC = 0;
     const void* k = prop1d_kernel(D, skip);
-    if (!k || !fix || !prop1d_geometry(D, &OD, &NC) || nwaves <= 0 ||
-        nwaves >= (int64_t(1) << 31))
+    if (!k || !prop1d_geometry(D, &OD, &NC) || nwaves <= 0 || nwaves >= (int64_t(1) << 31))
         return hipErrorInvalidValue;
-    void* args[] = {&segs_dev, &waves_dev, &D, &OD, &fix};
-    hipError_t e = hipLaunchKernel(k, dim3((unsigned)nwaves), dim3(64), args, 0, stream);
-    return e != hipSuccess ? e : launch_fix(segs_dev, fix, D, stream);
+    void* args[] = {&segs_dev, &waves_dev, &D, &OD};
+    return hipLaunchKernel(k, dim3((unsigned)nwaves), dim3(64), args, 0, stream);
 }
 
 hipError_t launch_prop1d_il(const PropSeg* segs_dev, int64_t nblocks, int64_t bps, int64_t nwaves,
-                            int D, int skip, uint32_t* fix, hipStream_t stream) {
+                            int D, int skip, hipStream_t stream) {
     int OD = 0, NC = 0;
     const void* k = prop1d_kernel(D, skip, true);
-    if (!k || !fix || !prop1d_geometry(D, &OD, &NC) || nblocks <= 0 ||
-        nblocks >= (int64_t(1) << 32) || bps <= 0 || nblocks % bps != 0 || nwaves <= 0 ||
-        nwaves > nblocks)
+    if (!k || !prop1d_geometry(D, &OD, &NC) || nblocks <= 0 || nblocks >= (int64_t(1) << 32) ||
+        bps <= 0 || nblocks % bps != 0 || nwaves <= 0 || nwaves > nblocks ||
+        (nblocks + nwaves - 1) / nwaves > kIlMax)
         return hipErrorInvalidValue;
     uint32_t nb = (uint32_t)nblocks, bp = (uint32_t)bps;
-    void* args[] = {&segs_dev, &nb, &bp, &D, &OD, &fix};
-    hipError_t e = hipLaunchKernel(k, dim3((unsigned)nwaves), dim3(64), args, 0, stream);
-    return e != hipSuccess ? e : launch_fix(segs_dev, fix, D, stream);
+    void* args[] = {&segs_dev, &nb, &bp, &D, &OD};
+    return hipLaunchKernel(k, dim3((unsigned)nwaves), dim3(64), args, 0, stream);
 }
 
 }  // namespace hx

@@ -294,15 +294,16 @@ def test_interleaved_halo_coupled_partitions(ctx, D, hw):
 
 
 def test_interleaved_walk_rejections(ctx):
-    """span_blocks = -1 needs segments of one size and one rate; below -1 is
-    invalid; unequal segments with span_blocks = 0 take the span walk."""
+    """span_blocks = -1 needs segments of one size and one rate; below -1 and
+    above 256 are invalid; unequal segments with span_blocks = 0 take the span
+    walk."""
     b = hx.hx_buffer_create(ctx, 1 << 16)
     c = hx.hx_buffer_create(ctx, 1 << 16)
     per = dict(bc_lo=hx.HX_BC_PERIODIC, bc_hi=hx.HX_BC_PERIODIC)
     s1 = hx.segment(inp=b, out=c, n=1024, r=0.2, **per)
     s2 = hx.segment(inp=b, in_offset=4096, out=c, out_offset=4096, n=2048, r=0.2, **per)
     s3 = hx.segment(inp=b, in_offset=4096, out=c, out_offset=4096, n=1024, r=0.1, **per)
-    for segs, span in (([s1, s2], -1), ([s1, s3], -1), ([s1], -2)):
+    for segs, span in (([s1, s2], -1), ([s1, s3], -1), ([s1], -2), ([s1], 257)):
         with pytest.raises(hx.HxError) as e:
             hx.hx_plan_create_batched(ctx, hx.HX_F32, 20, segs, hx.HX_BATCH_PERSISTENT,
                                       form=hx.HX_FORM_PROPAGATOR, span_blocks=span)
@@ -445,3 +446,23 @@ def test_non_finite_cells_reach_what_stepping_reaches(ctx, span):
         fin = np.isfinite(ref)
         assert np.isfinite(ref).sum() < n  # the reach is not empty
         assert per_cell(got[fin], ref[fin]) <= 1e-5, k
+
+
+@pytest.mark.parametrize("span", [-1, 5])
+def test_every_block_stepped(ctx, span):
+    """3 x 2^20 cells of (-1)^i plus a smooth part of 1e-5: at r = 1/4 one step
+    annihilates the alternating part, so every output is about 1e-5 of its
+    window's largest value, every block fails the accuracy check and its wave
+    steps it after its other blocks.  Against the oracle, to 1e-5 of the
+    magnitude envelope (not of the outputs themselves: the cancellation of the
+    alternating part leaves f32 stepping an error of a few 2^-24 of the
+    envelope, i.e. about 1e-2 of the outputs, as stepping directly would)."""
+    n, D, r = 1 << 20, 50, 0.25
+    i = np.arange(n, dtype=np.float64)
+    vals = [np.where(i % 2 == 0, 1.0, -1.0) + 1e-5 * (1.5 + np.sin(2 * np.pi * (k + 2) * i / n))
+            for k in range(3)]
+    u, out = run_segments(ctx, vals, r, D, span)
+    for k in range(3):
+        ref = oracle.heat1d_periodic(u[k].astype(np.float64), r, D)
+        err = np.max(np.abs(out[k] - ref) / envelope(u[k], r, D))
+        assert err <= 1e-5, (k, span, err)
