@@ -211,7 +211,7 @@ class BatchedPass:
     plan's direct form (tile geometry `cpl`) or its propagator form (`span`
     blocks per wave, 0 = the plan's choice)."""
 
-    def __init__(self, hx, ctx, P, tb, cpl, form=0, span=0, hw=None):
+    def __init__(self, hx, ctx, P, tb, cpl, form=0, span=0, hw=None, wpg=0, grid=-1):
         self.hx, self.ctx, self.P, self.tb, self.cpl = hx, ctx, P, tb, cpl
         hw = tb if hw is None else hw
         self.plans = []
@@ -225,7 +225,8 @@ class BatchedPass:
                                        halo_hi=src[rp], halo_width=hw))
             self.plans.append(hx.hx_plan_create_batched(ctx, hx.HX_F32, tb, segs,
                                                         hx.HX_BATCH_PERSISTENT, cells_per_lane=cpl,
-                                                        grid_waves_per_cu=-1, form=form,
+                                                        waves_per_group=wpg,
+                                                        grid_waves_per_cu=grid, form=form,
                                                         span_blocks=span))
         self.passes = P.steps // tb
         assert self.passes * tb == P.steps, "the time block must divide the step count"
@@ -324,8 +325,35 @@ def main():
         bp.close()
         swept.append((t, form, cpl_c or 16, span_c))
         log(f"sweep batched pass form={form} cpl={cpl_c} span={span_c}: {t * 1e3:.3f} ms/step")
-    _, form, cpl, span = min(swept)
+    # the project's autotuner decides the timed configuration: pass depth,
+    # form, walk or tile geometry (the sweep above only reports the forms)
+    tsegs = []
+    for p in range(P.parts):
+        lp, rp = (p - 1) % P.parts, (p + 1) % P.parts
+        tsegs.append(hx.segment(inp=P.A[p], out=P.B[p], n=P.sizes[p], r=r,
+                                bc_lo=hx.HX_BC_GHOST, bc_hi=hx.HX_BC_GHOST, halo_lo=P.A[lp],
+                                halo_lo_offset=(P.sizes[lp] - hw) * 4, halo_hi=P.A[rp],
+                                halo_width=hw))
+    if args.form == "auto" and not args.span_blocks and not args.cells_per_lane:
+        t0 = time.perf_counter()
+        tb_ = hx.hx_tune_batched(ctx, hx.HX_F32, T, tsegs, 4000)
+        tuned = {"tuner": "hx_tune_batched", "seconds": time.perf_counter() - t0,
+                 "depth": tb_.steps, "passes": T // tb_.steps,
+                 "form": "propagator" if tb_.form == hx.HX_FORM_PROPAGATOR else "direct",
+                 "span_blocks": tb_.span_blocks, "cells_per_lane": tb_.cells_per_lane,
+                 "waves_per_group": tb_.waves_per_group,
+                 "grid_waves_per_cu": tb_.grid_waves_per_cu}
+        form, tb = tuned["form"], tb_.steps
+        cpl = tb_.cells_per_lane or 16
+        span = tb_.span_blocks if form == "propagator" else 0
+        t_wpg, t_grid = tb_.waves_per_group, tb_.grid_waves_per_cu or -1
+        log(f"tuner: {tuned}")
+    else:
+        _, form, cpl, span = min(swept)
+        tuned, t_wpg, t_grid = None, 0, -1
     fcode = hx.HX_FORM_PROPAGATOR if form == "propagator" else hx.HX_FORM_DIRECT
+    if span == 0 and form == "propagator":
+        span = -1  # the plan's own choice for equal partitions: the interleaved walk
     by_form = {}
     for t, f, c_, s_ in swept:
         key = (f"{f}_cpl{c_}" if f == "direct" else
@@ -334,7 +362,7 @@ def main():
 
     # ------------------------------------------------------------ timed region
     P.reset()
-    bp = BatchedPass(hx, ctx, P, tb, cpl, fcode, span, hw)
+    bp = BatchedPass(hx, ctx, P, tb, cpl, fcode, span, hw, t_wpg, t_grid)
     bp.run(args.warmup)
     if P.last:
         P.wait()
@@ -359,7 +387,7 @@ def main():
     # one pass from the initial state, every cell against the oracle (the same
     # serial FP64 run the CPU baseline times)
     P.reset()
-    bp = BatchedPass(hx, ctx, P, tb, cpl, fcode, span, hw)
+    bp = BatchedPass(hx, ctx, P, tb, cpl, fcode, span, hw, t_wpg, t_grid)
     bp.run(1)
     P.wait()
     bp.close()
@@ -474,6 +502,7 @@ def main():
                    "halo_width": hw, "launches_per_step": bp.passes,
                    "error_vs_oracle_every_cell": full_err},
         "roofline": roof,
+        "tuned": tuned,
         "pass_ms_by_form": by_form,
         "no_mfma": no_mfma,
     }
@@ -576,25 +605,76 @@ def batched_leg(hx, ctx, reps=5):
         hx.hx_event_release(ctx, e)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        evs = [hx.hx_launch_batched(ctx, plan) for _ in range(n)]
+        evs = []
+        for _ in range(n):  # chained, so the launches run one after another
+            evs.append(hx.hx_launch_batched(ctx, plan, deps=evs[-1:]))
         assert hx.hx_wait(ctx, evs[-1]) == hx.HX_OK
         sec = (time.perf_counter() - t0) / n
         for e in evs:
             hx.hx_event_release(ctx, e)
         return sec
 
-    best = None
-    for cpl, grid in ((16, 16), (16, 64), (16, -1), (32, -1)):
-        plan = hx.hx_plan_create_batched(ctx, hx.HX_F32, spec.steps, segs, hx.HX_BATCH_PERSISTENT,
-                                         cells_per_lane=cpl, grid_waves_per_cu=grid)
-        sec = timed(plan, reps)
-        log(f"batched persistent cpl={cpl} grid/CU={grid}: {sec * 1e3:.3f} ms")
-        if best is None or sec < best[0]:
-            best = (sec, cpl, grid)
-        hx.hx_plan_destroy(ctx, plan)
-    res["persistent"] = {"ms": best[0] * 1e3, "cell_updates_per_s": updates / best[0],
-                         "hbm_algorithmic_GBps": total * 8 / best[0] / 1e9,
-                         "cells_per_lane": best[1], "grid_waves_per_cu": best[2]}
+    # the project's autotuner picks the pass depth (20 steps in one pass, or
+    # several passes ping-ponging between two buffers), the form and the tile
+    # geometry, timing each candidate on the GPU
+    t0 = time.perf_counter()
+    tb_ = hx.hx_tune_batched(ctx, hx.HX_F32, spec.steps, segs, 4000)
+    tune_s = time.perf_counter() - t0
+    D = tb_.steps
+    passes = spec.steps // D
+    kw = dict(cells_per_lane=tb_.cells_per_lane, waves_per_group=tb_.waves_per_group,
+              grid_waves_per_cu=tb_.grid_waves_per_cu, form=tb_.form,
+              span_blocks=tb_.span_blocks)
+    plans = [hx.hx_plan_create_batched(ctx, hx.HX_F32, D, segs, hx.HX_BATCH_PERSISTENT, **kw)]
+    if passes > 1:  # the return pass: out -> in
+        back = [hx.segment(inp=bufs[1], in_offset=int(o) * 4, out=bufs[0],
+                           out_offset=int(o) * 4, n=int(n), r=float(rr),
+                           bc_lo=hx.HX_BC_PERIODIC, bc_hi=hx.HX_BC_PERIODIC)
+                for o, n, rr in zip(offs, sizes, rs)]
+        plans.append(hx.hx_plan_create_batched(ctx, hx.HX_F32, D, back, hx.HX_BATCH_PERSISTENT,
+                                               **kw))
+
+    def run_tuned(n_runs):
+        """n_runs whole 20-step runs, chained; returns the last event."""
+        last = 0
+        for _ in range(n_runs):
+            for k in range(passes):
+                e = hx.hx_launch_batched(ctx, plans[k % 2], deps=[last] if last else [])
+                if last:
+                    hx.hx_event_release(ctx, last)
+                last = e
+        return last
+
+    e = run_tuned(1)
+    assert hx.hx_wait(ctx, e) == hx.HX_OK, hx.hx_last_error(ctx)
+    hx.hx_event_release(ctx, e)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e = run_tuned(reps)
+    assert hx.hx_wait(ctx, e) == hx.HX_OK, hx.hx_last_error(ctx)
+    hx.hx_event_release(ctx, e)
+    sec = (time.perf_counter() - t0) / reps
+    tuned = {"tuner": "hx_tune_batched", "tuner_seconds": tune_s, "depth": D, "passes": passes,
+             "form": "propagator" if tb_.form == hx.HX_FORM_PROPAGATOR else "direct",
+             "cells_per_lane": tb_.cells_per_lane, "waves_per_group": tb_.waves_per_group,
+             "grid_waves_per_cu": tb_.grid_waves_per_cu, "span_blocks": tb_.span_blocks}
+    log(f"batched persistent, tuned {tuned}: {sec * 1e3:.3f} ms")
+    res["persistent"] = {"ms": sec * 1e3, "cell_updates_per_s": updates / sec,
+                         "hbm_algorithmic_GBps": total * 8 * passes / sec / 1e9,
+                         "hbm_algorithmic_frac": total * 8 * passes / sec / HBM_PEAK,
+                         "tuned": tuned}
+    # the run's result for the check below: in bufs[1] after an odd number of
+    # passes, else in bufs[0]; one run from the initial state
+    ev = hx.hx_copy_async(ctx, hx.hx_copy_desc(hx.HX_H2D, u0.ctypes.data, bufs[0], 0, 0, 0,
+                                               total * 4))
+    assert hx.hx_wait(ctx, ev) == hx.HX_OK
+    hx.hx_event_release(ctx, ev)
+    e = run_tuned(1)
+    assert hx.hx_wait(ctx, e) == hx.HX_OK
+    hx.hx_event_release(ctx, e)
+    result_buf = bufs[1] if passes % 2 == 1 else bufs[0]
+    for pl in plans:
+        hx.hx_plan_destroy(ctx, pl)
     # sampled correctness of the persistent result
     rng = np.random.default_rng(9)
     errs = []
@@ -602,7 +682,7 @@ def batched_leg(hx, ctx, reps=5):
         o, n = int(offs[k]), int(sizes[k])
         i = int(rng.integers(0, n))
         got = np.empty(1, np.float32)
-        e = hx.hx_copy_async(ctx, hx.hx_copy_desc(hx.HX_D2H, got.ctypes.data, bufs[1],
+        e = hx.hx_copy_async(ctx, hx.hx_copy_desc(hx.HX_D2H, got.ctypes.data, result_buf,
                                                   (o + i) * 4, 0, 0, 4))
         assert hx.hx_wait(ctx, e) == hx.HX_OK
         hx.hx_event_release(ctx, e)
@@ -610,8 +690,12 @@ def batched_leg(hx, ctx, reps=5):
                                         spec.steps, [i])[0]
         errs.append(abs(got[0] - ref) / abs(ref))
     res["persistent"]["sampled_max_rel_err"] = float(max(errs))
+    ev = hx.hx_copy_async(ctx, hx.hx_copy_desc(hx.HX_H2D, u0.ctypes.data, bufs[0], 0, 0, 0,
+                                               total * 4))
+    assert hx.hx_wait(ctx, ev) == hx.HX_OK
+    hx.hx_event_release(ctx, ev)
     plan = hx.hx_plan_create_batched(ctx, hx.HX_F32, spec.steps, segs, hx.HX_BATCH_GRAPH,
-                                     cells_per_lane=best[1])
+                                     cells_per_lane=16)
     sec = timed(plan, reps)
     hx.hx_plan_destroy(ctx, plan)
     res["graph"] = {"ms": sec * 1e3, "cell_updates_per_s": updates / sec}
@@ -920,10 +1004,30 @@ def banded2d_leg(hx, ctx):
                                                   u0.nbytes))
         assert hx.hx_wait(ctx, e) == hx.HX_OK
         hx.hx_event_release(ctx, e)
+    # the project's autotuner picks the 2D geometry (time block, columns per
+    # lane, rows per wave) on the whole grid as one array, 200 steps, timing
+    # each candidate on the GPU; the band graph then runs with it, next to two
+    # fixed geometries for comparison
+    upload()
+    t0 = time.perf_counter()
+    arena_t = hx.hx_buffer_create(ctx, cells * 4)
+    targs = hx.stencil_args(dims=2, dtype=hx.HX_F32, nx=spec.nx, ny=spec.ny, steps=spec.steps,
+                            r=spec.r, inp=arena_a, out=arena_b, tmp=arena_t,
+                            bc_lo=hx.HX_BC_DIRICHLET0, bc_hi=hx.HX_BC_DIRICHLET0)
+    tbest = hx.hx_tune_stencil(ctx, targs, 4000)
+    hx.hx_buffer_destroy(ctx, arena_t)
+    tuned = {"tuner": "hx_tune_stencil", "seconds": time.perf_counter() - t0,
+             "time_block": tbest.time_block, "cells_per_lane": tbest.cells_per_lane,
+             "rows_per_block": tbest.rows_per_block, "waves_per_group": tbest.waves_per_group}
+    log(f"2D tuner: {tuned}")
     best = None
     per_mode = {}
-    cands = [(mode, tb, 4, rows) for mode in (hx.HX_PART_BATCHED, hx.HX_PART_GRAPH)
-             for tb, rows in ((16, 128), (12, 128), (8, 64))]
+    geoms = [(tbest.time_block, tbest.cells_per_lane, tbest.rows_per_block)]
+    for g in ((16, 4, 128), (8, 4, 64)):
+        if g not in geoms:
+            geoms.append(g)
+    cands = [(mode, tb, cpl, rows) for mode in (hx.HX_PART_BATCHED, hx.HX_PART_GRAPH)
+             for tb, cpl, rows in geoms]
     for mode, tb, cpl, rows in cands:
         upload()
         d = hx.partitioned_desc(hx.HX_F32, [s for _, s in bounds], A, B, spec.steps, spec.r,
@@ -952,7 +1056,9 @@ def banded2d_leg(hx, ctx):
            "form": "one launch per pass over all bands" if mode == hx.HX_PART_BATCHED
            else "one launch per band per pass",
            "ms_by_form": {k: v * 1e3 for k, v in per_mode.items()},
-           "hbm_algorithmic_GBps": cells * 8 * passes / sec / 1e9}
+           "tuned": tuned,
+           "hbm_algorithmic_GBps": cells * 8 * passes / sec / 1e9,
+           "hbm_algorithmic_frac": cells * 8 * passes / sec / HBM_PEAK}
     # sampled correctness of the best configuration against the oracle
     import oracle
     d = hx.partitioned_desc(hx.HX_F32, [s for _, s in bounds], A, B, spec.steps, spec.r,

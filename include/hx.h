@@ -558,11 +558,22 @@ hx_status hx_hazard_report(hx_ctx ctx, char* buf, size_t len);
  * buffers (out and tmp are overwritten) for about `budget_ms` (at least one
  * candidate runs), store the fastest in the process-wide cache under the
  * problem's key (dims, dtype, size class, steps), and return it in *best.
- * Later launches with geometry fields 0 use the cached entry. */
+ * Later launches with geometry fields 0 use the cached entry.  Each candidate
+ * runs once to warm up, then three times chained on one stream: in a timing
+ * context (hx_ctx_opts.timing) its time is the mean HIP-event span of those
+ * launches, otherwise their host time over three. */
 hx_status hx_tune_stencil(hx_ctx ctx, const hx_stencil_args* args, int budget_ms,
                           hx_stencil_args* best);
 
-/* The same for a persistent batch: cells per lane and grid size. */
+/* The same for a persistent batch (desc->mode PERSISTENT), timed the same way.
+ * desc->steps is the whole run's step count T.  The search covers the pass
+ * depth D (the divisors of T up to 64, from the deepest down to T/8), and per
+ * depth the form (PROPAGATOR for f32, over its walks: the plan's choice,
+ * interleaved, spans of 128 and 40 blocks; DIRECT over cells per lane 8..64,
+ * waves per group 1, 2, 4 and a persistent grid of 16 or 64 waves per CU);
+ * a candidate costs T / D times its pass.  *best is the fastest, with
+ * best->steps = D: the run is T / D passes of that plan (ping-ponging in and
+ * out).  It is cached under the key of T and of D. */
 hx_status hx_tune_batched(hx_ctx ctx, const hx_batch_desc* desc, int budget_ms,
                           hx_batch_desc* best);
 

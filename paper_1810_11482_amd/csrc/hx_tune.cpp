@@ -150,19 +150,39 @@ namespace {
 
 using clk = std::chrono::steady_clock;
 
+// One launch of `a`, in seconds, timed like time_plan: `reps` launches
+// chained on one stream after a warm-up, their HIP-event spans in a timing
+// context, else their host time over reps.  Negative on any failure.
 double time_stencil(hx_ctx ctx, const hx_stencil_args& a, int reps) {
-    double best = 1e30;
-    for (int r = 0; r < reps + 1; ++r) {
-        const auto t0 = clk::now();
-        hx_event ev = 0;
-        if (hx_launch_stencil(ctx, &a, nullptr, 0, &ev) != HX_OK) return -1;
-        const hx_status st = hx_wait(ctx, ev, -1);
-        hx_event_release(ctx, ev);
-        if (st != HX_OK) return -1;
-        const double s = std::chrono::duration<double>(clk::now() - t0).count();
-        if (r > 0 && s < best) best = s;  // the first run warms up
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    hx_event warm = 0;
+    if (hx_launch_stencil(ctx, &a, nullptr, 0, &warm) != HX_OK) return -1;
+    if (hx_wait(ctx, warm, -1) != HX_OK) {
+        hx_event_release(ctx, warm);
+        return -1;
     }
-    return best;
+    std::vector<hx_event> evs;
+    hx_event prev = warm;
+    const auto t0 = clk::now();
+    bool ok = true;
+    for (int r = 0; r < reps && ok; ++r) {
+        hx_event ev = 0;
+        ok = hx_launch_stencil(ctx, &a, &prev, 1, &ev) == HX_OK;
+        if (ok) evs.push_back(prev = ev);
+    }
+    if (ok) ok = hx_wait(ctx, prev, -1) == HX_OK;
+    const double host = std::chrono::duration<double>(clk::now() - t0).count() / reps;
+    double gpu = 0.0;
+    bool spans = ok && c->timing;
+    for (hx_event e : evs) {
+        double x = 0, y = 0;
+        if (spans && hx_event_span(ctx, e, e, &x, &y) == HX_OK) gpu += (y - x) * 1e-3;
+        else spans = false;
+    }
+    hx_event_release(ctx, warm);
+    for (hx_event e : evs) hx_event_release(ctx, e);
+    if (!ok || evs.empty()) return -1;
+    return spans ? gpu / (double)evs.size() : host;
 }
 
 }  // namespace
@@ -193,10 +213,10 @@ extern "C" hx_status hx_tune_stencil(hx_ctx ctx, const hx_stencil_args* args, in
             }
     } else {
         for (int cpl : {4, 8})
-            for (int tb : {8, 4, 6, 10, 12, 16}) {
+            for (int tb : {16, 12, 10, 8, 6, 4}) {
                 const int d = std::min(tb, S);
                 if (!stencil2d_supported(args->dtype, cpl, d)) continue;
-                for (int rows : {256, 128, 512}) add(cpl, d, 4, rows);
+                for (int rows : {128, 256, 64, 512}) add(cpl, d, 4, rows);
                 if (tb >= S) break;
             }
     }
@@ -226,52 +246,108 @@ extern "C" hx_status hx_tune_stencil(hx_ctx ctx, const hx_stencil_args* args, in
     return HX_OK;
 }
 
+namespace {
+
+// One launch of `plan`, in seconds: `reps` launches chained on one stream
+// after a warm-up launch; in a timing context the mean of their HIP-event
+// spans (GPU time of each launch), otherwise the host time of the chained
+// launches over reps (the launches are queued back to back, so only the
+// GPU-side gaps between them add).  Negative on any failure.
+double time_plan(hx_ctx ctx, hx_plan plan, int reps) {
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    hx_event warm = 0;
+    if (hx_launch_batched(ctx, plan, nullptr, 0, &warm) != HX_OK) return -1;
+    if (hx_wait(ctx, warm, -1) != HX_OK) {
+        hx_event_release(ctx, warm);
+        return -1;
+    }
+    std::vector<hx_event> evs;
+    hx_event prev = warm;
+    const auto t0 = clk::now();
+    bool ok = true;
+    for (int r = 0; r < reps && ok; ++r) {
+        hx_event ev = 0;
+        ok = hx_launch_batched(ctx, plan, &prev, 1, &ev) == HX_OK;
+        if (ok) evs.push_back(prev = ev);
+    }
+    if (ok) ok = hx_wait(ctx, prev, -1) == HX_OK;
+    const double host = std::chrono::duration<double>(clk::now() - t0).count() / reps;
+    double gpu = 0.0;
+    bool spans = ok && c->timing;
+    for (hx_event e : evs) {
+        double a = 0, b = 0;
+        if (spans && hx_event_span(ctx, e, e, &a, &b) == HX_OK) gpu += (b - a) * 1e-3;
+        else spans = false;
+    }
+    hx_event_release(ctx, warm);
+    for (hx_event e : evs) hx_event_release(ctx, e);
+    if (!ok || evs.empty()) return -1;
+    return spans ? gpu / (double)evs.size() : host;
+}
+
+}  // namespace
+
+// The pass depths worth trying for a run of T steps: the divisors of T that a
+// fused pass can take (at most 64 steps), from the deepest, down to T/8 steps
+// (eight passes), and at least the deepest one.
+static std::vector<int> pass_depths(int T) {
+    std::vector<int> ds;
+    for (int d = std::min(T, 64); d >= 1; --d)
+        if (T % d == 0 && (ds.empty() || T / d <= 8)) ds.push_back(d);
+    if (ds.empty()) ds.push_back(std::max(T, 0));
+    return ds;
+}
+
 extern "C" hx_status hx_tune_batched(hx_ctx ctx, const hx_batch_desc* desc, int budget_ms,
                                      hx_batch_desc* best) {
-    if (!ctx || !desc || !best || desc->mode != HX_BATCH_PERSISTENT) return HX_ERR_ARG;
+    if (!ctx || !desc || !best || desc->mode != HX_BATCH_PERSISTENT || desc->steps < 0)
+        return HX_ERR_ARG;
     const auto t_start = clk::now();
+    const int T = desc->steps;
     double best_t = 1e30;
     bool found = false;
-    // candidates: the direct form over tile geometries, then (f32) the
-    // propagator form over a few spans; a candidate the plan rejects is skipped
+    // candidates, the likely fastest first: per pass depth D (deepest first),
+    // the propagator form (f32) over its walks, then the direct form over
+    // cells per lane, waves per group and the persistent grid; a candidate the
+    // plan rejects (depth beyond a geometry's limit, halos too short, ...) is
+    // skipped.  The cost of a candidate is T / D times its pass.
     std::vector<hx_batch_desc> cands;
-    for (int cpl : {16, 32, 8, 64})
-        for (int grid : {-1, 64, 16}) {
-            hx_batch_desc d = *desc;
-            d.form = HX_FORM_DIRECT;
-            d.cells_per_lane = cpl;
-            d.grid_waves_per_cu = grid;
-            d.waves_per_group = 4;
-            d.span_blocks = 0;
-            cands.push_back(d);
-        }
-    if (desc->dtype == HX_F32)
-        for (int span : {0, -1, 16, 24, 40}) {
-            hx_batch_desc d = *desc;
-            d.form = HX_FORM_PROPAGATOR;
-            d.span_blocks = span;
-            cands.insert(cands.begin() + (span == 0 ? 0 : (long)cands.size()), d);
-        }
+    for (int D : pass_depths(T)) {
+        if (desc->dtype == HX_F32)
+            for (int span : {0, -1, 128, 40}) {
+                hx_batch_desc d = *desc;
+                d.steps = D;
+                d.form = HX_FORM_PROPAGATOR;
+                d.span_blocks = span;
+                cands.push_back(d);
+            }
+        for (int cpl : {16, 32, 8, 64})
+            for (int wpg : {4, 2, 1})
+                for (int grid : {-1, 64, 16}) {
+                    if (grid != -1 && wpg != 4) continue;  // the persistent grid at 4 only
+                    if (cpl == 64 && (wpg != 4 || grid != -1)) continue;
+                    hx_batch_desc d = *desc;
+                    d.steps = D;
+                    d.form = HX_FORM_DIRECT;
+                    d.cells_per_lane = cpl;
+                    d.grid_waves_per_cu = grid;
+                    d.waves_per_group = wpg;
+                    d.span_blocks = 0;
+                    cands.push_back(d);
+                }
+    }
     for (const hx_batch_desc& d : cands) {
         if (found &&
             std::chrono::duration<double, std::milli>(clk::now() - t_start).count() > budget_ms)
             break;
         hx_plan plan = 0;
         if (hx_plan_create_batched(ctx, &d, &plan) != HX_OK) continue;
-        double bt = 1e30;
-        for (int r = 0; r < 3; ++r) {
-            const auto t0 = clk::now();
-            hx_event ev = 0;
-            if (hx_launch_batched(ctx, plan, nullptr, 0, &ev) != HX_OK) break;
-            const hx_status st = hx_wait(ctx, ev, -1);
-            hx_event_release(ctx, ev);
-            if (st != HX_OK) break;
-            const double s = std::chrono::duration<double>(clk::now() - t0).count();
-            if (r > 0) bt = std::min(bt, s);
-        }
+        const double pass = time_plan(ctx, plan, 3);
         hx_plan_destroy(ctx, plan);
-        if (bt < best_t) {
-            best_t = bt;
+        if (pass <= 0) continue;
+        const double t = pass * (d.steps > 0 ? T / d.steps : 1);
+        if (t < best_t) {
+            best_t = t;
             *best = d;
             found = true;
         }
@@ -281,10 +357,14 @@ extern "C" hx_status hx_tune_batched(hx_ctx ctx, const hx_batch_desc* desc, int 
     for (int i = 0; i < desc->count; ++i) total += desc->segs[i].n;
     TunedGeom g;
     g.cpl = best->cells_per_lane;
+    g.steps = best->steps;
     g.wpg = best->waves_per_group;
     g.grid = best->grid_waves_per_cu;
     g.mode = 1 + best->form;
     g.rows = best->form == HX_FORM_PROPAGATOR ? best->span_blocks : 0;
-    tune_store(tune_key_batched(desc->dtype, total, desc->count, desc->steps), g);
+    // under the run's key (its depth is the answer) and the pass's key (a plan
+    // made for one pass of that depth finds its geometry)
+    tune_store(tune_key_batched(desc->dtype, total, desc->count, T), g);
+    if (best->steps != T) tune_store(tune_key_batched(desc->dtype, total, desc->count, best->steps), g);
     return HX_OK;
 }

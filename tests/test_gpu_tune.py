@@ -81,3 +81,48 @@ def test_tune_batched(ctx):
     ref = oracle.heat1d_periodic(u0[o:o + n].astype(np.float64), float(rs[k]), spec.steps)
     assert rel_l2(got, ref) <= 1e-5
     hx.hx_plan_destroy(ctx, plan)
+
+
+def test_tune_batched_depth_runs_the_whole_run(ctx):
+    """The batched tuner searches the pass depth: its answer divides the run's
+    steps, and T / D passes of the tuned plan (ping-ponging between two
+    buffers) equal the oracle's T steps.  In a timing context it times the
+    candidates with HIP events."""
+    tctx = hx.hx_ctx_create(0, timing=True)
+    try:
+        spec = workloads.Batched1D(count=64, nmax=200000, steps=20)
+        sizes, rs, offs = workloads.batched1d_problems(spec)
+        total = int(sizes.sum())
+        u0 = workloads.batched1d_u0(spec)
+        a, b = upload(tctx, u0), hx.hx_buffer_create(tctx, total * 4)
+        fwd = [hx.segment(inp=a, in_offset=int(o) * 4, out=b, out_offset=int(o) * 4, n=int(n),
+                          r=float(r), bc_lo=0, bc_hi=0) for o, n, r in zip(offs, sizes, rs)]
+        back = [hx.segment(inp=b, in_offset=int(o) * 4, out=a, out_offset=int(o) * 4, n=int(n),
+                           r=float(r), bc_lo=0, bc_hi=0) for o, n, r in zip(offs, sizes, rs)]
+        best = hx.hx_tune_batched(tctx, hx.HX_F32, spec.steps, fwd, 1500)
+        D = best.steps
+        assert 1 <= D <= 64 and spec.steps % D == 0
+        # the run, from the initial state again (the tuner wrote b only)
+        kw = dict(cells_per_lane=best.cells_per_lane, waves_per_group=best.waves_per_group,
+                  grid_waves_per_cu=best.grid_waves_per_cu, form=best.form,
+                  span_blocks=best.span_blocks)
+        plans = [hx.hx_plan_create_batched(tctx, hx.HX_F32, D, segs, hx.HX_BATCH_PERSISTENT, **kw)
+                 for segs in (fwd, back)]
+        last = []
+        for k in range(spec.steps // D):
+            e = hx.hx_launch_batched(tctx, plans[k % 2], deps=last)
+            for x in last:
+                hx.hx_event_release(tctx, x)
+            last = [e]
+        assert hx.hx_wait(tctx, last[0]) == hx.HX_OK, hx.hx_last_error(tctx)
+        hx.hx_event_release(tctx, last[0])
+        res = b if (spec.steps // D) % 2 == 1 else a
+        got = download(tctx, res, total, np.float32)
+        ref = oracle.heat1d_batched(sizes, rs, u0.astype(np.float64), spec.steps)
+        assert rel_l2(got, ref) <= 1e-5
+        for pl in plans:
+            hx.hx_plan_destroy(tctx, pl)
+        hx.hx_buffer_destroy(tctx, a)
+        hx.hx_buffer_destroy(tctx, b)
+    finally:
+        hx.hx_ctx_destroy(tctx)
