@@ -474,13 +474,20 @@ struct Split8h {
 // milliseconds into sustained launches.
 template <int NC, int S0>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NC - 2 * S0 <= 7 ? 3 : 1, 8)))
-void k_prop1d_il(const PropSeg* __restrict__ segs, uint32_t nblocks, uint32_t bps, int D, int OD) {
+void k_prop1d_il(const PropSeg* __restrict__ segs, uint32_t nblocks, uint32_t bps, int D, int OD,
+                 uint32_t xcd) {
     __shared__ __attribute__((aligned(16))) char lds[2 * kWPlane];
     __shared__ uint16_t fails[kIlMax];  // this wave's blocks that failed the check
     const int l = threadIdx.x, i = l & 31, g = l >> 5;
     const uint32_t w = blockIdx.x, nw = gridDim.x;
     if (w >= nblocks) return;
-    const int nk = (int)((nblocks - 1 - w) / nw) + 1;  // at most kIlMax (the host's grid)
+    // The wave's position in each round of nw blocks.  Workgroups are handed
+    // to the 8 XCDs in turn (workgroup w to XCD w mod 8), so with xcd set the
+    // waves of one XCD take consecutive positions (XCD x the x-th eighth of
+    // the round): neighbouring blocks, whose windows share 64 cells, then
+    // meet in one L2.
+    const uint32_t wpos = xcd ? (w % 8) * (nw / 8) + w / 8 : w;
+    const int nk = (int)((nblocks - 1 - wpos) / nw) + 1;  // at most kIlMax (the host's grid)
     int nfail = 0;
     const uint32_t lv = segs[0].levels16;
     const int texp = segs[0].texp;
@@ -554,7 +561,7 @@ void k_prop1d_il(const PropSeg* __restrict__ segs, uint32_t nblocks, uint32_t bp
         thr = mx > 0.f ? chk : 0.f;
     };
     auto fetch = [&](int k, f32x4 v[5]) {
-        const uint32_t b = w + (uint32_t)k * nw;
+        const uint32_t b = wpos + (uint32_t)k * nw;
         const uint32_t sg = b / bps;
         const PropSeg& s = segs[sg];
         const int64_t c0 = 1024 * (int64_t)(b - sg * bps);
@@ -591,7 +598,7 @@ void k_prop1d_il(const PropSeg* __restrict__ segs, uint32_t nblocks, uint32_t bp
         f32x4 v[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) v[j] = *reinterpret_cast<const f32x4*>(lds + rd[j]);
-        const uint32_t b = w + (uint32_t)k * nw;
+        const uint32_t b = wpos + (uint32_t)k * nw;
         const uint32_t sg = b / bps;
         const PropSeg& s = segs[sg];
         const int64_t o = 1024 * (int64_t)(b - sg * bps) + 4 * l;
@@ -649,7 +656,7 @@ void k_prop1d_il(const PropSeg* __restrict__ segs, uint32_t nblocks, uint32_t bp
     // the listed blocks, stepped now that the pipeline's registers are free
     __syncthreads();
     for (int f = 0; f < nfail; ++f) {
-        const uint32_t b = w + (uint32_t)fails[f] * nw;
+        const uint32_t b = wpos + (uint32_t)fails[f] * nw;
         const uint32_t sg = b / bps;
         step_block(segs[sg], 1024 * (int64_t)(b - sg * bps), D,
                    [&](int c) -> float& { return reinterpret_cast<float*>(lds)[c]; });
@@ -715,7 +722,10 @@ hipError_t launch_prop1d_il(const PropSeg* segs_dev, int64_t nblocks, int64_t bp
         (nblocks + nwaves - 1) / nwaves > kIlMax)
         return hipErrorInvalidValue;
     uint32_t nb = (uint32_t)nblocks, bp = (uint32_t)bps;
-    void* args[] = {&segs_dev, &nb, &bp, &D, &OD};
+    // XCD-aware positions need whole rounds of 8 workgroups
+    const char* env = getenv("HX_IL_XCD");
+    uint32_t xcd = (nwaves % 8 == 0 && !(env && env[0] == '0')) ? 1u : 0u;
+    void* args[] = {&segs_dev, &nb, &bp, &D, &OD, &xcd};
     return hipLaunchKernel(k, dim3((unsigned)nwaves), dim3(64), args, 0, stream);
 }
 
