@@ -132,14 +132,40 @@ hx_status hx_heat_vc_forward(hx_ctx ctx, const hx_vc_args* a, const hx_event* de
         if (t % S == 0) return pck + (size_t)(t / S - 1) * bytes;
         return pw + (size_t)(t % 2) * bytes;
     };
+    // Aligned grids run each stretch between kept states (u0, the checkpoints,
+    // uT) in fused passes of up to kVcFusedMax steps, as even as the stretch
+    // allows, ping-ponging through the two work states; the others step by
+    // step.  Both give the same bits.
+    VCArgs probe{pu0, pk, nullptr, puT, nullptr, nx, ny, tau, rows};
+    const bool fused = vc_fused_supported(dt, probe) &&
+                       (T <= 1 || (((uintptr_t)pw & 15u) == 0 && (bytes & 15u) == 0)) &&
+                       (sc.nseg <= 1 || (((uintptr_t)pck & 15u) == 0));
     return c->submit(SC_COMPUTE, deps, ndeps, acc, "heat_vc_forward",
                      [=](hipStream_t st) -> hipError_t {
                          if (T == 0)
                              return hipMemcpyAsync(puT, pu0, bytes, hipMemcpyDeviceToDevice, st);
-                         for (int t = 0; t < T; ++t) {
-                             VCArgs v{loc(t), pk, nullptr, loc(t + 1), nullptr, nx, ny, tau, rows};
-                             hipError_t e = launch_vc_step(dt, false, v, st);
-                             if (e != hipSuccess) return e;
+                         if (!fused) {
+                             for (int t = 0; t < T; ++t) {
+                                 VCArgs v{loc(t), pk, nullptr, loc(t + 1), nullptr, nx, ny, tau,
+                                          rows};
+                                 hipError_t e = launch_vc_step(dt, false, v, st);
+                                 if (e != hipSuccess) return e;
+                             }
+                             return hipSuccess;
+                         }
+                         for (int t0 = 0; t0 < T; t0 += S) {
+                             const int t1 = std::min(t0 + S, T);
+                             const int L = t1 - t0;
+                             const int np = (L + kVcFusedMax - 1) / kVcFusedMax;
+                             char* src = loc(t0);
+                             for (int j = 0; j < np; ++j) {
+                                 const int d = L / np + (j < L % np ? 1 : 0);
+                                 char* dst = j + 1 == np ? loc(t1) : pw + (size_t)(j % 2) * bytes;
+                                 VCArgs v{src, pk, nullptr, dst, nullptr, nx, ny, tau, rows};
+                                 hipError_t e = launch_vc_forward(dt, d, v, st);
+                                 if (e != hipSuccess) return e;
+                                 src = dst;
+                             }
                          }
                          return hipSuccess;
                      },

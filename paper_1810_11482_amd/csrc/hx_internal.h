@@ -344,6 +344,12 @@ struct VCArgs {
 };
 
 hipError_t launch_vc_step(int dtype, bool adjoint, const VCArgs& v, hipStream_t stream);
+// `steps` (1..4) forward steps fused in one pass, u -> out (the same bits as
+// that many single steps); for grids whose rows are 16-byte aligned with nx a
+// multiple of 4 and under 2 GiB (vc_fused_supported), else hipErrorInvalidValue.
+constexpr int kVcFusedMax = 4;
+bool vc_fused_supported(int dtype, const VCArgs& v);
+hipError_t launch_vc_forward(int dtype, int steps, const VCArgs& v, hipStream_t stream);
 hipError_t launch_fold(int dtype, void* acc, double* total, int64_t n, hipStream_t stream);
 hipError_t launch_fill(int dtype, void* p, int64_t n, double v, hipStream_t stream);
 hipError_t launch_cast64(int dtype, const double* src, void* dst, int64_t n, hipStream_t stream);

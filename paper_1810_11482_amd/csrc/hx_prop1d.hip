@@ -417,8 +417,11 @@ __global__ __launch_bounds__(64) void k_prop1d(const PropSeg* __restrict__ segs,
 // band of the arrays instead of nw bands far apart, which measured 9 % more
 // HBM bandwidth for the same bytes than contiguous spans.  A block is read
 // with the 64 cells on each side that its windows reach (12.5 % more read
-// requests, mostly served by the caches, since the neighbouring blocks are in
-// flight on neighbouring waves); loads and stores are nontemporal.
+// requests; the counters put about 14 % more bytes fetched than the block's
+// own, because the neighbouring blocks run on other XCDs, and placing them on
+// one XCD measured slower).  Loads are ordinary cached loads and stores are
+// nontemporal: the launch measured 4 % faster than with nontemporal loads,
+// and ordinary stores were no faster.
 //
 // Because a block's whole window (1152 cells) is loaded at once, it can share
 // one scale: the window's largest finite |x| is brought into [2^14, 2^15) by
@@ -474,20 +477,13 @@ struct Split8h {
 // milliseconds into sustained launches.
 template <int NC, int S0>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NC - 2 * S0 <= 7 ? 3 : 1, 8)))
-void k_prop1d_il(const PropSeg* __restrict__ segs, uint32_t nblocks, uint32_t bps, int D, int OD,
-                 uint32_t xcd) {
+void k_prop1d_il(const PropSeg* __restrict__ segs, uint32_t nblocks, uint32_t bps, int D, int OD) {
     __shared__ __attribute__((aligned(16))) char lds[2 * kWPlane];
     __shared__ uint16_t fails[kIlMax];  // this wave's blocks that failed the check
     const int l = threadIdx.x, i = l & 31, g = l >> 5;
     const uint32_t w = blockIdx.x, nw = gridDim.x;
     if (w >= nblocks) return;
-    // The wave's position in each round of nw blocks.  Workgroups are handed
-    // to the 8 XCDs in turn (workgroup w to XCD w mod 8), so with xcd set the
-    // waves of one XCD take consecutive positions (XCD x the x-th eighth of
-    // the round): neighbouring blocks, whose windows share 64 cells, then
-    // meet in one L2.
-    const uint32_t wpos = xcd ? (w % 8) * (nw / 8) + w / 8 : w;
-    const int nk = (int)((nblocks - 1 - wpos) / nw) + 1;  // at most kIlMax (the host's grid)
+    const int nk = (int)((nblocks - 1 - w) / nw) + 1;  // at most kIlMax (the host's grid)
     int nfail = 0;
     const uint32_t lv = segs[0].levels16;
     const int texp = segs[0].texp;
@@ -561,19 +557,19 @@ void k_prop1d_il(const PropSeg* __restrict__ segs, uint32_t nblocks, uint32_t bp
         thr = mx > 0.f ? chk : 0.f;
     };
     auto fetch = [&](int k, f32x4 v[5]) {
-        const uint32_t b = wpos + (uint32_t)k * nw;
+        const uint32_t b = w + (uint32_t)k * nw;
         const uint32_t sg = b / bps;
         const PropSeg& s = segs[sg];
         const int64_t c0 = 1024 * (int64_t)(b - sg * bps);
         const int64_t cx = (left ? c0 - 64 : c0 + 1024) + 4 * q;
         if (c0 >= 1024 && c0 + 1024 + 64 <= s.n) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) v[j] = gload<true>(s.in + c0 + 256 * j + 4 * l);
-            v[4] = gload<true>(s.in + cx);
+            for (int j = 0; j < 4; ++j) v[j] = gload(s.in + c0 + 256 * j + 4 * l);
+            v[4] = gload(s.in + cx);
         } else {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) v[j] = load4<false, true>(s, c0 + 256 * j + 4 * l);
-            v[4] = load4<false, true>(s, cx);
+            for (int j = 0; j < 4; ++j) v[j] = load4<false>(s, c0 + 256 * j + 4 * l);
+            v[4] = load4<false>(s, cx);
         }
     };
     // Output transposition, as in the span walk, through the two planes of
@@ -598,7 +594,7 @@ void k_prop1d_il(const PropSeg* __restrict__ segs, uint32_t nblocks, uint32_t bp
         f32x4 v[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) v[j] = *reinterpret_cast<const f32x4*>(lds + rd[j]);
-        const uint32_t b = wpos + (uint32_t)k * nw;
+        const uint32_t b = w + (uint32_t)k * nw;
         const uint32_t sg = b / bps;
         const PropSeg& s = segs[sg];
         const int64_t o = 1024 * (int64_t)(b - sg * bps) + 4 * l;
@@ -656,7 +652,7 @@ void k_prop1d_il(const PropSeg* __restrict__ segs, uint32_t nblocks, uint32_t bp
     // the listed blocks, stepped now that the pipeline's registers are free
     __syncthreads();
     for (int f = 0; f < nfail; ++f) {
-        const uint32_t b = wpos + (uint32_t)fails[f] * nw;
+        const uint32_t b = w + (uint32_t)fails[f] * nw;
         const uint32_t sg = b / bps;
         step_block(segs[sg], 1024 * (int64_t)(b - sg * bps), D,
                    [&](int c) -> float& { return reinterpret_cast<float*>(lds)[c]; });
@@ -722,10 +718,7 @@ hipError_t launch_prop1d_il(const PropSeg* segs_dev, int64_t nblocks, int64_t bp
         (nblocks + nwaves - 1) / nwaves > kIlMax)
         return hipErrorInvalidValue;
     uint32_t nb = (uint32_t)nblocks, bp = (uint32_t)bps;
-    // XCD-aware positions need whole rounds of 8 workgroups
-    const char* env = getenv("HX_IL_XCD");
-    uint32_t xcd = (nwaves % 8 == 0 && !(env && env[0] == '0')) ? 1u : 0u;
-    void* args[] = {&segs_dev, &nb, &bp, &D, &OD, &xcd};
+    void* args[] = {&segs_dev, &nb, &bp, &D, &OD};
     return hipLaunchKernel(k, dim3((unsigned)nwaves), dim3(64), args, 0, stream);
 }
 

@@ -159,7 +159,7 @@ __device__ __forceinline__ void load_row2d(const Band2D& b, const Strip& w, int6
         const VT* src = reinterpret_cast<const VT*>(rp + w.xl);
 #pragma unroll
         for (int q = 0; q < C / VN; ++q) {
-            const VT x = __builtin_nontemporal_load(src + q);
+            const VT x = src[q];
 #pragma unroll
             for (int e = 0; e < VN; ++e) dst[q * VN + e] = x[e];
         }
@@ -312,7 +312,7 @@ __device__ __forceinline__ void load_fast(const FastIO<T, C>& io, int64_t y, T (
                          : (ys < io.ny ? io.in + ys * io.nx : io.bot + (ys - io.ny) * io.nx);
 #pragma unroll
     for (int q = 0; q < C / VN; ++q) {
-        const VT x = __builtin_nontemporal_load(reinterpret_cast<const VT*>(rp + io.xload[q]));
+        const VT x = *(reinterpret_cast<const VT*>(rp + io.xload[q]));
 #pragma unroll
         for (int e = 0; e < VN; ++e)
             dst[q * VN + e] = (EDGE && (zr || !io.colin[q])) ? T(0) : x[e];

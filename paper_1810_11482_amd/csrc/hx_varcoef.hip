@@ -83,7 +83,7 @@ __device__ __forceinline__ void fetch_row(const T* __restrict__ f, int64_t y, in
         const int64_t xv = lin ? xl : nx - C;
 #pragma unroll
         for (int q = 0; q < C / VN; ++q) {
-            const V2 x = __builtin_nontemporal_load((GV2*)(row + xv) + q);
+            const V2 x = *((GV2*)(row + xv) + q);
 #pragma unroll
             for (int e = 0; e < VN; ++e) r.c[q * VN + e] = lin ? x[e] : T(0);
         }
@@ -404,6 +404,145 @@ unsigned grid_for(int64_t n) {
     return (unsigned)g;
 }
 
+// D fused forward steps (temporal blocking), for aligned grids (every row
+// 16-byte aligned, nx a multiple of C, under 2 GiB).  A wave owns 64*C
+// columns, of which lanes 1..62 are its output: the strips overlap by one
+// lane on each side, and the outer lanes' values go stale one column per step
+// (from lanes 0 and 63 inward), which D <= C steps keep out of lanes 1..62.
+// Rows stream top to bottom once: input row i (u and kappa) enters level 0;
+// level k (1..D) then produces row i - k from level k-1's rows i-k-1 .. i-k+1
+// and kappa rows i-k-1 .. i-k+1, so u and kappa are read once and u written
+// once per D steps.  Each level keeps three rows of C cells, kappa D + 2.  The
+// arithmetic, and its order, is the single step's (k_vc_step), so a fused
+// pass gives the same bits as D single steps.
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_vc_fwd(VCDev a, int64_t nstrips, int64_t nwaves) {
+    static_assert(D >= 1 && D <= C, "the halo lane covers at most C steps");
+    typedef T V2 __attribute__((ext_vector_type(16 / sizeof(T))));
+    typedef __attribute__((address_space(1))) const V2 GV2;
+    constexpr int VN = 16 / sizeof(T);
+    constexpr int W = S - 2 * C;  // output columns per strip
+    const int wpg = blockDim.x >> 6;
+    const int64_t wave =
+        (int64_t)blockIdx.x * wpg + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wave >= nwaves) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t strip = wave % nstrips, chunk = wave / nstrips;
+    const int64_t nx = a.nx, ny = a.ny;
+    const int64_t xl = strip * W - C + (int64_t)lane * C;  // this lane's first column
+    const int64_t y0 = chunk * a.rows;
+    const int64_t y1 = (y0 + a.rows < ny) ? y0 + a.rows : ny;
+    const T dt = static_cast<T>(a.dt);
+    const T* U = static_cast<const T*>(a.u);
+    const T* K = static_cast<const T*>(a.kappa);
+    const bool lin = xl >= 0 && xl + C <= nx;  // the lane's cells: all inside or all outside
+    const int64_t xv = lin ? xl : 0;
+    // row y of f for this lane: a clamped address, zeros outside the domain
+    auto load = [&](const T* f, int64_t y, T (&v)[C]) {
+        const bool rin = y >= 0 && y < ny;
+        const T* row = f + (y < 0 ? 0 : (y >= ny ? ny - 1 : y)) * nx;
+#pragma unroll
+        for (int q = 0; q < C / VN; ++q) {
+            const V2 x = *((GV2*)(row + xv) + q);
+#pragma unroll
+            for (int e = 0; e < VN; ++e) v[q * VN + e] = (rin && lin) ? x[e] : T(0);
+        }
+    };
+    const int bytes = (int)(ny * nx * (int64_t)sizeof(T));
+    const __amdgpu_buffer_rsrc_t rso =
+        __builtin_amdgcn_make_buffer_rsrc(a.out, (short)0, bytes, BUF_DWORD3);
+    const bool store_lane = lane >= 1 && lane <= 62 && lin;
+    const uint32_t lane_off = store_lane ? (uint32_t)(xl * (int64_t)sizeof(T)) : OOB_OFFSET;
+
+    T ur[D][3][C];     // level k: rows i-k-1, i-k, i-k+1 (after the shift below)
+    T kr[D + 2][C];    // kappa rows i-D-1 .. i
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+#pragma unroll
+            for (int j = 0; j < C; ++j) ur[k][m][j] = T(0);
+#pragma unroll
+    for (int m = 0; m < D + 2; ++m)
+#pragma unroll
+        for (int j = 0; j < C; ++j) kr[m][j] = T(0);
+    T un[C], kn[C];
+    load(U, y0 - D, un);
+    load(K, y0 - D, kn);
+    for (int64_t i = y0 - D; i < y1 + D; ++i) {
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                ur[k][0][j] = ur[k][1][j];
+                ur[k][1][j] = ur[k][2][j];
+            }
+#pragma unroll
+        for (int m = 0; m < D + 1; ++m)
+#pragma unroll
+            for (int j = 0; j < C; ++j) kr[m][j] = kr[m + 1][j];
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            ur[0][2][j] = un[j];
+            kr[D + 1][j] = kn[j];
+        }
+        // row i+1 in flight (rows past the domain are clamped reads)
+        load(U, i + 1, un);
+        load(K, i + 1, kn);
+        T out[C];
+#pragma unroll
+        for (int k = 1; k <= D; ++k) {
+            const int64_t r = i - k;  // the row level k produces
+            const T* fm = ur[k - 1][0];
+            const T* f0 = ur[k - 1][1];
+            const T* fp = ur[k - 1][2];
+            const T* km = kr[D - k];
+            const T* k0 = kr[D - k + 1];
+            const T* kp = kr[D - k + 2];
+            const bool nin = r - 1 >= 0, sin = r + 1 < ny;
+            const T fwl = dpp_move<DPP_WAVE_SHR1>(f0[C - 1]);
+            const T fel = dpp_move<DPP_WAVE_SHL1>(f0[0]);
+            const T kwl = dpp_move<DPP_WAVE_SHR1>(k0[C - 1]);
+            const T kel = dpp_move<DPP_WAVE_SHL1>(k0[0]);
+            T v[C];
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                const T fc = f0[j];
+                const T kc = k0[j];
+                const int64_t x = xl + j;
+                const T fw = j > 0 ? f0[j - 1] : fwl;
+                const T fe = j + 1 < C ? f0[j + 1] : fel;
+                const T kw = (x - 1 >= 0) ? (j > 0 ? k0[j - 1] : kwl) : kc;
+                const T ke = (x + 1 < nx) ? (j + 1 < C ? k0[j + 1] : kel) : kc;
+                const T fW = (x - 1 >= 0) ? fw : T(0);
+                const T fE = (x + 1 < nx) ? fe : T(0);
+                const T kN = nin ? km[j] : kc;
+                const T kS = sin ? kp[j] : kc;
+                const T fN = nin ? fm[j] : T(0);
+                const T fS = sin ? fp[j] : T(0);
+                const T kfw = (kc + kw) * T(0.5);
+                const T kfe = (kc + ke) * T(0.5);
+                const T kfn = (kc + kN) * T(0.5);
+                const T kfs = (kc + kS) * T(0.5);
+                T acc = kfw * (fW - fc);
+                acc = fmaT(kfe, fE - fc, acc);
+                acc = fmaT(kfn, fN - fc, acc);
+                acc = fmaT(kfs, fS - fc, acc);
+                v[j] = fmaT(dt, acc, fc);
+            }
+            if (k < D) {
+#pragma unroll
+                for (int j = 0; j < C; ++j) ur[k][2][j] = v[j];
+            } else {
+#pragma unroll
+                for (int j = 0; j < C; ++j) out[j] = v[j];
+            }
+        }
+        const int64_t r = i - D;
+        if (r >= y0 && r < y1) store_row<T>(rso, lane_off, r, nx, out);
+    }
+}
+
 }  // namespace
 
 hipError_t launch_vc_step(int dtype, bool adjoint, const VCArgs& v, hipStream_t st) {
@@ -431,6 +570,41 @@ hipError_t launch_vc_step(int dtype, bool adjoint, const VCArgs& v, hipStream_t 
         else { if (vecform) HX_VC_LAUNCH(double, false, true); else HX_VC_LAUNCH(double, false, false); }
     }
 #undef HX_VC_LAUNCH
+    return hipGetLastError();
+}
+
+bool vc_fused_supported(int dtype, const VCArgs& v) {
+    auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; };
+    const int es = dtype == 0 ? 4 : 8;
+    return v.nx % C == 0 && (v.nx * es) % 16 == 0 && al(v.u) && al(v.kappa) && al(v.out) &&
+           v.nx * v.ny * es < (int64_t(1) << 31) && v.nx > 0 && v.ny > 0;
+}
+
+hipError_t launch_vc_forward(int dtype, int steps, const VCArgs& v, hipStream_t st) {
+    if (steps < 1 || steps > C || !vc_fused_supported(dtype, v)) return hipErrorInvalidValue;
+    VCDev a{v.u, v.kappa, nullptr, v.out, nullptr, v.nx, v.ny, v.dt, v.rows > 0 ? v.rows : 64, 1};
+    const int64_t nstrips = (v.nx + (S - 2 * C) - 1) / (S - 2 * C);
+    const int64_t nchunks = (v.ny + a.rows - 1) / a.rows;
+    const int64_t nwaves = nstrips * nchunks;
+    const int wpg = 4;
+    const dim3 block(64 * wpg), grid((unsigned)((nwaves + wpg - 1) / wpg));
+#define HX_VC_FWD(T, D) hipLaunchKernelGGL((k_vc_fwd<T, D>), grid, block, 0, st, a, nstrips, nwaves)
+    if (dtype == 0) {
+        switch (steps) {
+            case 1: HX_VC_FWD(float, 1); break;
+            case 2: HX_VC_FWD(float, 2); break;
+            case 3: HX_VC_FWD(float, 3); break;
+            default: HX_VC_FWD(float, 4); break;
+        }
+    } else {
+        switch (steps) {
+            case 1: HX_VC_FWD(double, 1); break;
+            case 2: HX_VC_FWD(double, 2); break;
+            case 3: HX_VC_FWD(double, 3); break;
+            default: HX_VC_FWD(double, 4); break;
+        }
+    }
+#undef HX_VC_FWD
     return hipGetLastError();
 }
 

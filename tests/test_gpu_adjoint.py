@@ -283,3 +283,57 @@ def test_full_size_against_oracle_windows(ctx):
     an = float(np.sum(lam64 * du) + np.sum(gk64 * dk))
     print(f"full size fp64 directional derivative: analytic {an:.10e} fd {fd:.10e}")
     assert abs(fd - an) <= 1e-6 * abs(an)
+
+
+def vc_forward(ctx, u0, kappa, dt, T, ckpt, dtype):
+    """u_T from hx_heat_vc_forward (fused passes where the grid is aligned)."""
+    ny, nx = u0.shape
+    n = ny * nx
+    es = np.dtype(dtype).itemsize
+    S, nseg = hx.hx_vc_schedule(T, ckpt)
+    bu0, bk = upload(ctx, u0.astype(dtype)), upload(ctx, kappa.astype(dtype))
+    buT = hx.hx_buffer_create(ctx, n * es)
+    bck = hx.hx_buffer_create(ctx, max(nseg - 1, 1) * n * es)
+    bw = hx.hx_buffer_create(ctx, 2 * n * es)
+    a = hx.hx_vc_args(code(dtype), nx, ny, dt, T, ckpt, bu0, bk, buT, bck if nseg > 1 else 0,
+                      bw if T > 1 else 0, 0, 0, 0, 0, 0, 0)
+    wait(ctx, hx.hx_heat_vc_forward(ctx, a))
+    out = download(ctx, buT, (ny, nx), dtype)
+    cks = download(ctx, bck, (max(nseg - 1, 1), ny, nx), dtype)
+    for b in (bu0, bk, buT, bck, bw):
+        hx.hx_buffer_destroy(ctx, b)
+    return out, cks[:nseg - 1]
+
+
+def vc_stepped(ctx, u0, kappa, dt, T, dtype):
+    """u_T by T single steps (hx_heat_vc_step), for bitwise comparison."""
+    ny, nx = u0.shape
+    bk = upload(ctx, kappa.astype(dtype))
+    bufs = [upload(ctx, u0.astype(dtype)), hx.hx_buffer_create(ctx, u0.astype(dtype).nbytes)]
+    for t in range(T):
+        wait(ctx, hx.hx_heat_vc_step(ctx, code(dtype), nx, ny, dt, bufs[t % 2], bk,
+                                     bufs[(t + 1) % 2]))
+    out = download(ctx, bufs[T % 2], (ny, nx), dtype)
+    for b in bufs + [bk]:
+        hx.hx_buffer_destroy(ctx, b)
+    return out
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("shape,T,ckpt", [((300, 1000), 10, 10), ((130, 496), 7, 3),
+                                          ((64, 248), 9, 0), ((5, 8), 4, 4), ((1, 4), 3, 0),
+                                          ((257, 252), 13, 5)])
+def test_fused_forward_equals_steps_and_oracle(ctx, dtype, shape, T, ckpt):
+    """The forward run in fused passes of up to four steps (strips of 248
+    output columns, chunks of 64 rows, ragged at the ends): the same bits as T
+    single steps, every checkpoint equal to the stepped state, and the oracle's
+    forward to the suite's bar."""
+    u0 = workloads.gaussian_bumps(*shape, 3, 7.0, 616, np.float64).astype(dtype)
+    kappa = kappa_field(shape, 9, dtype)
+    out, cks = vc_forward(ctx, u0, kappa, 0.2, T, ckpt, dtype)
+    assert np.array_equal(out, vc_stepped(ctx, u0, kappa, 0.2, T, dtype))
+    S, nseg = hx.hx_vc_schedule(T, ckpt)
+    for k in range(nseg - 1):
+        assert np.array_equal(cks[k], vc_stepped(ctx, u0, kappa, 0.2, (k + 1) * S, dtype)), k
+    ref = oracle.heatvc_forward(u0.astype(np.float64), kappa.astype(np.float64), 0.2, T)
+    assert rel_l2(out, ref) <= TOL[dtype] and rel_max(out, ref) <= 10 * TOL[dtype]
