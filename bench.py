@@ -10,10 +10,14 @@ resident in HBM (laid out back to back in one arena): each pass of 50 fused
 steps is one node of the future graph, launched as one batched kernel over
 all 64 partitions with every partition's halos read from its neighbours.  One
 bench "step" is the whole 50-step run over the whole array.  The pass runs in
-the faster of the batched plan's two forms, chosen by a short untimed sweep:
-the direct form (the tile kernel stepping in registers, vector ALUs only) or
-the propagator form (the 50 steps as one convolution with the 50-step
-propagator on the matrix cores; see `config.update_form`).
+the batched plan's form, pass depth and walk that the library's autotuner
+picks: the direct form (the tile kernel stepping in registers, vector ALUs
+only) or the propagator form (the 50 steps as one convolution with the
+50-step propagator on the matrix cores; see `config.update_form`).  The
+default warm-up (100 passes, about 40 ms) runs before the timed region so
+that the card's clocks have settled: in the first 50-100 back-to-back passes
+after an idle spell its power management first lets them run fast, then pulls
+them down, then settles (per-launch times are in the log).
 
 The same configuration host to host (pinned host partitions, per-partition
 H2D -> 50-step kernel -> D2H, overlapped) is `host_to_host`, with the copy
@@ -47,7 +51,7 @@ MFMA_16BIT_PEAK = 2.5e15     # flop/s, dense bf16 and fp16 matrix cores
 FLOPS_PER_UPDATE_1D = 3      # rescaled update w' = fma(b, l + rt, w): one add + one fma
 BYTES_PER_CELL_PASS = 8      # one fp32 read + one fp32 write per cell per pass
 MFMA_FLOPS_PER_CHUNK = 6 * 32 * 32 * 16 * 2   # span walk: six bf16 32x32x16 products per chunk
-MFMA_FLOPS_PER_CHUNK_IL = 3 * 32 * 32 * 16 * 2  # interleaved walk: three fp16 products
+MFMA_FLOPS_PER_CHUNK_IL = 3 * 32 * 32 * 16 * 2  # block/interleaved walks: three fp16 products
 ROOT = os.path.dirname(os.path.abspath(__file__))
 # per form: the committed counter summary of its kernel and the sources it is built from
 KERNELS = {
@@ -58,6 +62,9 @@ KERNELS = {
                    ("paper_1810_11482_amd/csrc/hx_prop1d.hip",
                     "paper_1810_11482_amd/csrc/hx_internal.h")),
     "propagator_il": ("prop1d_il_2p28_fp32_traffic.md",
+                      ("paper_1810_11482_amd/csrc/hx_prop1d.hip",
+                       "paper_1810_11482_amd/csrc/hx_internal.h")),
+    "propagator_bw": ("prop1d_bw_2p28_fp32_traffic.md",
                       ("paper_1810_11482_amd/csrc/hx_prop1d.hip",
                        "paper_1810_11482_amd/csrc/hx_internal.h")),
 }
@@ -252,8 +259,10 @@ class BatchedPass:
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    # the card's clocks settle over the first 50-100 back-to-back passes after
+    # an idle spell (power management): the warm-up covers that transient
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--log2n", type=int, default=28)
     ap.add_argument("--parts", type=int, default=64)
     ap.add_argument("--cells-per-lane", type=int, default=0, help="0 = pick by a short sweep")
@@ -261,7 +270,7 @@ def main():
                     help="form of the headline pass; auto = the faster in a short sweep")
     ap.add_argument("--span-blocks", type=int, default=0,
                     help="propagator form: 1024-cell blocks per wave, -1 = the interleaved "
-                         "walk, 0 = sweep both walks")
+                         "walk, -2 = the block walk, 0 = sweep the walks")
     ap.add_argument("--streams", type=int, default=4,
                     help="compute streams of the context (the per-partition graph spreads its "
                          "nodes over them)")
@@ -312,10 +321,10 @@ def main():
         cands += [("direct", c, 0) for c in ([args.cells_per_lane] if args.cells_per_lane
                                             else [32, 16])]
     if args.form in ("auto", "propagator"):
-        # the interleaved walk (-1, the plan's choice for equal partitions) and
-        # contiguous spans of 128 blocks per wave
+        # the block walk (-2, the plan's choice for equal partitions), the
+        # interleaved walk and contiguous spans of 128 blocks per wave
         cands += [("propagator", 0, sp) for sp in ([args.span_blocks] if args.span_blocks
-                                                  else [-1, 128])]
+                                                  else [-2, -1, 128])]
     swept = []
     for form, cpl_c, span_c in cands:
         fcode = hx.HX_FORM_PROPAGATOR if form == "propagator" else hx.HX_FORM_DIRECT
@@ -360,11 +369,11 @@ def main():
         tuned, t_wpg, t_grid = None, 0, -1
     fcode = hx.HX_FORM_PROPAGATOR if form == "propagator" else hx.HX_FORM_DIRECT
     if span == 0 and form == "propagator":
-        span = -1  # the plan's own choice for equal partitions: the interleaved walk
+        span = -2  # the plan's own choice for equal partitions: the block walk
     by_form = {}
     for t, f, c_, s_ in swept:
-        key = (f"{f}_cpl{c_}" if f == "direct" else
-               f"{f}_interleaved" if s_ == -1 else f"{f}_span{s_ or 'auto'}")
+        key = (f"{f}_cpl{c_}" if f == "direct" else f"{f}_interleaved" if s_ == -1 else
+               f"{f}_block_walk" if s_ == -2 else f"{f}_span{s_ or 'auto'}")
         by_form[key] = t * 1e3
 
     # ------------------------------------------------------------ timed region
@@ -423,29 +432,29 @@ def main():
     bytes_per_launch = cells_per_launch * BYTES_PER_CELL_PASS
     bw = bytes_per_launch / (avg_ms * 1e-3)
     hbm_frac = bw / HBM_PEAK
-    kform = "propagator_il" if form == "propagator" and span == -1 else form
+    fp16_walk = form == "propagator" and span in (-1, -2)
+    kform = ({-1: "propagator_il", -2: "propagator_bw"}.get(span, form) if form == "propagator"
+             else form)
     traffic = measured_traffic(kform)
     if form == "propagator":
-        # matrix-core work, unpruned: 1024-cell iterations x NC window chunks x
-        # six 32x32x16 bf16 products (span walk) or three fp16 ones (interleaved
-        # walk); NC = 9 at 50 steps
+        # matrix-core work, unpruned: 1024-cell blocks x NC window chunks x
+        # six 32x32x16 bf16 products (span walk) or three fp16 ones (block and
+        # interleaved walks); NC = 9 at 50 steps
         od = 8 * ((tb + 7) // 8)
         nc = (32 + tb + od + 15) // 16
-        mf_per_launch = cells_per_launch / 1024 * nc * (MFMA_FLOPS_PER_CHUNK_IL if span == -1
+        mf_per_launch = cells_per_launch / 1024 * nc * (MFMA_FLOPS_PER_CHUNK_IL if fp16_walk
                                                         else MFMA_FLOPS_PER_CHUNK)
         mf = mf_per_launch / (avg_ms * 1e-3)
         mfma_frac = mf / MFMA_16BIT_PEAK
-        kname = f"k_prop1d_il<{nc}>" if span == -1 else f"k_prop1d<{nc}>"
+        kname = {-1: f"k_prop1d_il<{nc}>", -2: f"k_prop1d_bw<{nc}>"}.get(span, f"k_prop1d<{nc}>")
         if mfma_frac >= hbm_frac:
             roof = {"bound": "mfma", "achieved": mf / 1e12, "peak": MFMA_16BIT_PEAK / 1e12,
                     "unit": "TFLOP/s", "frac": mfma_frac}
         else:
             roof = {"bound": "hbm", "achieved": bw / 1e9, "peak": HBM_PEAK / 1e9,
                     "unit": "GB/s", "frac": hbm_frac}
-        mkey = "mfma_fp16_flops_per_launch" if span == -1 else "mfma_bf16_flops_per_launch"
-        roof.update({mkey: mf_per_launch, "mfma_frac": mfma_frac,
-                     "fixup_kernel": "k_prop1d_fix (steps the blocks that fail the accuracy "
-                                     "check; inside the launch's HIP-event span)"})
+        mkey = "mfma_fp16_flops_per_launch" if fp16_walk else "mfma_bf16_flops_per_launch"
+        roof.update({mkey: mf_per_launch, "mfma_frac": mfma_frac})
     else:
         flops_per_launch = cells_per_launch * tb * FLOPS_PER_UPDATE_1D
         fl = flops_per_launch / (avg_ms * 1e-3)
@@ -465,10 +474,13 @@ def main():
     log(f"headline ({form}): {ms_per_step:.3f} ms/step, {value:.4e} cell-updates/s, kernel avg "
         f"{avg_ms:.4f} ms")
     check = ("; every 1024-cell block checks its outputs against the split's and the "
-             "pruning's absolute error bound and is stepped in f32 by a fix-up kernel when "
-             "an output is non-finite or too small for that bound")
-    if form == "propagator" and span == -1:
-        form_desc = ("propagator, interleaved walk: the 50 steps as one convolution with the "
+             "pruning's absolute error bound and is stepped in f32 by its own wave, in the "
+             "same launch, when an output is non-finite or too small for that bound")
+    if fp16_walk:
+        walk = ("block walk (one wave per 1024-cell block, the tap operands staged in LDS "
+                "from a table the plan builds)" if span == -2 else
+                "interleaved walk (a persistent grid)")
+        form_desc = (f"propagator, {walk}: the 50 steps as one convolution with the "
                      "50-step propagator (101 taps, FP64 on the host), a banded Toeplitz product "
                      "on 32x32x16 fp16 matrix-core tiles; each 1152-cell window scaled by a "
                      "power of two and split into two fp16 terms (hi + lo), the taps likewise, "
@@ -504,8 +516,8 @@ def main():
                    "cells": n, "parts": args.parts, "time_steps": T, "time_block": tb,
                    "update_form": form_desc,
                    "cells_per_lane": cpl if form == "direct" else None,
-                   "span_blocks": ("interleaved walk" if span == -1 else span or "plan's choice")
-                   if form == "propagator" else None,
+                   "span_blocks": ({-1: "interleaved walk", -2: "block walk"}.get(
+                       span, span or "plan's choice") if form == "propagator" else None),
                    "halo_width": hw, "launches_per_step": bp.passes,
                    "error_vs_oracle_every_cell": full_err},
         "roofline": roof,
@@ -1134,10 +1146,14 @@ def adjoint_leg(hx, ctx):
             hx.hx_event_release(ctx, e)
         times = {"forward_ms": (t1 - t0) * 1e3, "backward_ms": (t2 - t1) * 1e3}
     T = spec.steps
-    fwd_bytes = n * T * 12            # u read + write, kappa read per step
-    rec_bytes = n * (T - nseg) * 12   # recomputed steps
+    # The forward runs each stretch between kept states in fused passes of at
+    # most four steps (aligned grids, as here); one pass reads u and kappa and
+    # writes u once, whatever its depth.
+    fwd_passes = sum(-(-min(S, T - t0) // 4) for t0 in range(0, T, S))
+    fwd_bytes = n * fwd_passes * 12   # u read + write, kappa read per pass
+    rec_bytes = n * (T - nseg) * 12   # recomputed single steps
     adj_bytes = n * T * 24            # u_t, lam in/out, kappa, accumulator read + write
-    res = {"cells": n, "steps": T, "segment": S, **times,
+    res = {"cells": n, "steps": T, "segment": S, **times, "forward_passes": fwd_passes,
            "forward_cell_updates_per_s": n * T / (times["forward_ms"] * 1e-3),
            "forward_hbm_algorithmic_GBps": fwd_bytes / (times["forward_ms"] * 1e-3) / 1e9,
            "backward_hbm_algorithmic_GBps": (rec_bytes + adj_bytes) /

@@ -325,10 +325,13 @@ typedef struct {
                                    contiguous spans of that many blocks per wave (at most
                                    256, else HX_ERR_ARG); -1 = the
                                    interleaved walk (a persistent grid, wave w taking blocks
-                                   w, w + grid, ... of all segments numbered back to back;
-                                   HX_ERR_ARG unless every segment has the same n and r);
-                                   0 = the tuned walk, else interleaved where allowed, else
-                                   spans chosen to fill the device in whole rounds */
+                                   w, w + grid, ... of all segments numbered back to back);
+                                   -2 = the block walk (one wave per block, the grid covering
+                                   every block; at most 65535 segments); -1 and -2 are
+                                   HX_ERR_ARG unless every segment has the same n and r, and
+                                   give the same bits;
+                                   0 = the tuned walk, else the block walk where allowed,
+                                   else spans chosen to fill the device in whole rounds */
 } hx_batch_desc;
 
 /* Build a batch: `count` 1D segments, each with its own size, r, boundaries
@@ -343,16 +346,16 @@ hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* desc, hx_plan*
  * [r, 1-2r, r], see hx_propagator_coefficients), a banded Toeplitz product run
  * on matrix-core tiles and accumulated in f32.  Walked in spans, every f32
  * operand takes an exact three-term bf16 split (six products per pair, each
- * within 2^-20 of itself); walked interleaved (segments of one size and one
- * rate), each 1152-cell window is scaled by a power of two and split into two
- * fp16 terms (three products per pair, each within about 3 * 2^-22 of
- * itself).  Both walks prune product levels whose taps are tiny, and the fp16
+ * within 2^-20 of itself); walked interleaved or one wave per block
+ * (segments of one size and one rate), each 1152-cell window is scaled by a
+ * power of two and split into two fp16 terms (three products per pair, each
+ * within about 3 * 2^-22 of itself).  All walks prune product levels whose
+ * taps are tiny, and the fp16
  * split has absolute floors; so every 1024-cell block checks its outputs
  * against the bound E of those absolute terms: unless every output is finite
  * and at least 2^21 E times the largest finite |x| of the block's window (E
  * is a few 2^-32 of the tap mass at r = 1/4, steps = 50), the block is
- * advanced by f32 stepping instead, in the same launch (by its wave, after
- * the wave's other blocks).  Each
+ * advanced by f32 stepping instead, in the same launch (by its wave).  Each
  * output is then either within a few 2^-22 of sum_j |p_j u_{i+j}| plus 2^-21
  * of itself, or the stepped f32 result: f32 accuracy cell by cell, also next
  * to cells many orders of magnitude larger, and a non-finite input cell
@@ -361,8 +364,8 @@ hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* desc, hx_plan*
  * 1 <= steps <= 64; both ends PERIODIC (then n >= steps) or both GHOST with
  * halo_width >= 4 * ceil(steps / 4); n is a multiple of 4; and in, out, the
  * end of the left halo and the start of the right halo are 16-byte aligned.
- * Results agree with stepping to f32 rounding (not bit for bit, and not
- * between the two walks). */
+ * Results agree with stepping to f32 rounding (not bit for bit; the
+ * interleaved and the block walk give the same bits, the span walk others). */
 
 /* Run a batch plan once after `deps`. */
 hx_status hx_launch_batched(hx_ctx ctx, hx_plan plan, const hx_event* deps, int ndeps,
@@ -568,7 +571,7 @@ hx_status hx_tune_stencil(hx_ctx ctx, const hx_stencil_args* args, int budget_ms
 /* The same for a persistent batch (desc->mode PERSISTENT), timed the same way.
  * desc->steps is the whole run's step count T.  The search covers the pass
  * depth D (the divisors of T up to 64, from the deepest down to T/8), and per
- * depth the form (PROPAGATOR for f32, over its walks: the plan's choice,
+ * depth the form (PROPAGATOR for f32, over its walks: the plan's choice (the block walk where it applies),
  * interleaved, spans of 128 and 40 blocks; DIRECT over cells per lane 8..64,
  * waves per group 1, 2, 4 and a persistent grid of 16 or 64 waves per CU);
  * a candidate costs T / D times its pass.  *best is the fastest, with

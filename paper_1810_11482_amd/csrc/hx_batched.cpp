@@ -54,6 +54,8 @@ struct BatchPlan {
     int64_t pwaves = 0;
     int pskip = 0;         // outer window chunks no segment multiplies
     bool pil = false;      // interleaved walk (segments of one size and one rate)
+    bool pbw = false;      // block walk (the same segments), its tap table
+    void* ptab_dev = nullptr;
     int64_t pblocks = 0;   // interleaved: 1024-cell blocks in all, and per segment
     int64_t pbps = 0;
     hipStream_t cap = nullptr;
@@ -76,6 +78,7 @@ void destroy_plan(void* p) {
     if (b->psegs_dev) hipFree(b->psegs_dev);
     if (b->pwaves_dev) hipFree(b->pwaves_dev);
     if (b->taps_dev) hipFree(b->taps_dev);
+    if (b->ptab_dev) hipFree(b->ptab_dev);
     delete b;
 }
 
@@ -161,8 +164,8 @@ extern "C" hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* d, 
         return c->fail(HX_ERR_ARG, "bad form");
     if (d->form == HX_FORM_PROPAGATOR && (d->mode != HX_BATCH_PERSISTENT || d->dtype != HX_F32))
         return c->fail(HX_ERR_ARG, "the propagator form needs a PERSISTENT f32 batch");
-    if (d->span_blocks < -1 || d->span_blocks > kSpanMax)
-        return c->fail(HX_ERR_ARG, "span_blocks must be -1 .. " + std::to_string(kSpanMax));
+    if (d->span_blocks < -2 || d->span_blocks > kSpanMax)
+        return c->fail(HX_ERR_ARG, "span_blocks must be -2 .. " + std::to_string(kSpanMax));
     hipSetDevice(c->device);
     const size_t es = esz(d->dtype);
     const int vn = vecn(d->dtype);
@@ -308,23 +311,32 @@ extern "C" hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* d, 
             skip = std::min(skip, k);
         }
         bp->pskip = std::min(skip, std::min(2, (NC - 1) / 2));
-        // the walk: interleaved when asked (span_blocks = -1) or, with no span
-        // given or tuned, whenever every segment has the same size and rate;
-        // otherwise contiguous spans
+        // the walk: one wave per block or interleaved when asked
+        // (span_blocks = -2, -1) or, with no span given or tuned, whenever
+        // every segment has the same size and rate; otherwise contiguous spans
         bool il_ok = levels_of.size() == 1;
         for (const Seg1D& sg : bp->segs) il_ok = il_ok && sg.n == bp->segs[0].n;
         const int64_t bps = (bp->segs[0].n + 1023) / 1024;
         il_ok = il_ok && bps * (int64_t)bp->segs.size() < (int64_t(1) << 32);
-        if (d->span_blocks == -1 && !il_ok) {
+        if (d->span_blocks < 0 && !il_ok) {
             destroy_plan(bp);
-            return c->fail(HX_ERR_ARG, "span_blocks = -1 (the interleaved walk) needs segments "
-                                       "of one size and one rate");
+            return c->fail(HX_ERR_ARG, "span_blocks = -1 or -2 (the interleaved or the block "
+                                       "walk) needs segments of one size and one rate");
+        }
+        if (d->span_blocks == -2 && bp->segs.size() > 65535) {
+            destroy_plan(bp);
+            return c->fail(HX_ERR_ARG, "span_blocks = -2 (the block walk) takes at most 65535 "
+                                       "segments");
         }
         const bool tuned_span = d->form == HX_FORM_AUTO && tuned && tg.rows != 0;
-        bp->pil = il_ok && (d->span_blocks == -1 ||
-                            (d->span_blocks == 0 && (!tuned_span || tg.rows == -1)));
-        if (bp->pil) {
-            // the interleaved walk's fp16 levels decide its dropped chunks
+        // untuned, equal segments take the block walk (the interleaved walk
+        // where there are more segments than a grid dimension holds)
+        const bool bw_ok = il_ok && bp->segs.size() <= 65535;
+        const bool dflt = d->span_blocks == 0 && (!tuned_span || tg.rows < 0);
+        bp->pbw = bw_ok && (d->span_blocks == -2 || (dflt && (!tuned_span || tg.rows == -2)));
+        bp->pil = !bp->pbw && il_ok && (d->span_blocks == -1 || dflt);
+        if (bp->pil || bp->pbw) {
+            // the fp16 walks' levels decide their dropped chunks
             const uint32_t m = levels16_of.begin()->second;
             int k = 0;
             while (k < NC / 2 && ((m >> (2 * k)) & 3) == 0 && ((m >> (2 * (NC - 1 - k))) & 3) == 0)
@@ -332,16 +344,17 @@ extern "C" hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* d, 
             bp->pskip = std::min(k, std::min(2, (NC - 1) / 2));
         }
         const int64_t slots =
-            (int64_t)prop.multiProcessorCount * prop1d_waves_per_cu(D, bp->pskip, bp->pil);
+            (int64_t)prop.multiProcessorCount *
+            prop1d_waves_per_cu(D, bp->pskip, bp->pil ? PROP_IL : PROP_SPAN);
         std::vector<int64_t> blocks;
         for (const Seg1D& sg : bp->segs) blocks.push_back((sg.n + 1023) / 1024);
-        const int ni = bp->pil               ? 0
+        const int ni = (bp->pil || bp->pbw) ? 0
                        : d->span_blocks > 0 ? d->span_blocks
                        : (tuned_span && tg.rows > 0)
                            ? tg.rows
                            : choose_span(blocks, slots);
         std::vector<PropWave> waves;
-        if (bp->pil) {
+        if (bp->pil || bp->pbw) {
             bp->pbps = bps;
             bp->pblocks = bps * (int64_t)bp->segs.size();
             // one round of resident waves, unless a wave would then take more
@@ -349,7 +362,7 @@ extern "C" hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* d, 
             bp->pwaves = std::max(std::min<int64_t>(bp->pblocks, slots),
                                   (bp->pblocks + kIlMax - 1) / kIlMax);
         }
-        for (size_t i = 0; i < bp->segs.size() && !bp->pil; ++i)
+        for (size_t i = 0; i < bp->segs.size() && !bp->pil && !bp->pbw; ++i)
             for (int64_t b0 = 0; b0 < blocks[i]; b0 += ni) {
                 PropWave w{};
                 w.seg = (uint32_t)i;
@@ -362,11 +375,19 @@ extern "C" hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* d, 
             destroy_plan(bp);
             return c->fail(HX_ERR_RANGE, "the batch has too many propagator waves");
         }
-        if (!bp->pil) bp->pwaves = (int64_t)waves.size();
+        if (!bp->pil && !bp->pbw) bp->pwaves = (int64_t)waves.size();
+        std::vector<uint16_t> tab16;
+        if (bp->pbw) {
+            const double r0 = bp->segs[0].r;
+            tab16 = prop1d_bw_table(taps.data() + tap_at[r0], D, bp->pskip, texp_of[r0]);
+            bp->pwaves = bp->pblocks;
+        }
         bool ok = hipMalloc(&bp->taps_dev, 4 * taps.size()) == hipSuccess &&
                   hipMalloc(&bp->psegs_dev, sizeof(PropSeg) * bp->segs.size()) == hipSuccess &&
-                  (bp->pil ||
-                   hipMalloc(&bp->pwaves_dev, sizeof(PropWave) * waves.size()) == hipSuccess);
+                  (bp->pil || bp->pbw ||
+                   hipMalloc(&bp->pwaves_dev, sizeof(PropWave) * waves.size()) == hipSuccess) &&
+                  (!bp->pbw || (!tab16.empty() &&
+                                hipMalloc(&bp->ptab_dev, 2 * tab16.size()) == hipSuccess));
         std::vector<PropSeg> ps;
         if (ok) {
             for (const Seg1D& sg : bp->segs) {
@@ -380,8 +401,9 @@ extern "C" hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* d, 
                 q.texp = texp_of[sg.r];
                 q.r = (float)sg.r;
                 // the accuracy check's threshold for the walk this plan runs
-                q.chk = bp->pil ? (float)std::ldexp(err16_of[sg.r], 21 + 15 + q.texp)
-                                : (float)std::ldexp(err_of[sg.r], 21);
+                q.chk = (bp->pil || bp->pbw)
+                            ? (float)std::ldexp(err16_of[sg.r], 21 + 15 + q.texp)
+                            : (float)std::ldexp(err_of[sg.r], 21);
                 if (sg.bc_lo == HX_BC_PERIODIC) {
                     q.lo_base = q.in + sg.n;
                     q.hi_base = q.in;
@@ -397,9 +419,11 @@ extern "C" hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* d, 
                      hipSuccess &&
                  hipMemcpy(bp->psegs_dev, ps.data(), sizeof(PropSeg) * ps.size(),
                            hipMemcpyHostToDevice) == hipSuccess &&
-                 (bp->pil || hipMemcpy(bp->pwaves_dev, waves.data(),
-                                       sizeof(PropWave) * waves.size(),
-                                       hipMemcpyHostToDevice) == hipSuccess);
+                 (bp->pil || bp->pbw ||
+                  hipMemcpy(bp->pwaves_dev, waves.data(), sizeof(PropWave) * waves.size(),
+                            hipMemcpyHostToDevice) == hipSuccess) &&
+                 (!bp->pbw || hipMemcpy(bp->ptab_dev, tab16.data(), 2 * tab16.size(),
+                                        hipMemcpyHostToDevice) == hipSuccess);
         }
         if (!ok) {
             hipGetLastError();
@@ -500,6 +524,10 @@ extern "C" hx_status hx_launch_batched(hx_ctx ctx, hx_plan plan, const hx_event*
     return c->submit(
         SC_COMPUTE, deps, ndeps, bp->acc, what,
         [bp](hipStream_t st) -> hipError_t {
+            if (bp->prop && bp->pbw)
+                return launch_prop1d_bw(bp->psegs_dev, bp->ptab_dev,
+                                        (int64_t)bp->segs.size(), bp->pbps, bp->steps,
+                                        bp->pskip, st);
             if (bp->prop && bp->pil)
                 return launch_prop1d_il(bp->psegs_dev, bp->pblocks, bp->pbps, bp->pwaves,
                                         bp->steps, bp->pskip, st);

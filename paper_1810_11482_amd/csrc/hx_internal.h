@@ -5,6 +5,8 @@
 #include <hip/hip_runtime_api.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace hx {
 
 // One 1D segment: a contiguous run of n cells advanced `steps` steps from `in`
@@ -262,14 +264,26 @@ constexpr int kSpanMax = 256;
 constexpr int kIlMax = 128;
 hipError_t launch_prop1d(const PropSeg* segs_dev, const PropWave* waves_dev, int64_t nwaves, int D,
                          int skip, hipStream_t stream);
-// Waves of that kernel resident per CU (registers and LDS permitting).
-int prop1d_waves_per_cu(int D, int skip, bool il = false);
+// The walks of the propagator pass: contiguous spans of blocks per wave, the
+// interleaved persistent grid, and one wave per block.
+enum { PROP_SPAN = 0, PROP_IL = 1, PROP_BW = 2 };
+// Waves of that walk's kernel resident per CU (registers and LDS permitting).
+int prop1d_waves_per_cu(int D, int skip, int walk = PROP_SPAN);
 // Interleaved walk of the same pass: `nblocks` 1024-cell blocks, bps per
 // segment (every segment has the same n and the same taps, those of segs[0]);
 // a persistent grid of nwaves <= nblocks waves, wave w taking blocks w,
 // w + nwaves, ...  nblocks < 2^32 and a multiple of bps.
 hipError_t launch_prop1d_il(const PropSeg* segs_dev, int64_t nblocks, int64_t bps, int64_t nwaves,
                             int D, int skip, hipStream_t stream);
+// Block walk of the same pass: one wave per block, bps blocks in each of
+// `nsegs` segments (same n and taps, as the interleaved walk; nsegs <= 65535,
+// bps < 2^31), the tap operands read from `tab_dev`, the table
+// prop1d_bw_table builds for (taps, D, skip, texp) of segs[0]
+// (prop1d_bw_table_bytes of device memory, 16-byte aligned).
+size_t prop1d_bw_table_bytes(int D, int skip);
+std::vector<uint16_t> prop1d_bw_table(const float* taps, int D, int skip, int texp);
+hipError_t launch_prop1d_bw(const PropSeg* segs_dev, const void* tab_dev, int64_t nsegs,
+                            int64_t bps, int D, int skip, hipStream_t stream);
 
 // One 2D band: ny rows of nx cells, row-major, advanced `steps` steps from in
 // into out.  Rows outside [0, ny) come from the top/bottom rule; columns

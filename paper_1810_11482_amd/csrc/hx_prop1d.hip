@@ -51,6 +51,9 @@
 // issued just before.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
+
 #include "hx_internal.h"
 
 namespace hx {
@@ -659,18 +662,212 @@ void k_prop1d_il(const PropSeg* __restrict__ segs, uint32_t nblocks, uint32_t bp
     }
 }
 
+
+// Block walk (every segment of the launch has the same n and the same taps,
+// as in the interleaved walk): one workgroup of one wave per 1024-cell block,
+// blockIdx.x the block within its segment and blockIdx.y the segment, so the
+// grid covers every block once and the hardware dispatcher, not a persistent
+// loop, keeps the memory system busy.  A persistent grid moved the same bytes
+// at 5.3-5.5 TB/s in a probe without arithmetic, one wave per block at
+// 5.9-6.0 TB/s.
+//
+// A wave that lives for one block cannot build its tap operands from the taps
+// (56 values per lane to select, scale and split).  The plan builds them once
+// (prop1d_bw_table): the two fp16 terms of the scaled taps, in eight copies
+// shifted by one element each, so that the 8 consecutive taps a lane's A
+// operand holds for a chunk are one aligned 16-byte unit of one copy.  Each
+// wave stages the table (5 KiB, L2-resident) in LDS while its window loads are
+// in flight, and reads its A operands from there with the B operands.  The
+// lanes of an 8-lane group read 8 distinct copies, and the odd stride of a copy
+// (U units of 16 bytes) puts their units in distinct banks.
+//
+// Everything else is the interleaved walk's arithmetic, in the same order, so
+// the two give the same bits: the window's shared power-of-two scale, the
+// two-term fp16 split of every cell (here with the packed conversion), the
+// products chunk by chunk, the accuracy check, and the stepped fallback for a
+// block that fails it (right away, in the window's LDS).
+constexpr int bw_units(int NC, int S0) { return 2 * (NC - S0) + 3; }
+
+// x 2^e for two f32 values split into packed fp16 pairs: x 2^e = hi + lo,
+// each rounded to nearest (the packed form of split16_pair).
+__device__ __forceinline__ void split16_pk(float x0, float x1, int e, uint32_t& h, uint32_t& l) {
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    const f2 s = {ldexpf(x0, e), ldexpf(x1, e)};
+    const h2 hi = __builtin_convertvector(s, h2);
+    const f2 rem = s - __builtin_convertvector(hi, f2);
+    h = __builtin_bit_cast(uint32_t, hi);
+    l = __builtin_bit_cast(uint32_t, __builtin_convertvector(rem, h2));
+}
+
+template <int NC, int S0>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8)))
+void k_prop1d_bw(const PropSeg* __restrict__ segs, const u32x4* __restrict__ tab, int D, int OD) {
+    constexpr int U = bw_units(NC, S0);
+    constexpr int kUnits = 16 * U;               // 16-byte units of the table
+    constexpr int kLoads = (kUnits + 63) / 64;   // per lane
+    __shared__ __attribute__((aligned(16))) char lds[2 * kWPlane + 16 * kUnits];
+    char* const tl = lds + 2 * kWPlane;
+    const int l = threadIdx.x, i = l & 31, g = l >> 5;
+    const PropSeg& s = segs[blockIdx.y];
+    const int64_t c0 = 1024 * (int64_t)blockIdx.x;
+    const uint32_t lv = s.levels16;
+    // the table first, so that waiting for it leaves the window's loads in flight
+    u32x4 T[kLoads];
+#pragma unroll
+    for (int k = 0; k < kLoads; ++k)
+        if (k + 1 < kLoads || l + 64 * k < kUnits) T[k] = tab[l + 64 * k];
+    // the window: this lane's 16-byte pieces of the block (cells 256 j + 4 l)
+    // and of the left or right 64 context cells, as in the interleaved walk
+    const int q = l & 15;
+    const bool left = (l & 31) < 16;
+    f32x4 v[5];
+    {
+        const int64_t cx = (left ? c0 - 64 : c0 + 1024) + 4 * q;
+        if (c0 >= 1024 && c0 + 1024 + 64 <= s.n) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[j] = gload(s.in + c0 + 256 * j + 4 * l);
+            v[4] = gload(s.in + cx);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[j] = load4<false>(s, c0 + 256 * j + 4 * l);
+            v[4] = load4<false>(s, cx);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kLoads; ++k)
+        if (k + 1 < kLoads || l + 64 * k < kUnits)
+            *reinterpret_cast<u32x4*>(tl + 16 * (l + 64 * k)) = T[k];
+    // the window's scale: its largest |x| if all are finite (a NaN or an
+    // infinity makes the maximum non-finite), else the largest finite one
+    float mx = 0.f;
+#pragma unroll
+    for (int j = 0; j < 5; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) mx = __builtin_elementwise_maximum(mx, fabsf(v[j][e]));
+    if (__ballot(!(mx <= 3.402823466e38f))) {
+        mx = 0.f;
+#pragma unroll
+        for (int j = 0; j < 5; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float a = fabsf(v[j][e]);
+                mx = (a <= 3.402823466e38f && a > mx) ? a : mx;
+            }
+    }
+    mx = wave_max(mx);
+    const int ex = __builtin_amdgcn_readfirstlane(
+        mx > 0.f ? 15 - __builtin_amdgcn_frexp_expf(mx) : 0);
+    const float thr = mx > 0.f ? s.chk : 0.f;
+    // the two fp16 planes of the window (the interleaved walk's layout)
+    {
+        int woff[5];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            woff[j] = swz(2 + 8 * j + (l >> 3), (l & 7) >> 1) + 8 * (l & 1);
+        woff[4] = swz((left ? 0 : 34) + (q >> 3), (q & 7) >> 1) + 8 * (q & 1);
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            uint32_t h0, l0, h1, l1;
+            split16_pk(v[j][0], v[j][1], ex, h0, l0);
+            split16_pk(v[j][2], v[j][3], ex, h1, l1);
+            char* p = lds + woff[j];
+            *reinterpret_cast<u32x2*>(p) = u32x2{h0, h1};
+            *reinterpret_cast<u32x2*>(p + kWPlane) = u32x2{l0, l1};
+        }
+    }
+    __syncthreads();
+    // A operand of chunk c for lane (m = i, g): taps 16c + 8g - OD - i + 0..7,
+    // unit (d - d mod 8) / 8 of copy d mod 8, d = 16c + 8g + 31 - i (the table
+    // starts at tap -OD - 31); one chunk further is two units further on
+    const int d0 = 16 * S0 + 8 * g + 31 - i;
+    const char* ta = tl + 16 * ((d0 & 7) * U + (d0 >> 3));
+    f32x16 acc = {};
+    {
+        int roff[NC];
+#pragma unroll
+        for (int c = S0; c < NC - S0; ++c) {
+            const int X = 16 * c + 8 * g - OD;
+            roff[c] = swz(2 + i + (X >> 5), (X & 31) >> 3);
+        }
+        u32x4 bh = *reinterpret_cast<const u32x4*>(lds + roff[S0]);
+        u32x4 bl = *reinterpret_cast<const u32x4*>(lds + roff[S0] + kWPlane);
+        u32x4 ah = *reinterpret_cast<const u32x4*>(ta);
+        u32x4 al = *reinterpret_cast<const u32x4*>(ta + 16 * 8 * U);
+#pragma unroll
+        for (int c = S0; c < NC - S0; ++c) {
+            const int L = (lv >> (2 * c)) & 3;
+            u32x4 nbh = bh, nbl = bl, nah = ah, nal = al;
+            if (c + 1 < NC - S0) {
+                const char* p = lds + roff[c + 1];
+                const char* pa = ta + 32 * (c + 1 - S0);
+                nbh = *reinterpret_cast<const u32x4*>(p);
+                nbl = *reinterpret_cast<const u32x4*>(p + kWPlane);
+                nah = *reinterpret_cast<const u32x4*>(pa);
+                nal = *reinterpret_cast<const u32x4*>(pa + 16 * 8 * U);
+            }
+            if (L >= 1) acc = mfma16(ah, bh, acc);
+            if (L >= 2) {
+                acc = mfma16(ah, bl, acc);
+                acc = mfma16(al, bh, acc);
+            }
+            bh = nbh;
+            bl = nbl;
+            ah = nah;
+            al = nal;
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // the accuracy check: every output finite and at least thr in magnitude
+    float mn = fabsf(acc[0]), mo = mn;
+#pragma unroll
+    for (int e = 1; e < 16; ++e) {
+        mn = __builtin_elementwise_minimum(mn, fabsf(acc[e]));
+        mo = __builtin_elementwise_maximum(mo, fabsf(acc[e]));
+    }
+    if (__ballot(!(mn >= thr) || !(mo <= 3.402823466e38f))) {
+        step_block(s, c0, D, [&](int c) -> float& { return reinterpret_cast<float*>(lds)[c]; });
+        return;
+    }
+    // the outputs, scaled back and transposed through the window's planes
+    // (whose reads are all issued) so that each store writes 1 KiB of cells
+    auto tpos = [](int row, int unit) {
+        return (row < 16 ? 0 : kWPlane) + (row & 15) * 128 + ((unit ^ (row & 7)) << 4);
+    };
+    const int sc = -(ex + s.texp);
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        *reinterpret_cast<f32x4*>(lds + tpos(i, 2 * e + g)) =
+            f32x4{ldexpf(acc[4 * e], sc), ldexpf(acc[4 * e + 1], sc),
+                  ldexpf(acc[4 * e + 2], sc), ldexpf(acc[4 * e + 3], sc)};
+    f32x4 o[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) o[j] = *reinterpret_cast<const f32x4*>(lds + tpos(8 * j + (l >> 3), l & 7));
+    const int64_t oc = c0 + 4 * l;
+    if (c0 + 1024 <= s.n) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) gstore<true>(o[j], s.out + oc + 256 * j);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (oc + 256 * j < s.n) gstore<true>(o[j], s.out + oc + 256 * j);
+    }
+}
+
 }  // namespace
 
 // The kernel instantiation for depth D and `skip` dropped chunks per side
-// (nullptr when there is none); `il` selects the interleaved walk.
-static const void* prop1d_kernel(int D, int skip, bool il = false) {
+// (nullptr when there is none), for the walk `walk` (PROP_SPAN, PROP_IL or
+// PROP_BW).
+static const void* prop1d_kernel(int D, int skip, int walk = PROP_SPAN) {
     int OD = 0, NC = 0;
     if (!prop1d_geometry(D, &OD, &NC) || skip < 0 || NC - 2 * skip < 1) return nullptr;
     switch (NC * 4 + (skip > 2 ? 2 : skip)) {
 #define HX_PROP_CASE(N, S)                                                      \
     case N * 4 + S:                                                             \
-        return il ? reinterpret_cast<const void*>(&k_prop1d_il<N, S>)         \
-                  : reinterpret_cast<const void*>(&k_prop1d<N, S>);
+        return walk == PROP_IL   ? reinterpret_cast<const void*>(&k_prop1d_il<N, S>) \
+               : walk == PROP_BW ? reinterpret_cast<const void*>(&k_prop1d_bw<N, S>) \
+                                 : reinterpret_cast<const void*>(&k_prop1d<N, S>);
 #define HX_PROP_CASES(N) HX_PROP_CASE(N, 0) HX_PROP_CASE(N, 1) HX_PROP_CASE(N, 2)
         HX_PROP_CASE(3, 0)
         HX_PROP_CASE(3, 1)
@@ -689,8 +886,8 @@ static const void* prop1d_kernel(int D, int skip, bool il = false) {
     }
 }
 
-int prop1d_waves_per_cu(int D, int skip, bool il) {
-    const void* k = prop1d_kernel(D, skip, il);
+int prop1d_waves_per_cu(int D, int skip, int walk) {
+    const void* k = prop1d_kernel(D, skip, walk);
     int blocks = 0;
     if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k, 64, 0) != hipSuccess) {
         hipGetLastError();
@@ -712,7 +909,7 @@ hipError_t launch_prop1d(const PropSeg* segs_dev, const PropWave* waves_dev, int
 hipError_t launch_prop1d_il(const PropSeg* segs_dev, int64_t nblocks, int64_t bps, int64_t nwaves,
                             int D, int skip, hipStream_t stream) {
     int OD = 0, NC = 0;
-    const void* k = prop1d_kernel(D, skip, true);
+    const void* k = prop1d_kernel(D, skip, PROP_IL);
     if (!k || !prop1d_geometry(D, &OD, &NC) || nblocks <= 0 || nblocks >= (int64_t(1) << 32) ||
         bps <= 0 || nblocks % bps != 0 || nwaves <= 0 || nwaves > nblocks ||
         (nblocks + nwaves - 1) / nwaves > kIlMax)
@@ -720,6 +917,46 @@ hipError_t launch_prop1d_il(const PropSeg* segs_dev, int64_t nblocks, int64_t bp
     uint32_t nb = (uint32_t)nblocks, bp = (uint32_t)bps;
     void* args[] = {&segs_dev, &nb, &bp, &D, &OD};
     return hipLaunchKernel(k, dim3((unsigned)nwaves), dim3(64), args, 0, stream);
+}
+
+size_t prop1d_bw_table_bytes(int D, int skip) {
+    int OD = 0, NC = 0;
+    if (!prop1d_geometry(D, &OD, &NC) || skip < 0 || NC - 2 * skip < 1) return 0;
+    return (size_t)256 * bw_units(NC, std::min(skip, 2));
+}
+
+// Copy c (0..7) of level v (0 = hi, 1 = lo), unit u, element e holds that term
+// of tap j = -OD - 31 + c + 8 u + e (zero outside [-D, D]), the tap scaled by
+// 2^texp and split as split16_pair splits it: round to nearest fp16 for hi,
+// then the rounded exact remainder for lo.
+std::vector<uint16_t> prop1d_bw_table(const float* taps, int D, int skip, int texp) {
+    int OD = 0, NC = 0;
+    if (!prop1d_geometry(D, &OD, &NC) || skip < 0 || NC - 2 * skip < 1) return {};
+    const int U = bw_units(NC, std::min(skip, 2));
+    std::vector<uint16_t> t((size_t)2 * 8 * U * 8);
+    for (int c = 0; c < 8; ++c)
+        for (int u = 0; u < U; ++u)
+            for (int e = 0; e < 8; ++e) {
+                const int j = -OD - 31 + c + 8 * u + e;
+                const float p = (j >= -D && j <= D) ? taps[j + D] : 0.f;
+                const float sc = std::ldexp(p, texp);
+                const _Float16 hi = (_Float16)sc;
+                const _Float16 lo = (_Float16)(sc - (float)hi);
+                t[((size_t)(0 * 8 + c) * U + u) * 8 + e] = __builtin_bit_cast(uint16_t, hi);
+                t[((size_t)(1 * 8 + c) * U + u) * 8 + e] = __builtin_bit_cast(uint16_t, lo);
+            }
+    return t;
+}
+
+hipError_t launch_prop1d_bw(const PropSeg* segs_dev, const void* tab_dev, int64_t nsegs,
+                            int64_t bps, int D, int skip, hipStream_t stream) {
+    int OD = 0, NC = 0;
+    const void* k = prop1d_kernel(D, skip, PROP_BW);
+    if (!k || !prop1d_geometry(D, &OD, &NC) || !tab_dev || nsegs <= 0 || nsegs > 65535 ||
+        bps <= 0 || bps >= (int64_t(1) << 31))
+        return hipErrorInvalidValue;
+    void* args[] = {&segs_dev, &tab_dev, &D, &OD};
+    return hipLaunchKernel(k, dim3((unsigned)bps, (unsigned)nsegs), dim3(64), args, 0, stream);
 }
 
 }  // namespace hx

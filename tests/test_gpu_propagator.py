@@ -195,8 +195,10 @@ def test_auto_takes_the_propagator_where_every_segment_fits(ctx):
 def test_full_size_headline_form_every_cell(ctx):
     """2^28 fp32 cells as 64 partition views of one HBM arena, r = 0.25,
     50 steps as one propagator launch (halos of 52 cells from the neighbour
-    views): the whole array against the oracle's serial FP64 run (about 8 s on
-    one core), 1e-5 relative L2 and 1e-5 of itself in every cell."""
+    views), in the plan's own walk and in the block walk: the whole array
+    against the oracle's serial FP64 run (about 8 s on one core), 1e-5
+    relative L2 and 1e-5 of itself in every cell, and the two walks bit for
+    bit."""
     n, parts, T, r, hw = 1 << 28, 64, 50, 0.25, 52
     spec = workloads.Partitioned1D()
     hin = hx.hx_host_alloc(ctx, n * 4)
@@ -218,13 +220,17 @@ def test_full_size_headline_form_every_cell(ctx):
                                bc_hi=hx.HX_BC_GHOST, halo_lo=A[lp],
                                halo_lo_offset=(bounds[lp][1] - hw) * 4, halo_hi=A[rp],
                                halo_width=hw))
-    plan = hx.hx_plan_create_batched(ctx, hx.HX_F32, T, segs, hx.HX_BATCH_PERSISTENT,
-                                     form=hx.HX_FORM_PROPAGATOR)
-    ev = hx.hx_launch_batched(ctx, plan)
-    assert hx.hx_wait(ctx, ev) == hx.HX_OK, hx.hx_last_error(ctx)
-    hx.hx_event_release(ctx, ev)
-    hx.hx_plan_destroy(ctx, plan)
-    got = download(ctx, arena_b, n, np.float32)
+    outs = []
+    for span in (0, -2):
+        plan = hx.hx_plan_create_batched(ctx, hx.HX_F32, T, segs, hx.HX_BATCH_PERSISTENT,
+                                         form=hx.HX_FORM_PROPAGATOR, span_blocks=span)
+        ev = hx.hx_launch_batched(ctx, plan)
+        assert hx.hx_wait(ctx, ev) == hx.HX_OK, hx.hx_last_error(ctx)
+        hx.hx_event_release(ctx, ev)
+        hx.hx_plan_destroy(ctx, plan)
+        outs.append(download(ctx, arena_b, n, np.float32))
+    got = outs[0]
+    assert np.array_equal(outs[1], got)
     ref = oracle.heat1d_periodic(u0.astype(np.float64), r, T)
     for b in A + B + [arena_a, arena_b]:
         hx.hx_buffer_destroy(ctx, b)
@@ -240,7 +246,8 @@ def test_full_size_headline_form_every_cell(ctx):
 def test_interleaved_walk_matches_oracle_and_spans(ctx, D, n, count):
     """Segments of one size and one rate, walked interleaved (span_blocks = -1):
     the oracle on every segment, the span walk within the tolerance, and the
-    same bits as the plan's own choice (which is this walk).  With
+    same bits as the block walk (span_blocks = -2) and the plan's own choice
+    (the block walk).  With
     1.2 x 10^7 cells the launch has about four times as many blocks as the
     persistent grid has waves, so waves take several blocks; n = 1000 and
     1028 leave a partial last block, n = 64 a segment of one partial block."""
@@ -248,7 +255,10 @@ def test_interleaved_walk_matches_oracle_and_spans(ctx, D, n, count):
     u, il, offs = periodic_batch(ctx, sizes, rs, D, hx.HX_FORM_PROPAGATOR, span=-1, seed=D + 7)
     span = periodic_batch(ctx, sizes, rs, D, hx.HX_FORM_PROPAGATOR, span=5, seed=D + 7)[1]
     auto = periodic_batch(ctx, sizes, rs, D, hx.HX_FORM_PROPAGATOR, span=0, seed=D + 7)[1]
+    bw = periodic_batch(ctx, sizes, rs, D, hx.HX_FORM_PROPAGATOR, span=-2, seed=D + 7)[1]
     assert np.array_equal(il, auto)
+    # the block walk runs the same arithmetic in the same order
+    assert np.array_equal(bw, il)
     mask = np.ones(il.size, bool)
     for k, o in enumerate(offs):
         mask[o:o + n] = False
@@ -269,7 +279,7 @@ def test_interleaved_halo_coupled_partitions(ctx, D, hw):
     u0 = workloads.uniform(n, 511, D, 0, 1, np.float32)
     a = upload(ctx, u0)
     results = []
-    for span in (-1, 3):
+    for span in (-1, 3, -2):
         b = hx.hx_buffer_create(ctx, n * 4)
         segs = []
         for p in range(P):
@@ -288,22 +298,24 @@ def test_interleaved_halo_coupled_partitions(ctx, D, hw):
         hx.hx_buffer_destroy(ctx, b)
     hx.hx_buffer_destroy(ctx, a)
     ref = oracle.heat1d_periodic(u0.astype(np.float64), 0.25, D)
-    il, span = results
+    il, span, bw = results
     assert rel_l2(il, ref) <= 1e-5 and rel_max(il, ref) <= 1e-5
     assert rel_l2(il, span) <= 1e-5
+    assert np.array_equal(bw, il)
 
 
 def test_interleaved_walk_rejections(ctx):
-    """span_blocks = -1 needs segments of one size and one rate; below -1 and
-    above 256 are invalid; unequal segments with span_blocks = 0 take the span
-    walk."""
+    """span_blocks = -1 and -2 need segments of one size and one rate; below
+    -2 and above 256 are invalid; unequal segments with span_blocks = 0 take
+    the span walk."""
     b = hx.hx_buffer_create(ctx, 1 << 16)
     c = hx.hx_buffer_create(ctx, 1 << 16)
     per = dict(bc_lo=hx.HX_BC_PERIODIC, bc_hi=hx.HX_BC_PERIODIC)
     s1 = hx.segment(inp=b, out=c, n=1024, r=0.2, **per)
     s2 = hx.segment(inp=b, in_offset=4096, out=c, out_offset=4096, n=2048, r=0.2, **per)
     s3 = hx.segment(inp=b, in_offset=4096, out=c, out_offset=4096, n=1024, r=0.1, **per)
-    for segs, span in (([s1, s2], -1), ([s1, s3], -1), ([s1], -2), ([s1], 257)):
+    for segs, span in (([s1, s2], -1), ([s1, s3], -1), ([s1, s2], -2), ([s1, s3], -2),
+                       ([s1], -3), ([s1], 257)):
         with pytest.raises(hx.HxError) as e:
             hx.hx_plan_create_batched(ctx, hx.HX_F32, 20, segs, hx.HX_BATCH_PERSISTENT,
                                       form=hx.HX_FORM_PROPAGATOR, span_blocks=span)
@@ -318,8 +330,9 @@ def test_interleaved_walk_rejections(ctx):
 
 def run_segments(ctx, vals, r, D, span):
     """Periodic segments holding `vals` (f32), one propagator pass walked
-    interleaved (span = -1, segments of one size) or in spans; returns the
-    f32 inputs and outputs per segment."""
+    interleaved (span = -1, segments of one size), one wave per block
+    (span = -2, likewise) or in spans; returns the f32 inputs and outputs per
+    segment."""
     n = len(vals[0])
     offs, o = [], GUARD
     for _ in vals:
@@ -369,7 +382,7 @@ def per_cell(got, ref):
     return float(np.max(np.abs(got[nz] - ref[nz]) / np.abs(ref[nz]))) if nz.any() else 0.0
 
 
-@pytest.mark.parametrize("span", [-1, 5])
+@pytest.mark.parametrize("span", [-1, -2, 5])
 @pytest.mark.parametrize("spike", [1e6, 1e8, 1e10, 1e30])
 def test_spikes_keep_every_cell_to_f32(ctx, span, spike):
     """U[0,1] segments with spikes many orders of magnitude above the
@@ -396,7 +409,7 @@ def test_spikes_keep_every_cell_to_f32(ctx, span, spike):
         assert err <= 1e-5, (k, spike, span, err)
 
 
-@pytest.mark.parametrize("span", [-1, 5])
+@pytest.mark.parametrize("span", [-1, -2, 5])
 def test_wide_dynamic_range_and_mixed_signs(ctx, span):
     """A steep exponential (e^-i/24 down to about 1e-37, so each window spans
     about 20 orders of magnitude), U[0,1] times 1e-30, 1 and 1e30, zeros, and
@@ -423,7 +436,7 @@ def test_wide_dynamic_range_and_mixed_signs(ctx, span):
             assert per_cell(got[big], ref[big]) <= 1e-5, k
 
 
-@pytest.mark.parametrize("span", [-1, 5])
+@pytest.mark.parametrize("span", [-1, -2, 5])
 def test_non_finite_cells_reach_what_stepping_reaches(ctx, span):
     """NaN, +inf and -inf input cells: the outputs that are NaN, +inf or -inf
     are exactly those of the oracle's stepping (within D cells of each such
@@ -448,7 +461,7 @@ def test_non_finite_cells_reach_what_stepping_reaches(ctx, span):
         assert per_cell(got[fin], ref[fin]) <= 1e-5, k
 
 
-@pytest.mark.parametrize("span", [-1, 5])
+@pytest.mark.parametrize("span", [-1, -2, 5])
 def test_every_block_stepped(ctx, span):
     """3 x 2^20 cells of (-1)^i plus a smooth part of 1e-5: at r = 1/4 one step
     annihilates the alternating part, so every output is about 1e-5 of its
