@@ -541,6 +541,7 @@ def main():
         log(f"plain: {t_plain * 1e3:.3f} ms/step")
         hx.hx_event_release(ctx, P.last)
         P.last = 0
+        result["plain"].update(plain_graph_leg(hx, ctx, P, T, r))
     result["host_to_host"] = pipeline_leg(hx, ctx, P, T, r, cpl, ref)
     del ref
     result["host_link"] = host_link_leg(hx, P)
@@ -1169,6 +1170,109 @@ def adjoint_leg(hx, ctx):
     return res
 
 
+def plain_chain(hx, ctx, P, T, r, deps=()):
+    """The plain form's launches submitted one by one from here: for each of
+    the T steps, one one-step launch per partition (halos of one cell read
+    from the neighbours' views), every launch after the previous one, as
+    HX_PART_PLAIN issues them.  Returns the launch events and where the
+    result is (True: the B views)."""
+    evs, last = [], list(deps)
+    src, dst = P.A, P.B
+    for _ in range(T):
+        for p in range(P.parts):
+            lp, rp = (p - 1) % P.parts, (p + 1) % P.parts
+            a = hx.stencil_args(dims=1, dtype=hx.HX_F32, nx=P.sizes[p], steps=1, r=r,
+                                inp=src[p], out=dst[p], bc_lo=hx.HX_BC_GHOST,
+                                bc_hi=hx.HX_BC_GHOST, halo_lo=src[lp],
+                                halo_lo_offset=(P.sizes[lp] - 1) * 4, halo_hi=src[rp],
+                                halo_hi_offset=0, halo_width=1, cells_per_lane=8)
+            e = hx.hx_launch_stencil(ctx, a, last)
+            evs.append(e)
+            last = [e]
+        src, dst = dst, src
+    return evs, T % 2 == 1
+
+
+def plain_graph_leg(hx, ctx, P, T, r, reps=5):
+    """Per-operation cost of the plain form (3200 dependent one-step launches
+    per 50-step run): submitted one by one through the futures, against the
+    same launches captured once as a graph (hx_graph_begin/end) and replayed
+    with one hx_graph_launch.  The captured replay is checked bit for bit
+    against the eager run."""
+    import torch
+    ops = T * P.parts
+    # eager, timed on the host, with per-launch spans
+    best = None
+    for _ in range(2):
+        P.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        evs, in_b = plain_chain(hx, ctx, P, T, r)
+        t_sub = time.perf_counter() - t0
+        assert hx.hx_wait(ctx, evs[-1]) == hx.HX_OK, hx.hx_last_error(ctx)
+        t_all = time.perf_counter() - t0
+        spans = [b - a for a, b in (hx.hx_event_span(ctx, e, e) for e in evs)]
+        for e in evs:
+            hx.hx_event_release(ctx, e)
+        if best is None or t_all < best[1]:
+            best = (t_sub, t_all, float(np.mean(spans)))
+    eager_out = np.empty(P.n, np.float32)
+    for (o, s_), b in zip(P.bounds, P.B if in_b else P.A):
+        eager_out[o:o + s_] = download_f32(hx, ctx, b, s_)
+    # the same launches captured once, replayed
+    P.reset()
+    t0 = time.perf_counter()
+    hx.hx_graph_begin(ctx)
+    evs, in_b2 = plain_chain(hx, ctx, P, T, r)
+    g = hx.hx_graph_end(ctx)
+    t_cap = time.perf_counter() - t0
+    for e in evs:
+        hx.hx_event_release(ctx, e)
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev = hx.hx_graph_launch(ctx, g)
+        assert hx.hx_wait(ctx, ev) == hx.HX_OK, hx.hx_last_error(ctx)
+        ts.append(time.perf_counter() - t0)
+        hx.hx_event_release(ctx, ev)
+    # one replay from the initial state against the eager run
+    P.reset()
+    ev = hx.hx_graph_launch(ctx, g)
+    assert hx.hx_wait(ctx, ev) == hx.HX_OK
+    hx.hx_event_release(ctx, ev)
+    graph_out = np.empty(P.n, np.float32)
+    for (o, s_), b in zip(P.bounds, P.B if in_b2 else P.A):
+        graph_out[o:o + s_] = download_f32(hx, ctx, b, s_)
+    same = bool(np.array_equal(graph_out, eager_out))
+    hx.hx_plan_destroy(ctx, g)
+    P.reset()
+    t_graph = float(np.median(ts))
+    res = {"operations": ops,
+           "eager_submit_us_per_op": best[0] / ops * 1e6,
+           "eager_us_per_op": best[1] / ops * 1e6,
+           "graph_replay_ms_per_step": t_graph * 1e3,
+           "graph_replay_us_per_op": t_graph / ops * 1e6,
+           "graph_capture_ms": t_cap * 1e3,
+           "eager_span_us_per_op": best[2] * 1e3,
+           "graph_equals_eager_bitwise": same,
+           "method": "host clock around each run (eager: best of 2; replay: median of 5); "
+                     "eager span: mean HIP-event span of the eager launches (the kernel plus "
+                     "the markers and dispatch between launches; the kernels' own duration "
+                     "is in the kernel-trace profile of this leg)"}
+    log(f"plain chain: {res}")
+    assert same, "the captured plain chain differs from the eager run"
+    return res
+
+
+def download_f32(hx, ctx, buf, n):
+    out = np.empty(n, np.float32)
+    e = hx.hx_copy_async(ctx, hx.hx_copy_desc(hx.HX_D2H, out.ctypes.data, buf, 0, 0, 0, n * 4))
+    assert hx.hx_wait(ctx, e) == hx.HX_OK
+    hx.hx_event_release(ctx, e)
+    return out
+
+
 def copy_leg(hx, ctx, P, reps=5):
     """A one-pass device copy of the whole arena (hx_copy_async D2D: the
     library's vector copy kernel, one 16-byte nontemporal load and store per
@@ -1207,7 +1311,10 @@ extern "C" __global__ void kprk(const double* x, double* y, long n) {
 class NativeHip:
     """The same partition benchmark written straight against the HIP runtime
     (the one torch loaded): one stream per partition, async copies and a
-    module launch per partition, then a synchronize of every stream."""
+    module launch per partition, then a synchronize of every stream
+    (`run`); or the layout hx uses (`run_layered`): all copies in on one
+    stream, all copies out on another, each partition's kernel on its own
+    stream, ordered by HIP events."""
 
     def __init__(self, parts):
         import ctypes
@@ -1216,10 +1323,20 @@ class NativeHip:
         self.ct = ctypes
         self.hip = ctypes.CDLL(os.path.join(libdir, "libamdhip64.so"))
         self.streams = []
-        for _ in range(parts):
+        for _ in range(parts + 2):
             s = ctypes.c_void_p()
             assert self.hip.hipStreamCreateWithFlags(ctypes.byref(s), 1) == 0
             self.streams.append(s)
+        self.h2d, self.d2h = self.streams[parts], self.streams[parts + 1]
+        self.streams = self.streams[:parts]
+        self.evs = []
+        for _ in range(2 * parts):
+            e = ctypes.c_void_p()
+            assert self.hip.hipEventCreateWithFlags(ctypes.byref(e), 2) == 0  # no timing
+            self.evs.append(e)
+        self.hip.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        self.hip.hipStreamWaitEvent.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint]
+        self.hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
         self.hip.hipMemcpyAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                             ctypes.c_int, ctypes.c_void_p]
         self.hip.hipModuleLaunchKernel.argtypes = [ctypes.c_void_p] + [ctypes.c_uint] * 7 + [
@@ -1242,9 +1359,30 @@ class NativeHip:
         for st in self.streams:
             assert self.hip.hipStreamSynchronize(st) == 0
 
+    def run_layered(self, fn, host_in, host_out, dptrs, bounds):
+        ct, hip = self.ct, self.hip
+        keep = []
+        for p, ((o, s), d, st) in enumerate(zip(bounds, dptrs, self.streams)):
+            e_in, e_k = self.evs[2 * p], self.evs[2 * p + 1]
+            assert hip.hipMemcpyAsync(d, host_in + o * 8, s * 8, 1, self.h2d) == 0
+            assert hip.hipEventRecord(e_in, self.h2d) == 0
+            assert hip.hipStreamWaitEvent(st, e_in, 0) == 0
+            a0, a1 = ct.c_void_p(d), ct.c_int64(s)
+            params = (ct.c_void_p * 2)(ct.cast(ct.byref(a0), ct.c_void_p),
+                                       ct.cast(ct.byref(a1), ct.c_void_p))
+            keep.append((a0, a1, params))
+            assert hip.hipModuleLaunchKernel(fn, (s + 255) // 256, 1, 1, 256, 1, 1, 0, st,
+                                             params, None) == 0
+            assert hip.hipEventRecord(e_k, st) == 0
+            assert hip.hipStreamWaitEvent(self.d2h, e_k, 0) == 0
+            assert hip.hipMemcpyAsync(host_out + o * 8, d, s * 8, 2, self.d2h) == 0
+        assert hip.hipStreamSynchronize(self.d2h) == 0
+
     def close(self):
-        for st in self.streams:
+        for st in self.streams + [self.h2d, self.d2h]:
             self.hip.hipStreamDestroy(st)
+        for e in self.evs:
+            self.hip.hipEventDestroy(e)
 
 
 def overhead_in_child():
@@ -1318,8 +1456,12 @@ def overhead_leg(hx, which="e2", parts=4, iters=11):
         def run_native():
             native.run(fn, hin, hout, dptrs, bounds)
 
+        def run_native_layered():
+            native.run_layered(fn, hin, hout, dptrs, bounds)
+
         res = {}
-        for name, f in (("hx", run_hx), ("native", run_native)):
+        for name, f in (("hx", run_hx), ("native", run_native),
+                        ("native_layered", run_native_layered)):
             ts = []
             for _ in range(iters):
                 torch.cuda.synchronize()
@@ -1335,9 +1477,12 @@ def overhead_leg(hx, which="e2", parts=4, iters=11):
             continue
         rows.append({"m": m, "n": n, "hx_ms": res["hx"], "native_ms": res["native"],
                      "hx_over_native": res["hx"] / res["native"],
+                     "native_layered_ms": res["native_layered"],
+                     "hx_over_native_layered": res["hx"] / res["native_layered"],
                      "host_link_GBps_hx": 2 * n * 8 / (res["hx"] * 1e-3) / 1e9,
                      "max_abs_err_vs_1": err})
-        log(f"overhead m={m} n={n}: hx {res['hx']:.3f} ms, native {res['native']:.3f} ms")
+        log(f"overhead m={m} n={n}: hx {res['hx']:.3f} ms, native {res['native']:.3f} ms, "
+            f"native with hx's stream layout {res['native_layered']:.3f} ms")
     # E1 (Sec. V-A.1): the 3-point stencil, one vector, copy in -> kernel ->
     # copy out as a dependent chain, against the same chain with synchronous
     # HIP calls.
@@ -1349,7 +1494,7 @@ def overhead_leg(hx, which="e2", parts=4, iters=11):
         by = hx.hx_buffer_create(ctx, n * 8)
         px, py = hx.hx_buffer_ptr(ctx, bx)[0], hx.hx_buffer_ptr(ctx, by)[0]
 
-        def run_hx():
+        def submit_chain():
             e1 = hx.hx_copy_async(ctx, hx.hx_copy_desc(hx.HX_H2D, hin, bx, 0, 0, 0, n * 8))
             e2 = hx.hx_program_run(ctx, prog, "kprk",
                                    [hx.karg_buffer(bx, 0, hx.HX_ACCESS_READ),
@@ -1357,9 +1502,24 @@ def overhead_leg(hx, which="e2", parts=4, iters=11):
                                     hx.karg_value(np.int64(n))], ((n + 255) // 256,), (256,),
                                    deps=[e1])
             e3 = hx.hx_copy_async(ctx, hx.hx_copy_desc(hx.HX_D2H, hout, by, 0, 0, 0, n * 8), [e2])
-            assert hx.hx_wait(ctx, e3) == hx.HX_OK
-            for e in (e1, e2, e3):
+            return (e1, e2, e3)
+
+        def run_hx():
+            evs = submit_chain()
+            assert hx.hx_wait(ctx, evs[-1]) == hx.HX_OK
+            for e in evs:
                 hx.hx_event_release(ctx, e)
+
+        # the same chain captured once as a graph, replayed
+        hx.hx_graph_begin(ctx)
+        for e in submit_chain():
+            hx.hx_event_release(ctx, e)
+        graph = hx.hx_graph_end(ctx)
+
+        def run_graph():
+            e = hx.hx_graph_launch(ctx, graph)
+            assert hx.hx_wait(ctx, e) == hx.HX_OK
+            hx.hx_event_release(ctx, e)
 
         def run_native():
             ct = native.ct
@@ -1373,7 +1533,7 @@ def overhead_leg(hx, which="e2", parts=4, iters=11):
             assert native.hip.hipStreamSynchronize(st) == 0
 
         res = {}
-        for name, f in (("hx", run_hx), ("native", run_native)):
+        for name, f in (("hx", run_hx), ("native", run_native), ("hx_graph", run_graph)):
             ts = []
             for _ in range(iters):
                 torch.cuda.synchronize()
@@ -1381,13 +1541,17 @@ def overhead_leg(hx, which="e2", parts=4, iters=11):
                 f()
                 ts.append(time.perf_counter() - t0)
             res[name] = float(np.mean(ts[1:])) * 1e3
+        hx.hx_plan_destroy(ctx, graph)
         for b in (bx, by):
             hx.hx_buffer_destroy(ctx, b)
         if k == 0:
             continue
         e1_rows.append({"m": m, "n": n, "hx_ms": res["hx"], "native_ms": res["native"],
-                        "hx_over_native": res["hx"] / res["native"]})
-        log(f"overhead E1 m={m} n={n}: hx {res['hx']:.3f} ms, native {res['native']:.3f} ms")
+                        "hx_over_native": res["hx"] / res["native"],
+                        "hx_graph_ms": res["hx_graph"],
+                        "hx_graph_over_native": res["hx_graph"] / res["native"]})
+        log(f"overhead E1 m={m} n={n}: hx {res['hx']:.3f} ms, native {res['native']:.3f} ms, "
+            f"hx graph replay {res['hx_graph']:.3f} ms")
     native.close()
     hx.hx_program_destroy(ctx, prog)
     hx.hx_host_free(ctx, hin)

@@ -539,6 +539,43 @@ hx_status hx_host_task(hx_ctx ctx, hx_host_fn fn, void* user, const hx_event* de
 hx_status hx_event_record_stream(hx_ctx ctx, void* hip_stream, hx_event* out);
 hx_status hx_stream_wait_event(hx_ctx ctx, void* hip_stream, hx_event ev);
 
+/* ------------------------------------------------------- captured graphs */
+/* Record a future graph once and replay it as one operation.  The futures of
+ * Sec. III-A cost host work per operation (dependency resolution, stream
+ * waits and markers), which Sec. V-A.1 and V-A.2 measure against the native
+ * API; a program that submits the same graph of operations many times pays
+ * it once with these calls.
+ *
+ * hx_graph_begin opens a capture: every GPU operation submitted to the context
+ * until hx_graph_end (copies, stencils, batched plans in PERSISTENT or PLAIN
+ * mode, programs, when_all) is recorded into one HIP graph instead of
+ * running, in submission order on one stream (so the graph replays them one
+ * after another, which honours every dependency; operations that would run
+ * concurrently on separate streams do not overlap in the graph).  The events those
+ * calls return stand for the recorded operations: they order the later
+ * operations of the same capture, may be released, and are complete once the
+ * capture ends (recorded, not run).  During a capture a dependency must be an
+ * operation of the capture or already complete (else HX_ERR_ARG); waiting on
+ * a captured operation, hx_ctx_synchronize, the destroy and host-free calls,
+ * host tasks and the foreign-stream calls return HX_ERR_ARG; timing spans are
+ * not taken.  Not available on a host-only context (HX_ERR_NO_DEVICE) or one
+ * created on a caller's stream (HX_ERR_UNSUPPORTED).
+ *
+ * hx_graph_end closes the capture and returns the instantiated graph as a
+ * plan handle (freed by hx_plan_destroy); if the capture failed, every
+ * captured event completes with HX_ERR_HIP and so does the call.
+ * hx_graph_launch runs the whole graph once after `deps`, as one operation
+ * whose event completes when every recorded operation has; the graph keeps
+ * the device addresses, sizes and kernel arguments of the capture, so its
+ * buffers must still exist (HX_ERR_INVALID otherwise) and hold what the
+ * replay should read.  hx_graph_info gives the number of operations recorded.
+ */
+hx_status hx_graph_begin(hx_ctx ctx);
+hx_status hx_graph_end(hx_ctx ctx, hx_plan* graph);
+hx_status hx_graph_launch(hx_ctx ctx, hx_plan graph, const hx_event* deps, int ndeps,
+                          hx_event* out);
+hx_status hx_graph_info(hx_ctx ctx, hx_plan graph, int64_t* operations);
+
 /* ------------------------------------------------------ diagnostics/testing */
 /* Sequence number the next submitted operation will get. */
 hx_status hx_debug_next_seq(hx_ctx ctx, uint64_t* seq);

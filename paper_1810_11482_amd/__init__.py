@@ -162,6 +162,11 @@ _PROTOS = {
     "hx_launch_batched": (_i32, [_vp, _u64, ctypes.POINTER(_u64), ctypes.c_int,
                                  ctypes.POINTER(_u64)]),
     "hx_plan_destroy": (_i32, [_vp, _u64]),
+    "hx_graph_begin": (_i32, [_vp]),
+    "hx_graph_end": (_i32, [_vp, ctypes.POINTER(_u64)]),
+    "hx_graph_launch": (_i32, [_vp, _u64, ctypes.POINTER(_u64), ctypes.c_int,
+                               ctypes.POINTER(_u64)]),
+    "hx_graph_info": (_i32, [_vp, _u64, ctypes.POINTER(ctypes.c_int64)]),
     "hx_plan_create_halo": (_i32, [_vp, ctypes.POINTER(hx_halo_desc), ctypes.c_int,
                                    ctypes.POINTER(_u64)]),
     "hx_launch_halo": (_i32, [_vp, _u64, ctypes.POINTER(_u64), ctypes.c_int,
@@ -409,6 +414,29 @@ def hx_launch_batched(ctx, plan: int, deps=()) -> int:
 
 def hx_plan_destroy(ctx, plan: int) -> None:
     _ok(ctx, lib.hx_plan_destroy(ctx, plan))
+
+
+def hx_graph_begin(ctx) -> None:
+    _ok(ctx, lib.hx_graph_begin(ctx))
+
+
+def hx_graph_end(ctx) -> int:
+    g = _u64()
+    _ok(ctx, lib.hx_graph_end(ctx, ctypes.byref(g)))
+    return g.value
+
+
+def hx_graph_launch(ctx, graph: int, deps=()) -> int:
+    arr, n = _deps(deps)
+    ev = _u64()
+    _ok(ctx, lib.hx_graph_launch(ctx, graph, arr, n, ctypes.byref(ev)))
+    return ev.value
+
+
+def hx_graph_info(ctx, graph: int) -> int:
+    n = ctypes.c_int64()
+    _ok(ctx, lib.hx_graph_info(ctx, graph, ctypes.byref(n)))
+    return n.value
 
 
 def hx_plan_create_halo(ctx, descs) -> int:

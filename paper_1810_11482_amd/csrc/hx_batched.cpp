@@ -518,6 +518,7 @@ extern "C" hx_status hx_launch_batched(hx_ctx ctx, hx_plan plan, const hx_event*
     if (!out) return c->fail(HX_ERR_ARG, "null output event");
     Plan* p = c->get_plan(plan, PLAN_BATCHED);
     if (!p) return c->fail(HX_ERR_INVALID, "invalid batched plan");
+    c->capture_plan(plan);
     hipSetDevice(c->device);
     BatchPlan* bp = static_cast<BatchPlan*>(p->impl);
     std::string what = "batched1d x" + std::to_string(bp->segs.size());
@@ -566,6 +567,10 @@ extern "C" hx_status hx_plan_destroy(hx_ctx ctx, hx_plan plan) {
     std::lock_guard<std::recursive_mutex> lk(c->mu);
     Plan* p = c->get_plan(plan, -1);
     if (!p) return HX_ERR_INVALID;
+    if (hx_status s = c->no_capture("hx_plan_destroy")) return s;
+    if (p->graph_refs > 0)
+        return c->fail(HX_ERR_ARG, "a captured graph still uses this plan: destroy the graph "
+                                   "first");
     for (hipStream_t s : c->streams) hipStreamSynchronize(s);
     if (p->destroy) p->destroy(p->impl);
     p->live = false;

@@ -93,6 +93,7 @@ extern "C" hx_status hx_launch_halo(hx_ctx ctx, hx_plan plan, const hx_event* de
     if (!out) return c->fail(HX_ERR_ARG, "null output event");
     Plan* p = c->get_plan(plan, PLAN_HALO);
     if (!p) return c->fail(HX_ERR_INVALID, "invalid halo plan");
+    c->capture_plan(plan);
     hipSetDevice(c->device);
     HaloPlan* h = static_cast<HaloPlan*>(p->impl);
     return c->submit(SC_COMPUTE, deps, ndeps, h->acc, "halo x" + std::to_string(h->nd),

@@ -177,6 +177,7 @@ hx_status hx_program_run(hx_ctx ctx, hx_program prog, const char* kernel, const 
     if (c->host_only) return c->fail(HX_ERR_NO_DEVICE, "host-only context");
     Program* pr = get_program(c, prog);
     if (!pr) return c->fail(HX_ERR_INVALID, "invalid program handle");
+    c->capture_plan(prog);
     hipFunction_t fn = nullptr;
     hx_status s = lookup(c, pr, kernel, &fn);
     if (s) return s;
@@ -236,6 +237,10 @@ hx_status hx_program_destroy(hx_ctx ctx, hx_program prog) {
     std::lock_guard<std::recursive_mutex> lk(c->mu);
     Plan* p = c->get_plan(prog, PLAN_PROGRAM);
     if (!p) return HX_ERR_INVALID;
+    if (hx_status s = c->no_capture("hx_program_destroy")) return s;
+    if (p->graph_refs > 0)
+        return c->fail(HX_ERR_ARG, "a captured graph still uses this program: destroy the graph "
+                                   "first");
     if (!c->host_only)
         for (hipStream_t s : c->streams) hipStreamSynchronize(s);
     if (p->destroy) p->destroy(p->impl);

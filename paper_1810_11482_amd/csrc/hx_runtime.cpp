@@ -82,6 +82,7 @@ uint32_t Ctx::new_event(EventKind k) {
     e.deps.clear();
     e.waiters.clear();
     e.fn = nullptr;
+    e.captured = false;
     return slot;
 }
 
@@ -122,9 +123,17 @@ void Ctx::collect_leaves(uint32_t slot, std::vector<uint32_t>& out) {
     }
 }
 
+bool Ctx::has_captured_leaf(uint32_t slot) {
+    std::vector<uint32_t> leaves;
+    collect_leaves(slot, leaves);
+    for (uint32_t l : leaves)
+        if (events[l].captured && events[l].status == HX_PENDING) return true;
+    return false;
+}
+
 hx_status Ctx::refresh(uint32_t slot) {
     Event& e = events[slot];
-    if (e.status != HX_PENDING) return e.status;
+    if (e.status != HX_PENDING || e.captured) return e.status;
     switch (e.kind) {
     case EK_GPU: {
         hipError_t q = hipEventQuery(e.hev);
@@ -206,7 +215,9 @@ hx_status Ctx::enqueue_now(uint32_t slot) {
     for (uint32_t d : events[slot].deps) collect_leaves(d, leaves);
     Event& e0 = events[slot];
     int s;
-    if (e0.sclass == SC_H2D) {
+    if (capturing) {
+        s = 0;  // a captured graph is recorded on the capture's one stream
+    } else if (e0.sclass == SC_H2D) {
         s = h2d;
     } else if (e0.sclass == SC_D2H) {
         s = d2h;
@@ -232,7 +243,7 @@ hx_status Ctx::enqueue_now(uint32_t slot) {
         if (le.stream == s) continue;  // ordered by the stream itself
         hipStreamWaitEvent(st, le.hev, 0);
     }
-    if (timing) {
+    if (timing && !capturing) {
         events[slot].hev_start = take_hev();
         hipEventRecord(events[slot].hev_start, st);
     }
@@ -255,6 +266,11 @@ hx_status Ctx::enqueue_now(uint32_t slot) {
     e.stream = s;
     e.kind = EK_GPU;
     e.enqueued = true;
+    if (capturing) {
+        e.captured = true;
+        cap_events.push_back(slot);
+        ref_event(slot);
+    }
     if (stream_tail[s]) unref_event(stream_tail[s]);
     stream_tail[s] = slot;
     ref_event(slot);
@@ -274,6 +290,19 @@ hx_status Ctx::submit(StreamClass sc, const hx_event* deps, int ndeps,
         if (deps[i] == 0) continue;
         if (!get_event(deps[i])) return fail(HX_ERR_INVALID, "invalid dependency event");
         dslots.push_back(handle_slot(deps[i]));
+    }
+    if (capturing) {
+        // inside a graph a dependency is another captured operation, or
+        // work that has already completed
+        for (uint32_t d : dslots) {
+            std::vector<uint32_t> leaves;
+            collect_leaves(d, leaves);
+            for (uint32_t l : leaves)
+                if (!events[l].captured && refresh(l) != HX_OK)
+                    return fail(HX_ERR_ARG, "while a graph is being captured, a dependency must "
+                                            "be an operation of that graph or complete");
+        }
+        cap_acc.insert(cap_acc.end(), acc.begin(), acc.end());
     }
     sweep();
     uint32_t slot = new_event(EK_DEFERRED);
@@ -395,7 +424,7 @@ void Ctx::worker_loop() {
 }
 
 void Ctx::sweep() {
-    if (zombies.empty()) return;
+    if (zombies.empty() || capturing) return;
     std::vector<Zombie> keep;
     for (Zombie& z : zombies) {
         bool busy = false;
@@ -616,6 +645,7 @@ hx_status hx_ctx_synchronize(hx_ctx ctx) {
     {
         std::lock_guard<std::recursive_mutex> lk(c->mu);
         if (c->host_only) return HX_OK;
+        if (hx_status s = c->no_capture("hx_ctx_synchronize")) return s;
         hipSetDevice(c->device);
         ss = c->streams;
     }
@@ -640,6 +670,13 @@ hx_status hx_ctx_destroy(hx_ctx ctx) {
     }
     if (!c->host_only) {
         hipSetDevice(c->device);
+        if (c->capturing) {
+            // an open capture is abandoned: end it, drop the graph
+            hipGraph_t g = nullptr;
+            if (hipStreamEndCapture(c->streams[0], &g) == hipSuccess && g) hipGraphDestroy(g);
+            hipGetLastError();
+            c->capturing = false;
+        }
         for (hipStream_t s : c->streams) hipStreamSynchronize(s);
     }
     for (Plan& p : c->plans)
@@ -713,6 +750,7 @@ hx_status hx_buffer_wrap(hx_ctx ctx, void* dev_ptr, size_t bytes, hx_buffer* out
 hx_status hx_buffer_destroy(hx_ctx ctx, hx_buffer h) {
     Ctx* c = C(ctx);
     CTX_OR_FAIL(c);
+    if (hx_status s_ = c->no_capture("hx_buffer_destroy")) return s_;
     Buffer* b = c->get_buffer(h);
     if (!b) return HX_ERR_INVALID;
     b->live = false;
@@ -759,6 +797,7 @@ hx_status hx_host_alloc(hx_ctx ctx, size_t bytes, void** out) {
 hx_status hx_host_free(hx_ctx ctx, void* p) {
     Ctx* c = C(ctx);
     CTX_OR_FAIL(c);
+    if (hx_status s_ = c->no_capture("hx_host_free")) return s_;
     auto it = std::find(c->host_allocs.begin(), c->host_allocs.end(), p);
     if (it == c->host_allocs.end()) return HX_ERR_ARG;
     c->host_allocs.erase(it);
@@ -896,6 +935,8 @@ hx_status hx_wait(hx_ctx ctx, hx_event ev, int64_t timeout_ns) {
     const auto t0 = clk::now();
     std::unique_lock<std::recursive_mutex> lk(c->mu);
     if (!c->get_event(ev)) return HX_ERR_INVALID;
+    if (c->capturing && c->has_captured_leaf(handle_slot(ev)))
+        return c->fail(HX_ERR_ARG, "an operation of a graph being captured cannot be waited on");
     if (!c->host_only) hipSetDevice(c->device);
     const uint32_t slot = handle_slot(ev);
     c->ref_event(slot);  // keep the slot alive while unlocked
@@ -1009,6 +1050,7 @@ hx_status hx_user_event_set(hx_ctx ctx, hx_event ev, hx_status status) {
 hx_status hx_event_record_stream(hx_ctx ctx, void* stream, hx_event* out) {
     Ctx* c = C(ctx);
     CTX_OR_FAIL(c);
+    if (hx_status s_ = c->no_capture("hx_event_record_stream")) return s_;
     if (!out) return HX_ERR_ARG;
     if (c->host_only) return c->fail(HX_ERR_NO_DEVICE, "host-only context");
     hipSetDevice(c->device);
@@ -1029,6 +1071,7 @@ hx_status hx_event_record_stream(hx_ctx ctx, void* stream, hx_event* out) {
 hx_status hx_stream_wait_event(hx_ctx ctx, void* stream, hx_event ev) {
     Ctx* c = C(ctx);
     CTX_OR_FAIL(c);
+    if (hx_status s_ = c->no_capture("hx_stream_wait_event")) return s_;
     if (ev == 0) return HX_OK;
     if (!c->get_event(ev)) return HX_ERR_INVALID;
     if (c->host_only) return c->fail(HX_ERR_NO_DEVICE, "host-only context");
@@ -1053,6 +1096,7 @@ hx_status hx_host_task(hx_ctx ctx, hx_host_fn fn, void* user, const hx_event* de
                        hx_event* out) {
     Ctx* c = C(ctx);
     CTX_OR_FAIL(c);
+    if (hx_status s_ = c->no_capture("hx_host_task")) return s_;
     if (!out || !fn) return c->fail(HX_ERR_ARG, "null function or output event");
     if (ndeps < 0 || (ndeps > 0 && !deps)) return c->fail(HX_ERR_ARG, "bad dependency list");
     std::vector<uint32_t> dslots;

@@ -6,6 +6,7 @@
 
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <atomic>
 #include <condition_variable>
 #include <thread>
@@ -77,6 +78,9 @@ struct Event {
     hx_host_fn hfn = nullptr;
     void* huser = nullptr;
     bool running = false;
+    // queued while the context captured a graph: stands for a node of that
+    // graph, never queried (final once the capture ends)
+    bool captured = false;
 };
 
 struct Plan {
@@ -85,6 +89,7 @@ struct Plan {
     int type = 0;
     void* impl = nullptr;
     std::function<void(void*)> destroy;
+    int graph_refs = 0;  // captured graphs whose nodes use this plan's tables or code
 };
 
 struct Ctx {
@@ -118,6 +123,27 @@ struct Ctx {
     void start_worker();
     void worker_loop();
     std::string last_error;
+
+    // graph capture (hx_graph_begin .. hx_graph_end): every operation queued in
+    // between goes to compute stream 0, in submission order, and is recorded
+    // there into one HIP graph by stream capture
+    bool capturing = false;
+    std::vector<uint32_t> cap_events;  // captured operations (internal refs)
+    std::vector<Access> cap_acc;       // the byte ranges they touch
+    std::vector<hx_plan> cap_plans;    // plans and programs the captured operations use
+    // note that a captured operation uses plan `h` (no-op outside a capture)
+    void capture_plan(hx_plan h) {
+        if (capturing && std::find(cap_plans.begin(), cap_plans.end(), h) == cap_plans.end())
+            cap_plans.push_back(h);
+    }
+    // HX_ERR_ARG with a message when a capture is open (calls that block on
+    // or free GPU work are not allowed then)
+    hx_status no_capture(const char* what) {
+        return capturing ? fail(HX_ERR_ARG, std::string(what) + " is not allowed while a graph "
+                                                                "is being captured")
+                         : HX_OK;
+    }
+    bool has_captured_leaf(uint32_t slot);
 
     // hazard checker
     struct CNode { std::vector<uint64_t> deps; bool joined = false; std::string what; };
