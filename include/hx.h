@@ -327,7 +327,9 @@ typedef struct {
                                    interleaved walk (a persistent grid, wave w taking blocks
                                    w, w + grid, ... of all segments numbered back to back);
                                    -2 = the block walk (one wave per block, the grid covering
-                                   every block; at most 65535 segments); -1 and -2 are
+                                   every block; at most 65535 segments; waves_per_group 1 or 4
+                                   waves on consecutive blocks per workgroup, 0 = tuned, else
+                                   1, other counts HX_ERR_ARG); -1 and -2 are
                                    HX_ERR_ARG unless every segment has the same n and r, and
                                    give the same bits;
                                    0 = the tuned walk, else the block walk where allowed,
@@ -608,8 +610,9 @@ hx_status hx_tune_stencil(hx_ctx ctx, const hx_stencil_args* args, int budget_ms
 /* The same for a persistent batch (desc->mode PERSISTENT), timed the same way.
  * desc->steps is the whole run's step count T.  The search covers the pass
  * depth D (the divisors of T up to 64, from the deepest down to T/8), and per
- * depth the form (PROPAGATOR for f32, over its walks: the plan's choice (the block walk where it applies),
- * interleaved, spans of 128 and 40 blocks; DIRECT over cells per lane 8..64,
+ * depth the form (PROPAGATOR for f32, over its walks: the block walk at one
+ * and four waves per group, interleaved, the plan's choice, spans of 128 and
+ * 40 blocks; DIRECT over cells per lane 8..64,
  * waves per group 1, 2, 4 and a persistent grid of 16 or 64 waves per CU);
  * a candidate costs T / D times its pass.  *best is the fastest, with
  * best->steps = D: the run is T / D passes of that plan (ping-ponging in and

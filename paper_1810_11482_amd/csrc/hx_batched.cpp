@@ -54,8 +54,9 @@ struct BatchPlan {
     int64_t pwaves = 0;
     int pskip = 0;         // outer window chunks no segment multiplies
     bool pil = false;      // interleaved walk (segments of one size and one rate)
-    bool pbw = false;      // block walk (the same segments), its tap table
-    void* ptab_dev = nullptr;
+    bool pbw = false;      // block walk (the same segments), its tap table and
+    void* ptab_dev = nullptr;  // waves per workgroup
+    int pwpg = 1;
     int64_t pblocks = 0;   // interleaved: 1024-cell blocks in all, and per segment
     int64_t pbps = 0;
     hipStream_t cap = nullptr;
@@ -378,6 +379,14 @@ extern "C" hx_status hx_plan_create_batched(hx_ctx ctx, const hx_batch_desc* d, 
         if (!bp->pil && !bp->pbw) bp->pwaves = (int64_t)waves.size();
         std::vector<uint16_t> tab16;
         if (bp->pbw) {
+            // waves per workgroup: given, tuned, else one (4 when asked, on
+            // consecutive blocks; other counts are rejected)
+            bp->pwpg = d->waves_per_group ? d->waves_per_group
+                                          : (tuned_span && tg.wpg ? tg.wpg : 1);
+            if (bp->pwpg != 1 && bp->pwpg != 4) {
+                destroy_plan(bp);
+                return c->fail(HX_ERR_ARG, "the block walk takes 1 or 4 waves per group");
+            }
             const double r0 = bp->segs[0].r;
             tab16 = prop1d_bw_table(taps.data() + tap_at[r0], D, bp->pskip, texp_of[r0]);
             bp->pwaves = bp->pblocks;
@@ -527,8 +536,8 @@ extern "C" hx_status hx_launch_batched(hx_ctx ctx, hx_plan plan, const hx_event*
         [bp](hipStream_t st) -> hipError_t {
             if (bp->prop && bp->pbw)
                 return launch_prop1d_bw(bp->psegs_dev, bp->ptab_dev,
-                                        (int64_t)bp->segs.size(), bp->pbps, bp->steps,
-                                        bp->pskip, st);
+                                        (int64_t)bp->segs.size(), bp->pbps, bp->pwpg,
+                                        bp->steps, bp->pskip, st);
             if (bp->prop && bp->pil)
                 return launch_prop1d_il(bp->psegs_dev, bp->pblocks, bp->pbps, bp->pwaves,
                                         bp->steps, bp->pskip, st);

@@ -277,13 +277,14 @@ hipError_t launch_prop1d_il(const PropSeg* segs_dev, int64_t nblocks, int64_t bp
                             int D, int skip, hipStream_t stream);
 // Block walk of the same pass: one wave per block, bps blocks in each of
 // `nsegs` segments (same n and taps, as the interleaved walk; nsegs <= 65535,
-// bps < 2^31), the tap operands read from `tab_dev`, the table
-// prop1d_bw_table builds for (taps, D, skip, texp) of segs[0]
-// (prop1d_bw_table_bytes of device memory, 16-byte aligned).
+// bps < 2^31), `wpg` (1 or 4) waves per workgroup on consecutive blocks, the
+// tap operands read from `tab_dev`, the table prop1d_bw_table builds for
+// (taps, D, skip, texp) of segs[0] (prop1d_bw_table_bytes of device memory,
+// 16-byte aligned).
 size_t prop1d_bw_table_bytes(int D, int skip);
 std::vector<uint16_t> prop1d_bw_table(const float* taps, int D, int skip, int texp);
 hipError_t launch_prop1d_bw(const PropSeg* segs_dev, const void* tab_dev, int64_t nsegs,
-                            int64_t bps, int D, int skip, hipStream_t stream);
+                            int64_t bps, int wpg, int D, int skip, hipStream_t stream);
 
 // One 2D band: ny rows of nx cells, row-major, advanced `steps` steps from in
 // into out.  Rows outside [0, ny) come from the top/bottom rule; columns

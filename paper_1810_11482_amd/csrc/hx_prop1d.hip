@@ -163,20 +163,37 @@ __device__ __forceinline__ float load1(const PropSeg& s, int64_t c) {
 // cells within D of the window's ends go stale and are never stored.  It
 // serves the blocks whose products fail the accuracy check, after the wave's
 // other blocks, so it is rare and kept simple (loops not unrolled): every cell
-// is one 4-byte load and one 4-byte store.
-template <typename Cell>
+// is one 4-byte load and one 4-byte store.  WAVE: the caller's workgroup has
+// other waves, which do not take part: the steps are ordered by wave-level
+// barriers (the wave's LDS operations execute in order) instead of the
+// workgroup barrier.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <bool WAVE = false>
+__device__ __forceinline__ void block_sync() {
+    if (WAVE)
+        wave_sync();
+    else
+        __syncthreads();
+}
+
+template <bool WAVE = false, typename Cell>
 __device__ __forceinline__ void step_block(const PropSeg& s, int64_t c0, int D, Cell cell) {
-    const int l = threadIdx.x;
+    const int l = threadIdx.x & 63;
     const float r = s.r;
     const int b = 18 * l;
-    __syncthreads();
+    block_sync<WAVE>();
 #pragma unroll 1
     for (int t = 0; t < 18; ++t) cell(b + t) = load1(s, c0 - 64 + b + t);
-    __syncthreads();
+    block_sync<WAVE>();
     for (int k = 0; k < D; ++k) {
         const float lf = l > 0 ? cell(b - 1) : 0.f;
         const float rt = l < 63 ? cell(b + 18) : 0.f;
-        __syncthreads();
+        block_sync<WAVE>();
         float prev = lf, cur = cell(b);
 #pragma unroll 1
         for (int t = 0; t < 18; ++t) {
@@ -185,14 +202,14 @@ __device__ __forceinline__ void step_block(const PropSeg& s, int64_t c0, int D, 
             prev = cur;
             cur = nx;
         }
-        __syncthreads();
+        block_sync<WAVE>();
     }
 #pragma unroll 1
     for (int t = 0; t < 18; ++t) {
         const int64_t c = c0 - 64 + b + t;
         if (c >= c0 && c < c0 + 1024 && c < s.n) s.out[c] = cell(b + t);
     }
-    __syncthreads();
+    block_sync<WAVE>();
 }
 
 // True on every lane when some output of the block fails the accuracy check:
@@ -700,29 +717,39 @@ __device__ __forceinline__ void split16_pk(float x0, float x1, int e, uint32_t& 
     l = __builtin_bit_cast(uint32_t, __builtin_convertvector(rem, h2));
 }
 
-template <int NC, int S0>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8)))
-void k_prop1d_bw(const PropSeg* __restrict__ segs, const u32x4* __restrict__ tab, int D, int OD) {
+template <int NC, int S0, int W>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8)))
+void k_prop1d_bw(const PropSeg* __restrict__ segs, const u32x4* __restrict__ tab, int D, int OD,
+                 int64_t bps) {
     constexpr int U = bw_units(NC, S0);
-    constexpr int kUnits = 16 * U;               // 16-byte units of the table
-    constexpr int kLoads = (kUnits + 63) / 64;   // per lane
-    __shared__ __attribute__((aligned(16))) char lds[2 * kWPlane + 16 * kUnits];
-    char* const tl = lds + 2 * kWPlane;
-    const int l = threadIdx.x, i = l & 31, g = l >> 5;
+    constexpr int kUnits = 16 * U;                     // 16-byte units of the table
+    constexpr int kLoads = (kUnits + 64 * W - 1) / (64 * W);  // per work-item
+    // W waves per workgroup (blocks W x + w of the segment): they share one
+    // staged table, and the context cells of a block that are its
+    // neighbours' own cells are read by the same CU
+    __shared__ __attribute__((aligned(16))) char lds_all[W * 2 * kWPlane + 16 * kUnits];
+    char* const tl = lds_all + W * 2 * kWPlane;
+    const int wv = threadIdx.x >> 6;
+    char* const lds = lds_all + wv * 2 * kWPlane;
+    const int l = threadIdx.x & 63, i = l & 31, g = l >> 5;
     const PropSeg& s = segs[blockIdx.y];
-    const int64_t c0 = 1024 * (int64_t)blockIdx.x;
+    const int64_t blk = (int64_t)blockIdx.x * W + wv;
+    const bool live = W == 1 || blk < bps;  // a wave past the segment's end only stages the table
+    const int64_t c0 = 1024 * blk;
     const uint32_t lv = s.levels16;
     // the table first, so that waiting for it leaves the window's loads in flight
     u32x4 T[kLoads];
 #pragma unroll
-    for (int k = 0; k < kLoads; ++k)
-        if (k + 1 < kLoads || l + 64 * k < kUnits) T[k] = tab[l + 64 * k];
+    for (int k = 0; k < kLoads; ++k) {
+        const int u = (int)threadIdx.x + 64 * W * k;
+        if (k + 1 < kLoads || u < kUnits) T[k] = tab[u];
+    }
     // the window: this lane's 16-byte pieces of the block (cells 256 j + 4 l)
     // and of the left or right 64 context cells, as in the interleaved walk
     const int q = l & 15;
     const bool left = (l & 31) < 16;
-    f32x4 v[5];
-    {
+    f32x4 v[5] = {};
+    if (live) {
         const int64_t cx = (left ? c0 - 64 : c0 + 1024) + 4 * q;
         if (c0 >= 1024 && c0 + 1024 + 64 <= s.n) {
 #pragma unroll
@@ -735,9 +762,10 @@ void k_prop1d_bw(const PropSeg* __restrict__ segs, const u32x4* __restrict__ tab
         }
     }
 #pragma unroll
-    for (int k = 0; k < kLoads; ++k)
-        if (k + 1 < kLoads || l + 64 * k < kUnits)
-            *reinterpret_cast<u32x4*>(tl + 16 * (l + 64 * k)) = T[k];
+    for (int k = 0; k < kLoads; ++k) {
+        const int u = (int)threadIdx.x + 64 * W * k;
+        if (k + 1 < kLoads || u < kUnits) *reinterpret_cast<u32x4*>(tl + 16 * u) = T[k];
+    }
     // the window's scale: its largest |x| if all are finite (a NaN or an
     // infinity makes the maximum non-finite), else the largest finite one
     float mx = 0.f;
@@ -777,6 +805,7 @@ void k_prop1d_bw(const PropSeg* __restrict__ segs, const u32x4* __restrict__ tab
         }
     }
     __syncthreads();
+    if (!live) return;
     // A operand of chunk c for lane (m = i, g): taps 16c + 8g - OD - i + 0..7,
     // unit (d - d mod 8) / 8 of copy d mod 8, d = 16c + 8g + 31 - i (the table
     // starts at tap -OD - 31); one chunk further is two units further on
@@ -826,7 +855,8 @@ void k_prop1d_bw(const PropSeg* __restrict__ segs, const u32x4* __restrict__ tab
         mo = __builtin_elementwise_maximum(mo, fabsf(acc[e]));
     }
     if (__ballot(!(mn >= thr) || !(mo <= 3.402823466e38f))) {
-        step_block(s, c0, D, [&](int c) -> float& { return reinterpret_cast<float*>(lds)[c]; });
+        step_block<(W > 1)>(s, c0, D,
+                            [&](int c) -> float& { return reinterpret_cast<float*>(lds)[c]; });
         return;
     }
     // the outputs, scaled back and transposed through the window's planes
@@ -858,16 +888,18 @@ void k_prop1d_bw(const PropSeg* __restrict__ segs, const u32x4* __restrict__ tab
 
 // The kernel instantiation for depth D and `skip` dropped chunks per side
 // (nullptr when there is none), for the walk `walk` (PROP_SPAN, PROP_IL or
-// PROP_BW).
-static const void* prop1d_kernel(int D, int skip, int walk = PROP_SPAN) {
+// PROP_BW, the last with `wpg` = 1 or 4 waves per workgroup).
+static const void* prop1d_kernel(int D, int skip, int walk = PROP_SPAN, int wpg = 1) {
+    if (walk == PROP_BW && wpg != 1 && wpg != 4) return nullptr;
     int OD = 0, NC = 0;
     if (!prop1d_geometry(D, &OD, &NC) || skip < 0 || NC - 2 * skip < 1) return nullptr;
     switch (NC * 4 + (skip > 2 ? 2 : skip)) {
 #define HX_PROP_CASE(N, S)                                                      \
     case N * 4 + S:                                                             \
-        return walk == PROP_IL   ? reinterpret_cast<const void*>(&k_prop1d_il<N, S>) \
-               : walk == PROP_BW ? reinterpret_cast<const void*>(&k_prop1d_bw<N, S>) \
-                                 : reinterpret_cast<const void*>(&k_prop1d<N, S>);
+        return walk == PROP_IL ? reinterpret_cast<const void*>(&k_prop1d_il<N, S>)           \
+               : walk != PROP_BW ? reinterpret_cast<const void*>(&k_prop1d<N, S>)       \
+               : wpg == 4 ? reinterpret_cast<const void*>(&k_prop1d_bw<N, S, 4>)        \
+                          : reinterpret_cast<const void*>(&k_prop1d_bw<N, S, 1>);
 #define HX_PROP_CASES(N) HX_PROP_CASE(N, 0) HX_PROP_CASE(N, 1) HX_PROP_CASE(N, 2)
         HX_PROP_CASE(3, 0)
         HX_PROP_CASE(3, 1)
@@ -949,14 +981,16 @@ std::vector<uint16_t> prop1d_bw_table(const float* taps, int D, int skip, int te
 }
 
 hipError_t launch_prop1d_bw(const PropSeg* segs_dev, const void* tab_dev, int64_t nsegs,
-                            int64_t bps, int D, int skip, hipStream_t stream) {
+                            int64_t bps, int wpg, int D, int skip, hipStream_t stream) {
     int OD = 0, NC = 0;
-    const void* k = prop1d_kernel(D, skip, PROP_BW);
+    const void* k = prop1d_kernel(D, skip, PROP_BW, wpg);
     if (!k || !prop1d_geometry(D, &OD, &NC) || !tab_dev || nsegs <= 0 || nsegs > 65535 ||
         bps <= 0 || bps >= (int64_t(1) << 31))
         return hipErrorInvalidValue;
-    void* args[] = {&segs_dev, &tab_dev, &D, &OD};
-    return hipLaunchKernel(k, dim3((unsigned)bps, (unsigned)nsegs), dim3(64), args, 0, stream);
+    void* args[] = {&segs_dev, &tab_dev, &D, &OD, &bps};
+    const int64_t groups = (bps + wpg - 1) / wpg;
+    return hipLaunchKernel(k, dim3((unsigned)groups, (unsigned)nsegs), dim3(64 * wpg), args, 0,
+                           stream);
 }
 
 }  // namespace hx

@@ -314,11 +314,15 @@ extern "C" hx_status hx_tune_batched(hx_ctx ctx, const hx_batch_desc* desc, int 
     std::vector<hx_batch_desc> cands;
     for (int D : pass_depths(T)) {
         if (desc->dtype == HX_F32)
-            for (int span : {0, -1, 128, 40}) {
+            // the block walk at one and four waves per group, the interleaved
+            // walk, the plan's own choice and spans
+            for (int k = 0; k < 6; ++k) {
+                static const int kSpan[6] = {-2, -2, -1, 0, 128, 40};
                 hx_batch_desc d = *desc;
                 d.steps = D;
                 d.form = HX_FORM_PROPAGATOR;
-                d.span_blocks = span;
+                d.span_blocks = kSpan[k];
+                d.waves_per_group = k == 1 ? 4 : (k == 0 ? 1 : 0);
                 cands.push_back(d);
             }
         for (int cpl : {16, 32, 8, 64})

@@ -328,7 +328,7 @@ def test_interleaved_walk_rejections(ctx):
     hx.hx_buffer_destroy(ctx, c)
 
 
-def run_segments(ctx, vals, r, D, span):
+def run_segments(ctx, vals, r, D, span, wpg=0):
     """Periodic segments holding `vals` (f32), one propagator pass walked
     interleaved (span = -1, segments of one size), one wave per block
     (span = -2, likewise) or in spans; returns the f32 inputs and outputs per
@@ -346,7 +346,8 @@ def run_segments(ctx, vals, r, D, span):
     segs = [hx.segment(inp=bin_, in_offset=o * 4, out=bout, out_offset=o * 4, n=n, r=r,
                        bc_lo=hx.HX_BC_PERIODIC, bc_hi=hx.HX_BC_PERIODIC) for o in offs]
     plan = hx.hx_plan_create_batched(ctx, hx.HX_F32, D, segs, hx.HX_BATCH_PERSISTENT,
-                                     form=hx.HX_FORM_PROPAGATOR, span_blocks=span)
+                                     form=hx.HX_FORM_PROPAGATOR, span_blocks=span,
+                                     waves_per_group=wpg)
     ev = hx.hx_launch_batched(ctx, plan)
     assert hx.hx_wait(ctx, ev) == hx.HX_OK, hx.hx_last_error(ctx)
     hx.hx_event_release(ctx, ev)
@@ -479,3 +480,44 @@ def test_every_block_stepped(ctx, span):
         ref = oracle.heat1d_periodic(u[k].astype(np.float64), r, D)
         err = np.max(np.abs(out[k] - ref) / envelope(u[k], r, D))
         assert err <= 1e-5, (k, span, err)
+
+
+@pytest.mark.parametrize("n,D", [(30000, 50), (8192, 50), (4100, 17), (1024, 64), (64, 20)])
+def test_block_walk_four_waves_per_group_same_bits(ctx, n, D):
+    """The block walk with four waves per workgroup (consecutive blocks, one
+    staged tap table; segments whose block count is not a multiple of four
+    leave waves with no block) gives the bits of one wave per workgroup and of
+    the interleaved walk, on U[0,1] data with a spike, a NaN and a field whose
+    every block fails the accuracy check and is stepped (by its wave alone)."""
+    i = np.arange(n, dtype=np.float64)
+    vals = [workloads.uniform(n, 516, k, 0, 1, np.float64) for k in range(3)]
+    vals[0][n // 3] = 1e9
+    vals[1][n // 2] = np.nan
+    vals[2] = np.where(i % 2 == 0, 1.0, -1.0) + 1e-5 * (1.5 + np.sin(2 * np.pi * 3 * i / n))
+    u, one = run_segments(ctx, vals, 0.25, D, -2, wpg=1)
+    _, four = run_segments(ctx, vals, 0.25, D, -2, wpg=4)
+    _, il = run_segments(ctx, vals, 0.25, D, -1)
+    for k in range(3):
+        assert np.array_equal(four[k], one[k], equal_nan=True), k
+        assert np.array_equal(four[k], il[k], equal_nan=True), k
+    ref = oracle.heat1d_periodic(u[0].astype(np.float64), 0.25, D)
+    assert per_cell(four[0], ref) <= 1e-5
+
+
+def test_block_walk_group_sizes(ctx):
+    """Waves per group for the block walk: 1 or 4; 2 is rejected."""
+    b = hx.hx_buffer_create(ctx, 1 << 16)
+    c = hx.hx_buffer_create(ctx, 1 << 16)
+    s1 = hx.segment(inp=b, out=c, n=4096, r=0.2, bc_lo=hx.HX_BC_PERIODIC,
+                    bc_hi=hx.HX_BC_PERIODIC)
+    for w in (1, 4):
+        plan = hx.hx_plan_create_batched(ctx, hx.HX_F32, 20, [s1], hx.HX_BATCH_PERSISTENT,
+                                         form=hx.HX_FORM_PROPAGATOR, span_blocks=-2,
+                                         waves_per_group=w)
+        hx.hx_plan_destroy(ctx, plan)
+    with pytest.raises(hx.HxError) as e:
+        hx.hx_plan_create_batched(ctx, hx.HX_F32, 20, [s1], hx.HX_BATCH_PERSISTENT,
+                                  form=hx.HX_FORM_PROPAGATOR, span_blocks=-2, waves_per_group=2)
+    assert e.value.status == hx.HX_ERR_ARG
+    hx.hx_buffer_destroy(ctx, b)
+    hx.hx_buffer_destroy(ctx, c)
