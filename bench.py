@@ -1152,7 +1152,11 @@ def adjoint_leg(hx, ctx):
     # writes u once, whatever its depth.
     fwd_passes = sum(-(-min(S, T - t0) // 4) for t0 in range(0, T, S))
     fwd_bytes = n * fwd_passes * 12   # u read + write, kappa read per pass
-    rec_bytes = n * (T - nseg) * 12   # recomputed single steps
+    # the backward recomputes each segment's inner states in fused passes
+    # that store every level: per pass one read of u and kappa, per state one
+    # write
+    inner = [min(S, T - t0) - 1 for t0 in range(0, T, S)]
+    rec_bytes = n * sum(8 * (-(-m // 4)) + 4 * m for m in inner)
     adj_bytes = n * T * 24            # u_t, lam in/out, kappa, accumulator read + write
     res = {"cells": n, "steps": T, "segment": S, **times, "forward_passes": fwd_passes,
            "forward_cell_updates_per_s": n * T / (times["forward_ms"] * 1e-3),

@@ -204,6 +204,13 @@ hx_status hx_heat_vc_backward(hx_ctx ctx, const hx_vc_args* a, const hx_event* d
         return (t + 1 == T) ? plT : pw + (size_t)((t + 1) % 2) * bytes;
     };
     auto lam_out = [=](int t) -> char* { return t == 0 ? pl0 : pw + (size_t)(t % 2) * bytes; };
+    // Aligned grids recompute each segment's states in fused passes that store
+    // every level (one read of the state and of kappa per pass instead of per
+    // step); the others step by step.  Both give the same bits.
+    VCArgs probe{pu0, pk, nullptr, pseg ? pseg : pu0, nullptr, nx, ny, tau, rows};
+    const bool fused = vc_fused_supported(dt, probe) && (bytes & 15u) == 0 &&
+                       (!pseg || ((uintptr_t)pseg & 15u) == 0) &&
+                       (sc.nseg <= 1 || ((uintptr_t)pck & 15u) == 0);
     return c->submit(
         SC_COMPUTE, deps, ndeps, acc, "heat_vc_backward",
         [=](hipStream_t st) -> hipError_t {
@@ -218,10 +225,27 @@ hx_status hx_heat_vc_backward(hx_ctx ctx, const hx_vc_args* a, const hx_event* d
                 auto ut = [=](int t) -> const char* {
                     return t == t0 ? uck : pseg + (size_t)(t - t0 - 1) * bytes;
                 };
-                for (int t = t0 + 1; t < t1; ++t) {  // recompute the segment
-                    VCArgs v{ut(t - 1), pk, nullptr, pseg + (size_t)(t - t0 - 1) * bytes, nullptr,
-                             nx, ny, tau, rows};
-                    if ((e = launch_vc_step(dt, false, v, st)) != hipSuccess) return e;
+                if (fused && t1 - t0 > 1) {  // recompute the segment, fused
+                    const int nst = t1 - t0 - 1;  // states t0+1 .. t1-1, slots 0 .. nst-1
+                    const int np = (nst + kVcFusedMax - 1) / kVcFusedMax;
+                    const char* src = uck;
+                    for (int j = 0, done = 0; j < np; ++j) {
+                        const int d = nst / np + (j < nst % np ? 1 : 0);
+                        char* mid = pseg + (size_t)done * bytes;
+                        char* dst = pseg + (size_t)(done + d - 1) * bytes;
+                        VCArgs v{src, pk, nullptr, dst, nullptr, nx, ny, tau, rows};
+                        if ((e = launch_vc_forward(dt, d, v, st, d > 1 ? mid : nullptr,
+                                                   (int64_t)bytes)) != hipSuccess)
+                            return e;
+                        src = dst;
+                        done += d;
+                    }
+                } else {
+                    for (int t = t0 + 1; t < t1; ++t) {  // recompute the segment
+                        VCArgs v{ut(t - 1), pk, nullptr, pseg + (size_t)(t - t0 - 1) * bytes,
+                                 nullptr, nx, ny, tau, rows};
+                        if ((e = launch_vc_step(dt, false, v, st)) != hipSuccess) return e;
+                    }
                 }
                 for (int t = t1 - 1; t >= t0; --t) {  // reverse sweep
                     VCArgs v{ut(t), pk, lam_in(t), lam_out(t), pga, nx, ny, tau, rows};

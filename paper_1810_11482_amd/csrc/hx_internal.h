@@ -364,7 +364,10 @@ hipError_t launch_vc_step(int dtype, bool adjoint, const VCArgs& v, hipStream_t 
 // multiple of 4 and under 2 GiB (vc_fused_supported), else hipErrorInvalidValue.
 constexpr int kVcFusedMax = 4;
 bool vc_fused_supported(int dtype, const VCArgs& v);
-hipError_t launch_vc_forward(int dtype, int steps, const VCArgs& v, hipStream_t stream);
+// mid (16-byte aligned, stride a multiple of 16 of at least one state):
+// also store the states after steps 1 .. steps-1 at mid + (k-1) * mid_stride.
+hipError_t launch_vc_forward(int dtype, int steps, const VCArgs& v, hipStream_t stream,
+                             void* mid = nullptr, int64_t mid_stride = 0);
 hipError_t launch_fold(int dtype, void* acc, double* total, int64_t n, hipStream_t stream);
 hipError_t launch_fill(int dtype, void* p, int64_t n, double v, hipStream_t stream);
 hipError_t launch_cast64(int dtype, const double* src, void* dst, int64_t n, hipStream_t stream);

@@ -414,9 +414,13 @@ unsigned grid_for(int64_t n) {
 // and kappa rows i-k-1 .. i-k+1, so u and kappa are read once and u written
 // once per D steps.  Each level keeps three rows of C cells, kappa D + 2.  The
 // arithmetic, and its order, is the single step's (k_vc_step), so a fused
-// pass gives the same bits as D single steps.
-template <typename T, int D>
-__global__ __launch_bounds__(256) void k_vc_fwd(VCDev a, int64_t nstrips, int64_t nwaves) {
+// pass gives the same bits as D single steps.  MID: levels 1..D-1 are stored
+// too, level k into mid + (k - 1) * mid_stride bytes (the states between the
+// pass's input and its output, as the checkpointed backward sweep recomputes
+// them): one read of u and kappa and D writes for D steps.
+template <typename T, int D, bool MID>
+__global__ __launch_bounds__(256) void k_vc_fwd(VCDev a, int64_t nstrips, int64_t nwaves,
+                                                void* mid, int64_t mid_stride) {
     static_assert(D >= 1 && D <= C, "the halo lane covers at most C steps");
     typedef T V2 __attribute__((ext_vector_type(16 / sizeof(T))));
     typedef __attribute__((address_space(1))) const V2 GV2;
@@ -453,6 +457,12 @@ __global__ __launch_bounds__(256) void k_vc_fwd(VCDev a, int64_t nstrips, int64_
         __builtin_amdgcn_make_buffer_rsrc(a.out, (short)0, bytes, BUF_DWORD3);
     const bool store_lane = lane >= 1 && lane <= 62 && lin;
     const uint32_t lane_off = store_lane ? (uint32_t)(xl * (int64_t)sizeof(T)) : OOB_OFFSET;
+    __amdgpu_buffer_rsrc_t rsm[D > 1 ? D - 1 : 1];
+    if constexpr (MID)
+#pragma unroll
+        for (int k = 0; k + 1 < D; ++k)
+            rsm[k] = __builtin_amdgcn_make_buffer_rsrc(static_cast<char*>(mid) + k * mid_stride,
+                                                       (short)0, bytes, BUF_DWORD3);
 
     T ur[D][3][C];     // level k: rows i-k-1, i-k, i-k+1 (after the shift below)
     T kr[D + 2][C];    // kappa rows i-D-1 .. i
@@ -533,6 +543,8 @@ __global__ __launch_bounds__(256) void k_vc_fwd(VCDev a, int64_t nstrips, int64_
             if (k < D) {
 #pragma unroll
                 for (int j = 0; j < C; ++j) ur[k][2][j] = v[j];
+                if constexpr (MID)
+                    if (r >= y0 && r < y1) store_row<T>(rsm[k - 1], lane_off, r, nx, v);
             } else {
 #pragma unroll
                 for (int j = 0; j < C; ++j) out[j] = v[j];
@@ -580,15 +592,28 @@ bool vc_fused_supported(int dtype, const VCArgs& v) {
            v.nx * v.ny * es < (int64_t(1) << 31) && v.nx > 0 && v.ny > 0;
 }
 
-hipError_t launch_vc_forward(int dtype, int steps, const VCArgs& v, hipStream_t st) {
+hipError_t launch_vc_forward(int dtype, int steps, const VCArgs& v, hipStream_t st, void* mid,
+                             int64_t mid_stride) {
     if (steps < 1 || steps > C || !vc_fused_supported(dtype, v)) return hipErrorInvalidValue;
+    const int es = dtype == 0 ? 4 : 8;
+    if (mid && (((reinterpret_cast<uintptr_t>(mid) | (uintptr_t)mid_stride) & 15u) ||
+                mid_stride < v.nx * v.ny * es))
+        return hipErrorInvalidValue;
     VCDev a{v.u, v.kappa, nullptr, v.out, nullptr, v.nx, v.ny, v.dt, v.rows > 0 ? v.rows : 64, 1};
     const int64_t nstrips = (v.nx + (S - 2 * C) - 1) / (S - 2 * C);
     const int64_t nchunks = (v.ny + a.rows - 1) / a.rows;
     const int64_t nwaves = nstrips * nchunks;
     const int wpg = 4;
     const dim3 block(64 * wpg), grid((unsigned)((nwaves + wpg - 1) / wpg));
-#define HX_VC_FWD(T, D) hipLaunchKernelGGL((k_vc_fwd<T, D>), grid, block, 0, st, a, nstrips, nwaves)
+#define HX_VC_FWD(T, D)                                                                     \
+    do {                                                                                    \
+        if (mid)                                                                            \
+            hipLaunchKernelGGL((k_vc_fwd<T, D, true>), grid, block, 0, st, a, nstrips,      \
+                               nwaves, mid, mid_stride);                                    \
+        else                                                                                \
+            hipLaunchKernelGGL((k_vc_fwd<T, D, false>), grid, block, 0, st, a, nstrips,     \
+                               nwaves, mid, mid_stride);                                    \
+    } while (0)
     if (dtype == 0) {
         switch (steps) {
             case 1: HX_VC_FWD(float, 1); break;

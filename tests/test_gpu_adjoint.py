@@ -111,7 +111,10 @@ def test_gpu_fp64_inner_product_identity(ctx, shape):
         hx.hx_buffer_destroy(ctx, b)
 
 
-def gpu_grad(ctx, u0, kappa, y, dt, T, ckpt, dtype):
+def gpu_grad(ctx, u0, kappa, y, dt, T, ckpt, dtype, seg_misaligned=False):
+    """(loss, lam0, dL/dkappa) from the library; seg_misaligned: the segment
+    buffer is a view 4 bytes into its allocation, so the backward sweep
+    recomputes its states by single steps instead of fused passes."""
     shape = u0.shape
     ny, nx = shape
     n = ny * nx
@@ -122,7 +125,9 @@ def gpu_grad(ctx, u0, kappa, y, dt, T, ckpt, dtype):
     buT = hx.hx_buffer_create(ctx, n * es)
     bck = hx.hx_buffer_create(ctx, max(nseg - 1, 1) * n * es)
     bw = hx.hx_buffer_create(ctx, 2 * n * es)
-    bseg = hx.hx_buffer_create(ctx, max(S - 1, 1) * n * es)
+    bseg_mem = hx.hx_buffer_create(ctx, max(S - 1, 1) * n * es + 16)
+    bseg = hx.hx_buffer_wrap(ctx, hx.hx_buffer_ptr(ctx, bseg_mem)[0] + (4 if seg_misaligned else 0),
+                             max(S - 1, 1) * n * es)
     blT = hx.hx_buffer_create(ctx, n * es)
     bl0 = hx.hx_buffer_create(ctx, n * es)
     bg64 = hx.hx_buffer_create(ctx, n * 8)
@@ -140,7 +145,7 @@ def gpu_grad(ctx, u0, kappa, y, dt, T, ckpt, dtype):
     loss = download(ctx, bloss, 1, np.float64)[0]
     lam0 = download(ctx, bl0, shape, dtype)
     gk = download(ctx, bg64, shape, np.float64)
-    for b in (bu0, bk, by, buT, bck, bw, bseg, blT, bl0, bg64, bga, bloss, work):
+    for b in (bu0, bk, by, buT, bck, bw, bseg, bseg_mem, blT, bl0, bg64, bga, bloss, work):
         hx.hx_buffer_destroy(ctx, b)
     return loss, lam0, gk
 
@@ -171,6 +176,23 @@ def test_checkpoint_length_does_not_change_bits(ctx):
         # the FP64 gradient total is folded once per segment, so its summation
         # grouping (not its terms) changes with S
         assert rel_l2(got[2], ref[2]) <= 1e-14
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("shape,T,ckpt", [((64, 248), 20, 10), ((130, 496), 17, 5),
+                                          ((40, 100), 12, 12), ((12, 8), 9, 3)])
+def test_fused_recompute_equals_stepped_recompute(ctx, dtype, shape, T, ckpt):
+    """The backward sweep's recomputation of each segment's states in fused
+    passes that store every level (aligned segment buffer) gives the same
+    loss, lam0 and kappa gradient bit for bit as single-step recomputation
+    (the same segment buffer misaligned by 4 bytes)."""
+    u0 = workloads.gaussian_bumps(*shape, 3, 5.0, 617, np.float64)
+    kappa = kappa_field(shape, 11, np.float64)
+    y = workloads.uniform(shape, 618, 0, 0, 1, np.float64)
+    fused = gpu_grad(ctx, u0, kappa, y, 0.2, T, ckpt, dtype)
+    stepped = gpu_grad(ctx, u0, kappa, y, 0.2, T, ckpt, dtype, seg_misaligned=True)
+    assert fused[0] == stepped[0]
+    assert np.array_equal(fused[1], stepped[1]) and np.array_equal(fused[2], stepped[2])
 
 
 def test_fd_directional_fp64(ctx):
