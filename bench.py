@@ -1157,7 +1157,11 @@ def adjoint_leg(hx, ctx):
     # write
     inner = [min(S, T - t0) - 1 for t0 in range(0, T, S)]
     rec_bytes = n * sum(8 * (-(-m // 4)) + 4 * m for m in inner)
-    adj_bytes = n * T * 24            # u_t, lam in/out, kappa, accumulator read + write
+    # the reverse sweep runs in fused passes of up to four adjoint steps: per
+    # pass lam, kappa and the accumulator read once and lam and the
+    # accumulator written once (20 B), per step its u_t read once (4 B)
+    segs_len = [min(S, T - t0) for t0 in range(0, T, S)]
+    adj_bytes = n * sum(20 * (-(-m // 4)) + 4 * m for m in segs_len)
     res = {"cells": n, "steps": T, "segment": S, **times, "forward_passes": fwd_passes,
            "forward_cell_updates_per_s": n * T / (times["forward_ms"] * 1e-3),
            "forward_hbm_algorithmic_GBps": fwd_bytes / (times["forward_ms"] * 1e-3) / 1e9,

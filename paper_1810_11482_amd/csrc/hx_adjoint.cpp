@@ -211,6 +211,11 @@ hx_status hx_heat_vc_backward(hx_ctx ctx, const hx_vc_args* a, const hx_event* d
     const bool fused = vc_fused_supported(dt, probe) && (bytes & 15u) == 0 &&
                        (!pseg || ((uintptr_t)pseg & 15u) == 0) &&
                        (sc.nseg <= 1 || ((uintptr_t)pck & 15u) == 0);
+    // ... and run the reverse sweep in fused passes of up to four adjoint
+    // steps with their gradient terms (lam moving between the two work slots,
+    // the last pass into lam0)
+    auto al16 = [](const void* q) { return ((uintptr_t)q & 15u) == 0; };
+    const bool fused_adj = fused && al16(plT) && al16(pl0) && al16(pga) && (T <= 1 || al16(pw));
     return c->submit(
         SC_COMPUTE, deps, ndeps, acc, "heat_vc_backward",
         [=](hipStream_t st) -> hipError_t {
@@ -218,6 +223,7 @@ hx_status hx_heat_vc_backward(hx_ctx ctx, const hx_vc_args* a, const hx_event* d
             if (e != hipSuccess) return e;
             if ((e = launch_fill(dt, pga, cells, 0.0, st)) != hipSuccess) return e;
             if (T == 0) return hipMemcpyAsync(pl0, plT, bytes, hipMemcpyDeviceToDevice, st);
+            const char* cur = plT;  // the fused sweep's lam_{t+1}
             for (int k = nseg - 1; k >= 0; --k) {
                 const int t0 = k * S;
                 const int t1 = std::min(T, t0 + S);
@@ -247,9 +253,25 @@ hx_status hx_heat_vc_backward(hx_ctx ctx, const hx_vc_args* a, const hx_event* d
                         if ((e = launch_vc_step(dt, false, v, st)) != hipSuccess) return e;
                     }
                 }
-                for (int t = t1 - 1; t >= t0; --t) {  // reverse sweep
-                    VCArgs v{ut(t), pk, lam_in(t), lam_out(t), pga, nx, ny, tau, rows};
-                    if ((e = launch_vc_step(dt, true, v, st)) != hipSuccess) return e;
+                if (fused_adj) {  // reverse sweep, fused
+                    const int L = t1 - t0;
+                    const int np = (L + kVcFusedMax - 1) / kVcFusedMax;
+                    int tb = t1 - 1;
+                    for (int j = 0; j < np; ++j) {
+                        const int d = L / np + (j < L % np ? 1 : 0);
+                        const void* us[kVcFusedMax] = {};
+                        for (int q = 0; q < d; ++q) us[q] = ut(tb - q);
+                        char* dst = tb - d + 1 == 0 ? pl0 : (cur == pw ? pw + bytes : pw);
+                        VCArgs v{nullptr, pk, cur, dst, pga, nx, ny, tau, rows};
+                        if ((e = launch_vc_adjoint(dt, d, v, us, st)) != hipSuccess) return e;
+                        cur = dst;
+                        tb -= d;
+                    }
+                } else {
+                    for (int t = t1 - 1; t >= t0; --t) {  // reverse sweep
+                        VCArgs v{ut(t), pk, lam_in(t), lam_out(t), pga, nx, ny, tau, rows};
+                        if ((e = launch_vc_step(dt, true, v, st)) != hipSuccess) return e;
+                    }
                 }
                 if ((e = launch_fold(dt, pga, reinterpret_cast<double*>(pg64), cells, st)) !=
                     hipSuccess)

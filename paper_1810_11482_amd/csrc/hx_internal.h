@@ -368,6 +368,14 @@ bool vc_fused_supported(int dtype, const VCArgs& v);
 // also store the states after steps 1 .. steps-1 at mid + (k-1) * mid_stride.
 hipError_t launch_vc_forward(int dtype, int steps, const VCArgs& v, hipStream_t stream,
                              void* mid = nullptr, int64_t mid_stride = 0);
+// `steps` (1..4) adjoint steps t = tb .. tb-steps+1 fused in one pass: v.lam
+// (lam_{tb+1}) -> v.out (lam_{tb+1-steps}), adding each step's
+// conductivity-gradient term to v.gacc in the single steps' order (the same
+// bits as that many launch_vc_step adjoint steps); ustates[k] is u_t of step
+// t = tb - k.  The grids vc_fused_supported takes, lam, gacc and the states
+// 16-byte aligned, else hipErrorInvalidValue.
+hipError_t launch_vc_adjoint(int dtype, int steps, const VCArgs& v, const void* const* ustates,
+                             hipStream_t stream);
 hipError_t launch_fold(int dtype, void* acc, double* total, int64_t n, hipStream_t stream);
 hipError_t launch_fill(int dtype, void* p, int64_t n, double v, hipStream_t stream);
 hipError_t launch_cast64(int dtype, const double* src, void* dst, int64_t n, hipStream_t stream);

@@ -555,6 +555,194 @@ __global__ __launch_bounds__(256) void k_vc_fwd(VCDev a, int64_t nstrips, int64_
     }
 }
 
+
+// D fused adjoint steps with their conductivity-gradient terms (temporal
+// blocking of the reverse sweep), for the grids k_vc_fwd takes.  Steps
+// t = tb, tb-1, ..., tb-D+1: level 0 is lam_{tb+1} (input rows), level k
+// (1..D) produces lam_t, t = tb+1-k, from level k-1's rows and kappa, and adds
+// -dt g_t to the accumulator, g_t from u_t (us.p[k-1], read row by row into a
+// three-row ring per level) and lam_{t+1} (level k-1).  Rows stream top to
+// bottom once: per row, lam, kappa and the accumulator are read once and
+// written once (lam at level D only), each u_t read once: (D + 3) reads and 2
+// writes per D steps instead of 6 reads and writes per step.  The
+// accumulator row of row r enters at level 1 and leaves after level D, taking
+// the D terms in the single step's order (t descending) with its fma, and
+// lam's arithmetic is the single step's: the same bits as D single adjoint
+// steps.
+struct UStates {
+    const void* p[4];
+};
+
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_vc_adj(VCDev a, UStates us, int64_t nstrips,
+                                                int64_t nwaves) {
+    static_assert(D >= 1 && D <= C && D <= 4, "the halo lane covers at most C steps");
+    typedef T V2 __attribute__((ext_vector_type(16 / sizeof(T))));
+    typedef __attribute__((address_space(1))) const V2 GV2;
+    constexpr int VN = 16 / sizeof(T);
+    constexpr int W = S - 2 * C;  // output columns per strip
+    const int wpg = blockDim.x >> 6;
+    const int64_t wave =
+        (int64_t)blockIdx.x * wpg + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wave >= nwaves) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t strip = wave % nstrips, chunk = wave / nstrips;
+    const int64_t nx = a.nx, ny = a.ny;
+    const int64_t xl = strip * W - C + (int64_t)lane * C;  // this lane's first column
+    const int64_t y0 = chunk * a.rows;
+    const int64_t y1 = (y0 + a.rows < ny) ? y0 + a.rows : ny;
+    const T dt = static_cast<T>(a.dt);
+    const T* L = static_cast<const T*>(a.lam);
+    const T* K = static_cast<const T*>(a.kappa);
+    const T* G = static_cast<const T*>(a.gacc);
+    const bool lin = xl >= 0 && xl + C <= nx;  // the lane's cells: all inside or all outside
+    const int64_t xv = lin ? xl : 0;
+    auto load = [&](const T* f, int64_t y, T (&v)[C]) {
+        const bool rin = y >= 0 && y < ny;
+        const T* row = f + (y < 0 ? 0 : (y >= ny ? ny - 1 : y)) * nx;
+#pragma unroll
+        for (int q = 0; q < C / VN; ++q) {
+            const V2 x = *((GV2*)(row + xv) + q);
+#pragma unroll
+            for (int e = 0; e < VN; ++e) v[q * VN + e] = (rin && lin) ? x[e] : T(0);
+        }
+    };
+    const int bytes = (int)(ny * nx * (int64_t)sizeof(T));
+    const __amdgpu_buffer_rsrc_t rso =
+        __builtin_amdgcn_make_buffer_rsrc(a.out, (short)0, bytes, BUF_DWORD3);
+    const __amdgpu_buffer_rsrc_t rsg =
+        __builtin_amdgcn_make_buffer_rsrc(a.gacc, (short)0, bytes, BUF_DWORD3);
+    const bool store_lane = lane >= 1 && lane <= 62 && lin;
+    const uint32_t lane_off = store_lane ? (uint32_t)(xl * (int64_t)sizeof(T)) : OOB_OFFSET;
+
+    T lr[D][3][C];     // lam level k: rows i-k-1, i-k, i-k+1 (after the shift below)
+    T ur[D][3][C];     // u_t of level k+1: rows i-k-2, i-k-1, i-k (after the shift)
+    T kr[D + 2][C];    // kappa rows i-D-1 .. i
+    T gr[D][C];        // accumulator of row i-1-m in gr[m] (level m+1's row)
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+#pragma unroll
+            for (int j = 0; j < C; ++j) lr[k][m][j] = ur[k][m][j] = T(0);
+#pragma unroll
+    for (int m = 0; m < D + 2; ++m)
+#pragma unroll
+        for (int j = 0; j < C; ++j) kr[m][j] = T(0);
+#pragma unroll
+    for (int m = 0; m < D; ++m)
+#pragma unroll
+        for (int j = 0; j < C; ++j) gr[m][j] = T(0);
+    T ln[C], kn[C], gn[C], un[D][C];
+    load(L, y0 - D, ln);
+    load(K, y0 - D, kn);
+    load(G, y0 - D - 1, gn);
+#pragma unroll
+    for (int k = 0; k < D; ++k) load(static_cast<const T*>(us.p[k]), y0 - D - k, un[k]);
+    for (int64_t i = y0 - D; i < y1 + D; ++i) {
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                lr[k][0][j] = lr[k][1][j];
+                lr[k][1][j] = lr[k][2][j];
+                ur[k][0][j] = ur[k][1][j];
+                ur[k][1][j] = ur[k][2][j];
+                ur[k][2][j] = un[k][j];
+            }
+#pragma unroll
+        for (int m = 0; m < D + 1; ++m)
+#pragma unroll
+            for (int j = 0; j < C; ++j) kr[m][j] = kr[m + 1][j];
+#pragma unroll
+        for (int m = D - 1; m > 0; --m)
+#pragma unroll
+            for (int j = 0; j < C; ++j) gr[m][j] = gr[m - 1][j];
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            lr[0][2][j] = ln[j];
+            kr[D + 1][j] = kn[j];
+            gr[0][j] = gn[j];
+        }
+        // the next rows in flight (rows past the domain are clamped reads)
+        load(L, i + 1, ln);
+        load(K, i + 1, kn);
+        load(G, i, gn);
+#pragma unroll
+        for (int k = 0; k < D; ++k) load(static_cast<const T*>(us.p[k]), i + 1 - k, un[k]);
+        T out[C];
+#pragma unroll
+        for (int k = 1; k <= D; ++k) {
+            const int64_t r = i - k;  // the row level k produces
+            const T* fm = lr[k - 1][0];
+            const T* f0 = lr[k - 1][1];
+            const T* fp = lr[k - 1][2];
+            const T* um = ur[k - 1][0];
+            const T* u0 = ur[k - 1][1];
+            const T* up = ur[k - 1][2];
+            const T* km = kr[D - k];
+            const T* k0 = kr[D - k + 1];
+            const T* kp = kr[D - k + 2];
+            const bool nin = r - 1 >= 0, sin = r + 1 < ny;
+            const T fwl = dpp_move<DPP_WAVE_SHR1>(f0[C - 1]);
+            const T fel = dpp_move<DPP_WAVE_SHL1>(f0[0]);
+            const T uwl = dpp_move<DPP_WAVE_SHR1>(u0[C - 1]);
+            const T uel = dpp_move<DPP_WAVE_SHL1>(u0[0]);
+            const T kwl = dpp_move<DPP_WAVE_SHR1>(k0[C - 1]);
+            const T kel = dpp_move<DPP_WAVE_SHL1>(k0[0]);
+            T v[C];
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                const T fc = f0[j];
+                const T kc = k0[j];
+                const T uc = u0[j];
+                const int64_t x = xl + j;
+                const T fw = j > 0 ? f0[j - 1] : fwl;
+                const T fe = j + 1 < C ? f0[j + 1] : fel;
+                const T uw = j > 0 ? u0[j - 1] : uwl;
+                const T ue = j + 1 < C ? u0[j + 1] : uel;
+                const T kw = (x - 1 >= 0) ? (j > 0 ? k0[j - 1] : kwl) : kc;
+                const T ke = (x + 1 < nx) ? (j + 1 < C ? k0[j + 1] : kel) : kc;
+                const T fW = (x - 1 >= 0) ? fw : T(0);
+                const T fE = (x + 1 < nx) ? fe : T(0);
+                const T kN = nin ? km[j] : kc;
+                const T kS = sin ? kp[j] : kc;
+                const T fN = nin ? fm[j] : T(0);
+                const T fS = sin ? fp[j] : T(0);
+                const T kfw = (kc + kw) * T(0.5);
+                const T kfe = (kc + ke) * T(0.5);
+                const T kfn = (kc + kN) * T(0.5);
+                const T kfs = (kc + kS) * T(0.5);
+                T acc = kfw * (fW - fc);
+                acc = fmaT(kfe, fE - fc, acc);
+                acc = fmaT(kfn, fN - fc, acc);
+                acc = fmaT(kfs, fS - fc, acc);
+                v[j] = fmaT(dt, acc, fc);
+                // the step's conductivity-gradient term, as the single step
+                const T prod = uc * fc;
+                const T hw = (x - 1 >= 0) ? (uw - uc) * (fw - fc) * T(0.5) : prod;
+                const T he = (x + 1 < nx) ? (ue - uc) * (fe - fc) * T(0.5) : prod;
+                const T hn = nin ? (um[j] - uc) * (fm[j] - fc) * T(0.5) : prod;
+                const T hs = sin ? (up[j] - uc) * (fp[j] - fc) * T(0.5) : prod;
+                const T g = ((hw + he) + (hn + hs));
+                gr[k - 1][j] = fmaT(-dt, g, gr[k - 1][j]);
+            }
+            if (k < D) {
+#pragma unroll
+                for (int j = 0; j < C; ++j) lr[k][2][j] = v[j];
+            } else {
+#pragma unroll
+                for (int j = 0; j < C; ++j) out[j] = v[j];
+            }
+        }
+        const int64_t r = i - D;
+        if (r >= y0 && r < y1) {
+            store_row<T>(rso, lane_off, r, nx, out);
+            store_row<T>(rsg, lane_off, r, nx, gr[D - 1]);
+        }
+    }
+}
+
 }  // namespace
 
 hipError_t launch_vc_step(int dtype, bool adjoint, const VCArgs& v, hipStream_t st) {
@@ -630,6 +818,44 @@ hipError_t launch_vc_forward(int dtype, int steps, const VCArgs& v, hipStream_t 
         }
     }
 #undef HX_VC_FWD
+    return hipGetLastError();
+}
+
+hipError_t launch_vc_adjoint(int dtype, int steps, const VCArgs& v, const void* const* ustates,
+                             hipStream_t st) {
+    auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; };
+    if (steps < 1 || steps > C || steps > 4 || !v.lam || !v.gacc || !al(v.lam) || !al(v.gacc) ||
+        !vc_fused_supported(dtype, v))
+        return hipErrorInvalidValue;
+    UStates us{};
+    for (int k = 0; k < steps; ++k) {
+        if (!ustates[k] || !al(ustates[k])) return hipErrorInvalidValue;
+        us.p[k] = ustates[k];
+    }
+    VCDev a{nullptr, v.kappa, v.lam, v.out, v.gacc, v.nx, v.ny, v.dt, v.rows > 0 ? v.rows : 64, 1};
+    const int64_t nstrips = (v.nx + (S - 2 * C) - 1) / (S - 2 * C);
+    const int64_t nchunks = (v.ny + a.rows - 1) / a.rows;
+    const int64_t nwaves = nstrips * nchunks;
+    const int wpg = 4;
+    const dim3 block(64 * wpg), grid((unsigned)((nwaves + wpg - 1) / wpg));
+#define HX_VC_ADJ(T, D) \
+    hipLaunchKernelGGL((k_vc_adj<T, D>), grid, block, 0, st, a, us, nstrips, nwaves)
+    if (dtype == 0) {
+        switch (steps) {
+            case 1: HX_VC_ADJ(float, 1); break;
+            case 2: HX_VC_ADJ(float, 2); break;
+            case 3: HX_VC_ADJ(float, 3); break;
+            default: HX_VC_ADJ(float, 4); break;
+        }
+    } else {
+        switch (steps) {
+            case 1: HX_VC_ADJ(double, 1); break;
+            case 2: HX_VC_ADJ(double, 2); break;
+            case 3: HX_VC_ADJ(double, 3); break;
+            default: HX_VC_ADJ(double, 4); break;
+        }
+    }
+#undef HX_VC_ADJ
     return hipGetLastError();
 }
 
