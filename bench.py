@@ -1159,9 +1159,11 @@ def adjoint_leg(hx, ctx):
     rec_bytes = n * sum(8 * (-(-m // 4)) + 4 * m for m in inner)
     # the reverse sweep runs in fused passes of up to four adjoint steps: per
     # pass lam, kappa and the accumulator read once and lam and the
-    # accumulator written once (20 B), per step its u_t read once (4 B)
+    # accumulator written once (20 B), per step its u_t read once (4 B); the
+    # segment's first pass does not read the accumulator (-4 B) and its last
+    # adds it to the FP64 total instead of storing it (+12 B)
     segs_len = [min(S, T - t0) for t0 in range(0, T, S)]
-    adj_bytes = n * sum(20 * (-(-m // 4)) + 4 * m for m in segs_len)
+    adj_bytes = n * sum(20 * (-(-m // 4)) + 4 * m + 8 for m in segs_len)
     res = {"cells": n, "steps": T, "segment": S, **times, "forward_passes": fwd_passes,
            "forward_cell_updates_per_s": n * T / (times["forward_ms"] * 1e-3),
            "forward_hbm_algorithmic_GBps": fwd_bytes / (times["forward_ms"] * 1e-3) / 1e9,

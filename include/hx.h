@@ -439,7 +439,8 @@ typedef struct {
     hx_buffer lamT;             /* backward input: dL/du_T */
     hx_buffer lam0;             /* backward output: dL/du_0 */
     hx_buffer gk64;             /* backward output: dL/dkappa, FP64 (cells x 8 bytes) */
-    hx_buffer gacc;             /* backward: one state of the dtype, per-segment accumulator */
+    hx_buffer gacc;             /* backward: one state of the dtype, per-segment accumulator
+                                   (scratch: its contents afterwards are unspecified) */
     int rows_per_block;         /* 0 = 64 */
 } hx_vc_args;
 

@@ -263,10 +263,17 @@ hx_status hx_heat_vc_backward(hx_ctx ctx, const hx_vc_args* a, const hx_event* d
                         for (int q = 0; q < d; ++q) us[q] = ut(tb - q);
                         char* dst = tb - d + 1 == 0 ? pl0 : (cur == pw ? pw + bytes : pw);
                         VCArgs v{nullptr, pk, cur, dst, pga, nx, ny, tau, rows};
-                        if ((e = launch_vc_adjoint(dt, d, v, us, st)) != hipSuccess) return e;
+                        // the first pass starts the segment's accumulator at
+                        // zero, the last folds it into the FP64 total
+                        if ((e = launch_vc_adjoint(
+                                 dt, d, v, us, st, j == 0,
+                                 j + 1 == np ? reinterpret_cast<double*>(pg64) : nullptr)) !=
+                            hipSuccess)
+                            return e;
                         cur = dst;
                         tb -= d;
                     }
+                    continue;  // folded
                 } else {
                     for (int t = t1 - 1; t >= t0; --t) {  // reverse sweep
                         VCArgs v{ut(t), pk, lam_in(t), lam_out(t), pga, nx, ny, tau, rows};

@@ -372,10 +372,13 @@ hipError_t launch_vc_forward(int dtype, int steps, const VCArgs& v, hipStream_t 
 // (lam_{tb+1}) -> v.out (lam_{tb+1-steps}), adding each step's
 // conductivity-gradient term to v.gacc in the single steps' order (the same
 // bits as that many launch_vc_step adjoint steps); ustates[k] is u_t of step
-// t = tb - k.  The grids vc_fused_supported takes, lam, gacc and the states
-// 16-byte aligned, else hipErrorInvalidValue.
+// t = tb - k.  zero_in: the accumulator starts at zero (not read);
+// fold_total: add the accumulator to this FP64 total (the segment's fold)
+// instead of storing it.  The grids vc_fused_supported takes, lam, gacc, the
+// total and the states 16-byte aligned, else hipErrorInvalidValue.
 hipError_t launch_vc_adjoint(int dtype, int steps, const VCArgs& v, const void* const* ustates,
-                             hipStream_t stream);
+                             hipStream_t stream, bool zero_in = false,
+                             double* fold_total = nullptr);
 hipError_t launch_fold(int dtype, void* acc, double* total, int64_t n, hipStream_t stream);
 hipError_t launch_fill(int dtype, void* p, int64_t n, double v, hipStream_t stream);
 hipError_t launch_cast64(int dtype, const double* src, void* dst, int64_t n, hipStream_t stream);

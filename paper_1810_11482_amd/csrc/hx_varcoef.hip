@@ -568,14 +568,17 @@ __global__ __launch_bounds__(256) void k_vc_fwd(VCDev a, int64_t nstrips, int64_
 // accumulator row of row r enters at level 1 and leaves after level D, taking
 // the D terms in the single step's order (t descending) with its fma, and
 // lam's arithmetic is the single step's: the same bits as D single adjoint
-// steps.
+// steps.  ZIN: the pass opens a checkpoint segment, whose accumulator starts
+// at zero (not read).  FOLD: the pass closes the segment: the accumulator's
+// rows are added to the FP64 total (as the fold of a segment does) instead of
+// being stored.
 struct UStates {
     const void* p[4];
 };
 
-template <typename T, int D>
-__global__ __launch_bounds__(256) void k_vc_adj(VCDev a, UStates us, int64_t nstrips,
-                                                int64_t nwaves) {
+template <typename T, int D, bool ZIN, bool FOLD>
+__global__ __launch_bounds__(256) void k_vc_adj(VCDev a, UStates us, double* __restrict__ total,
+                                                int64_t nstrips, int64_t nwaves) {
     static_assert(D >= 1 && D <= C && D <= 4, "the halo lane covers at most C steps");
     typedef T V2 __attribute__((ext_vector_type(16 / sizeof(T))));
     typedef __attribute__((address_space(1))) const V2 GV2;
@@ -636,7 +639,7 @@ __global__ __launch_bounds__(256) void k_vc_adj(VCDev a, UStates us, int64_t nst
     T ln[C], kn[C], gn[C], un[D][C];
     load(L, y0 - D, ln);
     load(K, y0 - D, kn);
-    load(G, y0 - D - 1, gn);
+    if (!ZIN) load(G, y0 - D - 1, gn);
 #pragma unroll
     for (int k = 0; k < D; ++k) load(static_cast<const T*>(us.p[k]), y0 - D - k, un[k]);
     for (int64_t i = y0 - D; i < y1 + D; ++i) {
@@ -662,12 +665,12 @@ __global__ __launch_bounds__(256) void k_vc_adj(VCDev a, UStates us, int64_t nst
         for (int j = 0; j < C; ++j) {
             lr[0][2][j] = ln[j];
             kr[D + 1][j] = kn[j];
-            gr[0][j] = gn[j];
+            gr[0][j] = ZIN ? T(0) : gn[j];
         }
         // the next rows in flight (rows past the domain are clamped reads)
         load(L, i + 1, ln);
         load(K, i + 1, kn);
-        load(G, i, gn);
+        if (!ZIN) load(G, i, gn);
 #pragma unroll
         for (int k = 0; k < D; ++k) load(static_cast<const T*>(us.p[k]), i + 1 - k, un[k]);
         T out[C];
@@ -738,7 +741,15 @@ __global__ __launch_bounds__(256) void k_vc_adj(VCDev a, UStates us, int64_t nst
         const int64_t r = i - D;
         if (r >= y0 && r < y1) {
             store_row<T>(rso, lane_off, r, nx, out);
-            store_row<T>(rsg, lane_off, r, nx, gr[D - 1]);
+            if constexpr (FOLD) {
+                if (store_lane) {
+                    double* tp = total + r * nx + xl;
+#pragma unroll
+                    for (int j = 0; j < C; ++j) tp[j] += (double)gr[D - 1][j];
+                }
+            } else {
+                store_row<T>(rsg, lane_off, r, nx, gr[D - 1]);
+            }
         }
     }
 }
@@ -822,10 +833,10 @@ hipError_t launch_vc_forward(int dtype, int steps, const VCArgs& v, hipStream_t 
 }
 
 hipError_t launch_vc_adjoint(int dtype, int steps, const VCArgs& v, const void* const* ustates,
-                             hipStream_t st) {
+                             hipStream_t st, bool zero_in, double* fold_total) {
     auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; };
     if (steps < 1 || steps > C || steps > 4 || !v.lam || !v.gacc || !al(v.lam) || !al(v.gacc) ||
-        !vc_fused_supported(dtype, v))
+        !al(fold_total) || !vc_fused_supported(dtype, v))
         return hipErrorInvalidValue;
     UStates us{};
     for (int k = 0; k < steps; ++k) {
@@ -838,8 +849,21 @@ hipError_t launch_vc_adjoint(int dtype, int steps, const VCArgs& v, const void* 
     const int64_t nwaves = nstrips * nchunks;
     const int wpg = 4;
     const dim3 block(64 * wpg), grid((unsigned)((nwaves + wpg - 1) / wpg));
-#define HX_VC_ADJ(T, D) \
-    hipLaunchKernelGGL((k_vc_adj<T, D>), grid, block, 0, st, a, us, nstrips, nwaves)
+#define HX_VC_ADJ(T, D)                                                                        \
+    do {                                                                                       \
+        if (zero_in && fold_total)                                                             \
+            hipLaunchKernelGGL((k_vc_adj<T, D, true, true>), grid, block, 0, st, a, us,        \
+                               fold_total, nstrips, nwaves);                                   \
+        else if (zero_in)                                                                      \
+            hipLaunchKernelGGL((k_vc_adj<T, D, true, false>), grid, block, 0, st, a, us,       \
+                               fold_total, nstrips, nwaves);                                   \
+        else if (fold_total)                                                                   \
+            hipLaunchKernelGGL((k_vc_adj<T, D, false, true>), grid, block, 0, st, a, us,       \
+                               fold_total, nstrips, nwaves);                                   \
+        else                                                                                   \
+            hipLaunchKernelGGL((k_vc_adj<T, D, false, false>), grid, block, 0, st, a, us,      \
+                               fold_total, nstrips, nwaves);                                   \
+    } while (0)
     if (dtype == 0) {
         switch (steps) {
             case 1: HX_VC_ADJ(float, 1); break;
