@@ -545,6 +545,13 @@ def main():
     result["host_to_host"] = pipeline_leg(hx, ctx, P, T, r, cpl, ref)
     del ref
     result["host_link"] = host_link_leg(hx, P)
+    # the floor any overlap can reach host to host: every byte over the link
+    # in both directions at once (1 GiB each way at the link's two-way rate)
+    floor = result["host_link"]["both"]["ms"]
+    result["host_to_host"]["host_link_floor_ms"] = floor
+    result["host_to_host"]["wall_over_floor"] = result["host_to_host"]["wall_ms"] / floor
+    result["host_to_host"]["copies_alone_over_floor"] = \
+        result["host_to_host"]["copies_alone_ms"] / floor
     if "pipeline2d" in legs:
         result["pipeline_2d"] = pipeline2d_leg(hx)
     if "copy" in legs:
