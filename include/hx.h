@@ -441,7 +441,10 @@ typedef struct {
     hx_buffer gk64;             /* backward output: dL/dkappa, FP64 (cells x 8 bytes) */
     hx_buffer gacc;             /* backward: one state of the dtype, per-segment accumulator
                                    (scratch: its contents afterwards are unspecified) */
-    int rows_per_block;         /* 0 = 64 */
+    int rows_per_block;         /* rows per wave; 0 = the library's choice: for the fused
+                                   passes, the height whose grid fills the device's resident
+                                   wave slots once; for single steps, 64.  Results do not
+                                   depend on it. */
 } hx_vc_args;
 
 /* Segment length and number of segments of the sqrt(T) checkpoint schedule. */

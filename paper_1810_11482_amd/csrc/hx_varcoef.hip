@@ -20,7 +20,10 @@
 // cells just outside the strip are loaded per row by lanes 0 and 63.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <mutex>
+#include <utility>
+#include <vector>
 
 #include "hx_internal.h"
 
@@ -190,6 +193,26 @@ __device__ __forceinline__ void store_row(__amdgpu_buffer_rsrc_t rs, uint32_t la
         u32x4 bits;
         __builtin_memcpy(&bits, &x, sizeof(bits));
         __builtin_amdgcn_raw_buffer_store_b128(bits, rs, (int)(lane_off + row + q * 16), 0, 0);
+    }
+}
+
+// store_row of a row that is stored only when `ok` (wave-uniform): otherwise
+// every lane stores to the out-of-range offset, so no branch splits the
+// caller's code
+template <typename T, int AUX = 0>
+__device__ __forceinline__ void store_row_if(__amdgpu_buffer_rsrc_t rs, uint32_t lane_off, bool ok,
+                                             int64_t y, int64_t nx, const T (&v)[C]) {
+    typedef T V2 __attribute__((ext_vector_type(16 / sizeof(T))));
+    constexpr int VN = 16 / sizeof(T);
+    const uint32_t off = ok ? lane_off + (uint32_t)(y * nx * (int64_t)sizeof(T)) : OOB_OFFSET;
+#pragma unroll
+    for (int q = 0; q < C / VN; ++q) {
+        V2 x;
+#pragma unroll
+        for (int e = 0; e < VN; ++e) x[e] = v[q * VN + e];
+        u32x4 bits;
+        __builtin_memcpy(&bits, &x, sizeof(bits));
+        __builtin_amdgcn_raw_buffer_store_b128(bits, rs, (int)(off + q * 16), 0, AUX);
     }
 }
 
@@ -404,24 +427,67 @@ unsigned grid_for(int64_t n) {
     return (unsigned)g;
 }
 
+// Row rings of the fused passes.  A pass streams rows base, base+1, ... (base
+// = the pass's first row); the ring entry of row rho sits in slot
+// (rho - base) mod 3 (field rows) or mod 6 (face rows, accumulator rows).  The
+// row loop is unrolled six times with the phase as a constant, so every slot
+// index is known at compile time: the rings live in registers and a row
+// advances by renaming, not by register moves.  Rows in flight (PF per
+// field) take slot t mod PF.
+template <int P>
+struct Phase {
+    static constexpr int value = P;
+};
+__host__ __device__ constexpr int m3(int x) { return (x % 3 + 3) % 3; }
+__host__ __device__ constexpr int m6(int x) { return (x % 6 + 6) % 6; }
+constexpr int PF = 2;     // rows in flight per field (a divisor of 6)
+constexpr int ST_NT = 2;  // buffer-store cache policy: nontemporal (the adjoint's two row
+                          // stores per row: measured 4-7 % faster than cached stores)
+
+// Face conductivities of one row for a lane's C cells, as the single step
+// forms them: the east face of cell j, (kappa_j + kappa_{j+1}) / 2, in e[j]
+// (kappa_{j+1} = kappa_j on the domain's east edge) and cell 0's west face in
+// e[C]; the west face of cell j > 0 is e[j - 1], the same sum with its
+// operands swapped, hence the same value.  The south faces of the row above,
+// (kappa_{rho-1} + kappa_rho) / 2, in s: the north face of row rho is the
+// south face of row rho - 1.  Rows outside the domain are clamped reads of the
+// edge row, so the edge faces come out as (kappa + kappa) / 2 = kappa.
+template <typename T>
+__device__ __forceinline__ void row_faces(const T (&kc)[C], const T (&ka)[C], bool wok, bool eok,
+                                          T (&e)[C + 1], T (&s)[C]) {
+    const T kel = dpp_move<DPP_WAVE_SHL1>(kc[0]);
+    const T kwl = dpp_move<DPP_WAVE_SHR1>(kc[C - 1]);
+#pragma unroll
+    for (int j = 0; j + 1 < C; ++j) e[j] = (kc[j] + kc[j + 1]) * T(0.5);
+    e[C - 1] = (kc[C - 1] + (eok ? kel : kc[C - 1])) * T(0.5);
+    e[C] = (kc[0] + (wok ? kwl : kc[0])) * T(0.5);
+#pragma unroll
+    for (int j = 0; j < C; ++j) s[j] = (ka[j] + kc[j]) * T(0.5);
+}
+
 // D fused forward steps (temporal blocking), for aligned grids (every row
 // 16-byte aligned, nx a multiple of C, under 2 GiB).  A wave owns 64*C
 // columns, of which lanes 1..62 are its output: the strips overlap by one
 // lane on each side, and the outer lanes' values go stale one column per step
 // (from lanes 0 and 63 inward), which D <= C steps keep out of lanes 1..62.
 // Rows stream top to bottom once: input row i (u and kappa) enters level 0;
-// level k (1..D) then produces row i - k from level k-1's rows i-k-1 .. i-k+1
-// and kappa rows i-k-1 .. i-k+1, so u and kappa are read once and u written
-// once per D steps.  Each level keeps three rows of C cells, kappa D + 2.  The
-// arithmetic, and its order, is the single step's (k_vc_step), so a fused
-// pass gives the same bits as D single steps.  MID: levels 1..D-1 are stored
-// too, level k into mid + (k - 1) * mid_stride bytes (the states between the
-// pass's input and its output, as the checkpointed backward sweep recomputes
-// them): one read of u and kappa and D writes for D steps.
+// level k (1..D) then produces row i - k from level k-1's rows i-k-1 .. i-k+1,
+// so u and kappa are read once and u written once per D steps.  The face
+// conductivities of a row are formed once, when its kappa row arrives, and
+// serve all D levels.  Lanes hold C whole cells inside or outside the domain
+// (nx a multiple of C), so only a lane's outer cells can border the domain's
+// west or east edge, and only those two take the edge rule; a level's rows
+// outside the domain are set to 0 (the ghost value), which gives the north and
+// south edge rule without a test per cell.  The arithmetic, and its order, is
+// the single step's (k_vc_step), so a fused pass gives the same bits as D
+// single steps.  MID: levels 1..D-1 are stored too, level k into mid + (k - 1)
+// * mid_stride bytes (the states between the pass's input and its output, as
+// the checkpointed backward sweep recomputes them): one read of u and kappa and
+// D writes for D steps.
 template <typename T, int D, bool MID>
 __global__ __launch_bounds__(256) void k_vc_fwd(VCDev a, int64_t nstrips, int64_t nwaves,
                                                 void* mid, int64_t mid_stride) {
-    static_assert(D >= 1 && D <= C, "the halo lane covers at most C steps");
+    static_assert(D >= 1 && D <= C && D <= 5, "the halo lane covers at most C steps");
     typedef T V2 __attribute__((ext_vector_type(16 / sizeof(T))));
     typedef __attribute__((address_space(1))) const V2 GV2;
     constexpr int VN = 16 / sizeof(T);
@@ -441,15 +507,21 @@ __global__ __launch_bounds__(256) void k_vc_fwd(VCDev a, int64_t nstrips, int64_
     const T* K = static_cast<const T*>(a.kappa);
     const bool lin = xl >= 0 && xl + C <= nx;  // the lane's cells: all inside or all outside
     const int64_t xv = lin ? xl : 0;
-    // row y of f for this lane: a clamped address, zeros outside the domain
-    auto load = [&](const T* f, int64_t y, T (&v)[C]) {
-        const bool rin = y >= 0 && y < ny;
+    const bool wok = xl >= 1;       // cell 0's west face is interior
+    const bool eok = xl + C < nx;   // cell C-1's east face is interior
+    // row y of f for this lane, from a clamped row address (values of lanes
+    // outside the domain are never used).  A pass reads each row once (a
+    // chunk's halo rows twice); nontemporal loads measured faster where the
+    // pass stores one row per row read (5.3 against 4.4 TB/s), cached loads
+    // where it stores every level (MID)
+    auto raw = [&](const T* f, int64_t y, T (&v)[C]) {
         const T* row = f + (y < 0 ? 0 : (y >= ny ? ny - 1 : y)) * nx;
 #pragma unroll
         for (int q = 0; q < C / VN; ++q) {
-            const V2 x = *((GV2*)(row + xv) + q);
+            const V2 x = MID ? *((GV2*)(row + xv) + q)
+                             : __builtin_nontemporal_load((GV2*)(row + xv) + q);
 #pragma unroll
-            for (int e = 0; e < VN; ++e) v[q * VN + e] = (rin && lin) ? x[e] : T(0);
+            for (int e = 0; e < VN; ++e) v[q * VN + e] = x[e];
         }
     };
     const int bytes = (int)(ny * nx * (int64_t)sizeof(T));
@@ -464,94 +536,94 @@ __global__ __launch_bounds__(256) void k_vc_fwd(VCDev a, int64_t nstrips, int64_
             rsm[k] = __builtin_amdgcn_make_buffer_rsrc(static_cast<char*>(mid) + k * mid_stride,
                                                        (short)0, bytes, BUF_DWORD3);
 
-    T ur[D][3][C];     // level k: rows i-k-1, i-k, i-k+1 (after the shift below)
-    T kr[D + 2][C];    // kappa rows i-D-1 .. i
+    T fr[D][3][C];    // level k's rows (level 0: u)
+    T kr[3][C];       // kappa rows
+    T ef[6][C + 1];   // east faces of a row, and cell 0's west face
+    T sf[6][C];       // south faces of a row
 #pragma unroll
     for (int k = 0; k < D; ++k)
 #pragma unroll
         for (int m = 0; m < 3; ++m)
 #pragma unroll
-            for (int j = 0; j < C; ++j) ur[k][m][j] = T(0);
+            for (int j = 0; j < C; ++j) fr[k][m][j] = T(0);
 #pragma unroll
-    for (int m = 0; m < D + 2; ++m)
+    for (int m = 0; m < 6; ++m)
 #pragma unroll
-        for (int j = 0; j < C; ++j) kr[m][j] = T(0);
-    T un[C], kn[C];
-    load(U, y0 - D, un);
-    load(K, y0 - D, kn);
-    for (int64_t i = y0 - D; i < y1 + D; ++i) {
+        for (int j = 0; j <= C; ++j) {
+            if (m < 3 && j < C) kr[m][j] = T(0);
+            ef[m][j] = T(0);
+            if (j < C) sf[m][j] = T(0);
+        }
+    const int64_t base = y0 - D;
+    const int64_t nt = y1 - y0 + 2 * D;  // rows base .. y1 + D - 1 enter level 0
+    T upf[PF][C], kpf[PF][C];            // rows in flight: row base + t in slot t mod PF
 #pragma unroll
-        for (int k = 0; k < D; ++k)
-#pragma unroll
-            for (int j = 0; j < C; ++j) {
-                ur[k][0][j] = ur[k][1][j];
-                ur[k][1][j] = ur[k][2][j];
-            }
-#pragma unroll
-        for (int m = 0; m < D + 1; ++m)
-#pragma unroll
-            for (int j = 0; j < C; ++j) kr[m][j] = kr[m + 1][j];
+    for (int m = 0; m < PF; ++m) {
+        raw(U, base + m, upf[m]);
+        raw(K, base + m, kpf[m]);
+    }
+    auto body = [&](auto ph, int64_t t) __attribute__((always_inline)) {
+        constexpr int P = decltype(ph)::value;  // t mod 6
+        constexpr int Q = P % PF;
+        const int64_t i = base + t;
+        const bool iin = i >= 0 && i < ny;
 #pragma unroll
         for (int j = 0; j < C; ++j) {
-            ur[0][2][j] = un[j];
-            kr[D + 1][j] = kn[j];
+            fr[0][m3(P)][j] = iin ? upf[Q][j] : T(0);
+            kr[m3(P)][j] = kpf[Q][j];
         }
-        // row i+1 in flight (rows past the domain are clamped reads)
-        load(U, i + 1, un);
-        load(K, i + 1, kn);
+        // row i+PF in flight (rows past the domain are clamped reads)
+        raw(U, i + PF, upf[Q]);
+        raw(K, i + PF, kpf[Q]);
+        row_faces<T>(kr[m3(P)], kr[m3(P - 1)], wok, eok, ef[m6(P)], sf[m6(P - 1)]);
         T out[C];
 #pragma unroll
         for (int k = 1; k <= D; ++k) {
             const int64_t r = i - k;  // the row level k produces
-            const T* fm = ur[k - 1][0];
-            const T* f0 = ur[k - 1][1];
-            const T* fp = ur[k - 1][2];
-            const T* km = kr[D - k];
-            const T* k0 = kr[D - k + 1];
-            const T* kp = kr[D - k + 2];
-            const bool nin = r - 1 >= 0, sin = r + 1 < ny;
+            const T* fm = fr[k - 1][m3(P - k - 1)];
+            const T* f0 = fr[k - 1][m3(P - k)];
+            const T* fp = fr[k - 1][m3(P - k + 1)];
+            const T* e = ef[m6(P - k)];
+            const T* fn = sf[m6(P - k - 1)];
+            const T* fs = sf[m6(P - k)];
             const T fwl = dpp_move<DPP_WAVE_SHR1>(f0[C - 1]);
             const T fel = dpp_move<DPP_WAVE_SHL1>(f0[0]);
-            const T kwl = dpp_move<DPP_WAVE_SHR1>(k0[C - 1]);
-            const T kel = dpp_move<DPP_WAVE_SHL1>(k0[0]);
             T v[C];
 #pragma unroll
             for (int j = 0; j < C; ++j) {
                 const T fc = f0[j];
-                const T kc = k0[j];
-                const int64_t x = xl + j;
-                const T fw = j > 0 ? f0[j - 1] : fwl;
-                const T fe = j + 1 < C ? f0[j + 1] : fel;
-                const T kw = (x - 1 >= 0) ? (j > 0 ? k0[j - 1] : kwl) : kc;
-                const T ke = (x + 1 < nx) ? (j + 1 < C ? k0[j + 1] : kel) : kc;
-                const T fW = (x - 1 >= 0) ? fw : T(0);
-                const T fE = (x + 1 < nx) ? fe : T(0);
-                const T kN = nin ? km[j] : kc;
-                const T kS = sin ? kp[j] : kc;
-                const T fN = nin ? fm[j] : T(0);
-                const T fS = sin ? fp[j] : T(0);
-                const T kfw = (kc + kw) * T(0.5);
-                const T kfe = (kc + ke) * T(0.5);
-                const T kfn = (kc + kN) * T(0.5);
-                const T kfs = (kc + kS) * T(0.5);
+                const T fW = j > 0 ? f0[j - 1] : (wok ? fwl : T(0));
+                const T fE = j + 1 < C ? f0[j + 1] : (eok ? fel : T(0));
+                const T kfw = j > 0 ? e[j - 1] : e[C];
                 T acc = kfw * (fW - fc);
-                acc = fmaT(kfe, fE - fc, acc);
-                acc = fmaT(kfn, fN - fc, acc);
-                acc = fmaT(kfs, fS - fc, acc);
+                acc = fmaT(e[j], fE - fc, acc);
+                acc = fmaT(fn[j], fm[j] - fc, acc);
+                acc = fmaT(fs[j], fp[j] - fc, acc);
                 v[j] = fmaT(dt, acc, fc);
             }
             if (k < D) {
+                const bool rin = r >= 0 && r < ny;
 #pragma unroll
-                for (int j = 0; j < C; ++j) ur[k][2][j] = v[j];
+                for (int j = 0; j < C; ++j) fr[k][m3(P - k)][j] = rin ? v[j] : T(0);
                 if constexpr (MID)
-                    if (r >= y0 && r < y1) store_row<T>(rsm[k - 1], lane_off, r, nx, v);
+                    store_row_if<T>(rsm[k - 1], lane_off, r >= y0 && r < y1, r, nx, v);
             } else {
 #pragma unroll
                 for (int j = 0; j < C; ++j) out[j] = v[j];
             }
         }
         const int64_t r = i - D;
-        if (r >= y0 && r < y1) store_row<T>(rso, lane_off, r, nx, out);
+        store_row_if<T>(rso, lane_off, r >= y0 && r < y1, r, nx, out);
+    };
+    // whole groups of six rows (one exit keeps the rings in registers): the
+    // up to five rows past the pass's last are clamped reads and not stored
+    for (int64_t t = 0; t < nt; t += 6) {
+        body(Phase<0>{}, t);
+        body(Phase<1>{}, t + 1);
+        body(Phase<2>{}, t + 2);
+        body(Phase<3>{}, t + 3);
+        body(Phase<4>{}, t + 4);
+        body(Phase<5>{}, t + 5);
     }
 }
 
@@ -568,10 +640,11 @@ __global__ __launch_bounds__(256) void k_vc_fwd(VCDev a, int64_t nstrips, int64_
 // accumulator row of row r enters at level 1 and leaves after level D, taking
 // the D terms in the single step's order (t descending) with its fma, and
 // lam's arithmetic is the single step's: the same bits as D single adjoint
-// steps.  ZIN: the pass opens a checkpoint segment, whose accumulator starts
-// at zero (not read).  FOLD: the pass closes the segment: the accumulator's
-// rows are added to the FP64 total (as the fold of a segment does) instead of
-// being stored.
+// steps.  Faces, rings and edge rules as in k_vc_fwd; a gradient term across
+// an edge face reads u_c lam_c, as the single step's.  ZIN: the pass opens a
+// checkpoint segment, whose accumulator starts at zero (not read).  FOLD: the
+// pass closes the segment: the accumulator's rows are added to the FP64 total
+// (as the fold of a segment does) instead of being stored.
 struct UStates {
     const void* p[4];
 };
@@ -600,14 +673,15 @@ __global__ __launch_bounds__(256) void k_vc_adj(VCDev a, UStates us, double* __r
     const T* G = static_cast<const T*>(a.gacc);
     const bool lin = xl >= 0 && xl + C <= nx;  // the lane's cells: all inside or all outside
     const int64_t xv = lin ? xl : 0;
-    auto load = [&](const T* f, int64_t y, T (&v)[C]) {
-        const bool rin = y >= 0 && y < ny;
+    const bool wok = xl >= 1;       // cell 0's west face is interior
+    const bool eok = xl + C < nx;   // cell C-1's east face is interior
+    auto raw = [&](const T* f, int64_t y, T (&v)[C]) {
         const T* row = f + (y < 0 ? 0 : (y >= ny ? ny - 1 : y)) * nx;
 #pragma unroll
         for (int q = 0; q < C / VN; ++q) {
             const V2 x = *((GV2*)(row + xv) + q);
 #pragma unroll
-            for (int e = 0; e < VN; ++e) v[q * VN + e] = (rin && lin) ? x[e] : T(0);
+            for (int e = 0; e < VN; ++e) v[q * VN + e] = x[e];
         }
     };
     const int bytes = (int)(ny * nx * (int64_t)sizeof(T));
@@ -618,10 +692,12 @@ __global__ __launch_bounds__(256) void k_vc_adj(VCDev a, UStates us, double* __r
     const bool store_lane = lane >= 1 && lane <= 62 && lin;
     const uint32_t lane_off = store_lane ? (uint32_t)(xl * (int64_t)sizeof(T)) : OOB_OFFSET;
 
-    T lr[D][3][C];     // lam level k: rows i-k-1, i-k, i-k+1 (after the shift below)
-    T ur[D][3][C];     // u_t of level k+1: rows i-k-2, i-k-1, i-k (after the shift)
-    T kr[D + 2][C];    // kappa rows i-D-1 .. i
-    T gr[D][C];        // accumulator of row i-1-m in gr[m] (level m+1's row)
+    T lr[D][3][C];    // lam of level k (level 0: lam_{tb+1})
+    T ur[D][3][C];    // u_t read by level k + 1
+    T kr[3][C];       // kappa rows
+    T ef[6][C + 1];   // east faces of a row, and cell 0's west face
+    T sf[6][C];       // south faces of a row
+    T gr[6][C];       // accumulator rows, from level 1 to level D
 #pragma unroll
     for (int k = 0; k < D; ++k)
 #pragma unroll
@@ -629,128 +705,123 @@ __global__ __launch_bounds__(256) void k_vc_adj(VCDev a, UStates us, double* __r
 #pragma unroll
             for (int j = 0; j < C; ++j) lr[k][m][j] = ur[k][m][j] = T(0);
 #pragma unroll
-    for (int m = 0; m < D + 2; ++m)
+    for (int m = 0; m < 6; ++m)
 #pragma unroll
-        for (int j = 0; j < C; ++j) kr[m][j] = T(0);
+        for (int j = 0; j <= C; ++j) {
+            if (m < 3 && j < C) kr[m][j] = T(0);
+            ef[m][j] = T(0);
+            if (j < C) sf[m][j] = gr[m][j] = T(0);
+        }
+    const int64_t base = y0 - D;
+    const int64_t nt = y1 - y0 + 2 * D;  // rows base .. y1 + D - 1 enter level 0
+    // rows in flight, in slot t mod PF for the iteration t that consumes them
+    T lpf[PF][C], kpf[PF][C], gpf[PF][C], upf[PF][D][C];
 #pragma unroll
-    for (int m = 0; m < D; ++m)
+    for (int m = 0; m < PF; ++m) {
+        raw(L, base + m, lpf[m]);
+        raw(K, base + m, kpf[m]);
+        if (!ZIN) raw(G, base + m - 1, gpf[m]);
 #pragma unroll
-        for (int j = 0; j < C; ++j) gr[m][j] = T(0);
-    T ln[C], kn[C], gn[C], un[D][C];
-    load(L, y0 - D, ln);
-    load(K, y0 - D, kn);
-    if (!ZIN) load(G, y0 - D - 1, gn);
+        for (int k = 0; k < D; ++k) raw(static_cast<const T*>(us.p[k]), base + m - k, upf[m][k]);
+    }
+    auto body = [&](auto ph, int64_t t) __attribute__((always_inline)) {
+        constexpr int P = decltype(ph)::value;  // t mod 6
+        constexpr int Q = P % PF;
+        const int64_t i = base + t;
+        const bool iin = i >= 0 && i < ny;
 #pragma unroll
-    for (int k = 0; k < D; ++k) load(static_cast<const T*>(us.p[k]), y0 - D - k, un[k]);
-    for (int64_t i = y0 - D; i < y1 + D; ++i) {
+        for (int j = 0; j < C; ++j) {
+            lr[0][m3(P)][j] = iin ? lpf[Q][j] : T(0);
+            kr[m3(P)][j] = kpf[Q][j];
+            gr[m6(P - 1)][j] = ZIN ? T(0) : gpf[Q][j];
+        }
 #pragma unroll
         for (int k = 0; k < D; ++k)
 #pragma unroll
-            for (int j = 0; j < C; ++j) {
-                lr[k][0][j] = lr[k][1][j];
-                lr[k][1][j] = lr[k][2][j];
-                ur[k][0][j] = ur[k][1][j];
-                ur[k][1][j] = ur[k][2][j];
-                ur[k][2][j] = un[k][j];
-            }
+            for (int j = 0; j < C; ++j) ur[k][m3(P - k)][j] = upf[Q][k][j];
+        // the rows PF ahead in flight (rows past the domain are clamped reads)
+        raw(L, i + PF, lpf[Q]);
+        raw(K, i + PF, kpf[Q]);
+        if (!ZIN) raw(G, i + PF - 1, gpf[Q]);
 #pragma unroll
-        for (int m = 0; m < D + 1; ++m)
-#pragma unroll
-            for (int j = 0; j < C; ++j) kr[m][j] = kr[m + 1][j];
-#pragma unroll
-        for (int m = D - 1; m > 0; --m)
-#pragma unroll
-            for (int j = 0; j < C; ++j) gr[m][j] = gr[m - 1][j];
-#pragma unroll
-        for (int j = 0; j < C; ++j) {
-            lr[0][2][j] = ln[j];
-            kr[D + 1][j] = kn[j];
-            gr[0][j] = ZIN ? T(0) : gn[j];
-        }
-        // the next rows in flight (rows past the domain are clamped reads)
-        load(L, i + 1, ln);
-        load(K, i + 1, kn);
-        if (!ZIN) load(G, i, gn);
-#pragma unroll
-        for (int k = 0; k < D; ++k) load(static_cast<const T*>(us.p[k]), i + 1 - k, un[k]);
+        for (int k = 0; k < D; ++k) raw(static_cast<const T*>(us.p[k]), i + PF - k, upf[Q][k]);
+        row_faces<T>(kr[m3(P)], kr[m3(P - 1)], wok, eok, ef[m6(P)], sf[m6(P - 1)]);
         T out[C];
 #pragma unroll
         for (int k = 1; k <= D; ++k) {
             const int64_t r = i - k;  // the row level k produces
-            const T* fm = lr[k - 1][0];
-            const T* f0 = lr[k - 1][1];
-            const T* fp = lr[k - 1][2];
-            const T* um = ur[k - 1][0];
-            const T* u0 = ur[k - 1][1];
-            const T* up = ur[k - 1][2];
-            const T* km = kr[D - k];
-            const T* k0 = kr[D - k + 1];
-            const T* kp = kr[D - k + 2];
+            const T* fm = lr[k - 1][m3(P - k - 1)];
+            const T* f0 = lr[k - 1][m3(P - k)];
+            const T* fp = lr[k - 1][m3(P - k + 1)];
+            const T* um = ur[k - 1][m3(P - k - 1)];
+            const T* u0 = ur[k - 1][m3(P - k)];
+            const T* up = ur[k - 1][m3(P - k + 1)];
+            const T* e = ef[m6(P - k)];
+            const T* fn = sf[m6(P - k - 1)];
+            const T* fs = sf[m6(P - k)];
+            T* g = gr[m6(P - k)];
             const bool nin = r - 1 >= 0, sin = r + 1 < ny;
             const T fwl = dpp_move<DPP_WAVE_SHR1>(f0[C - 1]);
             const T fel = dpp_move<DPP_WAVE_SHL1>(f0[0]);
             const T uwl = dpp_move<DPP_WAVE_SHR1>(u0[C - 1]);
             const T uel = dpp_move<DPP_WAVE_SHL1>(u0[0]);
-            const T kwl = dpp_move<DPP_WAVE_SHR1>(k0[C - 1]);
-            const T kel = dpp_move<DPP_WAVE_SHL1>(k0[0]);
             T v[C];
 #pragma unroll
             for (int j = 0; j < C; ++j) {
                 const T fc = f0[j];
-                const T kc = k0[j];
                 const T uc = u0[j];
-                const int64_t x = xl + j;
-                const T fw = j > 0 ? f0[j - 1] : fwl;
-                const T fe = j + 1 < C ? f0[j + 1] : fel;
+                const bool wi = j > 0 || wok, ei = j + 1 < C || eok;
+                const T fW = j > 0 ? f0[j - 1] : (wok ? fwl : T(0));
+                const T fE = j + 1 < C ? f0[j + 1] : (eok ? fel : T(0));
                 const T uw = j > 0 ? u0[j - 1] : uwl;
                 const T ue = j + 1 < C ? u0[j + 1] : uel;
-                const T kw = (x - 1 >= 0) ? (j > 0 ? k0[j - 1] : kwl) : kc;
-                const T ke = (x + 1 < nx) ? (j + 1 < C ? k0[j + 1] : kel) : kc;
-                const T fW = (x - 1 >= 0) ? fw : T(0);
-                const T fE = (x + 1 < nx) ? fe : T(0);
-                const T kN = nin ? km[j] : kc;
-                const T kS = sin ? kp[j] : kc;
-                const T fN = nin ? fm[j] : T(0);
-                const T fS = sin ? fp[j] : T(0);
-                const T kfw = (kc + kw) * T(0.5);
-                const T kfe = (kc + ke) * T(0.5);
-                const T kfn = (kc + kN) * T(0.5);
-                const T kfs = (kc + kS) * T(0.5);
-                T acc = kfw * (fW - fc);
-                acc = fmaT(kfe, fE - fc, acc);
-                acc = fmaT(kfn, fN - fc, acc);
-                acc = fmaT(kfs, fS - fc, acc);
+                const T kfw = j > 0 ? e[j - 1] : e[C];
+                const T dW = fW - fc, dE = fE - fc, dN = fm[j] - fc, dS = fp[j] - fc;
+                T acc = kfw * dW;
+                acc = fmaT(e[j], dE, acc);
+                acc = fmaT(fn[j], dN, acc);
+                acc = fmaT(fs[j], dS, acc);
                 v[j] = fmaT(dt, acc, fc);
                 // the step's conductivity-gradient term, as the single step
                 const T prod = uc * fc;
-                const T hw = (x - 1 >= 0) ? (uw - uc) * (fw - fc) * T(0.5) : prod;
-                const T he = (x + 1 < nx) ? (ue - uc) * (fe - fc) * T(0.5) : prod;
-                const T hn = nin ? (um[j] - uc) * (fm[j] - fc) * T(0.5) : prod;
-                const T hs = sin ? (up[j] - uc) * (fp[j] - fc) * T(0.5) : prod;
-                const T g = ((hw + he) + (hn + hs));
-                gr[k - 1][j] = fmaT(-dt, g, gr[k - 1][j]);
+                const T hw = wi ? (uw - uc) * dW * T(0.5) : prod;
+                const T he = ei ? (ue - uc) * dE * T(0.5) : prod;
+                const T hn = nin ? (um[j] - uc) * dN * T(0.5) : prod;
+                const T hs = sin ? (up[j] - uc) * dS * T(0.5) : prod;
+                const T gt = ((hw + he) + (hn + hs));
+                g[j] = fmaT(-dt, gt, g[j]);
             }
             if (k < D) {
+                const bool rin = r >= 0 && r < ny;
 #pragma unroll
-                for (int j = 0; j < C; ++j) lr[k][2][j] = v[j];
+                for (int j = 0; j < C; ++j) lr[k][m3(P - k)][j] = rin ? v[j] : T(0);
             } else {
 #pragma unroll
                 for (int j = 0; j < C; ++j) out[j] = v[j];
             }
         }
         const int64_t r = i - D;
-        if (r >= y0 && r < y1) {
-            store_row<T>(rso, lane_off, r, nx, out);
-            if constexpr (FOLD) {
-                if (store_lane) {
-                    double* tp = total + r * nx + xl;
+        const bool rout = r >= y0 && r < y1;
+        store_row_if<T, ST_NT>(rso, lane_off, rout, r, nx, out);
+        if constexpr (FOLD) {
+            if (rout && store_lane) {
+                double* tp = total + r * nx + xl;
 #pragma unroll
-                    for (int j = 0; j < C; ++j) tp[j] += (double)gr[D - 1][j];
-                }
-            } else {
-                store_row<T>(rsg, lane_off, r, nx, gr[D - 1]);
+                for (int j = 0; j < C; ++j) tp[j] += (double)gr[m6(P - D)][j];
             }
+        } else {
+            store_row_if<T, ST_NT>(rsg, lane_off, rout, r, nx, gr[m6(P - D)]);
         }
+    };
+    // whole groups of six rows (one exit keeps the rings in registers): the
+    // up to five rows past the pass's last are clamped reads and not stored
+    for (int64_t t = 0; t < nt; t += 6) {
+        body(Phase<0>{}, t);
+        body(Phase<1>{}, t + 1);
+        body(Phase<2>{}, t + 2);
+        body(Phase<3>{}, t + 3);
+        body(Phase<4>{}, t + 4);
+        body(Phase<5>{}, t + 5);
     }
 }
 
@@ -791,6 +862,79 @@ bool vc_fused_supported(int dtype, const VCArgs& v) {
            v.nx * v.ny * es < (int64_t(1) << 31) && v.nx > 0 && v.ny > 0;
 }
 
+// The fused kernel for (dtype, steps, variant): variant bit 0 = MID (forward)
+// or ZIN (adjoint), bit 1 = FOLD (adjoint).
+template <typename T>
+const void* fused_kernel(bool adjoint, int steps, int variant) {
+#define HX_VC_FWD_K(D) (variant & 1) ? (const void*)k_vc_fwd<T, D, true> : (const void*)k_vc_fwd<T, D, false>
+#define HX_VC_ADJ_K(D)                                                                   \
+    variant == 3   ? (const void*)k_vc_adj<T, D, true, true>                             \
+    : variant == 1 ? (const void*)k_vc_adj<T, D, true, false>                            \
+    : variant == 2 ? (const void*)k_vc_adj<T, D, false, true>                            \
+                   : (const void*)k_vc_adj<T, D, false, false>
+    switch (steps) {
+        case 1: return adjoint ? (HX_VC_ADJ_K(1)) : (HX_VC_FWD_K(1));
+        case 2: return adjoint ? (HX_VC_ADJ_K(2)) : (HX_VC_FWD_K(2));
+        case 3: return adjoint ? (HX_VC_ADJ_K(3)) : (HX_VC_FWD_K(3));
+        case 4: return adjoint ? (HX_VC_ADJ_K(4)) : (HX_VC_FWD_K(4));
+        default: return nullptr;
+    }
+#undef HX_VC_FWD_K
+#undef HX_VC_ADJ_K
+}
+
+// Rows per chunk when the caller leaves the choice to the library: enough
+// chunks that strips x chunks waves fill the device's resident wave slots for
+// this kernel once (one round of waves: no partly filled second round), at
+// least 16 rows.  A wave streams its chunk plus 2D halo rows, so taller
+// chunks also recompute fewer rows.  The result does not depend on the chunk
+// height.
+int fill_rows(const void* k, int64_t nstrips, int64_t ny) {
+    static std::mutex mu;
+    static std::vector<std::pair<std::pair<const void*, int>, int64_t>> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 64;
+    }
+    int64_t slots = 0;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        for (const auto& e : cache)
+            if (e.first.first == k && e.first.second == dev) slots = e.second;
+    }
+    if (slots == 0) {
+        int cus = 0, blocks = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k, 256, 0) != hipSuccess ||
+            cus < 1 || blocks < 1) {
+            (void)hipGetLastError();
+            return 64;
+        }
+        slots = (int64_t)cus * blocks * 4;  // four waves per workgroup
+        std::lock_guard<std::mutex> g(mu);
+        cache.push_back({{k, dev}, slots});
+    }
+    const int64_t chunks = std::max<int64_t>(1, slots / nstrips);
+    const int64_t rows = std::max<int64_t>(16, (ny + chunks - 1) / chunks);
+    return (int)std::min<int64_t>(rows, int64_t(1) << 30);
+}
+
+hipError_t launch_fused(const void* k, VCDev a, int rows_req, void* arg3, void* arg4,
+                        bool adjoint, hipStream_t st) {
+    if (!k) return hipErrorInvalidValue;
+    int64_t nstrips = (a.nx + (S - 2 * C) - 1) / (S - 2 * C);
+    a.rows = rows_req > 0 ? rows_req : fill_rows(k, nstrips, a.ny);
+    int64_t nwaves = nstrips * ((a.ny + a.rows - 1) / a.rows);
+    const int wpg = 4;
+    const int64_t groups = (nwaves + wpg - 1) / wpg;
+    if (groups >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+    // forward: (a, nstrips, nwaves, mid, mid_stride); adjoint: (a, us, total, nstrips, nwaves)
+    void* fargs[] = {&a, &nstrips, &nwaves, arg3, arg4};
+    void* aargs[] = {&a, arg3, arg4, &nstrips, &nwaves};
+    return hipLaunchKernel(k, dim3((unsigned)groups), dim3(64 * wpg), adjoint ? aargs : fargs, 0, st);
+}
+
 hipError_t launch_vc_forward(int dtype, int steps, const VCArgs& v, hipStream_t st, void* mid,
                              int64_t mid_stride) {
     if (steps < 1 || steps > C || !vc_fused_supported(dtype, v)) return hipErrorInvalidValue;
@@ -798,38 +942,11 @@ hipError_t launch_vc_forward(int dtype, int steps, const VCArgs& v, hipStream_t 
     if (mid && (((reinterpret_cast<uintptr_t>(mid) | (uintptr_t)mid_stride) & 15u) ||
                 mid_stride < v.nx * v.ny * es))
         return hipErrorInvalidValue;
-    VCDev a{v.u, v.kappa, nullptr, v.out, nullptr, v.nx, v.ny, v.dt, v.rows > 0 ? v.rows : 64, 1};
-    const int64_t nstrips = (v.nx + (S - 2 * C) - 1) / (S - 2 * C);
-    const int64_t nchunks = (v.ny + a.rows - 1) / a.rows;
-    const int64_t nwaves = nstrips * nchunks;
-    const int wpg = 4;
-    const dim3 block(64 * wpg), grid((unsigned)((nwaves + wpg - 1) / wpg));
-#define HX_VC_FWD(T, D)                                                                     \
-    do {                                                                                    \
-        if (mid)                                                                            \
-            hipLaunchKernelGGL((k_vc_fwd<T, D, true>), grid, block, 0, st, a, nstrips,      \
-                               nwaves, mid, mid_stride);                                    \
-        else                                                                                \
-            hipLaunchKernelGGL((k_vc_fwd<T, D, false>), grid, block, 0, st, a, nstrips,     \
-                               nwaves, mid, mid_stride);                                    \
-    } while (0)
-    if (dtype == 0) {
-        switch (steps) {
-            case 1: HX_VC_FWD(float, 1); break;
-            case 2: HX_VC_FWD(float, 2); break;
-            case 3: HX_VC_FWD(float, 3); break;
-            default: HX_VC_FWD(float, 4); break;
-        }
-    } else {
-        switch (steps) {
-            case 1: HX_VC_FWD(double, 1); break;
-            case 2: HX_VC_FWD(double, 2); break;
-            case 3: HX_VC_FWD(double, 3); break;
-            default: HX_VC_FWD(double, 4); break;
-        }
-    }
-#undef HX_VC_FWD
-    return hipGetLastError();
+    VCDev a{v.u, v.kappa, nullptr, v.out, nullptr, v.nx, v.ny, v.dt, 0, 1};
+    const int variant = mid ? 1 : 0;
+    const void* k = dtype == 0 ? fused_kernel<float>(false, steps, variant)
+                               : fused_kernel<double>(false, steps, variant);
+    return launch_fused(k, a, v.rows, &mid, &mid_stride, false, st);
 }
 
 hipError_t launch_vc_adjoint(int dtype, int steps, const VCArgs& v, const void* const* ustates,
@@ -843,44 +960,11 @@ hipError_t launch_vc_adjoint(int dtype, int steps, const VCArgs& v, const void* 
         if (!ustates[k] || !al(ustates[k])) return hipErrorInvalidValue;
         us.p[k] = ustates[k];
     }
-    VCDev a{nullptr, v.kappa, v.lam, v.out, v.gacc, v.nx, v.ny, v.dt, v.rows > 0 ? v.rows : 64, 1};
-    const int64_t nstrips = (v.nx + (S - 2 * C) - 1) / (S - 2 * C);
-    const int64_t nchunks = (v.ny + a.rows - 1) / a.rows;
-    const int64_t nwaves = nstrips * nchunks;
-    const int wpg = 4;
-    const dim3 block(64 * wpg), grid((unsigned)((nwaves + wpg - 1) / wpg));
-#define HX_VC_ADJ(T, D)                                                                        \
-    do {                                                                                       \
-        if (zero_in && fold_total)                                                             \
-            hipLaunchKernelGGL((k_vc_adj<T, D, true, true>), grid, block, 0, st, a, us,        \
-                               fold_total, nstrips, nwaves);                                   \
-        else if (zero_in)                                                                      \
-            hipLaunchKernelGGL((k_vc_adj<T, D, true, false>), grid, block, 0, st, a, us,       \
-                               fold_total, nstrips, nwaves);                                   \
-        else if (fold_total)                                                                   \
-            hipLaunchKernelGGL((k_vc_adj<T, D, false, true>), grid, block, 0, st, a, us,       \
-                               fold_total, nstrips, nwaves);                                   \
-        else                                                                                   \
-            hipLaunchKernelGGL((k_vc_adj<T, D, false, false>), grid, block, 0, st, a, us,      \
-                               fold_total, nstrips, nwaves);                                   \
-    } while (0)
-    if (dtype == 0) {
-        switch (steps) {
-            case 1: HX_VC_ADJ(float, 1); break;
-            case 2: HX_VC_ADJ(float, 2); break;
-            case 3: HX_VC_ADJ(float, 3); break;
-            default: HX_VC_ADJ(float, 4); break;
-        }
-    } else {
-        switch (steps) {
-            case 1: HX_VC_ADJ(double, 1); break;
-            case 2: HX_VC_ADJ(double, 2); break;
-            case 3: HX_VC_ADJ(double, 3); break;
-            default: HX_VC_ADJ(double, 4); break;
-        }
-    }
-#undef HX_VC_ADJ
-    return hipGetLastError();
+    VCDev a{nullptr, v.kappa, v.lam, v.out, v.gacc, v.nx, v.ny, v.dt, 0, 1};
+    const int variant = (zero_in ? 1 : 0) | (fold_total ? 2 : 0);
+    const void* k = dtype == 0 ? fused_kernel<float>(true, steps, variant)
+                               : fused_kernel<double>(true, steps, variant);
+    return launch_fused(k, a, v.rows, &us, &fold_total, true, st);
 }
 
 hipError_t launch_fold(int dtype, void* acc, double* total, int64_t n, hipStream_t st) {

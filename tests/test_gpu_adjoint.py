@@ -111,10 +111,11 @@ def test_gpu_fp64_inner_product_identity(ctx, shape):
         hx.hx_buffer_destroy(ctx, b)
 
 
-def gpu_grad(ctx, u0, kappa, y, dt, T, ckpt, dtype, seg_misaligned=False):
+def gpu_grad(ctx, u0, kappa, y, dt, T, ckpt, dtype, seg_misaligned=False, rows=0):
     """(loss, lam0, dL/dkappa) from the library; seg_misaligned: the segment
     buffer is a view 4 bytes into its allocation, so the backward sweep
-    recomputes its states by single steps instead of fused passes."""
+    recomputes its states by single steps instead of fused passes; rows: rows
+    per wave (0: the library's choice)."""
     shape = u0.shape
     ny, nx = shape
     n = ny * nx
@@ -135,7 +136,7 @@ def gpu_grad(ctx, u0, kappa, y, dt, T, ckpt, dtype, seg_misaligned=False):
     bloss = hx.hx_buffer_create(ctx, 8)
     work = hx.hx_buffer_create(ctx, 4096 * 8)
     a = hx.hx_vc_args(code(dtype), nx, ny, dt, T, ckpt, bu0, bk, buT, bck if nseg > 1 else 0,
-                      bw if T > 1 else 0, bseg if S > 1 else 0, blT, bl0, bg64, bga, 0)
+                      bw if T > 1 else 0, bseg if S > 1 else 0, blT, bl0, bg64, bga, rows)
     e1 = hx.hx_heat_vc_forward(ctx, a)
     e2 = hx.hx_launch_loss(ctx, code(dtype), n, buT, by, blT, bloss, work, deps=[e1])
     e3 = hx.hx_heat_vc_backward(ctx, a, deps=[e2])
@@ -176,6 +177,23 @@ def test_checkpoint_length_does_not_change_bits(ctx):
         # the FP64 gradient total is folded once per segment, so its summation
         # grouping (not its terms) changes with S
         assert rel_l2(got[2], ref[2]) <= 1e-14
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_chunk_height_does_not_change_bits(ctx, dtype):
+    """The rows per wave of the fused passes (the library's choice, which
+    fills the device once, or the caller's) change how many halo rows are
+    recomputed, not the result: loss, lam0 and the kappa gradient are the same
+    bits at every height, one row per wave included."""
+    shape, T, ckpt = (150, 496), 11, 4
+    u0 = workloads.gaussian_bumps(*shape, 3, 5.0, 619, np.float64)
+    kappa = kappa_field(shape, 12, np.float64)
+    y = workloads.uniform(shape, 620, 0, 0, 1, np.float64)
+    ref = gpu_grad(ctx, u0, kappa, y, 0.2, T, ckpt, dtype)
+    for rows in (1, 7, 64, 1000):
+        got = gpu_grad(ctx, u0, kappa, y, 0.2, T, ckpt, dtype, rows=rows)
+        assert got[0] == ref[0], rows
+        assert np.array_equal(got[1], ref[1]) and np.array_equal(got[2], ref[2]), rows
 
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
@@ -347,7 +365,7 @@ def vc_stepped(ctx, u0, kappa, dt, T, dtype):
                                           ((257, 252), 13, 5)])
 def test_fused_forward_equals_steps_and_oracle(ctx, dtype, shape, T, ckpt):
     """The forward run in fused passes of up to four steps (strips of 248
-    output columns, chunks of 64 rows, ragged at the ends): the same bits as T
+    output columns, chunks of the library's height, ragged at the ends): the same bits as T
     single steps, every checkpoint equal to the stepped state, and the oracle's
     forward to the suite's bar."""
     u0 = workloads.gaussian_bumps(*shape, 3, 7.0, 616, np.float64).astype(dtype)
