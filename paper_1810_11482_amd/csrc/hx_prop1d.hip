@@ -745,7 +745,10 @@ void k_prop1d_bw(const PropSeg* __restrict__ segs, const u32x4* __restrict__ tab
         if (k + 1 < kLoads || u < kUnits) T[k] = tab[u];
     }
     // the window: this lane's 16-byte pieces of the block (cells 256 j + 4 l)
-    // and of the left or right 64 context cells, as in the interleaved walk
+    // and of the left or right 64 context cells, as in the interleaved walk.
+    // The block's own cells are read nontemporally (about 1 % faster than
+    // cached loads); the context cells, which the neighbouring blocks read as
+    // their own, with cached loads
     const int q = l & 15;
     const bool left = (l & 31) < 16;
     f32x4 v[5] = {};
@@ -753,7 +756,7 @@ void k_prop1d_bw(const PropSeg* __restrict__ segs, const u32x4* __restrict__ tab
         const int64_t cx = (left ? c0 - 64 : c0 + 1024) + 4 * q;
         if (c0 >= 1024 && c0 + 1024 + 64 <= s.n) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) v[j] = gload(s.in + c0 + 256 * j + 4 * l);
+            for (int j = 0; j < 4; ++j) v[j] = gload<true>(s.in + c0 + 256 * j + 4 * l);
             v[4] = gload(s.in + cx);
         } else {
 #pragma unroll
