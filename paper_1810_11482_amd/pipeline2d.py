@@ -18,9 +18,13 @@ each band an extended input of its own rows plus T halo rows on each side
                zero-Dirichlet at the extended edges), into out[p]
   D2H(p)       the own rows of out[p] -> host rows of band p
 
-K(p) depends only on H2D(p-1), H2D(p) and H2D(p+1) (through the halo copies),
-and D2H(p) on K(p): copies out of early bands run while later bands are still
-copied in.  The extended edges' wrong boundary values move inward one row per
+K(p) depends only on H2D(p-1), H2D(p) and the first T rows of H2D(p+1)
+(through the halo copies), and D2H(p) on K(p): copies out of early bands run
+while later bands are still copied in.  Each band after the first is copied
+in as two copies, its first T rows (the halo its upper neighbour reads) and
+then the rest, so K(p) need not wait for all of band p+1 to arrive: the first
+copy out, which every later one queues behind, starts a band's copy time
+earlier.  The extended edges' wrong boundary values move inward one row per
 step, so after T steps they have reached exactly the T halo rows and the own
 rows equal the whole-grid run (the grid's true top and bottom edges have no
 halo: there the zero-Dirichlet edge is the real one).  The cost is the
@@ -62,13 +66,17 @@ class Pipeline2D:
         pinned for overlap, caller-owned until the final event completes);
         `deps` gate the copies in (a run reuses the device buffers, so a
         second run must follow the first's final event).  Returns (final
-        event, H2D events, kernel events, D2H events), one of each per band
-        (no kernel events when kernels is False: then each band's input rows
-        go straight back out, the copies alone).  The caller releases the
-        events."""
+        event, H2D events, kernel events, D2H events): the H2D events in
+        submission order, one or two per band (self.h2d_index[p] lists band
+        p's, the last of which completes after the others), one kernel and one
+        D2H event per band (no kernel events when kernels is False: then each
+        band's input rows go straight back out, the copies alone).  The caller
+        releases the events."""
         ctx, rb = self.ctx, self.nx * 4
         P = len(self.bounds)
         h2d, ker, d2h = [], [], []
+        head, whole = [], []  # per band: the copy of its first rows, and of all of it
+        self.h2d_index = []
 
         def queue_band(p):
             o, s = self.bounds[p]
@@ -78,7 +86,7 @@ class Pipeline2D:
                 src = (self.top[q] + self.bounds[q][1] - self.top[p]) * rb
                 halos.append(hx_copy_async(ctx, hx_copy_desc(HX_D2D, 0, self.ext[p], 0,
                                                              self.ext[q], src, self.top[p] * rb),
-                                           [h2d[q]]))
+                                           [whole[q]]))
             if kernels and self.bot[p]:
                 # chained on the top halo's copy: the runtime continues the
                 # compute stream whose last operation is a dependency, so a
@@ -90,13 +98,13 @@ class Pipeline2D:
                 halos.append(hx_copy_async(ctx, hx_copy_desc(HX_D2D, 0, self.ext[p], dst,
                                                              self.ext[q], self.top[q] * rb,
                                                              self.bot[p] * rb),
-                                           [h2d[q]] + halos[-1:]))
+                                           [head[q]] + halos[-1:]))
             if kernels:
-                k = hx_launch_stencil(ctx, self._kernel_args(p), [h2d[p]] + halos)
+                k = hx_launch_stencil(ctx, self._kernel_args(p), [whole[p]] + halos)
                 ker.append(k)
                 src_buf, dep = self.out[p], k
             else:
-                src_buf, dep = self.ext[p], h2d[p]
+                src_buf, dep = self.ext[p], whole[p]
             for e in halos:
                 hx_event_release(ctx, e)
             d2h.append(hx_copy_async(ctx, hx_copy_desc(HX_D2H, host_out + o * rb, src_buf,
@@ -107,9 +115,30 @@ class Pipeline2D:
         # copy in (its last dependency) has been
         for p in range(P):
             o, s = self.bounds[p]
-            h2d.append(hx_copy_async(ctx, hx_copy_desc(HX_H2D, host_in + o * rb, self.ext[p],
-                                                       self.top[p] * rb, 0, 0, s * rb),
-                                     list(deps)))
+            first = self.bot[p - 1] if kernels and p >= 1 and self.bot[p - 1] < s else 0
+            idx = []
+            if first:
+                # the rows band p-1 reads as its bottom halo, then the rest
+                # (ordered after them, so its event stands for the whole band)
+                e = hx_copy_async(ctx, hx_copy_desc(HX_H2D, host_in + o * rb, self.ext[p],
+                                                    self.top[p] * rb, 0, 0, first * rb),
+                                  list(deps))
+                idx.append(len(h2d))
+                h2d.append(e)
+                head.append(e)
+                e = hx_copy_async(ctx, hx_copy_desc(HX_H2D, host_in + (o + first) * rb,
+                                                    self.ext[p], (self.top[p] + first) * rb,
+                                                    0, 0, (s - first) * rb),
+                                  list(deps) + [e])
+            else:
+                e = hx_copy_async(ctx, hx_copy_desc(HX_H2D, host_in + o * rb, self.ext[p],
+                                                    self.top[p] * rb, 0, 0, s * rb),
+                                  list(deps))
+                head.append(e)
+            idx.append(len(h2d))
+            h2d.append(e)
+            whole.append(e)
+            self.h2d_index.append(idx)
             if p >= 1:
                 queue_band(p - 1)
         queue_band(P - 1)

@@ -46,13 +46,21 @@ def test_pipeline2d_matches_oracle(ctx, ny, nx, bands, steps, tb):
     ev, h2d, ker, d2h = pl.run(hin, hout)
     assert hx.hx_wait(ctx, ev) == hx.HX_OK, hx.hx_last_error(ctx)
     assert hx.hx_hazard_count(ctx) == n0, hx.hx_hazard_report(ctx)
-    # every band's kernel starts after its own and its neighbours' copies in
-    # have ended, and its copy out starts after it has ended
+    # every band's kernel starts after its own and its upper neighbour's
+    # copies in have ended and after its lower neighbour's first rows (its
+    # bottom halo) are in, and its copy out starts after it has ended
+    assert len(pl.h2d_index) == bands and sum(map(len, pl.h2d_index)) == len(h2d)
     for p in range(bands):
         ks, ke = hx.hx_event_span(ctx, ker[p], h2d[0])
-        for q in range(max(0, p - 1), min(bands, p + 2)):
-            assert hx.hx_event_span(ctx, h2d[q], h2d[0])[1] <= ks + 1e-6
+        need = [pl.h2d_index[q][-1] for q in range(max(0, p - 1), p + 1)]
+        if p + 1 < bands:
+            need.append(pl.h2d_index[p + 1][0])
+        for i in need:
+            assert hx.hx_event_span(ctx, h2d[i], h2d[0])[1] <= ks + 1e-6
         assert ke <= hx.hx_event_span(ctx, d2h[p], h2d[0])[0] + 1e-6
+    # a band's copy in is split in two exactly where a neighbour reads its first rows
+    assert all(len(pl.h2d_index[p]) == (2 if p >= 1 and pl.bot[p - 1] < bounds[p][1] else 1)
+               for p in range(bands))
     for e in [ev] + h2d + ker + d2h:
         hx.hx_event_release(ctx, e)
     ref = oracle.heat2d_dirichlet(u0.astype(np.float64), r, steps)
