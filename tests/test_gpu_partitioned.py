@@ -67,8 +67,12 @@ def test_single_partition_graph_is_periodic_run(ctx):
     assert rel_l2(got, oracle.heat1d_periodic(u0, 0.3, 33)) <= 1e-12
 
 
-@pytest.mark.parametrize("parts,steps", [(8, 50), (5, 13), (3, 0)])
+@pytest.mark.parametrize("parts,steps", [(8, 50), (5, 13), (3, 0), (2, 7), (1, 5)])
 def test_pipeline_host_to_host(ctx, parts, steps):
+    """Host to host through hx_run_pipeline, on a context with the hazard
+    checker and timing: the output against the oracle, no unordered access,
+    every kernel after the copies in it reads, every copy out after its kernel."""
+    ctx = hx.hx_ctx_create(0, compute_streams=4, check=True, timing=True)
     n = 100003
     u0 = workloads.uniform(n, 302, parts, 0, 1, np.float32)
     bounds = workloads.partition_bounds(n, parts)
@@ -84,6 +88,14 @@ def test_pipeline_host_to_host(ctx, parts, steps):
     pd = hx.hx_pipeline_desc(base, hin, hout)
     ev, h2d, ker, d2h = hx.hx_run_pipeline(ctx, pd, op_events=True)
     assert hx.hx_wait(ctx, ev) == hx.HX_OK, hx.hx_last_error(ctx)
+    assert hx.hx_hazard_count(ctx) == 0, hx.hx_hazard_report(ctx)
+    ref0 = h2d[0]
+    for p in range(parts):
+        ks, ke = hx.hx_event_span(ctx, ker[p], ref0)
+        reads = {p} | ({(p - 1) % parts, (p + 1) % parts} if steps > 0 else set())
+        for q in reads:
+            assert hx.hx_event_span(ctx, h2d[q], ref0)[1] <= ks + 1e-6, (p, q)
+        assert ke <= hx.hx_event_span(ctx, d2h[p], ref0)[0] + 1e-6, p
     for e in h2d + ker + d2h + [ev]:
         assert hx.hx_event_query(ctx, e) == hx.HX_OK
         hx.hx_event_release(ctx, e)
@@ -93,6 +105,7 @@ def test_pipeline_host_to_host(ctx, parts, steps):
         hx.hx_buffer_destroy(ctx, b)
     hx.hx_host_free(ctx, hin)
     hx.hx_host_free(ctx, hout)
+    hx.hx_ctx_destroy(ctx)
 
 
 def test_full_size_bench_configuration_sampled(ctx):
