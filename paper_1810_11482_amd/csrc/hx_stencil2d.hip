@@ -444,6 +444,17 @@ struct BandSet {
     int n;
 };
 
+// The dispatcher hands consecutive workgroups to the eight XCDs in turn, and
+// each XCD has its own L2.  Neighbouring waves (adjacent strips of one chunk)
+// share the lines at their strip edges; this bijection of [0, n) gives every
+// XCD a contiguous range of workgroups, so that neighbouring strips mostly run
+// under one L2 (measured 1.5-2 % faster on the 16384^2 pass).
+__device__ __forceinline__ uint32_t xcd_block2d(uint32_t b, uint32_t n) {
+    constexpr uint32_t X = 8;
+    const uint32_t q = n / X, r = n % X, x = b % X;
+    return x * q + (x < r ? x : r) + b / X;
+}
+
 template <typename T, int C, int D, bool FAST, bool SC>
 __global__ __launch_bounds__(256) void k_stencil2d(BandSet set, int rows, int halo,
                                                    int64_t nstrips) {
@@ -453,7 +464,8 @@ __global__ __launch_bounds__(256) void k_stencil2d(BandSet set, int rows, int ha
     static_assert(C % VN == 0, "columns per lane must be a multiple of the vector width");
     static_assert(Q % 3 == 0 && Q >= 6, "the level-0 ring must be a multiple of 3 rows");
     const int wpg = blockDim.x >> 6;
-    const int64_t wave = (int64_t)blockIdx.x * wpg + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t wave = (int64_t)xcd_block2d(blockIdx.x, gridDim.x) * wpg +
+                         __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (wave >= set.first[set.n]) return;
     int kb = 0;
     while (kb + 1 < set.n && wave >= set.first[kb + 1]) ++kb;
