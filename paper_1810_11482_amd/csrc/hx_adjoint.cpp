@@ -254,8 +254,12 @@ hx_status hx_heat_vc_backward(hx_ctx ctx, const hx_vc_args* a, const hx_event* d
                     }
                 }
                 if (fused_adj) {  // reverse sweep, fused
+                    // at most two steps per FP64 pass: deeper FP64 passes need
+                    // more than the 512 registers a wave can hold and spill
+                    // hundreds of them to scratch (any depth gives the same bits)
                     const int L = t1 - t0;
-                    const int np = (L + kVcFusedMax - 1) / kVcFusedMax;
+                    const int dmax = dt == HX_F32 ? kVcFusedMax : 2;
+                    const int np = (L + dmax - 1) / dmax;
                     int tb = t1 - 1;
                     for (int j = 0; j < np; ++j) {
                         const int d = L / np + (j < L % np ? 1 : 0);
